@@ -1,0 +1,209 @@
+#!/usr/bin/env python3
+"""Throughput of the stabilizer-tableau hot path on one MI355X.
+
+Workload (the 180,000-qubit, depth-1000 generator circuit): each step resets
+the tableau to |0...0>, applies all 1000 random layers (about 198 million
+non-identity gates, fused into passes) and then performs the first M Z
+measurements (qubits 0..M-1 in order) of the circuit's final all-qubit
+measurement. Inputs (the compiled gate passes) are resident in HBM before
+timing starts; outcomes stay on the device.
+
+Prints one JSON line: gates/s of the gate phase as `value`, measurements/s of
+the measurement phase, the roofline of the dominant kernel (algorithmic bytes
+per launch / average launch duration, both measured here with HIP events on
+the library's stream) and the CPU oracle timed on a bounded sample.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, AMD public specification
+
+
+def log(msg: str):
+    print(f"[bench {time.strftime('%H:%M:%S')}] {msg}", file=sys.stderr, flush=True)
+
+
+def build_ops(cfg, layers: int, nmeas: int):
+    from workload import OP_DTYPE, OP_MEASURE, iter_circuit
+    parts = []
+    t0 = time.time()
+    for k, (kind, arr) in enumerate(iter_circuit(cfg, depth=layers, final_measure=False)):
+        parts.append(arr)
+        if (k + 1) % 200 == 0:
+            log(f"generated {k + 1}/{layers} layers ({time.time() - t0:.1f} s)")
+    gates = np.concatenate(parts) if parts else np.empty(0, dtype=OP_DTYPE)
+    meas = np.empty(nmeas, dtype=OP_DTYPE)
+    meas["type"] = OP_MEASURE
+    meas["q0"] = np.arange(nmeas, dtype=np.uint32)
+    meas["q1"] = 0
+    return gates, meas, parts
+
+
+def cpu_baseline(cfg, layer_parts, seconds: float, nrows: int = 64):
+    """The oracle evolving a sample of rows (rows evolve independently under
+    gates) through as many layers as fit in about `seconds`; scaled to gates/s
+    of the whole 2n-row tableau."""
+    from oracle import oracle as orc
+    n = cfg.n
+    rows = list(range(n, n + nrows // 2)) + list(range(0, nrows // 2))
+    sub = orc.Tableau(n, rows=rows)
+    t0 = time.time()
+    gates_done = 0
+    layers_done = 0
+    for arr in layer_parts:
+        sub.run(arr)
+        gates_done += int(arr.size)
+        layers_done += 1
+        if time.time() - t0 > seconds:
+            break
+    dt = time.time() - t0
+    row_gate_rate = gates_done * nrows / dt
+    return {
+        "value": row_gate_rate / (2 * n),
+        "unit": "gates/s",
+        "cores": orc.num_threads(),
+        "kind": "oracle",
+        "sample": f"{nrows} of the {2 * n} tableau rows through the first {layers_done} layers "
+                  f"({gates_done} gates, {dt:.1f} s); rate scaled by {nrows}/{2 * n}",
+    }
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=2)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--layers", type=int, default=1000)
+    ap.add_argument("--meas", type=int, default=500)
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only; --gpus {args.gpus} is not supported "
+              "(the multi-GPU row-sharded design is not built).", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import paper_2603_14641_amd as sq
+    from paper_2603_14641_amd import binding as sqb
+    from workload import CONFIGS
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    torch.cuda.set_device(0)
+    sq.load()
+    cfg = CONFIGS[4]
+    n = cfg.n
+    log(f"generating {args.layers} layers of n={n}")
+    gates, meas, layer_parts = build_ops(cfg, args.layers, args.meas)
+    log(f"{gates.size} gates; compiling")
+    pg = sq.Program(n, gates)
+    pm = sq.Program(n, meas)
+    log(f"{pg.num_passes} gate passes, {pg.gate_bytes / 1e9:.1f} GB algorithmic per step")
+    stream = torch.cuda.current_stream()
+    t = sq.Tableau(n, stream=stream)
+    out_bits = torch.zeros(max(args.meas, 1), dtype=torch.uint8, device="cuda")
+    out_rand = torch.zeros(max(args.meas, 1), dtype=torch.uint8, device="cuda")
+
+    def step(record=None):
+        t.reset()
+        if record:
+            record[0].record(stream)
+        t.run(pg, cfg.seed, 0, 0, out_bits.data_ptr(), out_rand.data_ptr())
+        if record:
+            record[1].record(stream)
+        t.run(pm, cfg.seed, 0, 0, out_bits.data_ptr(), out_rand.data_ptr())
+        if record:
+            record[2].record(stream)
+
+    for w in range(args.warmup):
+        step()
+        torch.cuda.synchronize()
+        log(f"warmup step {w + 1}/{args.warmup} done")
+
+    t.profile_reset()
+    t.profile(True)
+    st0 = t.measure_stats()
+    events = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(args.steps)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        step(events[k])
+        if k + 1 < args.steps:
+            torch.cuda.synchronize()
+            log(f"step {k + 1}/{args.steps} done")
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    t.profile(False)
+    log(f"timed {args.steps} steps in {wall:.2f} s")
+    st1 = t.measure_stats()
+    gate_ms = sum(e[0].elapsed_time(e[1]) for e in events)
+    meas_ms = sum(e[1].elapsed_time(e[2]) for e in events)
+    assert t.error_flags() == 0
+
+    kern = {name: t.profile_read(i) for i, name in enumerate(sqb.KERNEL_NAMES)}
+    layer_ms, layer_n = kern["layer"]
+    rowsum_ms, rowsum_n = kern["rowsum"]
+    layer_bytes = pg.gate_bytes / max(pg.num_passes, 1)
+    layer_gbs = layer_bytes / (layer_ms / layer_n * 1e-3) / 1e9
+    n_random = st1.n_random - st0.n_random
+    rowsum_bytes = (st1.rowsum_bytes - st0.rowsum_bytes) / max(n_random, 1)
+    rowsum_gbs = rowsum_bytes / (rowsum_ms / max(rowsum_n, 1) * 1e-3) / 1e9 if rowsum_n else 0.0
+    roof_layer = {"kernel": "k_layer", "bound": "hbm", "achieved": round(layer_gbs, 1), "peak": HBM_PEAK_GBS,
+                  "unit": "GB/s", "frac": round(layer_gbs / HBM_PEAK_GBS, 4), "traffic": None,
+                  "bytes_per_launch": int(layer_bytes), "avg_launch_ms": round(layer_ms / layer_n, 4)}
+    roof_rowsum = {"kernel": "k_rowsum", "bound": "hbm", "achieved": round(rowsum_gbs, 1), "peak": HBM_PEAK_GBS,
+                   "unit": "GB/s", "frac": round(rowsum_gbs / HBM_PEAK_GBS, 4), "traffic": None,
+                   "bytes_per_launch": int(rowsum_bytes),
+                   "avg_launch_ms": round(rowsum_ms / max(rowsum_n, 1), 4)}
+    dominant, other = (roof_layer, roof_rowsum) if layer_ms >= rowsum_ms else (roof_rowsum, roof_layer)
+
+    gates_per_step = int(pg.num_gates)
+    result = {
+        "metric": "gates/s & measurements/s at n=180k (HBM % of peak); batched vs plain shots/s",
+        "value": gates_per_step * args.steps / (gate_ms * 1e-3),
+        "unit": "gates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": wall * 1e3 / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "u64",
+        "data": "synthetic",
+        "config": {
+            "workload": f"n=180000 generator circuit (seed {cfg.seed}): {args.layers} layers + first "
+                        f"{args.meas} of the final 180000 Z-measurements per step",
+            "n": n, "layers": args.layers, "gates_per_step": gates_per_step, "passes_per_step": pg.num_passes,
+            "measurements_per_step": args.meas,
+        },
+        "measurements_per_s": args.meas * args.steps / (meas_ms * 1e-3),
+        "gate_phase_ms_per_step": gate_ms / args.steps,
+        "meas_phase_ms_per_step": meas_ms / args.steps,
+        "random_measurements": int(n_random),
+        "roofline": dominant,
+        "roofline_other": other,
+        "kernel_ms": {k: round(v[0], 3) for k, v in kern.items()},
+        "kernel_launches": {k: v[1] for k, v in kern.items()},
+    }
+    if not args.no_cpu_baseline:
+        log(f"CPU oracle baseline (~{args.cpu_seconds:.0f} s)")
+        result["cpu_baseline"] = cpu_baseline(cfg, layer_parts, args.cpu_seconds)
+    else:
+        result["cpu_baseline"] = None
+    t.close()
+    print(json.dumps(result), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,218 @@
+/*
+ * sq.h -- C ABI of the MI355X stabilizer-tableau library (libsq.so).
+ *
+ * The library keeps a CHP tableau (Aaronson-Gottesman destabilizer form; the
+ * paper's "Tableau Formalism" and "The CHP algorithm" sections) of n qubits
+ * resident in GPU memory and evolves it with hand-written HIP kernels for
+ * gfx950:
+ *   - gate layers (H, S, S^dagger, X, Y, Z, CX, CZ), the column update rules
+ *     of the "Tableau Formalism" section (equation update_rules, extended by
+ *     conjugation to the other gates), all gates of a layer fused into passes
+ *     over the touched columns ("Tableau Evolution under Clifford Gates");
+ *   - projective Z measurement: pivot search, the parallel rowsum of every
+ *     anticommuting row with the pivot stabilizer (exact mod-4 phase), and
+ *     the destabilizer product for deterministic outcomes ("The CHP
+ *     algorithm", probabilistic and deterministic cases).
+ *
+ * Conventions shared by every call:
+ *   - All functions return sq_status (0 = SQ_OK, negative = error) unless
+ *     documented otherwise; sq_last_error() then describes the failure
+ *     (thread-local string, valid until the next call on that thread).
+ *   - Validation happens before any device work: a call that fails with
+ *     SQ_EINVAL or SQ_ERANGE leaves the tableau unchanged.
+ *   - A handle owns its device memory. Host buffers are owned by the caller
+ *     and are only read or written during the call, except where a call is
+ *     documented as asynchronous.
+ *   - All device work of a handle is ordered on the HIP stream given at
+ *     creation (NULL = the default stream). Calls that return results in
+ *     host memory synchronize that stream before returning.
+ *   - A handle must not be used from two threads at once; distinct handles
+ *     are independent.
+ *
+ * Tableau semantics: rows 0..n-1 are the destabilizers D_i, rows n..2n-1 the
+ * stabilizers S_i; row g is the Pauli string (-1)^{r_g} P_0 ... P_{n-1} with
+ * P_j = I, X, Z, Y for (x_gj, z_gj) = (0,0), (1,0), (0,1), (1,1). A new
+ * tableau is |0...0>: D_i = +X_i, S_i = +Z_i.
+ *
+ * Random outcomes: measurement number m of shot `shot` (counted over every
+ * measurement, deterministic ones included, starting at meas_base) draws
+ * coin = bit 0 of word 0 of Philox4x64-10(counter = (m, 0, 0, 0),
+ * key = (seed, shot)) (Salmon et al., SC'11). A random outcome equals its coin.
+ */
+#ifndef LIBSQ_SQ_H_
+#define LIBSQ_SQ_H_
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  SQ_OK = 0,
+  SQ_EINVAL = -1,   /* bad argument (NULL pointer, unknown gate type, qubit pair with a == b, ...) */
+  SQ_ENOMEM = -2,   /* device or host allocation failed */
+  SQ_EDEVICE = -3,  /* a HIP runtime call failed */
+  SQ_ERANGE = -5,   /* a qubit index >= n, or a size above a stated limit */
+  SQ_ESTATE = -6,   /* a device-side consistency check failed (see sq_error_flags) */
+} sq_status;
+
+/* Operation type codes. Gate records and programs use the same codes. */
+typedef enum {
+  SQ_I = 0, SQ_H = 1, SQ_S = 2, SQ_SDG = 3, SQ_X = 4, SQ_Y = 5, SQ_Z = 6,
+  SQ_CX = 7, /* q0 = control, q1 = target */
+  SQ_CZ = 8,
+  SQ_MEASURE = 15 /* Z measurement of q0 (programs only) */
+} sq_op_type;
+
+/* One operation: 12 bytes, three little-endian uint32. q1 is ignored by
+ * single-qubit gates and measurements. */
+typedef struct {
+  uint32_t type;
+  uint32_t q0;
+  uint32_t q1;
+} sq_op;
+
+typedef struct sq_tableau sq_tableau;   /* opaque; owns its device memory */
+typedef struct sq_program sq_program;   /* opaque; a compiled, device-resident circuit */
+
+/* Message of the last failed call on this thread ("" if none). */
+const char *sq_last_error(void);
+/* Library version string. */
+const char *sq_version(void);
+
+/* Device bytes a tableau of n qubits needs (tableau plus working buffers),
+ * for admission control. 0 if n is 0 or above SQ_MAX_QUBITS. */
+#define SQ_MAX_QUBITS 1048576u
+size_t sq_bytes_required(uint32_t n);
+
+/* Create a tableau of n qubits (1 <= n <= SQ_MAX_QUBITS) in |0...0> on the
+ * current HIP device. hip_stream is a hipStream_t (NULL = default stream);
+ * the caller keeps the stream alive for the handle's lifetime.
+ * Errors: SQ_EINVAL (out == NULL, n == 0), SQ_ERANGE (n too large),
+ * SQ_ENOMEM, SQ_EDEVICE. */
+sq_status sq_create(uint32_t n, void *hip_stream, sq_tableau **out);
+/* Wait for the handle's work, then free it. NULL is accepted. */
+sq_status sq_destroy(sq_tableau *t);
+/* Reset to |0...0> and clear the error flags (asynchronous). */
+sq_status sq_reset(sq_tableau *t);
+/* Block until all device work queued on the handle has finished. */
+sq_status sq_sync(sq_tableau *t);
+uint32_t sq_num_qubits(const sq_tableau *t);
+
+/* Apply gates (host array, program order) to every row. Qubits may repeat:
+ * the library groups the sequence into passes of disjoint one- or two-qubit
+ * groups and applies each pass in one fused launch. Asynchronous with
+ * respect to the device (the host array may be reused on return).
+ * Errors: SQ_EINVAL (NULL ops with count > 0, type not a gate, CX/CZ with
+ * q0 == q1), SQ_ERANGE (qubit >= n). */
+sq_status sq_apply_gates(sq_tableau *t, const sq_op *host_ops, uint64_t count);
+
+/* Measure Z on host_qubits[0..count) in that order (measurement index
+ * meas_base + i for the i-th), updating the tableau after each. Writes the
+ * outcome bits (0/1) to host_out_bits[0..count) and, if host_out_random is
+ * not NULL, 1/0 for random/deterministic outcomes. Blocks until written.
+ * Errors: SQ_EINVAL, SQ_ERANGE (qubit >= n), SQ_ESTATE (a device check of
+ * the phase arithmetic failed; the tableau is then unreliable). */
+sq_status sq_measure(sq_tableau *t, const uint32_t *host_qubits, uint32_t count,
+                     uint64_t seed, uint64_t shot, uint64_t meas_base,
+                     uint8_t *host_out_bits, uint8_t *host_out_random);
+
+/* Compile a circuit of n qubits (gates and SQ_MEASURE records in program
+ * order) into a device-resident program on the current device.
+ * Errors as sq_apply_gates, plus SQ_ENOMEM. */
+sq_status sq_program_create(uint32_t n, const sq_op *host_ops, uint64_t count, sq_program **out);
+sq_status sq_program_destroy(sq_program *p);
+uint64_t sq_program_num_measurements(const sq_program *p);
+uint64_t sq_program_num_gates(const sq_program *p);
+/* Number of fused gate passes the program launches. */
+uint64_t sq_program_num_passes(const sq_program *p);
+
+/* Host-only inspection of how a gate sequence is grouped into passes (no
+ * device work; usable without a GPU). Writes, per pass, one word with the
+ * pass's group count, then three words per group: slot-A qubit (bits 0..23)
+ * with changed-column flags xa, za, xb, zb (bits 24..27), slot-B qubit
+ * (0xFFFFFFFF for a one-qubit group), and up to 16 4-bit micro-ops, LSB
+ * first, 0-terminated (1..6: H, S, S^dagger, X, Y, Z on slot A; 7..12 the
+ * same on slot B; 13 CX A->B; 14 CX B->A; 15 CZ). *out_len receives the
+ * number of words needed; nothing is written past cap.
+ * Errors as sq_apply_gates. */
+sq_status sq_plan_gates(uint32_t n, const sq_op *host_ops, uint64_t count, uint64_t *out, uint64_t cap,
+                        uint64_t *out_len);
+
+/* Run a program on a tableau of the same n. Asynchronous: all work is queued
+ * on the handle's stream. Outcome i (i-th measurement of the program, index
+ * meas_base + i) is written to dev_out_bits[i] and, if not NULL,
+ * dev_out_random[i]; both are device buffers of sq_program_num_measurements
+ * bytes that must stay valid until the stream reaches that point.
+ * Errors: SQ_EINVAL (NULL, n mismatch). */
+sq_status sq_run(sq_tableau *t, const sq_program *p, uint64_t seed, uint64_t shot, uint64_t meas_base,
+                 uint8_t *dev_out_bits, uint8_t *dev_out_random);
+
+/* Copy rows out in canonical row-major form: for the k-th requested global
+ * row g (0 <= g < 2n), host_x[k*W + j/64] bit j%64 = x_gj (W = ceil(n/64)),
+ * likewise host_z, and host_r[k] = r_g. Blocks. */
+sq_status sq_export_rows(sq_tableau *t, const uint32_t *host_rows, uint32_t nrows,
+                         uint64_t *host_x, uint64_t *host_z, uint8_t *host_r);
+/* All 2n rows (host_x, host_z: 2n*W words; host_r: 2n bytes). Blocks. */
+sq_status sq_export(sq_tableau *t, uint64_t *host_x, uint64_t *host_z, uint8_t *host_r);
+/* Replace the whole tableau from the canonical row-major form (bits at
+ * positions >= n in the last word of a row must be 0). Blocks. */
+sq_status sq_import(sq_tableau *t, const uint64_t *host_x, const uint64_t *host_z, const uint8_t *host_r);
+
+/* Byte accounting of the measurements run since creation or reset: counts
+ * of random and deterministic outcomes, and the algorithmic bytes of their
+ * passes. Rowsum: for every row word holding an anticommuting row, read x and
+ * z of each non-identity column of the pivot row and write x (where the pivot
+ * has x) and z (where it has z). Deterministic: read x and z of every column
+ * at each word holding a destabilizer that anticommutes with Z_q. Blocks. */
+typedef struct {
+  uint64_t n_random;
+  uint64_t n_det;
+  uint64_t rowsum_bytes;
+  uint64_t det_bytes;
+} sq_meas_stats;
+sq_status sq_measure_stats(sq_tableau *t, sq_meas_stats *out);
+
+/* Algorithmic bytes of all gate passes of a program: per group, read x and z
+ * of its one or two columns and write the columns its gates change (the
+ * sign column, 2*L words per pass, is not counted). */
+uint64_t sq_program_gate_bytes(const sq_program *p);
+
+/* Device-side consistency flags accumulated since creation or reset
+ * (bit 0: a rowsum phase exponent was odd; bit 1: a deterministic product was
+ * not +-Z_q). Blocks. */
+sq_status sq_error_flags(sq_tableau *t, uint32_t *flags);
+
+/* Launch geometry. 0 in a field keeps the current value. Block sizes must be
+ * multiples of 64 in [64, 1024]; words per thread 1 or 2. */
+typedef struct {
+  uint32_t layer_block;        /* threads per workgroup of the gate-pass kernel */
+  uint32_t layer_wpt;          /* tableau words per thread in the gate-pass kernel */
+  uint32_t layer_groups;       /* gate groups per workgroup (per chunk) */
+  uint32_t rowsum_block;       /* threads per workgroup of the rowsum kernel */
+  uint32_t rowsum_wpt;         /* words per thread in the rowsum kernel */
+  uint32_t rowsum_cols;        /* pivot-row columns per workgroup (per chunk) */
+  uint32_t det_block;          /* threads per workgroup of the deterministic-phase kernel */
+  uint32_t det_cols;           /* columns per workgroup of the deterministic-phase kernel */
+} sq_tuning;
+sq_status sq_get_tuning(const sq_tableau *t, sq_tuning *out);
+sq_status sq_set_tuning(sq_tableau *t, const sq_tuning *in);
+
+/* Per-kernel timing with HIP events recorded on the handle's stream around
+ * every launch while enabled. Kernel ids: */
+enum {
+  SQ_K_LAYER = 0, SQ_K_SIGNS = 1, SQ_K_PIVOT = 2, SQ_K_GATHER = 3, SQ_K_ROWSUM = 4,
+  SQ_K_FINAL = 5, SQ_K_DET = 6, SQ_K_DETFINAL = 7, SQ_K_COUNT = 8
+};
+sq_status sq_profile_enable(sq_tableau *t, int on);
+/* Sum of kernel durations (ms) and launch count for one kernel id since the
+ * last sq_profile_reset. Blocks. */
+sq_status sq_profile_read(sq_tableau *t, int kernel, double *total_ms, uint64_t *launches);
+sq_status sq_profile_reset(sq_tableau *t);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* LIBSQ_SQ_H_ */

@@ -41,6 +41,7 @@ typedef struct {
   uint8_t *r;        /* nrows sign bits */
   uint64_t odd;      /* count of rowsums whose phase exponent was odd (must stay 0) */
   uint64_t badscratch; /* count of deterministic products that were not +-Z_q */
+  uint64_t det_phase2; /* deterministic outcomes whose summed phase exponents were 2 mod 4 */
 } sqo_tab;
 
 /* ------------------------------------------------------------------ */
@@ -159,15 +160,22 @@ int sqo_gsum_word(uint64_t x1, uint64_t z1, uint64_t x2, uint64_t z2) {
 /* rowsum(h, i): row h <- P_i * P_h. The phase exponent
  * e = 2 r_h + 2 r_i + sum_j g(x_ij, z_ij, x_hj, z_hj) (mod 4) must be 0 or 2;
  * r_h <- e / 2. Returns 1 if e was odd (an error: the product is not
- * Hermitian). */
-static int row_mul(uint64_t *xh, uint64_t *zh, uint8_t *rh,
-                   const uint64_t *xi, const uint64_t *zi, uint8_t ri, uint32_t W) {
-  int e = 2 * (int)*rh + 2 * (int)ri;
-  for (uint32_t w = 0; w < W; ++w) e += sqo_gsum_word(xi[w], zi[w], xh[w], zh[w]);
+ * Hermitian). If gsum is not NULL, the g sum (mod 4) is added to it. */
+static int row_mul_g(uint64_t *xh, uint64_t *zh, uint8_t *rh,
+                     const uint64_t *xi, const uint64_t *zi, uint8_t ri, uint32_t W, int *gsum) {
+  int g = 0;
+  for (uint32_t w = 0; w < W; ++w) g += sqo_gsum_word(xi[w], zi[w], xh[w], zh[w]);
+  if (gsum) *gsum = (*gsum + g) & 3;
+  int e = 2 * (int)*rh + 2 * (int)ri + g;
   e &= 3;
   for (uint32_t w = 0; w < W; ++w) { xh[w] ^= xi[w]; zh[w] ^= zi[w]; }
   *rh = (uint8_t)(e >> 1);
   return e & 1;
+}
+
+static int row_mul(uint64_t *xh, uint64_t *zh, uint8_t *rh,
+                   const uint64_t *xi, const uint64_t *zi, uint8_t ri, uint32_t W) {
+  return row_mul_g(xh, zh, rh, xi, zi, ri, W, NULL);
 }
 
 /* ------------------------------------------------------------------ */
@@ -224,6 +232,7 @@ uint32_t sqo_words(const sqo_tab *t) { return t->W; }
 uint32_t sqo_nrows(const sqo_tab *t) { return t->nrows; }
 uint64_t sqo_odd_count(const sqo_tab *t) { return t->odd; }
 uint64_t sqo_badscratch_count(const sqo_tab *t) { return t->badscratch; }
+uint64_t sqo_det_phase2_count(const sqo_tab *t) { return t->det_phase2; }
 
 /* Copy the held rows out (row k of the outputs is held row k). */
 void sqo_get_rows(const sqo_tab *t, uint64_t *x, uint64_t *z, uint8_t *r) {
@@ -310,11 +319,13 @@ static int measure(sqo_tab *t, uint32_t q, int coin, int *was_random) {
   uint64_t *sx = (uint64_t *)calloc(t->W, sizeof(uint64_t));
   uint64_t *sz = (uint64_t *)calloc(t->W, sizeof(uint64_t));
   uint8_t sr = 0;
+  int gsum = 0;
   for (uint32_t i = 0; i < n; ++i) {
     if (!getb(ROWX(t, (uint32_t)t->local[i]), q)) continue;
     uint32_t s = (uint32_t)t->local[n + i];
-    t->odd += (uint64_t)row_mul(sx, sz, &sr, ROWX(t, s), ROWZ(t, s), t->r[s], t->W);
+    t->odd += (uint64_t)row_mul_g(sx, sz, &sr, ROWX(t, s), ROWZ(t, s), t->r[s], t->W, &gsum);
   }
+  if (gsum == 2) t->det_phase2++;
   int ok = 1;
   for (uint32_t w = 0; w < t->W; ++w) {
     uint64_t want_z = (w == (q >> 6)) ? (1ULL << (q & 63)) : 0;

@@ -49,6 +49,8 @@ def _bind(lib):
     lib.sqo_odd_count.argtypes = [vp]
     lib.sqo_badscratch_count.restype = u64
     lib.sqo_badscratch_count.argtypes = [vp]
+    lib.sqo_det_phase2_count.restype = u64
+    lib.sqo_det_phase2_count.argtypes = [vp]
     lib.sqo_get_rows.restype = None
     lib.sqo_get_rows.argtypes = [vp, vp, vp, vp]
     lib.sqo_set_rows.restype = None
@@ -155,6 +157,11 @@ class Tableau:
     @property
     def odd_count(self) -> int:
         return int(self.lib.sqo_odd_count(self.h))
+
+    @property
+    def det_phase2_count(self) -> int:
+        """Deterministic outcomes whose summed phase exponents were 2 (mod 4)."""
+        return int(self.lib.sqo_det_phase2_count(self.h))
 
     @property
     def badscratch_count(self) -> int:

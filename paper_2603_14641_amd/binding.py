@@ -1,0 +1,299 @@
+"""ctypes binding of libsq.so: argument marshalling only.
+
+Every step of the simulation runs in the HIP kernels behind the C ABI
+(include/sq.h). There is no CPU fallback: if the library is missing, or a
+call fails, this module raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional, Sequence, Tuple
+
+import numpy as np
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "libsq.so")
+
+# status codes and op types (include/sq.h)
+SQ_OK, SQ_EINVAL, SQ_ENOMEM, SQ_EDEVICE, SQ_ERANGE, SQ_ESTATE = 0, -1, -2, -3, -5, -6
+I, H, S, SDG, X, Y, Z, CX, CZ, MEASURE = 0, 1, 2, 3, 4, 5, 6, 7, 8, 15
+K_LAYER, K_SIGNS, K_PIVOT, K_GATHER, K_ROWSUM, K_FINAL, K_DET, K_DETFINAL = range(8)
+KERNEL_NAMES = ["layer", "signs", "pivot", "gather", "rowsum", "finalize", "detphase", "detfinal"]
+
+EXPORTED = [
+    "sq_last_error", "sq_version", "sq_bytes_required", "sq_create", "sq_destroy", "sq_reset", "sq_sync",
+    "sq_num_qubits", "sq_apply_gates", "sq_measure", "sq_program_create", "sq_program_destroy",
+    "sq_program_num_measurements", "sq_program_num_gates", "sq_program_num_passes", "sq_program_gate_bytes",
+    "sq_plan_gates",
+    "sq_run", "sq_export_rows", "sq_export", "sq_import", "sq_measure_stats", "sq_error_flags",
+    "sq_get_tuning", "sq_set_tuning", "sq_profile_enable", "sq_profile_read", "sq_profile_reset",
+]
+
+
+class SqError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"sq error {status}: {msg}")
+        self.status = status
+
+
+class Tuning(ctypes.Structure):
+    _fields_ = [(name, ctypes.c_uint32) for name in (
+        "layer_block", "layer_wpt", "layer_groups", "rowsum_block", "rowsum_wpt", "rowsum_cols",
+        "det_block", "det_cols")]
+
+
+class MeasStats(ctypes.Structure):
+    _fields_ = [("n_random", ctypes.c_uint64), ("n_det", ctypes.c_uint64),
+                ("rowsum_bytes", ctypes.c_uint64), ("det_bytes", ctypes.c_uint64)]
+
+
+_lib = None
+
+
+def load(path: str = LIB_PATH):
+    """Load libsq.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise ImportError(f"{path} is missing: build it with __graft_entry__.build() "
+                          "(hipcc --offload-arch=gfx950)")
+    lib = ctypes.CDLL(path)
+    vp, u32, u64, i32 = ctypes.c_void_p, ctypes.c_uint32, ctypes.c_uint64, ctypes.c_int
+    pvp = ctypes.POINTER(ctypes.c_void_p)
+    sig = {
+        "sq_last_error": (ctypes.c_char_p, []),
+        "sq_version": (ctypes.c_char_p, []),
+        "sq_bytes_required": (ctypes.c_size_t, [u32]),
+        "sq_create": (i32, [u32, vp, pvp]),
+        "sq_destroy": (i32, [vp]),
+        "sq_reset": (i32, [vp]),
+        "sq_sync": (i32, [vp]),
+        "sq_num_qubits": (u32, [vp]),
+        "sq_apply_gates": (i32, [vp, vp, u64]),
+        "sq_measure": (i32, [vp, vp, u32, u64, u64, u64, vp, vp]),
+        "sq_program_create": (i32, [u32, vp, u64, pvp]),
+        "sq_program_destroy": (i32, [vp]),
+        "sq_program_num_measurements": (u64, [vp]),
+        "sq_program_num_gates": (u64, [vp]),
+        "sq_program_num_passes": (u64, [vp]),
+        "sq_program_gate_bytes": (u64, [vp]),
+        "sq_plan_gates": (i32, [u32, vp, u64, vp, u64, ctypes.POINTER(u64)]),
+        "sq_run": (i32, [vp, vp, u64, u64, u64, vp, vp]),
+        "sq_export_rows": (i32, [vp, vp, u32, vp, vp, vp]),
+        "sq_export": (i32, [vp, vp, vp, vp]),
+        "sq_import": (i32, [vp, vp, vp, vp]),
+        "sq_measure_stats": (i32, [vp, ctypes.POINTER(MeasStats)]),
+        "sq_error_flags": (i32, [vp, ctypes.POINTER(u32)]),
+        "sq_get_tuning": (i32, [vp, ctypes.POINTER(Tuning)]),
+        "sq_set_tuning": (i32, [vp, ctypes.POINTER(Tuning)]),
+        "sq_profile_enable": (i32, [vp, i32]),
+        "sq_profile_read": (i32, [vp, i32, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(u64)]),
+        "sq_profile_reset": (i32, [vp]),
+    }
+    for name, (res, args) in sig.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    _lib = lib
+    return lib
+
+
+def _check(status: int):
+    if status != SQ_OK:
+        raise SqError(status, load().sq_last_error().decode())
+
+
+def ops_array(ops) -> np.ndarray:
+    """(count, 3) uint32 records (type, q0, q1) from a structured or plain array."""
+    a = np.asarray(ops)
+    if a.dtype.names:
+        a = np.stack([a["type"], a["q0"], a["q1"]], axis=1)
+    return np.ascontiguousarray(np.asarray(a, dtype=np.uint32).reshape(-1, 3))
+
+
+def _stream_ptr(stream) -> Optional[int]:
+    if stream is None:
+        return None
+    if isinstance(stream, int):
+        return stream
+    return int(stream.cuda_stream)
+
+
+class Program:
+    """A compiled circuit resident on the device (sq_program)."""
+
+    def __init__(self, n: int, ops):
+        self.lib = load()
+        self._ops = ops_array(ops)
+        h = ctypes.c_void_p()
+        _check(self.lib.sq_program_create(int(n), self._ops.ctypes.data, self._ops.shape[0], ctypes.byref(h)))
+        self.h = h
+        self.n = int(n)
+        self.num_measurements = int(self.lib.sq_program_num_measurements(h))
+        self.num_gates = int(self.lib.sq_program_num_gates(h))
+        self.num_passes = int(self.lib.sq_program_num_passes(h))
+        self.gate_bytes = int(self.lib.sq_program_gate_bytes(h))
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.lib.sq_program_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Tableau:
+    """A CHP tableau of n qubits resident on the current HIP device."""
+
+    def __init__(self, n: int, stream=None):
+        self.lib = load()
+        h = ctypes.c_void_p()
+        _check(self.lib.sq_create(int(n), _stream_ptr(stream), ctypes.byref(h)))
+        self.h = h
+        self.n = int(n)
+        self.W = (self.n + 63) // 64
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.lib.sq_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    # -- evolution -----------------------------------------------------------
+    def reset(self):
+        _check(self.lib.sq_reset(self.h))
+
+    def sync(self):
+        _check(self.lib.sq_sync(self.h))
+
+    def apply_gates(self, ops):
+        a = ops_array(ops)
+        _check(self.lib.sq_apply_gates(self.h, a.ctypes.data, a.shape[0]))
+
+    def measure(self, qubits: Sequence[int], seed: int = 0, shot: int = 0, meas_base: int = 0
+                ) -> Tuple[np.ndarray, np.ndarray]:
+        q = np.ascontiguousarray(np.asarray(qubits, dtype=np.uint32).reshape(-1))
+        bits = np.zeros(max(q.size, 1), dtype=np.uint8)
+        rnd = np.zeros(max(q.size, 1), dtype=np.uint8)
+        _check(self.lib.sq_measure(self.h, q.ctypes.data, q.size, seed, shot, meas_base,
+                                   bits.ctypes.data, rnd.ctypes.data))
+        return bits[:q.size], rnd[:q.size]
+
+    def run(self, program: Program, seed: int, shot: int, meas_base: int, dev_bits_ptr: int,
+            dev_rand_ptr: Optional[int] = None):
+        """Queue a program; outcomes land in device buffers (e.g. torch uint8 tensors' data_ptr())."""
+        _check(self.lib.sq_run(self.h, program.h, seed, shot, meas_base, dev_bits_ptr, dev_rand_ptr))
+
+    def run_to_host(self, program: Program, seed: int = 0, shot: int = 0, meas_base: int = 0
+                    ) -> Tuple[np.ndarray, np.ndarray]:
+        """Run a program and copy its outcomes back (uses torch for the device buffers)."""
+        import torch
+        m = max(program.num_measurements, 1)
+        bits = torch.zeros(m, dtype=torch.uint8, device="cuda")
+        rnd = torch.zeros(m, dtype=torch.uint8, device="cuda")
+        torch.cuda.current_stream().synchronize()
+        self.run(program, seed, shot, meas_base, bits.data_ptr(), rnd.data_ptr())
+        self.sync()
+        k = program.num_measurements
+        return bits.cpu().numpy()[:k], rnd.cpu().numpy()[:k]
+
+    # -- state access --------------------------------------------------------
+    def export_rows(self, rows: Sequence[int]) -> Tuple[np.ndarray, np.ndarray, np.ndarray]:
+        r = np.ascontiguousarray(np.asarray(rows, dtype=np.uint32).reshape(-1))
+        x = np.zeros((r.size, self.W), dtype=np.uint64)
+        z = np.zeros((r.size, self.W), dtype=np.uint64)
+        s = np.zeros(r.size, dtype=np.uint8)
+        _check(self.lib.sq_export_rows(self.h, r.ctypes.data, r.size, x.ctypes.data, z.ctypes.data, s.ctypes.data))
+        return x, z, s
+
+    def export(self) -> Tuple[np.ndarray, np.ndarray, np.ndarray]:
+        rows = 2 * self.n
+        x = np.zeros((rows, self.W), dtype=np.uint64)
+        z = np.zeros((rows, self.W), dtype=np.uint64)
+        s = np.zeros(rows, dtype=np.uint8)
+        _check(self.lib.sq_export(self.h, x.ctypes.data, z.ctypes.data, s.ctypes.data))
+        return x, z, s
+
+    def import_(self, x: np.ndarray, z: np.ndarray, r: np.ndarray):
+        x = np.ascontiguousarray(x, dtype=np.uint64)
+        z = np.ascontiguousarray(z, dtype=np.uint64)
+        r = np.ascontiguousarray(r, dtype=np.uint8)
+        assert x.shape == (2 * self.n, self.W) and z.shape == x.shape and r.shape == (2 * self.n,)
+        _check(self.lib.sq_import(self.h, x.ctypes.data, z.ctypes.data, r.ctypes.data))
+
+    def error_flags(self) -> int:
+        f = ctypes.c_uint32(0)
+        _check(self.lib.sq_error_flags(self.h, ctypes.byref(f)))
+        return int(f.value)
+
+    def measure_stats(self) -> MeasStats:
+        s = MeasStats()
+        _check(self.lib.sq_measure_stats(self.h, ctypes.byref(s)))
+        return s
+
+    # -- tuning and profiling ------------------------------------------------
+    def tuning(self) -> Tuning:
+        t = Tuning()
+        _check(self.lib.sq_get_tuning(self.h, ctypes.byref(t)))
+        return t
+
+    def set_tuning(self, **kw):
+        t = Tuning()
+        for k, v in kw.items():
+            setattr(t, k, int(v))
+        _check(self.lib.sq_set_tuning(self.h, ctypes.byref(t)))
+
+    def profile(self, on: bool = True):
+        _check(self.lib.sq_profile_enable(self.h, 1 if on else 0))
+
+    def profile_reset(self):
+        _check(self.lib.sq_profile_reset(self.h))
+
+    def profile_read(self, kernel: int) -> Tuple[float, int]:
+        ms = ctypes.c_double(0)
+        n = ctypes.c_uint64(0)
+        _check(self.lib.sq_profile_read(self.h, kernel, ctypes.byref(ms), ctypes.byref(n)))
+        return float(ms.value), int(n.value)
+
+
+def plan_gates(n: int, ops) -> list:
+    """Host-only: the pass plan of a gate sequence as [[(q0word, q1, ops), ...], ...]."""
+    lib = load()
+    a = ops_array(ops)
+    need = ctypes.c_uint64(0)
+    _check(lib.sq_plan_gates(int(n), a.ctypes.data, a.shape[0], None, 0, ctypes.byref(need)))
+    buf = np.zeros(max(int(need.value), 1), dtype=np.uint64)
+    _check(lib.sq_plan_gates(int(n), a.ctypes.data, a.shape[0], buf.ctypes.data, buf.size, ctypes.byref(need)))
+    passes, k = [], 0
+    while k < int(need.value):
+        cnt = int(buf[k])
+        k += 1
+        groups = [(int(buf[k + 3 * g]), int(buf[k + 3 * g + 1]), int(buf[k + 3 * g + 2])) for g in range(cnt)]
+        k += 3 * cnt
+        passes.append(groups)
+    return passes
+
+
+def bytes_required(n: int) -> int:
+    return int(load().sq_bytes_required(int(n)))
+
+
+def version() -> str:
+    return load().sq_version().decode()

@@ -1,0 +1,97 @@
+// Private declarations shared by the kernels (sq_kernels.hip) and the host
+// runtime behind the C ABI (sq_runtime.hip).
+//
+// Device layout of a tableau of n qubits (column-major, the layout the paper
+// uses for gate application in "Tableau Layout and Indexing"):
+//   K  = ceil(n / 64) words per half column, L = 2K words per column;
+//   word w < K packs destabilizer rows 64w .. 64w+63 (bit b = row 64w+b),
+//   word K + w packs stabilizer rows S_{64w} .. S_{64w+63};
+//   X[q * Ls + w], Z[q * Ls + w] for qubit column q, with the column stride
+//   Ls = L rounded up to 16 words (128 bytes) so every column starts on a
+//   cache line; R[w] holds the sign bits of the same 64 rows.
+// Bits of rows >= n in the last word of each half are always 0: every gate
+// rule and every rowsum maps an all-zero row to itself with sign 0.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace sq {
+
+typedef unsigned long long u64;
+typedef uint32_t u32;
+
+// Gate-group micro-op codes (4 bits each, packed LSB first into Group::ops;
+// 0 ends the list). Slot A is Group::q0, slot B is Group::q1.
+enum : u32 {
+  UOP_END = 0,
+  UOP_H_A = 1, UOP_S_A = 2, UOP_SDG_A = 3, UOP_X_A = 4, UOP_Y_A = 5, UOP_Z_A = 6,
+  UOP_H_B = 7, UOP_S_B = 8, UOP_SDG_B = 9, UOP_X_B = 10, UOP_Y_B = 11, UOP_Z_B = 12,
+  UOP_CX_AB = 13, UOP_CX_BA = 14, UOP_CZ = 15
+};
+
+// Group::q0 carries the slot-A qubit in bits 0..23 and, in bits 24..27,
+// which columns the group's ops can change (xa, za, xb, zb): only those are
+// stored back.
+constexpr u32 GQ_MASK = 0x00FFFFFFu;
+constexpr u32 GD_XA = 1u << 24, GD_ZA = 1u << 25, GD_XB = 1u << 26, GD_ZB = 1u << 27;
+constexpr u32 G_SINGLE = 0xFFFFFFFFu;  // Group::q1 of a one-qubit group
+
+// A one- or two-qubit group of a gate pass: up to 16 ops on its own qubits.
+struct Group {
+  u32 q0;
+  u32 q1;
+  u64 ops;
+};
+static_assert(sizeof(Group) == 16, "Group must be 16 bytes");
+
+// Per-measurement device state (one per tableau, reused by every measurement).
+struct MeasState {
+  int32_t p;      // pivot stabilizer index, -1 if the outcome is deterministic
+  u32 ncols;      // number of non-identity columns of S_p (compacted list length)
+  u32 det_acc;    // deterministic case: sum of phase exponents (mod 2^32)
+  u32 flags;      // sticky error flags: bit 0 odd rowsum phase, bit 1 bad det product
+  u32 rp;         // sign bit of S_p before the update
+  u32 coin;       // coin of the current measurement
+  u32 mwords;     // nonzero words of the rowsum mask (row words the pass touches)
+  u32 awords;     // nonzero destabilizer-half words of column q (deterministic case)
+  u32 nx, nz;     // pivot-row columns with x_pj = 1, with z_pj = 1
+};
+
+// Running totals over all measurements of a tableau, for byte accounting.
+struct MeasStats {
+  u64 n_random, n_det;
+  u64 rowsum_bytes;   // algorithmic bytes of the rowsum passes (see k_finalize)
+  u64 det_bytes;      // algorithmic bytes of the deterministic-phase passes
+};
+
+struct TabDev {
+  u64 *X, *Z, *R;
+  u32 n, K, L, Ls;
+};
+
+struct LaunchTimer;  // host-side profiling hook (sq_runtime.hip)
+
+// Kernel launchers (sq_kernels.hip). All enqueue on `s` and return the
+// launch status.
+hipError_t launch_fill_zero(u64 *p, size_t words, hipStream_t s);
+hipError_t launch_init_diag(const TabDev &t, hipStream_t s);
+hipError_t launch_layer(const TabDev &t, const Group *groups, u32 ngroups, u32 block, u32 wpt, u32 gpc,
+                        u64 *sign_part, hipStream_t s);
+hipError_t launch_sign_reduce(const TabDev &t, const u64 *sign_part, u32 nchunks, hipStream_t s);
+hipError_t launch_pivot(const TabDev &t, u32 q, MeasState *st, u64 *mask, u64 seed, u64 shot, u64 m,
+                        uint8_t *out_bits, uint8_t *out_rand, hipStream_t s);
+hipError_t launch_gather(const TabDev &t, MeasState *st, u64 *pivx, u64 *pivz, u32 *cols, hipStream_t s);
+hipError_t launch_rowsum(const TabDev &t, const u64 *mask, const u32 *cols, const MeasState *st, u64 *cnt0,
+                         u64 *cnt1, u32 block, u32 wpt, u32 cpc, u32 max_chunks, hipStream_t s);
+hipError_t launch_finalize(const TabDev &t, u32 q, const u64 *mask, const u64 *pivx, const u64 *pivz,
+                           const u64 *cnt0, const u64 *cnt1, MeasState *st, MeasStats *stats, u32 cpc,
+                           hipStream_t s);
+hipError_t launch_detphase(const TabDev &t, u32 q, const u64 *mask, MeasState *st, u32 block, u32 cols_per_wg,
+                           hipStream_t s);
+hipError_t launch_detfinal(const TabDev &t, const u64 *mask, MeasState *st, MeasStats *stats, uint8_t *out_bits,
+                           hipStream_t s);
+hipError_t launch_export_rows(const TabDev &t, const u32 *rows, u32 nrows, u32 W, u64 *ox, u64 *oz, uint8_t *orr,
+                              hipStream_t s);
+hipError_t launch_import(const TabDev &t, const u64 *ix, const u64 *iz, const uint8_t *ir, u32 W, hipStream_t s);
+
+}  // namespace sq

@@ -1,0 +1,840 @@
+// Host runtime behind the C ABI declared in include/sq.h: tableau handles,
+// the gate-pass compiler, launch geometry, profiling and error handling.
+#include <algorithm>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <utility>
+#include <vector>
+
+#include "../../include/sq.h"
+#include "sq_internal.h"
+
+using namespace sq;
+
+namespace {
+
+thread_local std::string g_err;
+
+sq_status fail(sq_status code, const char *fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof(buf), fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return code;
+}
+
+#define HIP_TRY(expr)                                                                        \
+  do {                                                                                       \
+    hipError_t e_ = (expr);                                                                  \
+    if (e_ != hipSuccess) return fail(SQ_EDEVICE, "%s: %s", #expr, hipGetErrorString(e_));   \
+  } while (0)
+
+constexpr u32 kMaxChunks = 2048;  // per-launch cap on gate-group and column chunks
+
+inline u32 cdiv(u64 a, u64 b) { return (u32)((a + b - 1) / b); }
+inline u32 round_up(u32 a, u32 b) { return (a + b - 1) / b * b; }
+
+bool is_gate(u32 t) { return t <= SQ_CZ; }
+bool is_two_qubit(u32 t) { return t == SQ_CX || t == SQ_CZ; }
+
+// ----------------------------------------------------------------------------
+// Gate-pass compiler: groups a program-order gate sequence into passes of
+// disjoint one- or two-qubit groups (each at most 16 micro-ops). A gate joins
+// the group that already holds its qubits; two single-qubit groups merge when
+// a CX/CZ links them; any other overlap closes the pass. Gates in different
+// groups of a pass act on different qubits and commute, so applying a pass
+// group by group equals applying its gates in program order.
+struct HGroup {
+  u32 qa, qb;
+  u64 ops;
+  u32 nops;
+  bool alive;
+};
+
+u32 dirty_flags(u64 ops) {
+  u32 f = 0;
+  for (; ops; ops >>= 4) {
+    switch ((u32)(ops & 15)) {
+      case UOP_H_A: f |= GD_XA | GD_ZA; break;
+      case UOP_S_A: case UOP_SDG_A: f |= GD_ZA; break;
+      case UOP_H_B: f |= GD_XB | GD_ZB; break;
+      case UOP_S_B: case UOP_SDG_B: f |= GD_ZB; break;
+      case UOP_CX_AB: f |= GD_XB | GD_ZA; break;
+      case UOP_CX_BA: f |= GD_XA | GD_ZB; break;
+      case UOP_CZ: f |= GD_ZA | GD_ZB; break;
+      default: break;
+    }
+  }
+  return f;
+}
+
+u32 one_qubit_uop(u32 type) {
+  switch (type) {
+    case SQ_H: return UOP_H_A;
+    case SQ_S: return UOP_S_A;
+    case SQ_SDG: return UOP_SDG_A;
+    case SQ_X: return UOP_X_A;
+    case SQ_Y: return UOP_Y_A;
+    default: return UOP_Z_A;
+  }
+}
+
+struct PassRange {
+  u64 offset;
+  u32 count;
+  u64 bytes;  // algorithmic bytes of the pass: column reads + changed-column writes
+};
+
+class PassBuilder {
+ public:
+  std::vector<Group> groups;
+  std::vector<PassRange> passes;
+
+  void init(u32 n, u32 L) {
+    n_ = n;
+    L_ = L;
+    owner_.assign(n, -1);
+    epoch_of_.assign(n, 0);
+    epoch_ = 1;
+    groups.clear();
+    passes.clear();
+    cur_.clear();
+  }
+
+  void add(u32 type, u32 a, u32 b) {
+    if (type == SQ_I) return;
+    if (!is_two_qubit(type)) {
+      int g = find(a);
+      if (g >= 0 && cur_[g].nops >= 16) { flush(); g = -1; }
+      if (g < 0) g = open(a, G_SINGLE);
+      const u32 code = one_qubit_uop(type) + (cur_[g].qa == a ? 0u : 6u);
+      push(g, code);
+      return;
+    }
+    int ga = find(a), gb = find(b), g;
+    if (ga >= 0 && ga == gb) {
+      g = ga;
+      if (cur_[g].nops >= 16) { flush(); g = open(a, b); }
+    } else {
+      const bool pair_a = ga >= 0 && cur_[ga].qb != G_SINGLE;
+      const bool pair_b = gb >= 0 && cur_[gb].qb != G_SINGLE;
+      const u32 need = (ga >= 0 ? cur_[ga].nops : 0) + (gb >= 0 ? cur_[gb].nops : 0) + 1;
+      if (pair_a || pair_b || need > 16) { flush(); ga = gb = -1; }
+      if (ga < 0 && gb < 0) {
+        g = open(a, b);
+      } else if (gb < 0) {
+        g = ga;
+        cur_[g].qb = b;
+        bind(b, g);
+      } else if (ga < 0) {
+        g = gb;            // b stays slot A, a becomes slot B
+        cur_[g].qb = a;
+        bind(a, g);
+      } else {
+        g = ga;            // merge the single group of b into slot B of a's group
+        cur_[g].qb = b;
+        bind(b, g);
+        const u64 ob = cur_[gb].ops;
+        for (u32 k = 0; k < cur_[gb].nops; ++k) push(g, (u32)((ob >> (4 * k)) & 15) + 6u);
+        cur_[gb].alive = false;
+      }
+    }
+    const bool a_is_A = cur_[g].qa == a;
+    push(g, type == SQ_CZ ? UOP_CZ : (a_is_A ? UOP_CX_AB : UOP_CX_BA));
+  }
+
+  void flush() {
+    const u64 off = groups.size();
+    u64 bytes = 0;
+    for (const HGroup &h : cur_) {
+      if (!h.alive || h.nops == 0) continue;
+      const u32 f = dirty_flags(h.ops);
+      groups.push_back(Group{h.qa | f, h.qb, h.ops});
+      const u32 reads = (h.qb == G_SINGLE) ? 2 : 4;
+      const u32 writes = (u32)__builtin_popcount(f);
+      bytes += (u64)(reads + writes) * L_ * 8ULL;
+    }
+    const u32 cnt = (u32)(groups.size() - off);
+    if (cnt) passes.push_back(PassRange{off, cnt, bytes});
+    cur_.clear();
+    if (++epoch_ == 0) {
+      std::fill(epoch_of_.begin(), epoch_of_.end(), 0u);
+      epoch_ = 1;
+    }
+  }
+
+ private:
+  u32 n_ = 0, L_ = 0, epoch_ = 1;
+  std::vector<int32_t> owner_;
+  std::vector<u32> epoch_of_;
+  std::vector<HGroup> cur_;
+
+  int find(u32 q) const { return epoch_of_[q] == epoch_ ? owner_[q] : -1; }
+  void bind(u32 q, int g) {
+    epoch_of_[q] = epoch_;
+    owner_[q] = g;
+  }
+  int open(u32 a, u32 b) {
+    cur_.push_back(HGroup{a, b, 0, 0, true});
+    const int g = (int)cur_.size() - 1;
+    bind(a, g);
+    if (b != G_SINGLE) bind(b, g);
+    return g;
+  }
+  void push(int g, u32 code) {
+    cur_[g].ops |= (u64)code << (4 * cur_[g].nops);
+    cur_[g].nops += 1;
+  }
+};
+
+sq_status validate_ops(u32 n, const sq_op *ops, u64 count, bool allow_measure) {
+  if (count && !ops) return fail(SQ_EINVAL, "ops is NULL with count %llu", (unsigned long long)count);
+  for (u64 i = 0; i < count; ++i) {
+    const sq_op &o = ops[i];
+    if (o.type == SQ_MEASURE) {
+      if (!allow_measure) return fail(SQ_EINVAL, "op %llu: measurement not allowed here", (unsigned long long)i);
+      if (o.q0 >= n) return fail(SQ_ERANGE, "op %llu: qubit %u >= n=%u", (unsigned long long)i, o.q0, n);
+      continue;
+    }
+    if (!is_gate(o.type)) return fail(SQ_EINVAL, "op %llu: unknown type %u", (unsigned long long)i, o.type);
+    if (o.q0 >= n) return fail(SQ_ERANGE, "op %llu: qubit %u >= n=%u", (unsigned long long)i, o.q0, n);
+    if (is_two_qubit(o.type)) {
+      if (o.q1 >= n) return fail(SQ_ERANGE, "op %llu: qubit %u >= n=%u", (unsigned long long)i, o.q1, n);
+      if (o.q1 == o.q0) return fail(SQ_EINVAL, "op %llu: two-qubit gate on qubit %u twice", (unsigned long long)i, o.q0);
+    }
+  }
+  return SQ_OK;
+}
+
+struct Dims {
+  u32 n, K, L, Ls;
+};
+
+Dims dims_of(u32 n) {
+  Dims d;
+  d.n = n;
+  d.K = cdiv(n, 64);
+  d.L = 2 * d.K;
+  d.Ls = round_up(d.L, 16);
+  return d;
+}
+
+}  // namespace
+
+// ----------------------------------------------------------------------------
+struct sq_tableau {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  Dims d{};
+  TabDev t{};
+  u64 *base = nullptr;      // one allocation for every device buffer below
+  u64 *mask = nullptr, *pivx = nullptr, *pivz = nullptr, *cnt0 = nullptr, *cnt1 = nullptr, *sign_part = nullptr;
+  u32 *cols = nullptr;
+  MeasState *st = nullptr;
+  MeasStats *stats = nullptr;
+  uint8_t *dev_out = nullptr;
+  size_t dev_out_cap = 0;
+  Group *dev_groups = nullptr;
+  size_t dev_groups_cap = 0;
+  sq_tuning tun{};
+  PassBuilder builder;
+  // profiling
+  bool prof = false;
+  std::vector<std::pair<hipEvent_t, hipEvent_t>> pending[SQ_K_COUNT];
+  std::vector<hipEvent_t> pool;
+  double ms[SQ_K_COUNT] = {};
+  uint64_t launches[SQ_K_COUNT] = {};
+};
+
+struct sq_program {
+  int device = 0;
+  u32 n = 0;
+  Dims d{};
+  Group *dev_groups = nullptr;
+  std::vector<PassRange> passes;
+  struct Seg {
+    int kind;  // 0 gate passes [first, first+count), 1 measurements [first, first+count)
+    u64 first, count;
+  };
+  std::vector<Seg> segs;
+  std::vector<u32> meas_qubits;
+  u64 ngates = 0;
+  u64 gate_bytes = 0;
+};
+
+namespace {
+
+size_t layout_words(const Dims &d, size_t *off) {
+  // offsets (in words) of: X, Z, R, mask, pivx, pivz, cnt0, cnt1, sign_part, cols, st, stats
+  size_t o = 0;
+  auto take = [&](size_t words) {
+    size_t r = o;
+    o += (words + 31) / 32 * 32;  // 256-byte alignment
+    return r;
+  };
+  off[0] = take((size_t)d.n * d.Ls);
+  off[1] = take((size_t)d.n * d.Ls);
+  off[2] = take(d.Ls);
+  off[3] = take(d.Ls);
+  off[4] = take(d.K);
+  off[5] = take(d.K);
+  off[6] = take((size_t)kMaxChunks * d.Ls);
+  off[7] = take((size_t)kMaxChunks * d.Ls);
+  off[8] = take((size_t)kMaxChunks * d.Ls);
+  off[9] = take((d.n + 1) / 2);
+  off[10] = take(sizeof(MeasState) / 8 + 1);
+  off[11] = take(sizeof(MeasStats) / 8 + 1);
+  return o;
+}
+
+void default_tuning(const Dims &d, sq_tuning *t) {
+  t->layer_block = d.L >= 1024 ? 256 : 64;
+  t->layer_wpt = d.L >= 512 ? 2 : 1;
+  t->layer_groups = 0;  // automatic
+  t->rowsum_block = d.L >= 1024 ? 256 : 64;
+  t->rowsum_wpt = d.L >= 512 ? 2 : 1;
+  t->rowsum_cols = 0;   // automatic
+  t->det_block = d.K >= 512 ? 256 : 64;
+  t->det_cols = 0;      // automatic
+}
+
+u32 layer_gpc(const sq_tableau *T, u32 ngroups) {
+  const u32 tiles = cdiv(T->d.L, (u64)T->tun.layer_block * T->tun.layer_wpt);
+  u32 gpc = T->tun.layer_groups;
+  if (gpc == 0) {
+    const u32 want_chunks = std::max<u32>(1, 2048 / tiles);
+    gpc = std::max<u32>(16, cdiv(ngroups, want_chunks));
+  }
+  gpc = std::max<u32>(gpc, cdiv(ngroups, kMaxChunks));
+  return std::max<u32>(gpc, 1);
+}
+
+u32 rowsum_cpc(const sq_tableau *T) {
+  const u32 tiles = cdiv(T->d.L, (u64)T->tun.rowsum_block * T->tun.rowsum_wpt);
+  u32 cpc = T->tun.rowsum_cols;
+  if (cpc == 0) {
+    const u32 want_chunks = std::max<u32>(1, 2048 / tiles);
+    cpc = std::max<u32>(16, cdiv(T->d.n, want_chunks));
+  }
+  cpc = std::max<u32>(cpc, cdiv(T->d.n, kMaxChunks));
+  return std::max<u32>(cpc, 1);
+}
+
+u32 det_cpw(const sq_tableau *T) {
+  if (T->tun.det_cols) return T->tun.det_cols;
+  return std::max<u32>(1, cdiv(T->d.n, 4096));
+}
+
+hipEvent_t take_event(sq_tableau *T) {
+  if (!T->pool.empty()) {
+    hipEvent_t e = T->pool.back();
+    T->pool.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  if (hipEventCreate(&e) != hipSuccess) return nullptr;
+  return e;
+}
+
+// Launch `fn` (returning hipError_t), bracketed by events when profiling.
+template <class F>
+sq_status timed(sq_tableau *T, int kid, F &&fn) {
+  hipEvent_t a = nullptr, b = nullptr;
+  if (T->prof) {
+    a = take_event(T);
+    b = take_event(T);
+    if (a && b) HIP_TRY(hipEventRecord(a, T->stream));
+  }
+  const hipError_t e = fn();
+  if (e != hipSuccess) return fail(SQ_EDEVICE, "kernel %d launch: %s", kid, hipGetErrorString(e));
+  if (T->prof && a && b) {
+    HIP_TRY(hipEventRecord(b, T->stream));
+    T->pending[kid].emplace_back(a, b);
+  }
+  return SQ_OK;
+}
+
+sq_status collect_profile(sq_tableau *T) {
+  HIP_TRY(hipStreamSynchronize(T->stream));
+  for (int k = 0; k < SQ_K_COUNT; ++k) {
+    for (auto &pr : T->pending[k]) {
+      float ms = 0.f;
+      HIP_TRY(hipEventElapsedTime(&ms, pr.first, pr.second));
+      T->ms[k] += ms;
+      T->launches[k] += 1;
+      T->pool.push_back(pr.first);
+      T->pool.push_back(pr.second);
+    }
+    T->pending[k].clear();
+  }
+  return SQ_OK;
+}
+
+#define SQ_TRY(expr)                 \
+  do {                               \
+    sq_status s_ = (expr);           \
+    if (s_ != SQ_OK) return s_;      \
+  } while (0)
+
+sq_status run_passes(sq_tableau *T, const Group *dev_groups, const std::vector<PassRange> &passes, size_t first,
+                     size_t count) {
+  for (size_t i = first; i < first + count; ++i) {
+    const PassRange &p = passes[i];
+    const u32 gpc = layer_gpc(T, p.count);
+    const u32 chunks = cdiv(p.count, gpc);
+    const Group *g = dev_groups + p.offset;
+    SQ_TRY(timed(T, SQ_K_LAYER, [&] {
+      return launch_layer(T->t, g, p.count, T->tun.layer_block, T->tun.layer_wpt, gpc, T->sign_part, T->stream);
+    }));
+    SQ_TRY(timed(T, SQ_K_SIGNS, [&] { return launch_sign_reduce(T->t, T->sign_part, chunks, T->stream); }));
+  }
+  return SQ_OK;
+}
+
+sq_status measure_one(sq_tableau *T, u32 q, u64 seed, u64 shot, u64 m, uint8_t *dbits, uint8_t *drand) {
+  const u32 cpc = rowsum_cpc(T);
+  const u32 max_chunks = cdiv(T->d.n, cpc);
+  SQ_TRY(timed(T, SQ_K_PIVOT, [&] {
+    return launch_pivot(T->t, q, T->st, T->mask, seed, shot, m, dbits, drand, T->stream);
+  }));
+  SQ_TRY(timed(T, SQ_K_GATHER, [&] { return launch_gather(T->t, T->st, T->pivx, T->pivz, T->cols, T->stream); }));
+  SQ_TRY(timed(T, SQ_K_ROWSUM, [&] {
+    return launch_rowsum(T->t, T->mask, T->cols, T->st, T->cnt0, T->cnt1, T->tun.rowsum_block, T->tun.rowsum_wpt, cpc,
+                         max_chunks, T->stream);
+  }));
+  SQ_TRY(timed(T, SQ_K_FINAL, [&] {
+    return launch_finalize(T->t, q, T->mask, T->pivx, T->pivz, T->cnt0, T->cnt1, T->st, T->stats, cpc, T->stream);
+  }));
+  SQ_TRY(timed(T, SQ_K_DET, [&] {
+    return launch_detphase(T->t, q, T->mask, T->st, T->tun.det_block, det_cpw(T), T->stream);
+  }));
+  SQ_TRY(timed(T, SQ_K_DETFINAL, [&] { return launch_detfinal(T->t, T->mask, T->st, T->stats, dbits, T->stream); }));
+  return SQ_OK;
+}
+
+sq_status reset_device(sq_tableau *T) {
+  size_t off[12];
+  const size_t words = layout_words(T->d, off);
+  HIP_TRY(launch_fill_zero(T->base, words, T->stream));
+  HIP_TRY(launch_init_diag(T->t, T->stream));
+  return SQ_OK;
+}
+
+sq_status check_tuning(const sq_tuning &t) {
+  auto ok_block = [](u32 b) { return b >= 64 && b <= 1024 && b % 64 == 0; };
+  if (!ok_block(t.layer_block) || !ok_block(t.rowsum_block) || !ok_block(t.det_block))
+    return fail(SQ_EINVAL, "block sizes must be multiples of 64 in [64, 1024]");
+  if ((t.layer_wpt != 1 && t.layer_wpt != 2) || (t.rowsum_wpt != 1 && t.rowsum_wpt != 2))
+    return fail(SQ_EINVAL, "words per thread must be 1 or 2");
+  return SQ_OK;
+}
+
+}  // namespace
+
+// ============================================================================
+extern "C" {
+
+const char *sq_last_error(void) { return g_err.c_str(); }
+const char *sq_version(void) { return "sq 0.1 (gfx950)"; }
+
+size_t sq_bytes_required(uint32_t n) {
+  if (n == 0 || n > SQ_MAX_QUBITS) return 0;
+  size_t off[12];
+  return layout_words(dims_of(n), off) * 8;
+}
+
+sq_status sq_create(uint32_t n, void *hip_stream, sq_tableau **out) {
+  if (!out) return fail(SQ_EINVAL, "out is NULL");
+  *out = nullptr;
+  if (n == 0) return fail(SQ_EINVAL, "n must be >= 1");
+  if (n > SQ_MAX_QUBITS) return fail(SQ_ERANGE, "n=%u above the limit %u", n, SQ_MAX_QUBITS);
+  sq_tableau *T = new (std::nothrow) sq_tableau();
+  if (!T) return fail(SQ_ENOMEM, "host allocation failed");
+  if (hipGetDevice(&T->device) != hipSuccess) {
+    delete T;
+    return fail(SQ_EDEVICE, "no HIP device");
+  }
+  T->stream = (hipStream_t)hip_stream;
+  T->d = dims_of(n);
+  size_t off[12];
+  const size_t words = layout_words(T->d, off);
+  if (hipMalloc((void **)&T->base, words * 8) != hipSuccess) {
+    (void)hipGetLastError();
+    delete T;
+    return fail(SQ_ENOMEM, "device allocation of %zu bytes failed", words * 8);
+  }
+  u64 *b = T->base;
+  T->t = TabDev{b + off[0], b + off[1], b + off[2], T->d.n, T->d.K, T->d.L, T->d.Ls};
+  T->mask = b + off[3];
+  T->pivx = b + off[4];
+  T->pivz = b + off[5];
+  T->cnt0 = b + off[6];
+  T->cnt1 = b + off[7];
+  T->sign_part = b + off[8];
+  T->cols = reinterpret_cast<u32 *>(b + off[9]);
+  T->st = reinterpret_cast<MeasState *>(b + off[10]);
+  T->stats = reinterpret_cast<MeasStats *>(b + off[11]);
+  default_tuning(T->d, &T->tun);
+  T->builder.init(n, T->d.L);
+  sq_status s = reset_device(T);
+  if (s == SQ_OK && hipStreamSynchronize(T->stream) != hipSuccess) s = fail(SQ_EDEVICE, "initialisation failed");
+  if (s != SQ_OK) {
+    (void)hipFree(T->base);
+    delete T;
+    return s;
+  }
+  *out = T;
+  return SQ_OK;
+}
+
+sq_status sq_destroy(sq_tableau *T) {
+  if (!T) return SQ_OK;
+  (void)hipStreamSynchronize(T->stream);
+  for (int k = 0; k < SQ_K_COUNT; ++k)
+    for (auto &pr : T->pending[k]) {
+      (void)hipEventDestroy(pr.first);
+      (void)hipEventDestroy(pr.second);
+    }
+  for (hipEvent_t e : T->pool) (void)hipEventDestroy(e);
+  (void)hipFree(T->dev_out);
+  (void)hipFree(T->dev_groups);
+  (void)hipFree(T->base);
+  delete T;
+  return SQ_OK;
+}
+
+sq_status sq_reset(sq_tableau *T) {
+  if (!T) return fail(SQ_EINVAL, "tableau is NULL");
+  return reset_device(T);
+}
+
+sq_status sq_sync(sq_tableau *T) {
+  if (!T) return fail(SQ_EINVAL, "tableau is NULL");
+  HIP_TRY(hipStreamSynchronize(T->stream));
+  return SQ_OK;
+}
+
+uint32_t sq_num_qubits(const sq_tableau *T) { return T ? T->d.n : 0; }
+
+sq_status sq_apply_gates(sq_tableau *T, const sq_op *ops, uint64_t count) {
+  if (!T) return fail(SQ_EINVAL, "tableau is NULL");
+  SQ_TRY(validate_ops(T->d.n, ops, count, false));
+  if (count == 0) return SQ_OK;
+  PassBuilder &pb = T->builder;
+  pb.init(T->d.n, T->d.L);
+  for (u64 i = 0; i < count; ++i) pb.add(ops[i].type, ops[i].q0, ops[i].q1);
+  pb.flush();
+  if (pb.groups.empty()) return SQ_OK;
+  if (pb.groups.size() > T->dev_groups_cap) {
+    HIP_TRY(hipStreamSynchronize(T->stream));
+    (void)hipFree(T->dev_groups);
+    T->dev_groups = nullptr;
+    T->dev_groups_cap = 0;
+    const size_t cap = std::max<size_t>(pb.groups.size(), 1024);
+    if (hipMalloc((void **)&T->dev_groups, cap * sizeof(Group)) != hipSuccess) {
+      (void)hipGetLastError();
+      return fail(SQ_ENOMEM, "device allocation of %zu gate groups failed", cap);
+    }
+    T->dev_groups_cap = cap;
+  }
+  HIP_TRY(hipMemcpyAsync(T->dev_groups, pb.groups.data(), pb.groups.size() * sizeof(Group), hipMemcpyHostToDevice,
+                         T->stream));
+  return run_passes(T, T->dev_groups, pb.passes, 0, pb.passes.size());
+}
+
+sq_status sq_measure(sq_tableau *T, const uint32_t *qubits, uint32_t count, uint64_t seed, uint64_t shot,
+                     uint64_t meas_base, uint8_t *out_bits, uint8_t *out_random) {
+  if (!T) return fail(SQ_EINVAL, "tableau is NULL");
+  if (count == 0) return SQ_OK;
+  if (!qubits || !out_bits) return fail(SQ_EINVAL, "qubits/out_bits is NULL");
+  for (u32 i = 0; i < count; ++i)
+    if (qubits[i] >= T->d.n) return fail(SQ_ERANGE, "qubit %u >= n=%u", qubits[i], T->d.n);
+  const size_t need = 2 * (size_t)count;
+  if (need > T->dev_out_cap) {
+    HIP_TRY(hipStreamSynchronize(T->stream));
+    (void)hipFree(T->dev_out);
+    T->dev_out = nullptr;
+    T->dev_out_cap = 0;
+    if (hipMalloc((void **)&T->dev_out, need) != hipSuccess) {
+      (void)hipGetLastError();
+      return fail(SQ_ENOMEM, "device allocation of %zu bytes failed", need);
+    }
+    T->dev_out_cap = need;
+  }
+  MeasState before{}, after{};
+  HIP_TRY(hipMemcpyAsync(&before, T->st, sizeof(MeasState), hipMemcpyDeviceToHost, T->stream));
+  for (u32 i = 0; i < count; ++i)
+    SQ_TRY(measure_one(T, qubits[i], seed, shot, meas_base + i, T->dev_out + i, T->dev_out + count + i));
+  HIP_TRY(hipMemcpyAsync(out_bits, T->dev_out, count, hipMemcpyDeviceToHost, T->stream));
+  if (out_random)
+    HIP_TRY(hipMemcpyAsync(out_random, T->dev_out + count, count, hipMemcpyDeviceToHost, T->stream));
+  HIP_TRY(hipMemcpyAsync(&after, T->st, sizeof(MeasState), hipMemcpyDeviceToHost, T->stream));
+  HIP_TRY(hipStreamSynchronize(T->stream));
+  if (after.flags != before.flags)
+    return fail(SQ_ESTATE, "device consistency check failed (flags 0x%x)", after.flags);
+  return SQ_OK;
+}
+
+sq_status sq_program_create(uint32_t n, const sq_op *ops, uint64_t count, sq_program **out) {
+  if (!out) return fail(SQ_EINVAL, "out is NULL");
+  *out = nullptr;
+  if (n == 0 || n > SQ_MAX_QUBITS) return fail(SQ_ERANGE, "bad n=%u", n);
+  SQ_TRY(validate_ops(n, ops, count, true));
+  sq_program *P = new (std::nothrow) sq_program();
+  if (!P) return fail(SQ_ENOMEM, "host allocation failed");
+  (void)hipGetDevice(&P->device);
+  P->n = n;
+  P->d = dims_of(n);
+  PassBuilder pb;
+  pb.init(n, P->d.L);
+  u64 i = 0;
+  while (i < count) {
+    if (ops[i].type == SQ_MEASURE) {
+      sq_program::Seg s{1, P->meas_qubits.size(), 0};
+      while (i < count && ops[i].type == SQ_MEASURE) P->meas_qubits.push_back(ops[i++].q0);
+      s.count = P->meas_qubits.size() - s.first;
+      P->segs.push_back(s);
+    } else {
+      const size_t first = pb.passes.size();
+      while (i < count && ops[i].type != SQ_MEASURE) {
+        if (ops[i].type != SQ_I) P->ngates++;
+        pb.add(ops[i].type, ops[i].q0, ops[i].q1);
+        ++i;
+      }
+      pb.flush();
+      if (pb.passes.size() > first) P->segs.push_back(sq_program::Seg{0, first, pb.passes.size() - first});
+    }
+  }
+  P->passes = pb.passes;
+  for (const PassRange &r : P->passes) P->gate_bytes += r.bytes;
+  if (!pb.groups.empty()) {
+    if (hipMalloc((void **)&P->dev_groups, pb.groups.size() * sizeof(Group)) != hipSuccess) {
+      (void)hipGetLastError();
+      delete P;
+      return fail(SQ_ENOMEM, "device allocation of %zu gate groups failed", pb.groups.size());
+    }
+    if (hipMemcpy(P->dev_groups, pb.groups.data(), pb.groups.size() * sizeof(Group), hipMemcpyHostToDevice) !=
+        hipSuccess) {
+      (void)hipFree(P->dev_groups);
+      delete P;
+      return fail(SQ_EDEVICE, "upload of gate groups failed");
+    }
+  }
+  *out = P;
+  return SQ_OK;
+}
+
+sq_status sq_plan_gates(uint32_t n, const sq_op *ops, uint64_t count, uint64_t *out, uint64_t cap,
+                        uint64_t *out_len) {
+  if (!out_len || (cap && !out)) return fail(SQ_EINVAL, "NULL argument");
+  if (n == 0 || n > SQ_MAX_QUBITS) return fail(SQ_ERANGE, "bad n=%u", n);
+  SQ_TRY(validate_ops(n, ops, count, false));
+  PassBuilder pb;
+  pb.init(n, dims_of(n).L);
+  for (u64 i = 0; i < count; ++i) pb.add(ops[i].type, ops[i].q0, ops[i].q1);
+  pb.flush();
+  u64 k = 0;
+  auto put = [&](u64 v) {
+    if (k < cap) out[k] = v;
+    ++k;
+  };
+  for (const PassRange &r : pb.passes) {
+    put(r.count);
+    for (u32 g = 0; g < r.count; ++g) {
+      const Group &G = pb.groups[r.offset + g];
+      put(G.q0);
+      put(G.q1);
+      put(G.ops);
+    }
+  }
+  *out_len = k;
+  return SQ_OK;
+}
+
+sq_status sq_program_destroy(sq_program *P) {
+  if (!P) return SQ_OK;
+  (void)hipFree(P->dev_groups);
+  delete P;
+  return SQ_OK;
+}
+
+uint64_t sq_program_num_measurements(const sq_program *P) { return P ? P->meas_qubits.size() : 0; }
+uint64_t sq_program_num_gates(const sq_program *P) { return P ? P->ngates : 0; }
+uint64_t sq_program_num_passes(const sq_program *P) { return P ? P->passes.size() : 0; }
+
+sq_status sq_run(sq_tableau *T, const sq_program *P, uint64_t seed, uint64_t shot, uint64_t meas_base,
+                 uint8_t *dev_out_bits, uint8_t *dev_out_random) {
+  if (!T || !P) return fail(SQ_EINVAL, "tableau or program is NULL");
+  if (P->n != T->d.n) return fail(SQ_EINVAL, "program has n=%u, tableau n=%u", P->n, T->d.n);
+  if (!P->meas_qubits.empty() && !dev_out_bits) return fail(SQ_EINVAL, "dev_out_bits is NULL");
+  // The random flags need a place to go; without a caller buffer they land in the handle's scratch.
+  uint8_t *rand_base = dev_out_random;
+  if (!rand_base && !P->meas_qubits.empty()) {
+    const size_t need = P->meas_qubits.size();
+    if (need > T->dev_out_cap) {
+      HIP_TRY(hipStreamSynchronize(T->stream));
+      (void)hipFree(T->dev_out);
+      T->dev_out = nullptr;
+      T->dev_out_cap = 0;
+      if (hipMalloc((void **)&T->dev_out, need) != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(SQ_ENOMEM, "device allocation of %zu bytes failed", need);
+      }
+      T->dev_out_cap = need;
+    }
+    rand_base = T->dev_out;
+  }
+  for (const sq_program::Seg &s : P->segs) {
+    if (s.kind == 0) {
+      SQ_TRY(run_passes(T, P->dev_groups, P->passes, s.first, s.count));
+    } else {
+      for (u64 i = s.first; i < s.first + s.count; ++i)
+        SQ_TRY(measure_one(T, P->meas_qubits[i], seed, shot, meas_base + i, dev_out_bits + i, rand_base + i));
+    }
+  }
+  return SQ_OK;
+}
+
+sq_status sq_export_rows(sq_tableau *T, const uint32_t *rows, uint32_t nrows, uint64_t *hx, uint64_t *hz,
+                         uint8_t *hr) {
+  if (!T) return fail(SQ_EINVAL, "tableau is NULL");
+  if (nrows == 0) return SQ_OK;
+  if (!rows || !hx || !hz || !hr) return fail(SQ_EINVAL, "NULL buffer");
+  for (u32 k = 0; k < nrows; ++k)
+    if (rows[k] >= 2 * T->d.n) return fail(SQ_ERANGE, "row %u >= 2n=%u", rows[k], 2 * T->d.n);
+  const u32 W = T->d.K;
+  const size_t xwords = (size_t)nrows * W;
+  void *buf = nullptr;
+  const size_t bytes = nrows * 4 + 2 * xwords * 8 + nrows + 256;
+  if (hipMalloc(&buf, bytes) != hipSuccess) {
+    (void)hipGetLastError();
+    return fail(SQ_ENOMEM, "device allocation of %zu bytes failed", bytes);
+  }
+  u64 *dx = (u64 *)buf;
+  u64 *dz = dx + xwords;
+  u32 *drows = (u32 *)(dz + xwords);
+  uint8_t *dr = (uint8_t *)(drows + nrows);
+  sq_status s = SQ_OK;
+  if (hipMemcpyAsync(drows, rows, nrows * 4, hipMemcpyHostToDevice, T->stream) != hipSuccess ||
+      launch_export_rows(T->t, drows, nrows, W, dx, dz, dr, T->stream) != hipSuccess ||
+      hipMemcpyAsync(hx, dx, xwords * 8, hipMemcpyDeviceToHost, T->stream) != hipSuccess ||
+      hipMemcpyAsync(hz, dz, xwords * 8, hipMemcpyDeviceToHost, T->stream) != hipSuccess ||
+      hipMemcpyAsync(hr, dr, nrows, hipMemcpyDeviceToHost, T->stream) != hipSuccess ||
+      hipStreamSynchronize(T->stream) != hipSuccess)
+    s = fail(SQ_EDEVICE, "export failed: %s", hipGetErrorString(hipGetLastError()));
+  (void)hipFree(buf);
+  return s;
+}
+
+sq_status sq_export(sq_tableau *T, uint64_t *hx, uint64_t *hz, uint8_t *hr) {
+  if (!T) return fail(SQ_EINVAL, "tableau is NULL");
+  std::vector<u32> rows(2 * (size_t)T->d.n);
+  for (u32 k = 0; k < rows.size(); ++k) rows[k] = k;
+  return sq_export_rows(T, rows.data(), (u32)rows.size(), hx, hz, hr);
+}
+
+sq_status sq_import(sq_tableau *T, const uint64_t *hx, const uint64_t *hz, const uint8_t *hr) {
+  if (!T) return fail(SQ_EINVAL, "tableau is NULL");
+  if (!hx || !hz || !hr) return fail(SQ_EINVAL, "NULL buffer");
+  const u32 n = T->d.n, W = T->d.K;
+  const size_t rows = 2 * (size_t)n, xwords = rows * W;
+  if (n % 64) {
+    const u64 bad = ~0ULL << (n % 64);
+    for (size_t g = 0; g < rows; ++g)
+      if ((hx[g * W + W - 1] & bad) || (hz[g * W + W - 1] & bad))
+        return fail(SQ_EINVAL, "row %zu has bits at qubit positions >= n", g);
+  }
+  void *buf = nullptr;
+  const size_t bytes = 2 * xwords * 8 + rows + 256;
+  if (hipMalloc(&buf, bytes) != hipSuccess) {
+    (void)hipGetLastError();
+    return fail(SQ_ENOMEM, "device allocation of %zu bytes failed", bytes);
+  }
+  u64 *dx = (u64 *)buf;
+  u64 *dz = dx + xwords;
+  uint8_t *dr = (uint8_t *)(dz + xwords);
+  sq_status s = SQ_OK;
+  if (hipMemcpyAsync(dx, hx, xwords * 8, hipMemcpyHostToDevice, T->stream) != hipSuccess ||
+      hipMemcpyAsync(dz, hz, xwords * 8, hipMemcpyHostToDevice, T->stream) != hipSuccess ||
+      hipMemcpyAsync(dr, hr, rows, hipMemcpyHostToDevice, T->stream) != hipSuccess ||
+      launch_import(T->t, dx, dz, dr, W, T->stream) != hipSuccess || hipStreamSynchronize(T->stream) != hipSuccess)
+    s = fail(SQ_EDEVICE, "import failed: %s", hipGetErrorString(hipGetLastError()));
+  (void)hipFree(buf);
+  return s;
+}
+
+sq_status sq_measure_stats(sq_tableau *T, sq_meas_stats *out) {
+  if (!T || !out) return fail(SQ_EINVAL, "NULL argument");
+  MeasStats s{};
+  HIP_TRY(hipMemcpyAsync(&s, T->stats, sizeof(s), hipMemcpyDeviceToHost, T->stream));
+  HIP_TRY(hipStreamSynchronize(T->stream));
+  out->n_random = s.n_random;
+  out->n_det = s.n_det;
+  out->rowsum_bytes = s.rowsum_bytes;
+  out->det_bytes = s.det_bytes;
+  return SQ_OK;
+}
+
+uint64_t sq_program_gate_bytes(const sq_program *P) { return P ? P->gate_bytes : 0; }
+
+sq_status sq_error_flags(sq_tableau *T, uint32_t *flags) {
+  if (!T || !flags) return fail(SQ_EINVAL, "NULL argument");
+  MeasState s{};
+  HIP_TRY(hipMemcpyAsync(&s, T->st, sizeof(s), hipMemcpyDeviceToHost, T->stream));
+  HIP_TRY(hipStreamSynchronize(T->stream));
+  *flags = s.flags;
+  return SQ_OK;
+}
+
+sq_status sq_get_tuning(const sq_tableau *T, sq_tuning *out) {
+  if (!T || !out) return fail(SQ_EINVAL, "NULL argument");
+  *out = T->tun;
+  return SQ_OK;
+}
+
+sq_status sq_set_tuning(sq_tableau *T, const sq_tuning *in) {
+  if (!T || !in) return fail(SQ_EINVAL, "NULL argument");
+  sq_tuning t = T->tun;
+  if (in->layer_block) t.layer_block = in->layer_block;
+  if (in->layer_wpt) t.layer_wpt = in->layer_wpt;
+  if (in->layer_groups) t.layer_groups = in->layer_groups;
+  if (in->rowsum_block) t.rowsum_block = in->rowsum_block;
+  if (in->rowsum_wpt) t.rowsum_wpt = in->rowsum_wpt;
+  if (in->rowsum_cols) t.rowsum_cols = in->rowsum_cols;
+  if (in->det_block) t.det_block = in->det_block;
+  if (in->det_cols) t.det_cols = in->det_cols;
+  SQ_TRY(check_tuning(t));
+  T->tun = t;
+  return SQ_OK;
+}
+
+sq_status sq_profile_enable(sq_tableau *T, int on) {
+  if (!T) return fail(SQ_EINVAL, "tableau is NULL");
+  T->prof = on != 0;
+  return SQ_OK;
+}
+
+sq_status sq_profile_read(sq_tableau *T, int kernel, double *total_ms, uint64_t *launches) {
+  if (!T || kernel < 0 || kernel >= SQ_K_COUNT) return fail(SQ_EINVAL, "bad argument");
+  SQ_TRY(collect_profile(T));
+  if (total_ms) *total_ms = T->ms[kernel];
+  if (launches) *launches = T->launches[kernel];
+  return SQ_OK;
+}
+
+sq_status sq_profile_reset(sq_tableau *T) {
+  if (!T) return fail(SQ_EINVAL, "tableau is NULL");
+  SQ_TRY(collect_profile(T));
+  for (int k = 0; k < SQ_K_COUNT; ++k) {
+    T->ms[k] = 0;
+    T->launches[k] = 0;
+  }
+  return SQ_OK;
+}
+
+}  // extern "C"

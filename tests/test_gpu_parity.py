@@ -1,0 +1,284 @@
+"""Bit-exact parity of the HIP path with the CPU oracle (needs an MI355X).
+
+Every comparison is element by element with tolerance 0: tableau x/z bits,
+sign bits, measurement outcomes and the random/deterministic flags. The
+oracle never sees GPU output; the GPU sometimes starts from an oracle-made
+tableau (import).
+"""
+import numpy as np
+import pytest
+
+from gpu_util import gpu_run_calls, mixed_program, oracle_run, segments
+from oracle import oracle as orc
+from workload import CONFIGS, circuit_ops, iter_circuit
+
+pytestmark = pytest.mark.gpu
+
+SMALL_TILES = dict(layer_block=64, layer_wpt=1, layer_groups=3, rowsum_block=64, rowsum_wpt=1, rowsum_cols=5,
+                   det_block=64, det_cols=2)
+SMALL_TILES_W2 = dict(layer_block=64, layer_wpt=2, layer_groups=7, rowsum_block=128, rowsum_wpt=2, rowsum_cols=3,
+                      det_block=128, det_cols=3)
+
+
+@pytest.fixture(scope="module", autouse=True)
+def device():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    torch.cuda.set_device(0)
+    import paper_2603_14641_amd as sq
+    sq.load()
+    yield
+
+
+def _tab(n, tuning=None):
+    from paper_2603_14641_amd import Tableau
+    t = Tableau(n)
+    if tuning:
+        t.set_tuning(**tuning)
+    return t
+
+
+def _assert_same(got, want, what):
+    assert got.shape == want.shape, (what, got.shape, want.shape)
+    if not np.array_equal(got, want):
+        idx = np.argwhere(got != want)
+        raise AssertionError(f"{what}: {idx.shape[0]} mismatches, first at {idx[:5].tolist()}")
+
+
+def _compare_full(t, ref):
+    x, z, r = t.export()
+    rx, rz, rr = ref
+    _assert_same(x, rx, "x bits")
+    _assert_same(z, rz, "z bits")
+    _assert_same(r, rr, "signs")
+    assert t.error_flags() == 0
+
+
+# ------------------------------------------------------------------ configs
+@pytest.mark.parametrize("path", ["program", "calls"])
+def test_config1_full(path):
+    from paper_2603_14641_amd import Program
+    cfg = CONFIGS[1]
+    ops = circuit_ops(cfg)
+    seed = 11
+    rb, rr, x, z, r, _ = oracle_run(cfg.n, ops, seed)
+    t = _tab(cfg.n)
+    if path == "program":
+        bits, rnd = t.run_to_host(Program(cfg.n, ops), seed=seed, shot=0)
+    else:
+        bits, rnd = gpu_run_calls(t, ops, seed)
+    _assert_same(bits, rb, "outcomes")
+    _assert_same(rnd, rr, "random flags")
+    _compare_full(t, (x, z, r))
+
+
+def test_config2_full():
+    """n = 4096, depth 100, CZ on, nine mid-circuit rounds of 409 qubits, then all 4096."""
+    from paper_2603_14641_amd import Program
+    cfg = CONFIGS[2]
+    ops = circuit_ops(cfg)
+    seed = 2
+    rb, rr, x, z, r, _ = oracle_run(cfg.n, ops, seed)
+    t = _tab(cfg.n)
+    prog = Program(cfg.n, ops)
+    assert prog.num_measurements == 9 * 409 + 4096
+    bits, rnd = t.run_to_host(prog, seed=seed, shot=0)
+    _assert_same(bits, rb, "outcomes")
+    _assert_same(rnd, rr, "random flags")
+    _compare_full(t, (x, z, r))
+    st = t.measure_stats()
+    assert st.n_random + st.n_det == prog.num_measurements
+    assert st.n_random == int(rr.sum())
+
+
+# ------------------------------------------------------------------ tiles, ragged tails, all gate types
+@pytest.mark.parametrize("n", [1, 2, 3, 63, 64, 65, 130, 700, 2500])
+@pytest.mark.parametrize("tuning", [None, SMALL_TILES, SMALL_TILES_W2], ids=["default", "small", "small_w2"])
+def test_mixed_circuits(n, tuning):
+    rng = np.random.default_rng(1000 + n)
+    layers = 6 if n >= 700 else 12
+    ops = mixed_program(rng, n, layers, p_meas=0.15 if n > 3 else 0.4)
+    seed = int(rng.integers(1 << 40))
+    rb, rr, x, z, r, _ = oracle_run(n, ops, seed, shot=3, meas_base=5)
+    t = _tab(n, tuning)
+    bits, rnd = gpu_run_calls(t, ops, seed, shot=3, meas_base=5)
+    _assert_same(bits, rb, "outcomes")
+    _assert_same(rnd, rr, "random flags")
+    _compare_full(t, (x, z, r))
+
+
+def test_program_and_calls_agree_with_oracle_many_small():
+    """200 small circuits with dense measurement (many deterministic outcomes)."""
+    from paper_2603_14641_amd import Program
+    rng = np.random.default_rng(77)
+    det = 0
+    for k in range(200):
+        n = int(rng.integers(2, 20))
+        ops = mixed_program(rng, n, 8, p_meas=0.3)
+        rb, rr, x, z, r, _ = oracle_run(n, ops, seed=k, shot=k)
+        t = _tab(n)
+        bits, rnd = t.run_to_host(Program(n, ops), seed=k, shot=k)
+        _assert_same(bits, rb, f"outcomes circuit {k}")
+        _assert_same(rnd, rr, f"flags circuit {k}")
+        _compare_full(t, (x, z, r))
+        det += int((rr == 0).sum())
+    assert det > 200
+
+
+# ------------------------------------------------------------------ deterministic phase with mixed generators
+def _scrambled_state(n, rng, seed):
+    """An oracle tableau where half the qubits have been measured (so Z_q is in
+    the stabilizer group for those), then re-expressed in a random other
+    generator basis by symplectic row operations S_i <- S_j S_i, D_j <- D_i D_j."""
+    t = orc.Tableau(n)
+    t.run(mixed_program(rng, n, 10, p_meas=0.0), seed=seed)
+    meas = [[orc.MEASURE, q, 0] for q in range(0, n, 2)]
+    t.run(np.array(meas, dtype=np.uint32), seed=seed, shot=0, meas_base=0)
+    for _ in range(4 * n):
+        i, j = (int(v) for v in rng.choice(n, 2, replace=False))
+        assert t.rowsum(n + i, n + j) == 0
+        assert t.rowsum(j, i) == 0
+    return t
+
+
+@pytest.mark.parametrize("n", [5, 40, 200, 1000])
+def test_deterministic_phase_after_basis_scramble(n):
+    from paper_2603_14641_amd import Program
+    rng = np.random.default_rng(n)
+    ref = _scrambled_state(n, rng, seed=n)
+    x0, z0, r0 = ref.rows_array()
+    t = _tab(n, SMALL_TILES if n == 200 else None)
+    t.import_(x0, z0, r0)
+    _compare_full(t, (x0, z0, r0))
+    qs = list(range(0, n, 2)) + list(rng.permutation(n)[: n // 2])
+    prog_ops = np.array([[orc.MEASURE, int(q), 0] for q in qs], dtype=np.uint32)
+    rb, rr, _ = ref.run(prog_ops, seed=9, shot=1, meas_base=100)
+    assert ref.det_phase2_count > 0, "the scramble should give nonzero deterministic phase sums"
+    bits, rnd = t.run_to_host(Program(n, prog_ops), seed=9, shot=1, meas_base=100)
+    _assert_same(bits, rb, "outcomes")
+    _assert_same(rnd, rr, "random flags")
+    _compare_full(t, ref.rows_array())
+
+
+# ------------------------------------------------------------------ edge cases
+def test_empty_calls_and_errors_leave_state_unchanged():
+    from paper_2603_14641_amd import SqError
+    n = 70
+    rng = np.random.default_rng(5)
+    ops = mixed_program(rng, n, 3, p_meas=0.0)
+    t = _tab(n)
+    t.apply_gates(ops)
+    before = t.export()
+    t.apply_gates(np.zeros((0, 3), np.uint32))
+    b, r = t.measure([])
+    assert b.size == 0 and r.size == 0
+    for bad in ([[orc.H, n, 0]], [[orc.CX, 3, 3]], [[orc.CZ, 1, n + 5]], [[12, 0, 0]], [[orc.MEASURE, 0, 0]]):
+        with pytest.raises(SqError):
+            t.apply_gates(np.array(bad, dtype=np.uint32))
+    with pytest.raises(SqError):
+        t.measure([0, n])
+    after = t.export()
+    for u, v in zip(before, after):
+        _assert_same(u, v, "state after rejected calls")
+
+
+def test_reset_import_export_roundtrip():
+    n = 300
+    rng = np.random.default_rng(6)
+    ops = mixed_program(rng, n, 5, p_meas=0.1)
+    rb, rr, x, z, r, _ = oracle_run(n, ops, seed=4)
+    t = _tab(n)
+    t.import_(x, z, r)
+    _compare_full(t, (x, z, r))
+    t.reset()
+    fresh = orc.Tableau(n).rows_array()
+    _compare_full(t, fresh)
+    rows = rng.choice(2 * n, 37, replace=False)
+    t.import_(x, z, r)
+    ex, ez, er = t.export_rows(rows)
+    _assert_same(ex, x[rows], "export_rows x")
+    _assert_same(ez, z[rows], "export_rows z")
+    _assert_same(er, r[rows], "export_rows r")
+
+
+def test_measure_twice_and_program_mismatch():
+    from paper_2603_14641_amd import Program, SqError
+    n = 129
+    rng = np.random.default_rng(8)
+    t = _tab(n)
+    t.apply_gates(mixed_program(rng, n, 8, p_meas=0.0))
+    qs = rng.permutation(n)[:40]
+    b1, r1 = t.measure(qs, seed=1, meas_base=0)
+    b2, r2 = t.measure(qs, seed=2, meas_base=40)
+    _assert_same(b2, b1, "re-measured outcomes")
+    assert not r2.any()
+    with pytest.raises(SqError):
+        t.run(Program(n + 1, np.array([[orc.H, 0, 0]], dtype=np.uint32)), 0, 0, 0, 0)
+
+
+# ------------------------------------------------------------------ full sizes, sampled rows
+def _sampled_rows(n, rng, k_prefix=64, k_rand=32):
+    rows = list(range(n, n + k_prefix)) + list(range(0, 16))
+    extra = rng.choice(np.arange(16, 2 * n), k_rand, replace=False)
+    rows += [int(v) for v in extra if not (n <= v < n + k_prefix)]
+    return rows
+
+
+@pytest.mark.parametrize("cfg_id,depth,nmeas", [(3, 40, 16), (4, 100, 16)])
+def test_full_size_sampled_rows(cfg_id, depth, nmeas):
+    """n = 65,536 and 180,000 in the default launch configuration: after
+    `depth` generator layers and the first `nmeas` measurements of the final
+    sweep, the oracle (holding only a sample of rows, which evolve
+    independently under gates, and the stabilizer prefix that contains every
+    pivot) must agree on the outcomes and on every sampled row."""
+    from paper_2603_14641_amd import Program
+    cfg = CONFIGS[cfg_id]
+    n = cfg.n
+    rng = np.random.default_rng(cfg_id)
+    rows = _sampled_rows(n, rng)
+    ops = circuit_ops(cfg, depth=depth, final_measure=False)
+    meas = np.array([[orc.MEASURE, q, 0] for q in range(nmeas)], dtype=np.uint32)
+    allops = np.concatenate([np.stack([ops["type"], ops["q0"], ops["q1"]], 1).astype(np.uint32), meas])
+    sub = orc.Tableau(n, rows=rows)
+    rb, rr, done = sub.run(allops, seed=cfg.seed, shot=0)
+    assert rb.size == nmeas, "a pivot fell outside the sampled stabilizer prefix"
+    t = _tab(n)
+    prog = Program(n, allops)
+    bits, rnd = t.run_to_host(prog, seed=cfg.seed, shot=0)
+    _assert_same(bits, rb, "outcomes")
+    _assert_same(rnd, rr, "random flags")
+    x, z, r = t.export_rows(rows)
+    sx, sz, sr = sub.rows_array()
+    _assert_same(x, sx, "sampled x rows")
+    _assert_same(z, sz, "sampled z rows")
+    _assert_same(r, sr, "sampled signs")
+    assert t.error_flags() == 0
+    # measuring the same qubits again is deterministic and repeats the outcomes
+    b2, r2 = t.measure(np.arange(nmeas), seed=5, meas_base=nmeas)
+    _assert_same(b2, bits, "re-measured outcomes")
+    assert not r2.any()
+
+
+def test_layer_then_inverse_is_identity_at_180k():
+    """Any size: a generator layer followed by its inverse restores |0...0> exactly, signs included."""
+    cfg = CONFIGS[4]
+    n = cfg.n
+    layer = next(iter_circuit(cfg, depth=1, final_measure=False))[1]
+    a = np.stack([layer["type"], layer["q0"], layer["q1"]], 1).astype(np.uint32)
+    inv = a[::-1].copy()
+    inv[inv[:, 0] == orc.S, 0] = 99
+    inv[inv[:, 0] == orc.SDG, 0] = orc.S
+    inv[inv[:, 0] == 99, 0] = orc.SDG
+    t = _tab(n)
+    t.apply_gates(a)
+    rng = np.random.default_rng(0)
+    rows = rng.choice(2 * n, 512, replace=False)
+    x1, z1, _ = t.export_rows(rows)
+    assert x1.any() or z1.any()
+    t.apply_gates(inv)
+    x, z, r = t.export_rows(rows)
+    fresh = orc.Tableau(n, rows=rows).rows_array()
+    _assert_same(x, fresh[0], "x after inverse")
+    _assert_same(z, fresh[1], "z after inverse")
+    _assert_same(r, fresh[2], "signs after inverse")

@@ -30,7 +30,7 @@ MUTANTS = {
     "CX sign term": ("(xb ^ za ^ 1)", "(xb ^ za)"),
     "CX target z": ("putb(z, a, za ^ zb);", "putb(z, b, za ^ zb);"),
     "CZ misses b": ("putb(z, b, zb ^ xa);", "putb(z, b, zb);"),
-    "rowsum drops r_i": ("int e = 2 * (int)*rh + 2 * (int)ri;", "int e = 2 * (int)*rh;"),
+    "rowsum drops r_i": ("int e = 2 * (int)*rh + 2 * (int)ri + g;", "int e = 2 * (int)*rh + g;"),
     "g table Y sign": ("(p_y & ~x2 & z2)", "(p_y & x2 & ~z2)"),
     "pivot is largest": ("{ p = (int32_t)i; break; }", "{ p = (int32_t)i; }"),
     "skip D rows": ("if ((uint32_t)h == sp || (int32_t)h == dp) continue;",
