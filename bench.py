@@ -87,6 +87,8 @@ def main():
     ap.add_argument("--meas", type=int, default=500)
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="first run a plain 1 GiB device copy (scale reference for HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only; --gpus {args.gpus} is not supported "
@@ -101,6 +103,14 @@ def main():
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     torch.cuda.set_device(0)
     sq.load()
+    if args.copy_calibration:
+        src = torch.ones(1 << 27, dtype=torch.int64, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
+        log("copy calibration: 3 copies of 1 GiB done")
     cfg = CONFIGS[4]
     n = cfg.n
     log(f"generating {args.layers} layers of n={n}")
@@ -132,7 +142,6 @@ def main():
 
     t.profile_reset()
     t.profile(True)
-    st0 = t.measure_stats()
     events = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(args.steps)]
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -145,6 +154,8 @@ def main():
     wall = time.perf_counter() - t0
     t.profile(False)
     log(f"timed {args.steps} steps in {wall:.2f} s")
+    # Each step starts from reset (which also clears the byte accounting) and
+    # does identical work, so the counters now hold exactly one step.
     st1 = t.measure_stats()
     gate_ms = sum(e[0].elapsed_time(e[1]) for e in events)
     meas_ms = sum(e[1].elapsed_time(e[2]) for e in events)
@@ -155,8 +166,8 @@ def main():
     rowsum_ms, rowsum_n = kern["rowsum"]
     layer_bytes = pg.gate_bytes / max(pg.num_passes, 1)
     layer_gbs = layer_bytes / (layer_ms / layer_n * 1e-3) / 1e9
-    n_random = st1.n_random - st0.n_random
-    rowsum_bytes = (st1.rowsum_bytes - st0.rowsum_bytes) / max(n_random, 1)
+    n_random = st1.n_random
+    rowsum_bytes = st1.rowsum_bytes / max(n_random, 1)
     rowsum_gbs = rowsum_bytes / (rowsum_ms / max(rowsum_n, 1) * 1e-3) / 1e9 if rowsum_n else 0.0
     roof_layer = {"kernel": "k_layer", "bound": "hbm", "achieved": round(layer_gbs, 1), "peak": HBM_PEAK_GBS,
                   "unit": "GB/s", "frac": round(layer_gbs / HBM_PEAK_GBS, 4), "traffic": None,
@@ -190,7 +201,7 @@ def main():
         "measurements_per_s": args.meas * args.steps / (meas_ms * 1e-3),
         "gate_phase_ms_per_step": gate_ms / args.steps,
         "meas_phase_ms_per_step": meas_ms / args.steps,
-        "random_measurements": int(n_random),
+        "random_measurements_per_step": int(n_random),
         "roofline": dominant,
         "roofline_other": other,
         "kernel_ms": {k: round(v[0], 3) for k, v in kern.items()},

@@ -59,6 +59,13 @@ def load(path: str = LIB_PATH):
     if not os.path.exists(path):
         raise ImportError(f"{path} is missing: build it with __graft_entry__.build() "
                           "(hipcc --offload-arch=gfx950)")
+    # torch ships its own HIP runtime under the same soname as the system one;
+    # importing torch first makes libsq.so bind to that already-loaded copy, so
+    # the process holds a single HIP runtime and both see the same devices.
+    try:
+        import torch  # noqa: F401
+    except ImportError:
+        pass
     lib = ctypes.CDLL(path)
     vp, u32, u64, i32 = ctypes.c_void_p, ctypes.c_uint32, ctypes.c_uint64, ctypes.c_int
     pvp = ctypes.POINTER(ctypes.c_void_p)
