@@ -119,6 +119,21 @@ sq_status sq_measure(sq_tableau *t, const uint32_t *host_qubits, uint32_t count,
                      uint64_t seed, uint64_t shot, uint64_t meas_base,
                      uint8_t *host_out_bits, uint8_t *host_out_random);
 
+/* Sample `shots` shots of measuring host_qubits[0..count) (in that order) on
+ * the current state, without changing the tableau. Shot s (0 <= s < shots)
+ * is exactly the outcome string sq_measure would return on a copy of the
+ * tableau with shot number shot_begin + s, the same seed and measurement
+ * indices meas_base + i (the shots of the paper's sampling workload, drawn
+ * with the per-shot CHP semantics). Output: host_out[s * W + i/64] bit i%64,
+ * W = ceil(count/64), bits past count zero. Blocks.
+ * Work: one measurement sweep on a scratch copy in which stabilizer signs are
+ * tracked as affine functions of the coins, then one parity per outcome and
+ * shot. Scratch: about sq_bytes_required(n) plus (count+1)*ceil(n/64)*8 and
+ * count*W*8 bytes, allocated for the call.
+ * Errors: SQ_EINVAL, SQ_ERANGE (qubit >= n), SQ_ENOMEM, SQ_ESTATE. */
+sq_status sq_sample(sq_tableau *t, const uint32_t *host_qubits, uint32_t count, uint64_t seed, uint64_t shot_begin,
+                    uint32_t shots, uint64_t meas_base, uint64_t *host_out);
+
 /* Compile a circuit of n qubits (gates and SQ_MEASURE records in program
  * order) into a device-resident program on the current device.
  * Errors as sq_apply_gates, plus SQ_ENOMEM. */

@@ -23,7 +23,7 @@ KERNEL_NAMES = ["layer", "signs", "pivot", "gather", "rowsum", "finalize", "detp
 
 EXPORTED = [
     "sq_last_error", "sq_version", "sq_bytes_required", "sq_create", "sq_destroy", "sq_reset", "sq_sync",
-    "sq_num_qubits", "sq_apply_gates", "sq_measure", "sq_program_create", "sq_program_destroy",
+    "sq_num_qubits", "sq_apply_gates", "sq_measure", "sq_sample", "sq_program_create", "sq_program_destroy",
     "sq_program_num_measurements", "sq_program_num_gates", "sq_program_num_passes", "sq_program_gate_bytes",
     "sq_plan_gates",
     "sq_run", "sq_export_rows", "sq_export", "sq_import", "sq_measure_stats", "sq_error_flags",
@@ -80,6 +80,7 @@ def load(path: str = LIB_PATH):
         "sq_num_qubits": (u32, [vp]),
         "sq_apply_gates": (i32, [vp, vp, u64]),
         "sq_measure": (i32, [vp, vp, u32, u64, u64, u64, vp, vp]),
+        "sq_sample": (i32, [vp, vp, u32, u64, u64, u32, u64, vp]),
         "sq_program_create": (i32, [u32, vp, u64, pvp]),
         "sq_program_destroy": (i32, [vp]),
         "sq_program_num_measurements": (u64, [vp]),
@@ -202,6 +203,24 @@ class Tableau:
         _check(self.lib.sq_measure(self.h, q.ctypes.data, q.size, seed, shot, meas_base,
                                    bits.ctypes.data, rnd.ctypes.data))
         return bits[:q.size], rnd[:q.size]
+
+    def sample(self, qubits: Sequence[int], shots: int, seed: int = 0, shot_begin: int = 0,
+               meas_base: int = 0) -> np.ndarray:
+        """(shots, ceil(count/64)) uint64 words: bit i%64 of word i/64 = outcome i of that shot."""
+        q = np.ascontiguousarray(np.asarray(qubits, dtype=np.uint32).reshape(-1))
+        W = (q.size + 63) // 64
+        out = np.zeros((max(int(shots), 1), max(W, 1)), dtype=np.uint64)
+        _check(self.lib.sq_sample(self.h, q.ctypes.data, q.size, seed, shot_begin, int(shots), meas_base,
+                                  out.ctypes.data))
+        return out[:int(shots), :W]
+
+    def sample_bits(self, qubits: Sequence[int], shots: int, seed: int = 0, shot_begin: int = 0,
+                    meas_base: int = 0) -> np.ndarray:
+        """(shots, count) uint8 outcome bits."""
+        words = self.sample(qubits, shots, seed, shot_begin, meas_base)
+        count = len(np.asarray(qubits).reshape(-1))
+        bits = np.unpackbits(words.view(np.uint8), axis=1, bitorder="little")
+        return bits[:, :count]
 
     def run(self, program: Program, seed: int, shot: int, meas_base: int, dev_bits_ptr: int,
             dev_rand_ptr: Optional[int] = None):

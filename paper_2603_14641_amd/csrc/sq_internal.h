@@ -1,4 +1,5 @@
-// Private declarations shared by the kernels (sq_kernels.hip) and the host
+// Private declarations shared by the kernel files (sq_gates.hip,
+// sq_measure.hip, sq_io.hip) and the host
 // runtime behind the C ABI (sq_runtime.hip).
 //
 // Device layout of a tableau of n qubits (column-major, the layout the paper
@@ -55,6 +56,7 @@ struct MeasState {
   u32 mwords;     // nonzero words of the rowsum mask (row words the pass touches)
   u32 awords;     // nonzero destabilizer-half words of column q (deterministic case)
   u32 nx, nz;     // pivot-row columns with x_pj = 1, with z_pj = 1
+  u32 nsv;        // sampling: sign columns in which S_p has a 1 (compacted list length)
 };
 
 // Running totals over all measurements of a tableau, for byte accounting.
@@ -71,7 +73,7 @@ struct TabDev {
 
 struct LaunchTimer;  // host-side profiling hook (sq_runtime.hip)
 
-// Kernel launchers (sq_kernels.hip). All enqueue on `s` and return the
+// Kernel launchers (sq_gates.hip, sq_measure.hip, sq_io.hip). All enqueue on `s` and return the
 // launch status.
 hipError_t launch_fill_zero(u64 *p, size_t words, hipStream_t s);
 hipError_t launch_init_diag(const TabDev &t, hipStream_t s);
@@ -90,6 +92,22 @@ hipError_t launch_detphase(const TabDev &t, u32 q, const u64 *mask, MeasState *s
                            hipStream_t s);
 hipError_t launch_detfinal(const TabDev &t, const u64 *mask, MeasState *st, MeasStats *stats, uint8_t *out_bits,
                            hipStream_t s);
+// Shot sampling (sq_sample.hip): sign columns sg[v * Ks + w], v < count for
+// coins, v = count for the constant term.
+hipError_t launch_sample_init(const TabDev &t, u64 *sg, u32 Ks, u32 count, hipStream_t s);
+hipError_t launch_gather_signs(const u64 *sg, MeasState *st, u32 *svlist, u32 Ks, u32 i, u32 count, hipStream_t s);
+hipError_t launch_signcols(const TabDev &t, u64 *sg, const u64 *mask, const MeasState *st, const u32 *svlist, u32 Ks,
+                           u32 max_v, hipStream_t s);
+hipError_t launch_finalize_sym(const TabDev &t, u32 q, u64 *sgc, const u64 *mask, const u64 *pivx, const u64 *pivz,
+                               const u64 *cnt0, const u64 *cnt1, MeasState *st, u32 cpc, hipStream_t s);
+hipError_t launch_spvec(u64 *sg, const MeasState *st, const u32 *svlist, uint8_t *kind, u32 Ks, u32 i, u32 count,
+                        hipStream_t s);
+hipError_t launch_detfinal_sym(const TabDev &t, const u64 *sg, const u64 *mask, MeasState *st, uint8_t *kind,
+                               u64 *fm, uint8_t *fc, u32 Ks, u32 CW, u32 i, u32 count, hipStream_t s);
+hipError_t launch_coins(u64 *cw, u64 seed, u64 shot_begin, u64 meas_base, u32 shots, u32 count, u32 CW,
+                        hipStream_t s);
+hipError_t launch_eval(const u64 *cw, const uint8_t *kind, const u64 *fm, const uint8_t *fc, u64 *out, u32 shots,
+                       u32 count, u32 CW, hipStream_t s);
 hipError_t launch_export_rows(const TabDev &t, const u32 *rows, u32 nrows, u32 W, u64 *ox, u64 *oz, uint8_t *orr,
                               hipStream_t s);
 hipError_t launch_import(const TabDev &t, const u64 *ix, const u64 *iz, const uint8_t *ir, u32 W, hipStream_t s);

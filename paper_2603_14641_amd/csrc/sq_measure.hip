@@ -1,246 +1,8 @@
-// HIP kernels for gfx950 (CDNA4, wave64) of the stabilizer-tableau library.
-//
-// All arithmetic is GF(2) bit work on 64-bit words (64 tableau rows per
-// word), plus small integer phase counts; nothing here uses MFMA. Every hot
-// kernel streams coalesced 64-bit column words: consecutive lanes own
-// consecutive row words of one column.
-#include <algorithm>
-
-#include "sq_internal.h"
+// Z measurement (CHP): pivot search, pivot-row gather, rowsum pass and its
+// finalisation, and the deterministic-outcome product.
+#include "sq_device.h"
 
 namespace sq {
-
-typedef u64 u64x2 __attribute__((ext_vector_type(2)));
-
-// ---------------------------------------------------------------------------
-// Philox4x64-10 (Salmon, Moraes, Dror and Shaw, SC'11): 10 rounds, each
-// multiplying counter words 0 and 2 by two odd constants and folding the
-// high halves into words 1 and 3 with the round key; the key advances by two
-// Weyl constants between rounds.
-__device__ __forceinline__ u64 philox_word0(u64 c0, u64 c1, u64 c2, u64 c3, u64 k0, u64 k1) {
-  constexpr u64 M0 = 0xD2E7470EE14C6C93ULL, M1 = 0xCA5A826395121157ULL;
-  constexpr u64 W0 = 0x9E3779B97F4A7C15ULL, W1 = 0xBB67AE8584CAA73BULL;
-#pragma unroll
-  for (int r = 0; r < 10; ++r) {
-    if (r > 0) { k0 += W0; k1 += W1; }
-    const u64 hi0 = __umul64hi(M0, c0), lo0 = M0 * c0;
-    const u64 hi1 = __umul64hi(M1, c2), lo1 = M1 * c2;
-    const u64 n0 = hi1 ^ c1 ^ k0, n2 = hi0 ^ c3 ^ k1;
-    c0 = n0; c1 = lo1; c2 = n2; c3 = lo0;
-  }
-  return c0;
-}
-
-// Coin of measurement m of shot `shot`: bit 0 of output word 0, counter (m,0,0,0), key (seed, shot).
-__device__ __forceinline__ u32 coin_bit(u64 seed, u64 shot, u64 m) {
-  return (u32)(philox_word0(m, 0, 0, 0, seed, shot) & 1ULL);
-}
-
-__device__ __forceinline__ u64 lanemask_lt() {
-  const u32 lane = threadIdx.x & 63u;
-  return (lane == 0) ? 0ULL : ((~0ULL) >> (64u - lane));
-}
-
-template <int WPT>
-__device__ __forceinline__ void ldw(const u64 *p, u64 (&v)[WPT]) {
-  if constexpr (WPT == 2) {
-    const u64x2 t = *reinterpret_cast<const u64x2 *>(p);
-    v[0] = t.x;
-    v[1] = t.y;
-  } else {
-    v[0] = *p;
-  }
-}
-
-template <int WPT>
-__device__ __forceinline__ void stw(u64 *p, const u64 (&v)[WPT]) {
-  if constexpr (WPT == 2) {
-    u64x2 t;
-    t.x = v[0];
-    t.y = v[1];
-    *reinterpret_cast<u64x2 *>(p) = t;
-  } else {
-    *p = v[0];
-  }
-}
-
-// ---------------------------------------------------------------------------
-// a1: |0...0> -- zero everything, then D_i = +X_i and S_i = +Z_i.
-__global__ void k_fill_zero(u64 *__restrict__ p, size_t words) {
-  const size_t stride = (size_t)gridDim.x * blockDim.x;
-  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < words; i += stride) p[i] = 0;
-}
-
-__global__ void k_init_diag(u64 *__restrict__ X, u64 *__restrict__ Z, u32 n, u32 K, u32 Ls) {
-  const u32 i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  const u64 b = 1ULL << (i & 63u);
-  X[(size_t)i * Ls + (i >> 6)] = b;          // D_i = X_i: column i, destabilizer word i/64
-  Z[(size_t)i * Ls + K + (i >> 6)] = b;      // S_i = Z_i: column i, stabilizer word i/64
-}
-
-// ---------------------------------------------------------------------------
-// a2: one fused gate pass. Each group is a short sequence of gates on one or
-// two qubits; groups of a pass act on disjoint qubits, so every (group,
-// row word) update is independent. The column rules (pre-gate values on the
-// right-hand side) per 64 rows at once:
-//   H:   r ^= x&z;  (x, z) <- (z, x)
-//   S:   r ^= x&z;  z ^= x          S^dagger: r ^= x&~z; z ^= x
-//   X:   r ^= z     Y: r ^= x^z     Z: r ^= x
-//   CX(c,t): r ^= x_c & z_t & ~(x_t ^ z_c); x_t ^= x_c; z_c ^= z_t
-//   CZ(a,b): r ^= x_a & x_b & (z_a ^ z_b);  z_a ^= x_b; z_b ^= x_a
-// A thread owns WPT consecutive row words and walks the groups of its
-// chunk, keeping the sign changes in registers; the per-chunk sign words go
-// to sign_part and are XOR-reduced by k_sign_reduce.
-template <int WPT>
-__device__ __forceinline__ void run_uops(u64 ops, u64 (&xa)[WPT], u64 (&za)[WPT], u64 (&xb)[WPT], u64 (&zb)[WPT],
-                                         u64 (&s)[WPT]) {
-  for (; ops != 0; ops >>= 4) {
-    switch ((u32)(ops & 15ULL)) {
-      case UOP_H_A:
-#pragma unroll
-        for (int k = 0; k < WPT; ++k) { s[k] ^= xa[k] & za[k]; const u64 t = xa[k]; xa[k] = za[k]; za[k] = t; }
-        break;
-      case UOP_S_A:
-#pragma unroll
-        for (int k = 0; k < WPT; ++k) { s[k] ^= xa[k] & za[k]; za[k] ^= xa[k]; }
-        break;
-      case UOP_SDG_A:
-#pragma unroll
-        for (int k = 0; k < WPT; ++k) { s[k] ^= xa[k] & ~za[k]; za[k] ^= xa[k]; }
-        break;
-      case UOP_X_A:
-#pragma unroll
-        for (int k = 0; k < WPT; ++k) s[k] ^= za[k];
-        break;
-      case UOP_Y_A:
-#pragma unroll
-        for (int k = 0; k < WPT; ++k) s[k] ^= xa[k] ^ za[k];
-        break;
-      case UOP_Z_A:
-#pragma unroll
-        for (int k = 0; k < WPT; ++k) s[k] ^= xa[k];
-        break;
-      case UOP_H_B:
-#pragma unroll
-        for (int k = 0; k < WPT; ++k) { s[k] ^= xb[k] & zb[k]; const u64 t = xb[k]; xb[k] = zb[k]; zb[k] = t; }
-        break;
-      case UOP_S_B:
-#pragma unroll
-        for (int k = 0; k < WPT; ++k) { s[k] ^= xb[k] & zb[k]; zb[k] ^= xb[k]; }
-        break;
-      case UOP_SDG_B:
-#pragma unroll
-        for (int k = 0; k < WPT; ++k) { s[k] ^= xb[k] & ~zb[k]; zb[k] ^= xb[k]; }
-        break;
-      case UOP_X_B:
-#pragma unroll
-        for (int k = 0; k < WPT; ++k) s[k] ^= zb[k];
-        break;
-      case UOP_Y_B:
-#pragma unroll
-        for (int k = 0; k < WPT; ++k) s[k] ^= xb[k] ^ zb[k];
-        break;
-      case UOP_Z_B:
-#pragma unroll
-        for (int k = 0; k < WPT; ++k) s[k] ^= xb[k];
-        break;
-      case UOP_CX_AB:
-#pragma unroll
-        for (int k = 0; k < WPT; ++k) { s[k] ^= xa[k] & zb[k] & ~(xb[k] ^ za[k]); xb[k] ^= xa[k]; za[k] ^= zb[k]; }
-        break;
-      case UOP_CX_BA:
-#pragma unroll
-        for (int k = 0; k < WPT; ++k) { s[k] ^= xb[k] & za[k] & ~(xa[k] ^ zb[k]); xa[k] ^= xb[k]; zb[k] ^= za[k]; }
-        break;
-      case UOP_CZ:
-#pragma unroll
-        for (int k = 0; k < WPT; ++k) { s[k] ^= xa[k] & xb[k] & (za[k] ^ zb[k]); const u64 ta = za[k] ^ xb[k]; zb[k] ^= xa[k]; za[k] = ta; }
-        break;
-      default:
-        break;
-    }
-  }
-}
-
-template <int WPT, int B>
-__global__ __launch_bounds__(1024) void k_layer(u64 *__restrict__ X, u64 *__restrict__ Z, u64 *__restrict__ sign_part,
-                                                 const Group *__restrict__ groups, u32 ngroups, u32 gpc, u32 Ls, u32 L) {
-  const u32 w = (blockIdx.x * blockDim.x + threadIdx.x) * WPT;
-  if (w >= L) return;
-  const u32 g0 = blockIdx.y * gpc;
-  const u32 g1 = min(g0 + gpc, ngroups);
-  u64 s[WPT];
-#pragma unroll
-  for (int k = 0; k < WPT; ++k) s[k] = 0;
-
-  u32 g = g0;
-  for (; g + B <= g1; g += B) {
-    Group G[B];
-    u64 xa[B][WPT], za[B][WPT], xb[B][WPT], zb[B][WPT];
-#pragma unroll
-    for (int b = 0; b < B; ++b) G[b] = groups[g + b];
-#pragma unroll
-    for (int b = 0; b < B; ++b) {
-      const size_t ca = (size_t)(G[b].q0 & GQ_MASK) * Ls + w;
-      ldw<WPT>(X + ca, xa[b]);
-      ldw<WPT>(Z + ca, za[b]);
-      if (G[b].q1 != G_SINGLE) {
-        const size_t cb = (size_t)G[b].q1 * Ls + w;
-        ldw<WPT>(X + cb, xb[b]);
-        ldw<WPT>(Z + cb, zb[b]);
-      } else {
-#pragma unroll
-        for (int k = 0; k < WPT; ++k) { xb[b][k] = 0; zb[b][k] = 0; }
-      }
-    }
-#pragma unroll
-    for (int b = 0; b < B; ++b) {
-      run_uops<WPT>(G[b].ops, xa[b], za[b], xb[b], zb[b], s);
-      const u32 f = G[b].q0;
-      const size_t ca = (size_t)(f & GQ_MASK) * Ls + w;
-      if (f & GD_XA) stw<WPT>(X + ca, xa[b]);
-      if (f & GD_ZA) stw<WPT>(Z + ca, za[b]);
-      if (G[b].q1 != G_SINGLE) {
-        const size_t cb = (size_t)G[b].q1 * Ls + w;
-        if (f & GD_XB) stw<WPT>(X + cb, xb[b]);
-        if (f & GD_ZB) stw<WPT>(Z + cb, zb[b]);
-      }
-    }
-  }
-  for (; g < g1; ++g) {
-    const Group G = groups[g];
-    u64 xa[WPT], za[WPT], xb[WPT], zb[WPT];
-    const size_t ca = (size_t)(G.q0 & GQ_MASK) * Ls + w;
-    ldw<WPT>(X + ca, xa);
-    ldw<WPT>(Z + ca, za);
-    const bool two = G.q1 != G_SINGLE;
-    const size_t cb = two ? (size_t)G.q1 * Ls + w : 0;
-    if (two) {
-      ldw<WPT>(X + cb, xb);
-      ldw<WPT>(Z + cb, zb);
-    } else {
-#pragma unroll
-      for (int k = 0; k < WPT; ++k) { xb[k] = 0; zb[k] = 0; }
-    }
-    run_uops<WPT>(G.ops, xa, za, xb, zb, s);
-    if (G.q0 & GD_XA) stw<WPT>(X + ca, xa);
-    if (G.q0 & GD_ZA) stw<WPT>(Z + ca, za);
-    if (two) {
-      if (G.q0 & GD_XB) stw<WPT>(X + cb, xb);
-      if (G.q0 & GD_ZB) stw<WPT>(Z + cb, zb);
-    }
-  }
-  stw<WPT>(sign_part + (size_t)blockIdx.y * Ls + w, s);
-}
-
-__global__ void k_sign_reduce(u64 *__restrict__ R, const u64 *__restrict__ sign_part, u32 nchunks, u32 Ls, u32 L) {
-  const u32 w = blockIdx.x * blockDim.x + threadIdx.x;
-  if (w >= L) return;
-  u64 acc = 0;
-  for (u32 c = 0; c < nchunks; ++c) acc ^= sign_part[(size_t)c * Ls + w];
-  R[w] ^= acc;
-}
 
 // ---------------------------------------------------------------------------
 // a3: pivot search for measuring qubit q. p = the smallest stabilizer index
@@ -291,6 +53,7 @@ __global__ __launch_bounds__(1024) void k_pivot(const u64 *__restrict__ X, u32 L
     const u32 c = coin_bit(seed, shot, m);
     st->p = p;
     st->ncols = 0;
+    st->nsv = 0;
     st->nx = 0;
     st->nz = 0;
     st->mwords = s_mw;
@@ -599,84 +362,7 @@ __global__ __launch_bounds__(256) void k_detfinal(const u64 *__restrict__ R, con
   }
 }
 
-// ---------------------------------------------------------------------------
-// Canonical row-major export/import (checks and checkpoints; not a hot path).
-__global__ void k_export_rows(const u64 *__restrict__ X, const u64 *__restrict__ Z, const u64 *__restrict__ R,
-                              u32 Ls, u32 K, u32 n, const u32 *__restrict__ rows, u32 nrows, u32 W,
-                              u64 *__restrict__ ox, u64 *__restrict__ oz, uint8_t *__restrict__ orr) {
-  const u32 j = blockIdx.x * blockDim.x + threadIdx.x;
-  for (u32 k = blockIdx.y; k < nrows; k += gridDim.y) {
-    const u32 g = rows[k];
-    const u32 wr = (g < n) ? (g >> 6) : (K + ((g - n) >> 6));
-    const u32 br = ((g < n) ? g : (g - n)) & 63u;
-    u32 xb = 0, zb = 0;
-    if (j < n) {
-      xb = (u32)(X[(size_t)j * Ls + wr] >> br) & 1u;
-      zb = (u32)(Z[(size_t)j * Ls + wr] >> br) & 1u;
-    }
-    const u64 bx = __ballot(xb), bz = __ballot(zb);
-    if ((threadIdx.x & 63u) == 0 && (j >> 6) < W) {
-      ox[(size_t)k * W + (j >> 6)] = bx;
-      oz[(size_t)k * W + (j >> 6)] = bz;
-    }
-    if (j == 0) orr[k] = (uint8_t)((R[wr] >> br) & 1ULL);
-  }
-}
-
-// Column word (j, w) gathers bit j of the 64 rows that word w packs.
-__global__ void k_import(u64 *__restrict__ X, u64 *__restrict__ Z, u64 *__restrict__ R, u32 Ls, u32 K, u32 L, u32 n,
-                         const u64 *__restrict__ ix, const u64 *__restrict__ iz, const uint8_t *__restrict__ ir,
-                         u32 W, u32 wblocks) {
-  const u32 j = blockIdx.x / wblocks;
-  const u32 w = (blockIdx.x % wblocks) * blockDim.x + threadIdx.x;
-  if (w >= L) return;
-  const u32 half = (w < K) ? 0u : n;
-  const u32 r0 = ((w < K) ? w : (w - K)) * 64u;
-  u64 vx = 0, vz = 0, vr = 0;
-  for (u32 b = 0; b < 64u && r0 + b < n; ++b) {
-    const size_t g = (size_t)half + r0 + b;
-    vx |= ((ix[g * W + (j >> 6)] >> (j & 63u)) & 1ULL) << b;
-    vz |= ((iz[g * W + (j >> 6)] >> (j & 63u)) & 1ULL) << b;
-    if (j == 0) vr |= (u64)(ir[g] & 1u) << b;
-  }
-  X[(size_t)j * Ls + w] = vx;
-  Z[(size_t)j * Ls + w] = vz;
-  if (j == 0) R[w] = vr;
-}
-
-// ---------------------------------------------------------------------------
 // Launchers.
-static inline u32 cdiv(u64 a, u64 b) { return (u32)((a + b - 1) / b); }
-
-hipError_t launch_fill_zero(u64 *p, size_t words, hipStream_t s) {
-  if (words == 0) return hipSuccess;
-  const u32 blocks = (u32)std::min<u64>(cdiv(words, 256), 65536);
-  hipLaunchKernelGGL(k_fill_zero, dim3(blocks), dim3(256), 0, s, p, words);
-  return hipGetLastError();
-}
-
-hipError_t launch_init_diag(const TabDev &t, hipStream_t s) {
-  hipLaunchKernelGGL(k_init_diag, dim3(cdiv(t.n, 256)), dim3(256), 0, s, t.X, t.Z, t.n, t.K, t.Ls);
-  return hipGetLastError();
-}
-
-hipError_t launch_layer(const TabDev &t, const Group *groups, u32 ngroups, u32 block, u32 wpt, u32 gpc,
-                        u64 *sign_part, hipStream_t s) {
-  const u32 tiles = cdiv(t.L, (u64)block * wpt);
-  const u32 chunks = cdiv(ngroups, gpc);
-  dim3 grid(tiles, chunks);
-  if (wpt == 2)
-    hipLaunchKernelGGL((k_layer<2, 4>), grid, dim3(block), 0, s, t.X, t.Z, sign_part, groups, ngroups, gpc, t.Ls, t.L);
-  else
-    hipLaunchKernelGGL((k_layer<1, 4>), grid, dim3(block), 0, s, t.X, t.Z, sign_part, groups, ngroups, gpc, t.Ls, t.L);
-  return hipGetLastError();
-}
-
-hipError_t launch_sign_reduce(const TabDev &t, const u64 *sign_part, u32 nchunks, hipStream_t s) {
-  hipLaunchKernelGGL(k_sign_reduce, dim3(cdiv(t.L, 256)), dim3(256), 0, s, t.R, sign_part, nchunks, t.Ls, t.L);
-  return hipGetLastError();
-}
-
 hipError_t launch_pivot(const TabDev &t, u32 q, MeasState *st, u64 *mask, u64 seed, u64 shot, u64 m,
                         uint8_t *out_bits, uint8_t *out_rand, hipStream_t s) {
   hipLaunchKernelGGL(k_pivot, dim3(1), dim3(1024), 0, s, t.X, t.Ls, t.K, t.L, q, st, mask, seed, shot, m, out_bits,
@@ -722,23 +408,6 @@ hipError_t launch_detphase(const TabDev &t, u32 q, const u64 *mask, MeasState *s
 hipError_t launch_detfinal(const TabDev &t, const u64 *mask, MeasState *st, MeasStats *stats, uint8_t *out_bits,
                            hipStream_t s) {
   hipLaunchKernelGGL(k_detfinal, dim3(1), dim3(256), 0, s, t.R, mask, st, stats, t.K, t.n, out_bits);
-  return hipGetLastError();
-}
-
-hipError_t launch_export_rows(const TabDev &t, const u32 *rows, u32 nrows, u32 W, u64 *ox, u64 *oz, uint8_t *orr,
-                              hipStream_t s) {
-  if (nrows == 0) return hipSuccess;
-  const u32 cols_rounded = W * 64u;
-  dim3 grid(cdiv(cols_rounded, 256), std::min<u32>(nrows, 65535u));
-  hipLaunchKernelGGL(k_export_rows, grid, dim3(256), 0, s, t.X, t.Z, t.R, t.Ls, t.K, t.n, rows, nrows, W, ox, oz,
-                     orr);
-  return hipGetLastError();
-}
-
-hipError_t launch_import(const TabDev &t, const u64 *ix, const u64 *iz, const uint8_t *ir, u32 W, hipStream_t s) {
-  const u32 wblocks = cdiv(t.L, 256);
-  hipLaunchKernelGGL(k_import, dim3(wblocks * t.n), dim3(256), 0, s, t.X, t.Z, t.R, t.Ls, t.K, t.L, t.n, ix, iz, ir,
-                     W, wblocks);
   return hipGetLastError();
 }
 

@@ -580,6 +580,82 @@ sq_status sq_measure(sq_tableau *T, const uint32_t *qubits, uint32_t count, uint
   return SQ_OK;
 }
 
+sq_status sq_sample(sq_tableau *T, const uint32_t *qubits, uint32_t count, uint64_t seed, uint64_t shot_begin,
+                    uint32_t shots, uint64_t meas_base, uint64_t *host_out) {
+  if (!T) return fail(SQ_EINVAL, "tableau is NULL");
+  if (count == 0 || shots == 0) return SQ_OK;
+  if (!qubits || !host_out) return fail(SQ_EINVAL, "qubits/host_out is NULL");
+  for (u32 i = 0; i < count; ++i)
+    if (qubits[i] >= T->d.n) return fail(SQ_ERANGE, "qubit %u >= n=%u", qubits[i], T->d.n);
+  const Dims &d = T->d;
+  const u32 Ks = round_up(d.K, 16);
+  const u32 CW = cdiv(count, 64);
+  // workspace: X, Z copies | sign columns | Fm | cw | out | svlist | kind | fc | dummy
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    size_t r = off;
+    off += (bytes + 255) / 256 * 256;
+    return r;
+  };
+  const size_t o_x = take((size_t)d.n * d.Ls * 8), o_z = take((size_t)d.n * d.Ls * 8);
+  const size_t o_sg = take((size_t)(count + 1) * Ks * 8), o_fm = take((size_t)count * CW * 8);
+  const size_t o_cw = take((size_t)shots * CW * 8), o_out = take((size_t)shots * CW * 8);
+  const size_t o_sv = take((size_t)(count + 1) * 4), o_kind = take(count), o_fc = take(count), o_dummy = take(2);
+  uint8_t *ws = nullptr;
+  if (hipMalloc((void **)&ws, off) != hipSuccess) {
+    (void)hipGetLastError();
+    return fail(SQ_ENOMEM, "device allocation of %zu bytes for sampling failed", off);
+  }
+  u64 *sg = (u64 *)(ws + o_sg), *fm = (u64 *)(ws + o_fm), *cw = (u64 *)(ws + o_cw), *dout = (u64 *)(ws + o_out);
+  u32 *svlist = (u32 *)(ws + o_sv);
+  uint8_t *kind = ws + o_kind, *fc = ws + o_fc, *dummy = ws + o_dummy;
+  TabDev ts{(u64 *)(ws + o_x), (u64 *)(ws + o_z), T->t.R, d.n, d.K, d.L, d.Ls};
+  const u32 cpc = rowsum_cpc(T);
+  const u32 max_chunks = cdiv(d.n, cpc);
+  MeasState before{}, after{};
+  sq_status s = SQ_OK;
+  auto run = [&]() -> sq_status {
+    HIP_TRY(hipMemcpyAsync(&before, T->st, sizeof(MeasState), hipMemcpyDeviceToHost, T->stream));
+    HIP_TRY(hipMemcpyAsync(ts.X, T->t.X, (size_t)d.n * d.Ls * 8, hipMemcpyDeviceToDevice, T->stream));
+    HIP_TRY(hipMemcpyAsync(ts.Z, T->t.Z, (size_t)d.n * d.Ls * 8, hipMemcpyDeviceToDevice, T->stream));
+    HIP_TRY(launch_sample_init(T->t, sg, Ks, count, T->stream));
+    for (u32 i = 0; i < count; ++i) {
+      const u32 q = qubits[i];
+      SQ_TRY(timed(T, SQ_K_PIVOT, [&] { return launch_pivot(ts, q, T->st, T->mask, seed, 0, 0, dummy, dummy + 1, T->stream); }));
+      SQ_TRY(timed(T, SQ_K_GATHER, [&] { return launch_gather(ts, T->st, T->pivx, T->pivz, T->cols, T->stream); }));
+      HIP_TRY(launch_gather_signs(sg, T->st, svlist, Ks, i, count, T->stream));
+      SQ_TRY(timed(T, SQ_K_ROWSUM, [&] {
+        return launch_rowsum(ts, T->mask, T->cols, T->st, T->cnt0, T->cnt1, T->tun.rowsum_block, T->tun.rowsum_wpt,
+                             cpc, max_chunks, T->stream);
+      }));
+      HIP_TRY(launch_signcols(ts, sg, T->mask, T->st, svlist, Ks, i + 1, T->stream));
+      SQ_TRY(timed(T, SQ_K_FINAL, [&] {
+        return launch_finalize_sym(ts, q, sg + (size_t)count * Ks, T->mask, T->pivx, T->pivz, T->cnt0, T->cnt1, T->st,
+                                   cpc, T->stream);
+      }));
+      HIP_TRY(launch_spvec(sg, T->st, svlist, kind, Ks, i, count, T->stream));
+      SQ_TRY(timed(T, SQ_K_DET, [&] {
+        return launch_detphase(ts, q, T->mask, T->st, T->tun.det_block, det_cpw(T), T->stream);
+      }));
+      SQ_TRY(timed(T, SQ_K_DETFINAL, [&] {
+        return launch_detfinal_sym(ts, sg, T->mask, T->st, kind, fm, fc, Ks, CW, i, count, T->stream);
+      }));
+    }
+    HIP_TRY(launch_coins(cw, seed, shot_begin, meas_base, shots, count, CW, T->stream));
+    HIP_TRY(launch_eval(cw, kind, fm, fc, dout, shots, count, CW, T->stream));
+    HIP_TRY(hipMemcpyAsync(host_out, dout, (size_t)shots * CW * 8, hipMemcpyDeviceToHost, T->stream));
+    HIP_TRY(hipMemcpyAsync(&after, T->st, sizeof(MeasState), hipMemcpyDeviceToHost, T->stream));
+    HIP_TRY(hipStreamSynchronize(T->stream));
+    return SQ_OK;
+  };
+  s = run();
+  if (s != SQ_OK) (void)hipStreamSynchronize(T->stream);
+  (void)hipFree(ws);
+  if (s == SQ_OK && after.flags != before.flags)
+    s = fail(SQ_ESTATE, "device consistency check failed (flags 0x%x)", after.flags);
+  return s;
+}
+
 sq_status sq_program_create(uint32_t n, const sq_op *ops, uint64_t count, sq_program **out) {
   if (!out) return fail(SQ_EINVAL, "out is NULL");
   *out = nullptr;
