@@ -134,6 +134,39 @@ sq_status sq_measure(sq_tableau *t, const uint32_t *host_qubits, uint32_t count,
 sq_status sq_sample(sq_tableau *t, const uint32_t *host_qubits, uint32_t count, uint64_t seed, uint64_t shot_begin,
                     uint32_t shots, uint64_t meas_base, uint64_t *host_out);
 
+/* Batched sampling of many independent circuits (the batched/served
+ * workload: circuits of uneven size, each with its own shot count).
+ * Item k is, bit for bit, the result of sq_create(n), sq_apply_gates(ops),
+ * sq_sample(qubits, count, seed, shot_begin, shots, meas_base, out),
+ * sq_destroy. Circuits up to opts->max_batch_n qubits (and at most 16384
+ * qubits, fewer than 32768 measurements) run in one persistent launch in
+ * which a workgroup takes one circuit at a time, largest first, and runs its
+ * gates, measurement sweep and shots without further launches; larger
+ * circuits run through the single-tableau kernels. Blocks until every output
+ * is written. opts may be NULL (automatic choices).
+ * Errors: SQ_EINVAL, SQ_ERANGE, SQ_ENOMEM, SQ_EDEVICE, SQ_ESTATE (a device
+ * consistency check of some item failed). */
+typedef struct {
+  uint32_t n;
+  const sq_op *ops;        /* gates only, program order */
+  uint64_t nops;
+  const uint32_t *qubits;  /* measured list, in order */
+  uint32_t count;
+  uint32_t shots;
+  uint64_t seed;
+  uint64_t shot_begin;
+  uint64_t meas_base;
+  uint64_t *out;           /* host, shots * ceil(count/64) words */
+} sq_batch_item;
+
+typedef struct {
+  uint32_t block;        /* threads per workgroup of the batched kernel (multiple of 64, <= 512; 0 = automatic) */
+  uint32_t grid;         /* workgroups of the persistent launch (0 = automatic) */
+  uint32_t max_batch_n;  /* larger circuits take the single-tableau path (0 = automatic) */
+} sq_batch_opts;
+
+sq_status sq_batch_sample(const sq_batch_item *items, uint32_t nitems, const sq_batch_opts *opts, void *hip_stream);
+
 /* Compile a circuit of n qubits (gates and SQ_MEASURE records in program
  * order) into a device-resident program on the current device.
  * Errors as sq_apply_gates, plus SQ_ENOMEM. */

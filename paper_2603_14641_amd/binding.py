@@ -23,7 +23,8 @@ KERNEL_NAMES = ["layer", "signs", "pivot", "gather", "rowsum", "finalize", "detp
 
 EXPORTED = [
     "sq_last_error", "sq_version", "sq_bytes_required", "sq_create", "sq_destroy", "sq_reset", "sq_sync",
-    "sq_num_qubits", "sq_apply_gates", "sq_measure", "sq_sample", "sq_program_create", "sq_program_destroy",
+    "sq_num_qubits", "sq_apply_gates", "sq_measure", "sq_sample", "sq_batch_sample", "sq_program_create",
+    "sq_program_destroy",
     "sq_program_num_measurements", "sq_program_num_gates", "sq_program_num_passes", "sq_program_gate_bytes",
     "sq_plan_gates",
     "sq_run", "sq_export_rows", "sq_export", "sq_import", "sq_measure_stats", "sq_error_flags",
@@ -41,6 +42,17 @@ class Tuning(ctypes.Structure):
     _fields_ = [(name, ctypes.c_uint32) for name in (
         "layer_block", "layer_wpt", "layer_groups", "rowsum_block", "rowsum_wpt", "rowsum_cols",
         "det_block", "det_cols")]
+
+
+class BatchItem(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_uint32), ("ops", ctypes.c_void_p), ("nops", ctypes.c_uint64),
+                ("qubits", ctypes.c_void_p), ("count", ctypes.c_uint32), ("shots", ctypes.c_uint32),
+                ("seed", ctypes.c_uint64), ("shot_begin", ctypes.c_uint64), ("meas_base", ctypes.c_uint64),
+                ("out", ctypes.c_void_p)]
+
+
+class BatchOpts(ctypes.Structure):
+    _fields_ = [("block", ctypes.c_uint32), ("grid", ctypes.c_uint32), ("max_batch_n", ctypes.c_uint32)]
 
 
 class MeasStats(ctypes.Structure):
@@ -81,6 +93,7 @@ def load(path: str = LIB_PATH):
         "sq_apply_gates": (i32, [vp, vp, u64]),
         "sq_measure": (i32, [vp, vp, u32, u64, u64, u64, vp, vp]),
         "sq_sample": (i32, [vp, vp, u32, u64, u64, u32, u64, vp]),
+        "sq_batch_sample": (i32, [ctypes.POINTER(BatchItem), u32, ctypes.POINTER(BatchOpts), vp]),
         "sq_program_create": (i32, [u32, vp, u64, pvp]),
         "sq_program_destroy": (i32, [vp]),
         "sq_program_num_measurements": (u64, [vp]),
@@ -297,6 +310,47 @@ class Tableau:
         n = ctypes.c_uint64(0)
         _check(self.lib.sq_profile_read(self.h, kernel, ctypes.byref(ms), ctypes.byref(n)))
         return float(ms.value), int(n.value)
+
+
+def batch_sample(requests, block: int = 0, grid: int = 0, max_batch_n: int = 0, stream=None):
+    """Run many independent circuits in one batched launch (sq_batch_sample).
+
+    Each request is a dict with n, ops (gates), qubits, shots and optional
+    seed, shot_begin, meas_base. Returns a list of (shots, ceil(count/64))
+    uint64 outcome-word arrays."""
+    lib = load()
+    keep, outs = [], []
+    arr = (BatchItem * max(len(requests), 1))()
+    for k, r in enumerate(requests):
+        ops = ops_array(r["ops"])
+        q = np.ascontiguousarray(np.asarray(r["qubits"], dtype=np.uint32).reshape(-1))
+        W = (q.size + 63) // 64
+        out = np.zeros((max(int(r["shots"]), 1), max(W, 1)), dtype=np.uint64)
+        keep += [ops, q]
+        outs.append(out)
+        it = arr[k]
+        it.n = int(r["n"])
+        it.ops = ops.ctypes.data if ops.size else None
+        it.nops = ops.shape[0]
+        it.qubits = q.ctypes.data if q.size else None
+        it.count = q.size
+        it.shots = int(r["shots"])
+        it.seed = int(r.get("seed", 0))
+        it.shot_begin = int(r.get("shot_begin", 0))
+        it.meas_base = int(r.get("meas_base", 0))
+        it.out = out.ctypes.data
+    opts = BatchOpts(block, grid, max_batch_n)
+    _check(lib.sq_batch_sample(arr, len(requests), ctypes.byref(opts), _stream_ptr(stream)))
+    res = []
+    for r, out in zip(requests, outs):
+        W = (len(np.asarray(r["qubits"]).reshape(-1)) + 63) // 64
+        res.append(out[:int(r["shots"]), :W])
+    return res
+
+
+def words_to_bits(words: np.ndarray, count: int) -> np.ndarray:
+    bits = np.unpackbits(np.ascontiguousarray(words).view(np.uint8), axis=1, bitorder="little")
+    return bits[:, :count]
 
 
 def plan_gates(n: int, ops) -> list:

@@ -66,6 +66,24 @@ struct MeasStats {
   u64 det_bytes;      // algorithmic bytes of the deterministic-phase passes
 };
 
+// One circuit of a batched launch (sq_batch.hip): |0...0>, gate passes
+// groups[pass_off[p] .. pass_off[p+1]), then `shots` shots of measuring
+// qubits[0..count). All pointers are device memory owned by the batch.
+struct BatchItem {
+  u32 n, Ls, Ks, CW, count, shots, npasses, pad;
+  u64 *X, *Z;          // n * Ls words each
+  u64 *sg;             // (count + 1) * Ks sign-column words
+  u64 *fm;             // count * CW affine-form words
+  u64 *coinbuf;        // shots * CW coin words
+  u64 *out;            // shots * CW outcome words
+  uint8_t *fc, *kind;  // count bytes each
+  const Group *groups;
+  const u32 *pass_off; // npasses + 1 offsets into groups
+  const u32 *qubits;
+  u64 seed, shot_begin, meas_base;
+  u32 *flags;          // consistency flags of this circuit (OR-ed)
+};
+
 struct TabDev {
   u64 *X, *Z, *R;
   u32 n, K, L, Ls;
@@ -108,6 +126,7 @@ hipError_t launch_coins(u64 *cw, u64 seed, u64 shot_begin, u64 meas_base, u32 sh
                         hipStream_t s);
 hipError_t launch_eval(const u64 *cw, const uint8_t *kind, const u64 *fm, const uint8_t *fc, u64 *out, u32 shots,
                        u32 count, u32 CW, hipStream_t s);
+hipError_t launch_batch(const BatchItem *items, u32 nitems, u32 *next, u32 block, u32 grid, hipStream_t s);
 hipError_t launch_export_rows(const TabDev &t, const u32 *rows, u32 nrows, u32 W, u64 *ox, u64 *oz, uint8_t *orr,
                               hipStream_t s);
 hipError_t launch_import(const TabDev &t, const u64 *ix, const u64 *iz, const uint8_t *ir, u32 W, hipStream_t s);

@@ -656,6 +656,173 @@ sq_status sq_sample(sq_tableau *T, const uint32_t *qubits, uint32_t count, uint6
   return s;
 }
 
+namespace {
+constexpr u32 kBatchMaxN = 16384;
+constexpr u32 kBatchMaxCount = 32767;
+
+// One item through the single-tableau path: create, gates, sample, destroy.
+sq_status batch_item_plain(const sq_batch_item &it, hipStream_t stream) {
+  sq_tableau *T = nullptr;
+  SQ_TRY(sq_create(it.n, stream, &T));
+  sq_status s = sq_apply_gates(T, it.ops, it.nops);
+  if (s == SQ_OK) s = sq_sample(T, it.qubits, it.count, it.seed, it.shot_begin, it.shots, it.meas_base, it.out);
+  sq_destroy(T);
+  return s;
+}
+}  // namespace
+
+sq_status sq_batch_sample(const sq_batch_item *items, uint32_t nitems, const sq_batch_opts *opts, void *hip_stream) {
+  if (nitems == 0) return SQ_OK;
+  if (!items) return fail(SQ_EINVAL, "items is NULL");
+  hipStream_t stream = (hipStream_t)hip_stream;
+  u32 block = opts && opts->block ? opts->block : 256;
+  u32 max_n = opts && opts->max_batch_n ? opts->max_batch_n : 4096;
+  if (block % 64 || block < 64 || block > 512) return fail(SQ_EINVAL, "batch block must be a multiple of 64 in [64, 512]");
+  max_n = std::min(max_n, kBatchMaxN);
+  for (u32 k = 0; k < nitems; ++k) {
+    const sq_batch_item &it = items[k];
+    if (it.n == 0 || it.n > SQ_MAX_QUBITS) return fail(SQ_ERANGE, "item %u: bad n=%u", k, it.n);
+    SQ_TRY(validate_ops(it.n, it.ops, it.nops, false));
+    if (it.count && (!it.qubits || !it.out)) return fail(SQ_EINVAL, "item %u: NULL qubits/out", k);
+    for (u32 i = 0; i < it.count; ++i)
+      if (it.qubits[i] >= it.n) return fail(SQ_ERANGE, "item %u: qubit %u >= n=%u", k, it.qubits[i], it.n);
+  }
+  // split: batched (small) and single-tableau (large) items
+  std::vector<u32> small, large;
+  for (u32 k = 0; k < nitems; ++k) {
+    const sq_batch_item &it = items[k];
+    if (it.count == 0 || it.shots == 0) continue;
+    const u32 L = 2 * cdiv(it.n, 64);
+    if (it.n <= max_n && it.count <= kBatchMaxCount && L <= 2 * block) small.push_back(k);
+    else large.push_back(k);
+  }
+  // largest first: cost ~ n^2 * count (rowsum sweep) + gates
+  auto cost = [&](u32 k) {
+    const sq_batch_item &it = items[k];
+    return (double)it.n * it.n * it.count + (double)it.nops * it.n;
+  };
+  std::sort(small.begin(), small.end(), [&](u32 a, u32 b) { return cost(a) > cost(b); });
+  if (!small.empty()) {
+    // host-side compile and layout
+    std::vector<Group> groups;
+    std::vector<u32> pass_off, qubits;
+    struct Off {
+      size_t pass_off, groups, qubits, ws;
+    };
+    std::vector<Off> offs(small.size());
+    size_t ws_bytes = 0;
+    auto take = [&](size_t bytes) {
+      size_t r = ws_bytes;
+      ws_bytes += (bytes + 255) / 256 * 256;
+      return r;
+    };
+    std::vector<BatchItem> bi(small.size());
+    std::vector<size_t> o_x(small.size()), o_z(small.size()), o_sg(small.size()), o_fm(small.size()),
+        o_cb(small.size()), o_out(small.size()), o_fc(small.size()), o_kind(small.size());
+    PassBuilder pb;
+    for (size_t s = 0; s < small.size(); ++s) {
+      const sq_batch_item &it = items[small[s]];
+      const Dims d = dims_of(it.n);
+      pb.init(it.n, d.L);
+      for (u64 i = 0; i < it.nops; ++i) pb.add(it.ops[i].type, it.ops[i].q0, it.ops[i].q1);
+      pb.flush();
+      offs[s].pass_off = pass_off.size();
+      offs[s].groups = groups.size();
+      for (const PassRange &r : pb.passes) pass_off.push_back((u32)r.offset);
+      pass_off.push_back((u32)pb.groups.size());
+      groups.insert(groups.end(), pb.groups.begin(), pb.groups.end());
+      offs[s].qubits = qubits.size();
+      qubits.insert(qubits.end(), it.qubits, it.qubits + it.count);
+      const u32 Ks = round_up(d.K, 16), CW = cdiv(it.count, 64);
+      BatchItem &b = bi[s];
+      b.n = it.n;
+      b.Ls = d.Ls;
+      b.Ks = Ks;
+      b.CW = CW;
+      b.count = it.count;
+      b.shots = it.shots;
+      b.npasses = (u32)pb.passes.size();
+      b.pad = 0;
+      b.seed = it.seed;
+      b.shot_begin = it.shot_begin;
+      b.meas_base = it.meas_base;
+      o_x[s] = take((size_t)it.n * d.Ls * 8);
+      o_z[s] = take((size_t)it.n * d.Ls * 8);
+      o_sg[s] = take((size_t)(it.count + 1) * Ks * 8);
+      o_fm[s] = take((size_t)it.count * CW * 8);
+      o_cb[s] = take((size_t)it.shots * CW * 8);
+      o_out[s] = take((size_t)it.shots * CW * 8);
+      o_fc[s] = take(it.count);
+      o_kind[s] = take(it.count);
+    }
+    const size_t o_groups = take(groups.size() * sizeof(Group) + 16);
+    const size_t o_poff = take(pass_off.size() * 4);
+    const size_t o_q = take(qubits.size() * 4);
+    const size_t o_items = take(bi.size() * sizeof(BatchItem));
+    const size_t o_flags = take(bi.size() * 4);
+    const size_t o_next = take(4);
+    uint8_t *ws = nullptr;
+    if (hipMalloc((void **)&ws, ws_bytes) != hipSuccess) {
+      (void)hipGetLastError();
+      return fail(SQ_ENOMEM, "device allocation of %zu bytes for the batch failed", ws_bytes);
+    }
+    for (size_t s = 0; s < small.size(); ++s) {
+      BatchItem &b = bi[s];
+      b.X = (u64 *)(ws + o_x[s]);
+      b.Z = (u64 *)(ws + o_z[s]);
+      b.sg = (u64 *)(ws + o_sg[s]);
+      b.fm = (u64 *)(ws + o_fm[s]);
+      b.coinbuf = (u64 *)(ws + o_cb[s]);
+      b.out = (u64 *)(ws + o_out[s]);
+      b.fc = ws + o_fc[s];
+      b.kind = ws + o_kind[s];
+      b.groups = (const Group *)(ws + o_groups) + offs[s].groups;
+      b.pass_off = (const u32 *)(ws + o_poff) + offs[s].pass_off;
+      b.qubits = (const u32 *)(ws + o_q) + offs[s].qubits;
+      b.flags = (u32 *)(ws + o_flags) + s;
+    }
+    // pass offsets are relative to each item's own groups
+    std::vector<u32> flags(small.size(), 0);
+    int ncu = 256;
+    {
+      int dev = 0;
+      if (hipGetDevice(&dev) == hipSuccess) {
+        hipDeviceProp_t prop;
+        if (hipGetDeviceProperties(&prop, dev) == hipSuccess) ncu = prop.multiProcessorCount;
+      }
+    }
+    u32 grid = opts && opts->grid ? opts->grid : (u32)ncu * std::max<u32>(1, 1024 / block);
+    grid = std::min<u32>(grid, (u32)small.size());
+    sq_status st = SQ_OK;
+    auto run = [&]() -> sq_status {
+      HIP_TRY(hipMemcpyAsync(ws + o_groups, groups.data(), groups.size() * sizeof(Group), hipMemcpyHostToDevice,
+                             stream));
+      HIP_TRY(hipMemcpyAsync(ws + o_poff, pass_off.data(), pass_off.size() * 4, hipMemcpyHostToDevice, stream));
+      HIP_TRY(hipMemcpyAsync(ws + o_q, qubits.data(), qubits.size() * 4, hipMemcpyHostToDevice, stream));
+      HIP_TRY(hipMemcpyAsync(ws + o_items, bi.data(), bi.size() * sizeof(BatchItem), hipMemcpyHostToDevice, stream));
+      HIP_TRY(launch_fill_zero((u64 *)(ws + o_flags), (bi.size() * 4 + 4 + 7) / 8, stream));
+      HIP_TRY(launch_fill_zero((u64 *)(ws + o_next), 1, stream));
+      HIP_TRY(launch_batch((const BatchItem *)(ws + o_items), (u32)bi.size(), (u32 *)(ws + o_next), block, grid,
+                           stream));
+      for (size_t s = 0; s < small.size(); ++s) {
+        const sq_batch_item &it = items[small[s]];
+        HIP_TRY(hipMemcpyAsync(it.out, ws + o_out[s], (size_t)it.shots * bi[s].CW * 8, hipMemcpyDeviceToHost, stream));
+      }
+      HIP_TRY(hipMemcpyAsync(flags.data(), ws + o_flags, flags.size() * 4, hipMemcpyDeviceToHost, stream));
+      HIP_TRY(hipStreamSynchronize(stream));
+      return SQ_OK;
+    };
+    st = run();
+    if (st != SQ_OK) (void)hipStreamSynchronize(stream);
+    (void)hipFree(ws);
+    if (st != SQ_OK) return st;
+    for (size_t s = 0; s < small.size(); ++s)
+      if (flags[s]) return fail(SQ_ESTATE, "item %u: device consistency check failed (flags 0x%x)", small[s], flags[s]);
+  }
+  for (u32 k : large) SQ_TRY(batch_item_plain(items[k], stream));
+  return SQ_OK;
+}
+
 sq_status sq_program_create(uint32_t n, const sq_op *ops, uint64_t count, sq_program **out) {
   if (!out) return fail(SQ_EINVAL, "out is NULL");
   *out = nullptr;
