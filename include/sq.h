@@ -142,8 +142,9 @@ sq_status sq_sample(sq_tableau *t, const uint32_t *host_qubits, uint32_t count, 
  * qubits, fewer than 32768 measurements) run in one persistent launch in
  * which a workgroup takes one circuit at a time, largest first, and runs its
  * gates, measurement sweep and shots without further launches; larger
- * circuits run through the single-tableau kernels. Blocks until every output
- * is written. opts may be NULL (automatic choices).
+ * circuits run through the single-tableau kernels, several at once on worker
+ * threads with streams of their own, concurrently with that launch. Blocks
+ * until every output is written. opts may be NULL (automatic choices).
  * Errors: SQ_EINVAL, SQ_ERANGE, SQ_ENOMEM, SQ_EDEVICE, SQ_ESTATE (a device
  * consistency check of some item failed). */
 typedef struct {
@@ -163,6 +164,7 @@ typedef struct {
   uint32_t block;        /* threads per workgroup of the batched kernel (multiple of 64, <= 512; 0 = automatic) */
   uint32_t grid;         /* workgroups of the persistent launch (0 = automatic) */
   uint32_t max_batch_n;  /* larger circuits take the single-tableau path (0 = automatic) */
+  uint32_t streams;      /* concurrent streams (host worker threads) for those (0 = automatic) */
 } sq_batch_opts;
 
 sq_status sq_batch_sample(const sq_batch_item *items, uint32_t nitems, const sq_batch_opts *opts, void *hip_stream);

@@ -52,7 +52,8 @@ class BatchItem(ctypes.Structure):
 
 
 class BatchOpts(ctypes.Structure):
-    _fields_ = [("block", ctypes.c_uint32), ("grid", ctypes.c_uint32), ("max_batch_n", ctypes.c_uint32)]
+    _fields_ = [("block", ctypes.c_uint32), ("grid", ctypes.c_uint32), ("max_batch_n", ctypes.c_uint32),
+                ("streams", ctypes.c_uint32)]
 
 
 class MeasStats(ctypes.Structure):
@@ -312,7 +313,7 @@ class Tableau:
         return float(ms.value), int(n.value)
 
 
-def batch_sample(requests, block: int = 0, grid: int = 0, max_batch_n: int = 0, stream=None):
+def batch_sample(requests, block: int = 0, grid: int = 0, max_batch_n: int = 0, streams: int = 0, stream=None):
     """Run many independent circuits in one batched launch (sq_batch_sample).
 
     Each request is a dict with n, ops (gates), qubits, shots and optional
@@ -339,7 +340,7 @@ def batch_sample(requests, block: int = 0, grid: int = 0, max_batch_n: int = 0, 
         it.shot_begin = int(r.get("shot_begin", 0))
         it.meas_base = int(r.get("meas_base", 0))
         it.out = out.ctypes.data
-    opts = BatchOpts(block, grid, max_batch_n)
+    opts = BatchOpts(block, grid, max_batch_n, streams)
     _check(lib.sq_batch_sample(arr, len(requests), ctypes.byref(opts), _stream_ptr(stream)))
     res = []
     for r, out in zip(requests, outs):

@@ -16,30 +16,29 @@
 namespace sq {
 
 constexpr u32 BW = 2;  // row words per thread in the batched kernel (L <= BW * blockDim)
+constexpr u32 GB = 4;  // gate groups loaded together per thread
 
 __device__ __forceinline__ void bapply(u64 ops, u64 &xa, u64 &za, u64 &xb, u64 &zb, u64 &s) {
-  u64 a1[1] = {xa}, a2[1] = {za}, b1[1] = {xb}, b2[1] = {zb}, ss[1] = {s};
   for (; ops != 0; ops >>= 4) {
     switch ((u32)(ops & 15ULL)) {
-      case UOP_H_A: { ss[0] ^= a1[0] & a2[0]; const u64 t = a1[0]; a1[0] = a2[0]; a2[0] = t; } break;
-      case UOP_S_A: ss[0] ^= a1[0] & a2[0]; a2[0] ^= a1[0]; break;
-      case UOP_SDG_A: ss[0] ^= a1[0] & ~a2[0]; a2[0] ^= a1[0]; break;
-      case UOP_X_A: ss[0] ^= a2[0]; break;
-      case UOP_Y_A: ss[0] ^= a1[0] ^ a2[0]; break;
-      case UOP_Z_A: ss[0] ^= a1[0]; break;
-      case UOP_H_B: { ss[0] ^= b1[0] & b2[0]; const u64 t = b1[0]; b1[0] = b2[0]; b2[0] = t; } break;
-      case UOP_S_B: ss[0] ^= b1[0] & b2[0]; b2[0] ^= b1[0]; break;
-      case UOP_SDG_B: ss[0] ^= b1[0] & ~b2[0]; b2[0] ^= b1[0]; break;
-      case UOP_X_B: ss[0] ^= b2[0]; break;
-      case UOP_Y_B: ss[0] ^= b1[0] ^ b2[0]; break;
-      case UOP_Z_B: ss[0] ^= b1[0]; break;
-      case UOP_CX_AB: ss[0] ^= a1[0] & b2[0] & ~(b1[0] ^ a2[0]); b1[0] ^= a1[0]; a2[0] ^= b2[0]; break;
-      case UOP_CX_BA: ss[0] ^= b1[0] & a2[0] & ~(a1[0] ^ b2[0]); a1[0] ^= b1[0]; b2[0] ^= a2[0]; break;
-      case UOP_CZ: { ss[0] ^= a1[0] & b1[0] & (a2[0] ^ b2[0]); const u64 ta = a2[0] ^ b1[0]; b2[0] ^= a1[0]; a2[0] = ta; } break;
+      case UOP_H_A: { s ^= xa & za; const u64 t = xa; xa = za; za = t; } break;
+      case UOP_S_A: s ^= xa & za; za ^= xa; break;
+      case UOP_SDG_A: s ^= xa & ~za; za ^= xa; break;
+      case UOP_X_A: s ^= za; break;
+      case UOP_Y_A: s ^= xa ^ za; break;
+      case UOP_Z_A: s ^= xa; break;
+      case UOP_H_B: { s ^= xb & zb; const u64 t = xb; xb = zb; zb = t; } break;
+      case UOP_S_B: s ^= xb & zb; zb ^= xb; break;
+      case UOP_SDG_B: s ^= xb & ~zb; zb ^= xb; break;
+      case UOP_X_B: s ^= zb; break;
+      case UOP_Y_B: s ^= xb ^ zb; break;
+      case UOP_Z_B: s ^= xb; break;
+      case UOP_CX_AB: s ^= xa & zb & ~(xb ^ za); xb ^= xa; za ^= zb; break;
+      case UOP_CX_BA: s ^= xb & za & ~(xa ^ zb); xa ^= xb; zb ^= za; break;
+      case UOP_CZ: { s ^= xa & xb & (za ^ zb); const u64 ta = za ^ xb; zb ^= xa; za = ta; } break;
       default: break;
     }
   }
-  xa = a1[0]; za = a2[0]; xb = b1[0]; zb = b2[0]; s = ss[0];
 }
 
 // Limits of the batched path: L = 2 ceil(n/64) <= BATCH_MAX_WORDS (n <= 16384),
@@ -92,22 +91,44 @@ __global__ __launch_bounds__(512) void k_batch(const BatchItem *__restrict__ ite
     for (u32 p = 0; p < d.npasses; ++p) {
       const u32 g0 = d.pass_off[p], g1 = d.pass_off[p + 1];
       if (active) {
-        for (u32 g = g0 + sl; g < g1; g += S) {
-          const Group G = d.groups[g];
-          const size_t ca = (size_t)(G.q0 & GQ_MASK) * Ls;
-          const bool two = G.q1 != G_SINGLE;
-          const size_t cb = two ? (size_t)G.q1 * Ls : 0;
+        // GB groups of this slice at a time: all loads first, then apply and store
+        // (groups of one pass touch disjoint columns)
+        for (u32 gs = g0 + sl; gs < g1; gs += S * GB) {
+          Group G[GB];
+          u32 nb = 0;
+#pragma unroll
+          for (u32 b = 0; b < GB; ++b)
+            if (gs + b * S < g1) { G[b] = d.groups[gs + b * S]; nb = b + 1; }
           for (u32 k = 0; k < nw; ++k) {
             const u32 w = w0 + k * Lw;
             if (w >= L) break;
-            u64 xa = X[ca + w], za = Z[ca + w], xb = 0, zb = 0;
-            if (two) { xb = X[cb + w]; zb = Z[cb + w]; }
-            bapply(G.ops, xa, za, xb, zb, sgn[k]);
-            if (G.q0 & GD_XA) X[ca + w] = xa;
-            if (G.q0 & GD_ZA) Z[ca + w] = za;
-            if (two) {
-              if (G.q0 & GD_XB) X[cb + w] = xb;
-              if (G.q0 & GD_ZB) Z[cb + w] = zb;
+            u64 xa[GB], za[GB], xb[GB], zb[GB];
+#pragma unroll
+            for (u32 b = 0; b < GB; ++b) {
+              xa[b] = za[b] = xb[b] = zb[b] = 0;
+              if (b < nb) {
+                const size_t ca = (size_t)(G[b].q0 & GQ_MASK) * Ls + w;
+                xa[b] = X[ca];
+                za[b] = Z[ca];
+                if (G[b].q1 != G_SINGLE) {
+                  const size_t cb = (size_t)G[b].q1 * Ls + w;
+                  xb[b] = X[cb];
+                  zb[b] = Z[cb];
+                }
+              }
+            }
+#pragma unroll
+            for (u32 b = 0; b < GB; ++b) {
+              if (b >= nb) break;
+              bapply(G[b].ops, xa[b], za[b], xb[b], zb[b], sgn[k]);
+              const size_t ca = (size_t)(G[b].q0 & GQ_MASK) * Ls + w;
+              if (G[b].q0 & GD_XA) X[ca] = xa[b];
+              if (G[b].q0 & GD_ZA) Z[ca] = za[b];
+              if (G[b].q1 != G_SINGLE) {
+                const size_t cb = (size_t)G[b].q1 * Ls + w;
+                if (G[b].q0 & GD_XB) X[cb] = xb[b];
+                if (G[b].q0 & GD_ZB) Z[cb] = zb[b];
+              }
             }
           }
         }

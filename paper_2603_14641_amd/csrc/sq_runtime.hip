@@ -1,11 +1,13 @@
 // Host runtime behind the C ABI declared in include/sq.h: tableau handles,
 // the gate-pass compiler, launch geometry, profiling and error handling.
 #include <algorithm>
+#include <atomic>
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
 #include <new>
 #include <string>
+#include <thread>
 #include <utility>
 #include <vector>
 
@@ -463,7 +465,9 @@ sq_status sq_create(uint32_t n, void *hip_stream, sq_tableau **out) {
   T->d = dims_of(n);
   size_t off[12];
   const size_t words = layout_words(T->d, off);
-  if (hipMalloc((void **)&T->base, words * 8) != hipSuccess) {
+  // stream-ordered allocation: no device-wide synchronization, so handles can
+  // be created and destroyed while other streams keep working
+  if (hipMallocAsync((void **)&T->base, words * 8, T->stream) != hipSuccess) {
     (void)hipGetLastError();
     delete T;
     return fail(SQ_ENOMEM, "device allocation of %zu bytes failed", words * 8);
@@ -484,7 +488,8 @@ sq_status sq_create(uint32_t n, void *hip_stream, sq_tableau **out) {
   sq_status s = reset_device(T);
   if (s == SQ_OK && hipStreamSynchronize(T->stream) != hipSuccess) s = fail(SQ_EDEVICE, "initialisation failed");
   if (s != SQ_OK) {
-    (void)hipFree(T->base);
+    (void)hipFreeAsync(T->base, T->stream);
+    (void)hipStreamSynchronize(T->stream);
     delete T;
     return s;
   }
@@ -501,9 +506,10 @@ sq_status sq_destroy(sq_tableau *T) {
       (void)hipEventDestroy(pr.second);
     }
   for (hipEvent_t e : T->pool) (void)hipEventDestroy(e);
-  (void)hipFree(T->dev_out);
-  (void)hipFree(T->dev_groups);
-  (void)hipFree(T->base);
+  if (T->dev_out) (void)hipFreeAsync(T->dev_out, T->stream);
+  if (T->dev_groups) (void)hipFreeAsync(T->dev_groups, T->stream);
+  (void)hipFreeAsync(T->base, T->stream);
+  (void)hipStreamSynchronize(T->stream);
   delete T;
   return SQ_OK;
 }
@@ -531,12 +537,11 @@ sq_status sq_apply_gates(sq_tableau *T, const sq_op *ops, uint64_t count) {
   pb.flush();
   if (pb.groups.empty()) return SQ_OK;
   if (pb.groups.size() > T->dev_groups_cap) {
-    HIP_TRY(hipStreamSynchronize(T->stream));
-    (void)hipFree(T->dev_groups);
+    if (T->dev_groups) (void)hipFreeAsync(T->dev_groups, T->stream);
     T->dev_groups = nullptr;
     T->dev_groups_cap = 0;
     const size_t cap = std::max<size_t>(pb.groups.size(), 1024);
-    if (hipMalloc((void **)&T->dev_groups, cap * sizeof(Group)) != hipSuccess) {
+    if (hipMallocAsync((void **)&T->dev_groups, cap * sizeof(Group), T->stream) != hipSuccess) {
       (void)hipGetLastError();
       return fail(SQ_ENOMEM, "device allocation of %zu gate groups failed", cap);
     }
@@ -556,11 +561,10 @@ sq_status sq_measure(sq_tableau *T, const uint32_t *qubits, uint32_t count, uint
     if (qubits[i] >= T->d.n) return fail(SQ_ERANGE, "qubit %u >= n=%u", qubits[i], T->d.n);
   const size_t need = 2 * (size_t)count;
   if (need > T->dev_out_cap) {
-    HIP_TRY(hipStreamSynchronize(T->stream));
-    (void)hipFree(T->dev_out);
+    if (T->dev_out) (void)hipFreeAsync(T->dev_out, T->stream);
     T->dev_out = nullptr;
     T->dev_out_cap = 0;
-    if (hipMalloc((void **)&T->dev_out, need) != hipSuccess) {
+    if (hipMallocAsync((void **)&T->dev_out, need, T->stream) != hipSuccess) {
       (void)hipGetLastError();
       return fail(SQ_ENOMEM, "device allocation of %zu bytes failed", need);
     }
@@ -602,7 +606,7 @@ sq_status sq_sample(sq_tableau *T, const uint32_t *qubits, uint32_t count, uint6
   const size_t o_cw = take((size_t)shots * CW * 8), o_out = take((size_t)shots * CW * 8);
   const size_t o_sv = take((size_t)(count + 1) * 4), o_kind = take(count), o_fc = take(count), o_dummy = take(2);
   uint8_t *ws = nullptr;
-  if (hipMalloc((void **)&ws, off) != hipSuccess) {
+  if (hipMallocAsync((void **)&ws, off, T->stream) != hipSuccess) {
     (void)hipGetLastError();
     return fail(SQ_ENOMEM, "device allocation of %zu bytes for sampling failed", off);
   }
@@ -649,8 +653,8 @@ sq_status sq_sample(sq_tableau *T, const uint32_t *qubits, uint32_t count, uint6
     return SQ_OK;
   };
   s = run();
+  (void)hipFreeAsync(ws, T->stream);
   if (s != SQ_OK) (void)hipStreamSynchronize(T->stream);
-  (void)hipFree(ws);
   if (s == SQ_OK && after.flags != before.flags)
     s = fail(SQ_ESTATE, "device consistency check failed (flags 0x%x)", after.flags);
   return s;
@@ -702,6 +706,51 @@ sq_status sq_batch_sample(const sq_batch_item *items, uint32_t nitems, const sq_
     return (double)it.n * it.n * it.count + (double)it.nops * it.n;
   };
   std::sort(small.begin(), small.end(), [&](u32 a, u32 b) { return cost(a) > cost(b); });
+  std::sort(large.begin(), large.end(), [&](u32 a, u32 b) { return cost(a) > cost(b); });
+  // Large items: single-tableau path, several at once on worker threads with
+  // their own (default-priority) streams, overlapping each other's launch
+  // latency and the batched launch below.
+  const u32 nworkers = std::min<u32>((u32)large.size(), opts && opts->streams ? opts->streams : 4);
+  std::vector<sq_status> wstatus(nworkers, SQ_OK);
+  std::vector<std::string> werr(nworkers);
+  std::vector<std::thread> workers;
+  std::atomic<u32> next_large{0};
+  int dev = 0;
+  (void)hipGetDevice(&dev);
+  for (u32 wk = 0; wk < nworkers; ++wk) {
+    workers.emplace_back([&, wk]() {
+      if (hipSetDevice(dev) != hipSuccess) {
+        wstatus[wk] = SQ_EDEVICE;
+        werr[wk] = "hipSetDevice failed in a batch worker";
+        return;
+      }
+      hipStream_t ws = nullptr;
+      if (hipStreamCreate(&ws) != hipSuccess) {
+        wstatus[wk] = SQ_EDEVICE;
+        werr[wk] = "hipStreamCreate failed in a batch worker";
+        return;
+      }
+      for (;;) {
+        const u32 idx = next_large.fetch_add(1);
+        if (idx >= large.size()) break;
+        const sq_status st = batch_item_plain(items[large[idx]], ws);
+        if (st != SQ_OK) {
+          wstatus[wk] = st;
+          werr[wk] = g_err;
+          break;
+        }
+      }
+      (void)hipStreamSynchronize(ws);
+      (void)hipStreamDestroy(ws);
+    });
+  }
+  auto join_workers = [&]() -> sq_status {
+    for (std::thread &th : workers) th.join();
+    workers.clear();
+    for (u32 wk = 0; wk < nworkers; ++wk)
+      if (wstatus[wk] != SQ_OK) return fail(wstatus[wk], "%s", werr[wk].c_str());
+    return SQ_OK;
+  };
   if (!small.empty()) {
     // host-side compile and layout
     std::vector<Group> groups;
@@ -762,7 +811,7 @@ sq_status sq_batch_sample(const sq_batch_item *items, uint32_t nitems, const sq_
     const size_t o_flags = take(bi.size() * 4);
     const size_t o_next = take(4);
     uint8_t *ws = nullptr;
-    if (hipMalloc((void **)&ws, ws_bytes) != hipSuccess) {
+    if (hipMallocAsync((void **)&ws, ws_bytes, stream) != hipSuccess) {
       (void)hipGetLastError();
       return fail(SQ_ENOMEM, "device allocation of %zu bytes for the batch failed", ws_bytes);
     }
@@ -813,13 +862,19 @@ sq_status sq_batch_sample(const sq_batch_item *items, uint32_t nitems, const sq_
       return SQ_OK;
     };
     st = run();
-    if (st != SQ_OK) (void)hipStreamSynchronize(stream);
-    (void)hipFree(ws);
-    if (st != SQ_OK) return st;
+    (void)hipFreeAsync(ws, stream);
+    (void)hipStreamSynchronize(stream);
+    if (st != SQ_OK) {
+      (void)join_workers();
+      return st;
+    }
     for (size_t s = 0; s < small.size(); ++s)
-      if (flags[s]) return fail(SQ_ESTATE, "item %u: device consistency check failed (flags 0x%x)", small[s], flags[s]);
+      if (flags[s]) {
+        (void)join_workers();
+        return fail(SQ_ESTATE, "item %u: device consistency check failed (flags 0x%x)", small[s], flags[s]);
+      }
   }
-  for (u32 k : large) SQ_TRY(batch_item_plain(items[k], stream));
+  SQ_TRY(join_workers());
   return SQ_OK;
 }
 
@@ -920,11 +975,10 @@ sq_status sq_run(sq_tableau *T, const sq_program *P, uint64_t seed, uint64_t sho
   if (!rand_base && !P->meas_qubits.empty()) {
     const size_t need = P->meas_qubits.size();
     if (need > T->dev_out_cap) {
-      HIP_TRY(hipStreamSynchronize(T->stream));
-      (void)hipFree(T->dev_out);
+      if (T->dev_out) (void)hipFreeAsync(T->dev_out, T->stream);
       T->dev_out = nullptr;
       T->dev_out_cap = 0;
-      if (hipMalloc((void **)&T->dev_out, need) != hipSuccess) {
+      if (hipMallocAsync((void **)&T->dev_out, need, T->stream) != hipSuccess) {
         (void)hipGetLastError();
         return fail(SQ_ENOMEM, "device allocation of %zu bytes failed", need);
       }
@@ -954,7 +1008,7 @@ sq_status sq_export_rows(sq_tableau *T, const uint32_t *rows, uint32_t nrows, ui
   const size_t xwords = (size_t)nrows * W;
   void *buf = nullptr;
   const size_t bytes = nrows * 4 + 2 * xwords * 8 + nrows + 256;
-  if (hipMalloc(&buf, bytes) != hipSuccess) {
+  if (hipMallocAsync(&buf, bytes, T->stream) != hipSuccess) {
     (void)hipGetLastError();
     return fail(SQ_ENOMEM, "device allocation of %zu bytes failed", bytes);
   }
@@ -970,7 +1024,8 @@ sq_status sq_export_rows(sq_tableau *T, const uint32_t *rows, uint32_t nrows, ui
       hipMemcpyAsync(hr, dr, nrows, hipMemcpyDeviceToHost, T->stream) != hipSuccess ||
       hipStreamSynchronize(T->stream) != hipSuccess)
     s = fail(SQ_EDEVICE, "export failed: %s", hipGetErrorString(hipGetLastError()));
-  (void)hipFree(buf);
+  (void)hipFreeAsync(buf, T->stream);
+  (void)hipStreamSynchronize(T->stream);
   return s;
 }
 
@@ -994,7 +1049,7 @@ sq_status sq_import(sq_tableau *T, const uint64_t *hx, const uint64_t *hz, const
   }
   void *buf = nullptr;
   const size_t bytes = 2 * xwords * 8 + rows + 256;
-  if (hipMalloc(&buf, bytes) != hipSuccess) {
+  if (hipMallocAsync(&buf, bytes, T->stream) != hipSuccess) {
     (void)hipGetLastError();
     return fail(SQ_ENOMEM, "device allocation of %zu bytes failed", bytes);
   }
@@ -1007,7 +1062,8 @@ sq_status sq_import(sq_tableau *T, const uint64_t *hx, const uint64_t *hz, const
       hipMemcpyAsync(dr, hr, rows, hipMemcpyHostToDevice, T->stream) != hipSuccess ||
       launch_import(T->t, dx, dz, dr, W, T->stream) != hipSuccess || hipStreamSynchronize(T->stream) != hipSuccess)
     s = fail(SQ_EDEVICE, "import failed: %s", hipGetErrorString(hipGetLastError()));
-  (void)hipFree(buf);
+  (void)hipFreeAsync(buf, T->stream);
+  (void)hipStreamSynchronize(T->stream);
   return s;
 }
 
