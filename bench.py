@@ -78,6 +78,93 @@ def cpu_baseline(cfg, layer_parts, seconds: float, nrows: int = 64):
     }
 
 
+def served_mix(nreq: int, budget_bytes: int):
+    """The batched/served workload on its first `nreq` requests: the plain
+    per-circuit path (one tableau at a time: create, gates, sq_sample), one
+    batched call over all of them, and the serving loop with Poisson arrivals
+    at 0.8 x the plain path's request rate. Returns shots/s of each and the
+    served p50/p99 latency."""
+    import paper_2603_14641_amd as sq
+    from paper_2603_14641_amd import serving
+    from workload import circuit_ops, served_requests
+
+    base = served_requests()[:nreq]
+    reqs = []
+    for r in base:
+        cfg = r.config()
+        ops = circuit_ops(cfg, final_measure=False)
+        ops = np.stack([ops["type"], ops["q0"], ops["q1"]], 1).astype(np.uint32)
+        reqs.append(dict(n=cfg.n, ops=ops, qubits=np.arange(cfg.n, dtype=np.uint32), shots=r.shots,
+                         seed=r.coin_seed))
+    shots = sum(r["shots"] for r in reqs)
+    log(f"served mix: {nreq} requests, {shots} shots; plain path")
+    t0 = time.perf_counter()
+    plain_out = []
+    for r in reqs:
+        t = sq.Tableau(r["n"])
+        t.apply_gates(r["ops"])
+        plain_out.append(t.sample(r["qubits"], r["shots"], seed=r["seed"]))
+        t.close()
+    plain_s = time.perf_counter() - t0
+    log(f"plain {plain_s:.2f} s; batched")
+    t0 = time.perf_counter()
+    batch_out = sq.batch_sample(reqs)
+    batch_s = time.perf_counter() - t0
+    same = all(np.array_equal(a, b) for a, b in zip(plain_out, batch_out))
+    rate = 0.8 * nreq / plain_s
+    rng = np.random.Generator(np.random.PCG64(4))
+    arrivals = np.cumsum(rng.exponential(1.0 / rate, nreq))
+    sreqs = [serving.Request(rid=k, n=r["n"], ops=r["ops"], qubits=r["qubits"], shots=r["shots"], seed=r["seed"],
+                             arrival=float(a)) for k, (r, a) in enumerate(zip(reqs, arrivals))]
+    log(f"batched {batch_s:.2f} s; serving at {rate:.2f} requests/s")
+    st = serving.Server(budget_bytes=budget_bytes, workers=2).run(sreqs)
+    same = same and all(np.array_equal(r.result, b) for r, b in zip(sreqs, batch_out))
+    log(f"served makespan {st.makespan_s:.2f} s, p50 {st.latency_p50_s:.3f} s, p99 {st.latency_p99_s:.3f} s")
+    return {
+        "workload": f"first {nreq} of the 512 batched/served requests (n log-uniform 16..16384, depth 10..500, "
+                    f"1..4096 shots, final all-qubit Z measurement)",
+        "requests": nreq, "shots": shots,
+        "plain_shots_per_s": shots / plain_s,
+        "batched_shots_per_s": shots / batch_s,
+        "served_shots_per_s": st.shots_per_s,
+        "batched_vs_plain": plain_s / batch_s,
+        "served_arrival_rate_per_s": rate,
+        "served_latency_p50_s": st.latency_p50_s,
+        "served_latency_p99_s": st.latency_p99_s,
+        "served_batches": st.batches,
+        "served_mean_batch": st.mean_batch,
+        "served_budget_bytes": budget_bytes,
+        "outputs_identical_across_paths": bool(same),
+    }
+
+
+def stream_ceiling():
+    """Measured HBM ceiling of plain torch kernels on 4 GiB buffers (GB/s)."""
+    import torch
+    n = 1 << 29
+    a = torch.ones(n, dtype=torch.int64, device="cuda")
+    b = torch.empty_like(a)
+
+    def tm(fn, reps=5):
+        fn()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / reps
+
+    nb = 8 * n
+    res = {"copy_read_write": 2 * nb / tm(lambda: b.copy_(a)) / 1e6,
+           "read_only": nb / tm(lambda: a.sum()) / 1e6,
+           "write_only": nb / tm(lambda: b.fill_(7)) / 1e6}
+    del a, b
+    torch.cuda.empty_cache()
+    return {k: round(v, 1) for k, v in res.items()}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -87,6 +174,8 @@ def main():
     ap.add_argument("--meas", type=int, default=500)
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--served-requests", type=int, default=48,
+                    help="requests of the batched/served mix to time (0 skips that part)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="first run a plain 1 GiB device copy (scale reference for HBM byte counters)")
     args = ap.parse_args()
@@ -162,6 +251,7 @@ def main():
     assert t.error_flags() == 0
 
     kern = {name: t.profile_read(i) for i, name in enumerate(sqb.KERNEL_NAMES)}
+    assert kern["layer"][1] > 0
     layer_ms, layer_n = kern["layer"]
     rowsum_ms, rowsum_n = kern["rowsum"]
     layer_bytes = pg.gate_bytes / max(pg.num_passes, 1)
@@ -207,12 +297,15 @@ def main():
         "kernel_ms": {k: round(v[0], 3) for k, v in kern.items()},
         "kernel_launches": {k: v[1] for k, v in kern.items()},
     }
+    t.close()
+    result["hbm_stream_ceiling_gbs"] = stream_ceiling()
+    if args.served_requests > 0:
+        result["batched_served"] = served_mix(args.served_requests, budget_bytes=8 << 30)
     if not args.no_cpu_baseline:
         log(f"CPU oracle baseline (~{args.cpu_seconds:.0f} s)")
         result["cpu_baseline"] = cpu_baseline(cfg, layer_parts, args.cpu_seconds)
     else:
         result["cpu_baseline"] = None
-    t.close()
     print(json.dumps(result), flush=True)
 
 

@@ -244,8 +244,7 @@ typedef struct {
   uint32_t rowsum_block;       /* threads per workgroup of the rowsum kernel */
   uint32_t rowsum_wpt;         /* words per thread in the rowsum kernel */
   uint32_t rowsum_cols;        /* pivot-row columns per workgroup (per chunk) */
-  uint32_t det_block;          /* threads per workgroup of the deterministic-phase kernel */
-  uint32_t det_cols;           /* columns per workgroup of the deterministic-phase kernel */
+  uint32_t det_cols;           /* columns per workgroup of the deterministic-product phase */
 } sq_tuning;
 sq_status sq_get_tuning(const sq_tableau *t, sq_tuning *out);
 sq_status sq_set_tuning(sq_tableau *t, const sq_tuning *in);
@@ -253,8 +252,13 @@ sq_status sq_set_tuning(sq_tableau *t, const sq_tuning *in);
 /* Per-kernel timing with HIP events recorded on the handle's stream around
  * every launch while enabled. Kernel ids: */
 enum {
-  SQ_K_LAYER = 0, SQ_K_SIGNS = 1, SQ_K_PIVOT = 2, SQ_K_GATHER = 3, SQ_K_ROWSUM = 4,
-  SQ_K_FINAL = 5, SQ_K_DET = 6, SQ_K_DETFINAL = 7, SQ_K_COUNT = 8
+  SQ_K_LAYER = 0,   /* gate pass */
+  SQ_K_SIGNS = 1,   /* sign reduction after a gate pass */
+  SQ_K_PIVOT = 2,   /* pivot search (one per measurement) */
+  SQ_K_GATHER = 3,  /* pivot-row gather */
+  SQ_K_ROWSUM = 4,  /* rowsum pass */
+  SQ_K_POST = 5,    /* random-case finalisation or deterministic product */
+  SQ_K_COUNT = 6
 };
 sq_status sq_profile_enable(sq_tableau *t, int on);
 /* Sum of kernel durations (ms) and launch count for one kernel id since the

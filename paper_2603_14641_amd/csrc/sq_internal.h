@@ -56,7 +56,21 @@ struct MeasState {
   u32 mwords;     // nonzero words of the rowsum mask (row words the pass touches)
   u32 awords;     // nonzero destabilizer-half words of column q (deterministic case)
   u32 nx, nz;     // pivot-row columns with x_pj = 1, with z_pj = 1
-  u32 nsv;        // sampling: sign columns in which S_p has a 1 (compacted list length)
+  u32 nsv;        // sampling: coin columns in which S_p has a 1 (compacted list length)
+  u32 det_done;   // deterministic case: blocks of k_post that have added their phase sums
+};
+
+// Symbolic-sign context of the sampler's sweep (sq_sample.hip); unused (zero)
+// on the plain path. Sign column v < count holds the coefficient of coin v,
+// column count the constant term, one bit per stabilizer row (K words, stride
+// Ks); i is the index of the current measurement in the list.
+struct SymCtx {
+  u64 *sg;
+  u32 *svlist;     // coin columns in which S_p has a 1
+  uint8_t *kind;   // per measurement: 1 random, 0 deterministic
+  u64 *fm;         // per deterministic measurement: coin coefficients (CW words)
+  uint8_t *fc;     // ... and the constant term
+  u32 Ks, CW, count, i;
 };
 
 // Running totals over all measurements of a tableau, for byte accounting.
@@ -91,7 +105,8 @@ struct TabDev {
 
 struct LaunchTimer;  // host-side profiling hook (sq_runtime.hip)
 
-// Kernel launchers (sq_gates.hip, sq_measure.hip, sq_io.hip). All enqueue on `s` and return the
+// Kernel launchers (sq_gates.hip, sq_measure.hip, sq_sample.hip, sq_batch.hip,
+// sq_io.hip). All enqueue on `s` and return the
 // launch status.
 hipError_t launch_fill_zero(u64 *p, size_t words, hipStream_t s);
 hipError_t launch_init_diag(const TabDev &t, hipStream_t s);
@@ -100,28 +115,15 @@ hipError_t launch_layer(const TabDev &t, const Group *groups, u32 ngroups, u32 b
 hipError_t launch_sign_reduce(const TabDev &t, const u64 *sign_part, u32 nchunks, hipStream_t s);
 hipError_t launch_pivot(const TabDev &t, u32 q, MeasState *st, u64 *mask, u64 seed, u64 shot, u64 m,
                         uint8_t *out_bits, uint8_t *out_rand, hipStream_t s);
-hipError_t launch_gather(const TabDev &t, MeasState *st, u64 *pivx, u64 *pivz, u32 *cols, hipStream_t s);
+hipError_t launch_gather(const TabDev &t, MeasState *st, u64 *pivx, u64 *pivz, u32 *cols, const SymCtx *sym,
+                         hipStream_t s);
 hipError_t launch_rowsum(const TabDev &t, const u64 *mask, const u32 *cols, const MeasState *st, u64 *cnt0,
-                         u64 *cnt1, u32 block, u32 wpt, u32 cpc, u32 max_chunks, hipStream_t s);
-hipError_t launch_finalize(const TabDev &t, u32 q, const u64 *mask, const u64 *pivx, const u64 *pivz,
-                           const u64 *cnt0, const u64 *cnt1, MeasState *st, MeasStats *stats, u32 cpc,
-                           hipStream_t s);
-hipError_t launch_detphase(const TabDev &t, u32 q, const u64 *mask, MeasState *st, u32 block, u32 cols_per_wg,
-                           hipStream_t s);
-hipError_t launch_detfinal(const TabDev &t, const u64 *mask, MeasState *st, MeasStats *stats, uint8_t *out_bits,
-                           hipStream_t s);
-// Shot sampling (sq_sample.hip): sign columns sg[v * Ks + w], v < count for
-// coins, v = count for the constant term.
+                         u64 *cnt1, u32 block, u32 wpt, u32 cpc, u32 max_chunks, const SymCtx *sym, hipStream_t s);
+hipError_t launch_post(const TabDev &t, u32 q, const u64 *mask, const u64 *pivx, const u64 *pivz, const u64 *cnt0,
+                       const u64 *cnt1, MeasState *st, MeasStats *stats, uint8_t *out_bits, u32 cpc, u32 cpw,
+                       const SymCtx *sym, hipStream_t s);
+// Shot sampling (sq_sample.hip).
 hipError_t launch_sample_init(const TabDev &t, u64 *sg, u32 Ks, u32 count, hipStream_t s);
-hipError_t launch_gather_signs(const u64 *sg, MeasState *st, u32 *svlist, u32 Ks, u32 i, u32 count, hipStream_t s);
-hipError_t launch_signcols(const TabDev &t, u64 *sg, const u64 *mask, const MeasState *st, const u32 *svlist, u32 Ks,
-                           u32 max_v, hipStream_t s);
-hipError_t launch_finalize_sym(const TabDev &t, u32 q, u64 *sgc, const u64 *mask, const u64 *pivx, const u64 *pivz,
-                               const u64 *cnt0, const u64 *cnt1, MeasState *st, u32 cpc, hipStream_t s);
-hipError_t launch_spvec(u64 *sg, const MeasState *st, const u32 *svlist, uint8_t *kind, u32 Ks, u32 i, u32 count,
-                        hipStream_t s);
-hipError_t launch_detfinal_sym(const TabDev &t, const u64 *sg, const u64 *mask, MeasState *st, uint8_t *kind,
-                               u64 *fm, uint8_t *fc, u32 Ks, u32 CW, u32 i, u32 count, hipStream_t s);
 hipError_t launch_coins(u64 *cw, u64 seed, u64 shot_begin, u64 meas_base, u32 shots, u32 count, u32 CW,
                         hipStream_t s);
 hipError_t launch_eval(const u64 *cw, const uint8_t *kind, const u64 *fm, const uint8_t *fc, u64 *out, u32 shots,

@@ -1,8 +1,17 @@
-// Z measurement (CHP): pivot search, pivot-row gather, rowsum pass and its
-// finalisation, and the deterministic-outcome product.
+// Z measurement (CHP), four launches per measured qubit:
+//   k_pivot  (a3)  pivot search, rowsum mask snapshot, coin;
+//   k_gather (a4)  pivot row S_p packed and its non-identity columns compacted;
+//   k_rowsum (a5)  every anticommuting row times S_p with the exact phase;
+//   k_post   (a5/a6) random case: signs from the phase counters, D_p <- S_p,
+//            S_p <- +-Z_q; deterministic case: the ordered product of the
+//            stabilizers that A selects, whose sign is the outcome.
+// The same kernels serve the symbolic-sign sweep of the sampler (SYM), in
+// which stabilizer signs are affine forms over the coins (see sq_sample.hip).
 #include "sq_device.h"
 
 namespace sq {
+
+constexpr u32 SIGN_COLS_PER_BLOCK = 32;  // coin columns per sign-XOR block of k_rowsum
 
 // ---------------------------------------------------------------------------
 // a3: pivot search for measuring qubit q. p = the smallest stabilizer index
@@ -59,6 +68,7 @@ __global__ __launch_bounds__(1024) void k_pivot(const u64 *__restrict__ X, u32 L
     st->mwords = s_mw;
     st->awords = s_aw;
     st->det_acc = 0;
+    st->det_done = 0;
     st->coin = c;
     out_rand[0] = (uint8_t)(p >= 0);
     if (p >= 0) out_bits[0] = (uint8_t)c;
@@ -69,13 +79,29 @@ __global__ __launch_bounds__(1024) void k_pivot(const u64 *__restrict__ X, u32 L
 // pack it with wave ballots into pivx/pivz (bit j of word j/64), and compact
 // the columns where S_p is not the identity into `cols`
 // (entry = j | x_pj << 31 | z_pj << 30; order across waves is arbitrary).
+// r_p (st->rp) is S_p's sign, or in the sampler S_p's constant sign term; the
+// sampler's extra blocks compact the coins v < i in whose sign column S_p has
+// a 1 into svlist.
+template <bool SYM>
 __global__ void k_gather(const u64 *__restrict__ X, const u64 *__restrict__ Z, const u64 *__restrict__ R, u32 Ls,
                          u32 K, u32 n, MeasState *__restrict__ st, u64 *__restrict__ pivx, u64 *__restrict__ pivz,
-                         u32 *__restrict__ cols) {
+                         u32 *__restrict__ cols, SymCtx sym) {
   const int32_t p = st->p;
   if (p < 0) return;
-  const u32 j = blockIdx.x * blockDim.x + threadIdx.x;
   const u32 ws = K + ((u32)p >> 6), sh = (u32)p & 63u;
+  const u32 lane = threadIdx.x & 63u;
+  const u32 colblocks = (n + blockDim.x - 1) / blockDim.x;
+  if (SYM && blockIdx.x >= colblocks) {
+    const u32 v = (blockIdx.x - colblocks) * blockDim.x + threadIdx.x;
+    const u32 b = (v < sym.i) ? (u32)(sym.sg[(size_t)v * sym.Ks + ((u32)p >> 6)] >> sh) & 1u : 0u;
+    const u64 bb = __ballot(b);
+    u32 base = 0;
+    if (lane == 0 && bb) base = atomicAdd(&st->nsv, (u32)__popcll(bb));
+    base = (u32)__shfl((int)base, 0);
+    if (b) sym.svlist[base + (u32)__popcll(bb & lanemask_lt())] = v;
+    return;
+  }
+  const u32 j = blockIdx.x * blockDim.x + threadIdx.x;
   u32 xb = 0, zb = 0;
   if (j < n) {
     xb = (u32)(X[(size_t)j * Ls + ws] >> sh) & 1u;
@@ -83,7 +109,6 @@ __global__ void k_gather(const u64 *__restrict__ X, const u64 *__restrict__ Z, c
   }
   const u64 bx = __ballot(xb), bz = __ballot(zb);
   const u64 nz = bx | bz;
-  const u32 lane = threadIdx.x & 63u;
   u32 base = 0;
   if (lane == 0) {
     if (j < n) { pivx[j >> 6] = bx; pivz[j >> 6] = bz; }
@@ -93,7 +118,10 @@ __global__ void k_gather(const u64 *__restrict__ X, const u64 *__restrict__ Z, c
   }
   base = (u32)__shfl((int)base, 0);
   if (xb | zb) cols[base + (u32)__popcll(nz & lanemask_lt())] = j | (xb << 31) | (zb << 30);
-  if (j == 0) st->rp = (u32)(R[ws] >> sh) & 1u;
+  if (j == 0) {
+    const u64 *sw = SYM ? (sym.sg + (size_t)sym.count * sym.Ks + ((u32)p >> 6)) : (R + ws);
+    st->rp = (u32)(*sw >> sh) & 1u;
+  }
 }
 
 // a5: random-case rowsum pass. For every masked row h (x_hq = 1, h not D_p or
@@ -102,12 +130,34 @@ __global__ void k_gather(const u64 *__restrict__ X, const u64 *__restrict__ Z, c
 // g(P1, P_hj) in {-1, 0, +1} is added to a bit-sliced 2-bit counter per row
 // (a0 = bit 0, a1 = bit 1). g is +1 for (X,Y), (Y,Z), (Z,X) and -1 for
 // (X,Z), (Y,X), (Z,Y). Counters of each column chunk go to cnt0/cnt1.
-template <int WPT, int B>
+// Sampling (SYM): rows blockIdx.y >= rchunks of the grid instead XOR the
+// rowsum mask of the stabilizer half into every coin column in which S_p has
+// a 1 (the masked stabilizers take S_p's sign vector; its constant term is
+// folded in by k_post like r_p).
+template <int WPT, int B, bool SYM>
 __global__ __launch_bounds__(1024) void k_rowsum(u64 *__restrict__ X, u64 *__restrict__ Z,
                                                   const u64 *__restrict__ mask, const u32 *__restrict__ cols,
                                                   const MeasState *__restrict__ st, u64 *__restrict__ cnt0,
-                                                  u64 *__restrict__ cnt1, u32 Ls, u32 L, u32 cpc) {
+                                                  u64 *__restrict__ cnt1, u32 Ls, u32 L, u32 cpc, u32 rchunks,
+                                                  SymCtx sym) {
   if (st->p < 0) return;
+  if (SYM && blockIdx.y >= rchunks) {
+    const u32 nsv = st->nsv;
+    const u32 v0 = (blockIdx.y - rchunks) * SIGN_COLS_PER_BLOCK;
+    if (v0 >= nsv) return;
+    const u32 v1 = min(v0 + SIGN_COLS_PER_BLOCK, nsv);
+    const u32 K = L / 2;
+    const u32 wb = (blockIdx.x * blockDim.x + threadIdx.x) * WPT;
+#pragma unroll
+    for (int k = 0; k < WPT; ++k) {
+      const u32 w = wb + k;
+      if (w >= K) break;
+      const u64 m = mask[K + w];
+      if (m == 0) continue;
+      for (u32 v = v0; v < v1; ++v) sym.sg[(size_t)sym.svlist[v] * sym.Ks + w] ^= m;
+    }
+    return;
+  }
   const u32 ncols = st->ncols;
   const u32 c0 = blockIdx.y * cpc;
   if (c0 >= ncols) return;
@@ -195,70 +245,7 @@ __global__ __launch_bounds__(1024) void k_rowsum(u64 *__restrict__ X, u64 *__res
   stw<WPT>(cnt1 + (size_t)blockIdx.y * Ls + w, a1);
 }
 
-// a5 (end): add the chunk counters (mod 4) of every masked row; the total
-// exponent e = 2 r_h + 2 r_p + sum g must be even, and r_h <- e / 2, i.e.
-// r_h ^= r_p ^ bit1(sum g). Then D_p <- old S_p (bits from pivx/pivz, sign
-// r_p) and S_p <- (-1)^coin Z_q. Threads below L handle sign words, threads
-// below n handle the D_p / S_p bits of one column each.
-__global__ void k_finalize(u64 *__restrict__ X, u64 *__restrict__ Z, u64 *__restrict__ R,
-                           const u64 *__restrict__ mask, const u64 *__restrict__ pivx, const u64 *__restrict__ pivz,
-                           const u64 *__restrict__ cnt0, const u64 *__restrict__ cnt1, MeasState *__restrict__ st,
-                           MeasStats *__restrict__ stats, u32 Ls, u32 L, u32 K, u32 n, u32 q, u32 cpc) {
-  const int32_t p = st->p;
-  if (p < 0) return;
-  const u32 tid = blockIdx.x * blockDim.x + threadIdx.x;
-  if (tid == 0) {
-    // Algorithmic bytes of this rowsum: every touched row word reads x and z
-    // of each non-identity pivot column and writes x (if x_pj) and z (if z_pj).
-    stats->n_random += 1;
-    stats->rowsum_bytes += (u64)st->mwords * 8ULL * (2ULL * st->ncols + st->nx + st->nz);
-  }
-  const u32 wd = (u32)p >> 6, ws = K + wd;
-  const u64 bit = 1ULL << ((u32)p & 63u);
-  const u32 rp = st->rp;
-  if (tid < L) {
-    const u32 w = tid;
-    const u64 m = mask[w];
-    if (m != 0 || w == wd || w == ws) {
-      u64 r = R[w];
-      if (m != 0) {
-        const u32 nch = (st->ncols + cpc - 1) / cpc;
-        u64 s0 = 0, s1 = 0;
-        for (u32 c = 0; c < nch; ++c) {
-          const u64 b0 = cnt0[(size_t)c * Ls + w], b1 = cnt1[(size_t)c * Ls + w];
-          const u64 carry = s0 & b0;
-          s0 ^= b0;
-          s1 ^= b1 ^ carry;
-        }
-        if (s0 & m) atomicOr(&st->flags, 1u);
-        r ^= m & (s1 ^ (rp ? ~0ULL : 0ULL));
-      }
-      if (w == wd) r = (r & ~bit) | (rp ? bit : 0ULL);
-      if (w == ws) r = (r & ~bit) | (st->coin ? bit : 0ULL);
-      R[w] = r;
-    }
-  }
-  if (tid < n) {
-    const u32 j = tid;
-    const u64 xb = (pivx[j >> 6] >> (j & 63u)) & 1ULL, zb = (pivz[j >> 6] >> (j & 63u)) & 1ULL;
-    u64 *x = X + (size_t)j * Ls;
-    u64 *z = Z + (size_t)j * Ls;
-    x[wd] = (x[wd] & ~bit) | (xb ? bit : 0ULL);
-    z[wd] = (z[wd] & ~bit) | (zb ? bit : 0ULL);
-    x[ws] &= ~bit;
-    z[ws] = (z[ws] & ~bit) | ((j == q) ? bit : 0ULL);
-  }
-}
-
 // ---------------------------------------------------------------------------
-// a6: deterministic outcome. A = {i : x(D_i)_q = 1} (the destabilizer half of
-// the mask). The product of S_i over i in A, taken in ascending i, is
-// +-Z_q. Per column j, the running product before row i has x/z bits equal
-// to the exclusive prefix XOR over A of the stabilizer bits of column j; so
-// the phase exponent adds g(P_ij, prefix) for each i in A. A workgroup walks
-// each of its columns in rounds of blockDim*WPT words; the prefix across
-// words is a wave ballot scan plus a cross-wave LDS scan plus the carry of
-// earlier rounds. The column's total XOR must be 0 for x and [j == q] for z.
 __device__ __forceinline__ u64 prefix_xor_incl(u64 v) {
   v ^= v << 1;
   v ^= v << 2;
@@ -269,14 +256,98 @@ __device__ __forceinline__ u64 prefix_xor_incl(u64 v) {
   return v;
 }
 
-template <int WPT>
-__global__ __launch_bounds__(1024) void k_detphase(const u64 *__restrict__ X, const u64 *__restrict__ Z,
-                                                    const u64 *__restrict__ mask, MeasState *__restrict__ st, u32 Ls,
-                                                    u32 K, u32 n, u32 q, u32 cpw) {
-  if (st->p >= 0) return;
-  __shared__ u32 s_px[16], s_pz[16];
-  __shared__ int s_acc[16];
+// k_post. Random case (p >= 0), by global thread index t:
+//   * t < L (plain) or t < K (sampler): for a masked row word, add the chunk
+//     counters mod 4; the exponent 2 r_h + 2 r_p + sum g must be even and
+//     r_h <- r_h ^ r_p ^ bit1(sum g). D_p's sign <- r_p, S_p's <- coin (plain);
+//     the sampler updates the constant column and clears S_p's constant bit;
+//   * t < n: column t's bits of D_p <- S_p's, S_p <- Z_q;
+//   * sampler, t < nsv: clear S_p's bit in the listed coin columns; t = 0 sets
+//     coin column i (S_p's sign is now coin i).
+// Deterministic case (p < 0): A = {i : x(D_i)_q = 1} (destabilizer half of
+// the mask). The product of S_i over A in ascending i is +-Z_q. Per column j
+// the running product before row i has x/z bits equal to the exclusive prefix
+// XOR over A of column j's stabilizer bits, so the phase exponent adds
+// g(P_ij, prefix) for each i in A. Block b takes columns [b*cpw, (b+1)*cpw);
+// a column is walked in rounds of 2*blockDim words with a wave ballot scan, a
+// cross-wave LDS scan and the carry of earlier rounds. The column's total XOR
+// must be 0 for x and [j == q] for z. Blocks add their sums to det_acc; the
+// last block to finish (atomic ticket, no waiting) forms the outcome: parity of
+// S_i's signs over A xor bit 1 of the sum (which must be even). The sampler's
+// blocks also compute the coin coefficients of the outcome's affine form
+// (parity of sign column v over A, v < i), and the last block its constant.
+template <bool SYM>
+__global__ __launch_bounds__(256) void k_post(u64 *__restrict__ X, u64 *__restrict__ Z, u64 *__restrict__ R,
+                                              const u64 *__restrict__ mask, const u64 *__restrict__ pivx,
+                                              const u64 *__restrict__ pivz, const u64 *__restrict__ cnt0,
+                                              const u64 *__restrict__ cnt1, MeasState *__restrict__ st,
+                                              MeasStats *__restrict__ stats, uint8_t *__restrict__ out_bits, u32 Ls,
+                                              u32 L, u32 K, u32 n, u32 q, u32 cpc, u32 cpw, SymCtx sym) {
+  const int32_t p = st->p;
   const u32 tid = threadIdx.x, lane = tid & 63u, wave = tid >> 6, nwaves = blockDim.x >> 6;
+  const u32 t = blockIdx.x * blockDim.x + tid;
+  if (p >= 0) {
+    const u32 wd = (u32)p >> 6, ws = K + wd;
+    const u64 bit = 1ULL << ((u32)p & 63u);
+    const u32 rp = st->rp;
+    if (t == 0 && !SYM) {
+      // Algorithmic bytes of this rowsum: every touched row word reads x and z
+      // of each non-identity pivot column and writes x (if x_pj) and z (if z_pj).
+      stats->n_random += 1;
+      stats->rowsum_bytes += (u64)st->mwords * 8ULL * (2ULL * st->ncols + st->nx + st->nz);
+    }
+    const u32 nsign = SYM ? K : L;
+    if (t < nsign) {
+      const u32 w = SYM ? K + t : t;  // row word
+      const u64 m = mask[w];
+      const bool own = SYM ? (w == ws) : (w == wd || w == ws);
+      if (m != 0 || own) {
+        u64 r = SYM ? sym.sg[(size_t)sym.count * sym.Ks + t] : R[w];
+        if (m != 0) {
+          const u32 nch = (st->ncols + cpc - 1) / cpc;
+          u64 s0 = 0, s1 = 0;
+          for (u32 c = 0; c < nch; ++c) {
+            const u64 b0 = cnt0[(size_t)c * Ls + w], b1 = cnt1[(size_t)c * Ls + w];
+            const u64 carry = s0 & b0;
+            s0 ^= b0;
+            s1 ^= b1 ^ carry;
+          }
+          if (s0 & m) atomicOr(&st->flags, 1u);
+          r ^= m & (s1 ^ (rp ? ~0ULL : 0ULL));
+        }
+        if (SYM) {
+          if (w == ws) r &= ~bit;
+          sym.sg[(size_t)sym.count * sym.Ks + t] = r;
+        } else {
+          if (w == wd) r = (r & ~bit) | (rp ? bit : 0ULL);
+          if (w == ws) r = (r & ~bit) | (st->coin ? bit : 0ULL);
+          R[w] = r;
+        }
+      }
+    }
+    if (t < n) {
+      const u32 j = t;
+      const u64 xb = (pivx[j >> 6] >> (j & 63u)) & 1ULL, zb = (pivz[j >> 6] >> (j & 63u)) & 1ULL;
+      u64 *x = X + (size_t)j * Ls;
+      u64 *z = Z + (size_t)j * Ls;
+      x[wd] = (x[wd] & ~bit) | (xb ? bit : 0ULL);
+      z[wd] = (z[wd] & ~bit) | (zb ? bit : 0ULL);
+      x[ws] &= ~bit;
+      z[ws] = (z[ws] & ~bit) | ((j == q) ? bit : 0ULL);
+    }
+    if (SYM) {
+      if (t < st->nsv) sym.sg[(size_t)sym.svlist[t] * sym.Ks + wd] &= ~bit;
+      if (t == 0) {
+        sym.sg[(size_t)sym.i * sym.Ks + wd] |= bit;
+        sym.kind[sym.i] = 1;
+      }
+    }
+    return;
+  }
+
+  // ---- deterministic case
+  __shared__ u32 s_px[4], s_pz[4], s_last;
+  __shared__ int s_acc[4];
   int acc = 0;
   u32 bad = 0;
   const u32 j0 = blockIdx.x * cpw, j1 = min(j0 + cpw, n);
@@ -284,12 +355,12 @@ __global__ __launch_bounds__(1024) void k_detphase(const u64 *__restrict__ X, co
     const u64 *xc = X + (size_t)j * Ls + K;
     const u64 *zc = Z + (size_t)j * Ls + K;
     u32 carry_x = 0, carry_z = 0;
-    for (u32 base = 0; base < K; base += blockDim.x * WPT) {
-      const u32 w0 = base + tid * WPT;
-      u64 sx[WPT], sz[WPT];
+    for (u32 base = 0; base < K; base += blockDim.x * 2) {
+      const u32 w0 = base + tid * 2;
+      u64 sx[2], sz[2];
       u32 tpx = 0, tpz = 0;
 #pragma unroll
-      for (int k = 0; k < WPT; ++k) {
+      for (int k = 0; k < 2; ++k) {
         const u32 w = w0 + k;
         const u64 a = (w < K) ? mask[w] : 0ULL;
         sx[k] = a ? (xc[w] & a) : 0ULL;
@@ -312,7 +383,7 @@ __global__ __launch_bounds__(1024) void k_detphase(const u64 *__restrict__ X, co
       }
       __syncthreads();
 #pragma unroll
-      for (int k = 0; k < WPT; ++k) {
+      for (int k = 0; k < 2; ++k) {
         const u64 ex = (prefix_xor_incl(sx[k]) << 1) ^ (cx ? ~0ULL : 0ULL);
         const u64 ez = (prefix_xor_incl(sz[k]) << 1) ^ (cz ? ~0ULL : 0ULL);
         const u64 x1 = sx[k], z1 = sz[k];
@@ -326,6 +397,17 @@ __global__ __launch_bounds__(1024) void k_detphase(const u64 *__restrict__ X, co
     }
     if (carry_x != 0u || carry_z != (u32)(j == q)) bad = 1;
   }
+  if (SYM) {
+    // coin coefficients of the outcome's affine form: v = t < i
+    const u32 v = t;
+    u32 par = 0;
+    if (v < sym.i) {
+      const u64 *c = sym.sg + (size_t)v * sym.Ks;
+      for (u32 w = 0; w < K; ++w) par ^= (u32)__popcll(c[w] & mask[w]) & 1u;
+    }
+    const u64 bb = __ballot(par);
+    if (lane == 0 && v <= sym.i) sym.fm[(size_t)sym.i * sym.CW + (v >> 6)] = bb;
+  }
   for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off);
   if (lane == 0) s_acc[wave] = acc;
   __syncthreads();
@@ -334,31 +416,34 @@ __global__ __launch_bounds__(1024) void k_detphase(const u64 *__restrict__ X, co
     for (u32 v = 0; v < nwaves; ++v) tot += s_acc[v];
     atomicAdd(&st->det_acc, (u32)tot);
     if (bad) atomicOr(&st->flags, 2u);
+    __threadfence();
+    s_last = (atomicAdd(&st->det_done, 1u) == gridDim.x - 1) ? 1u : 0u;
   }
-}
-
-// Outcome = parity of the signs of S_i over A, xor bit 1 of the phase sum
-// (which must be even).
-__global__ __launch_bounds__(256) void k_detfinal(const u64 *__restrict__ R, const u64 *__restrict__ mask,
-                                                  MeasState *__restrict__ st, MeasStats *__restrict__ stats, u32 K,
-                                                  u32 n, uint8_t *__restrict__ out_bits) {
-  if (st->p >= 0) return;
-  __shared__ u32 s_par[4];
-  const u32 tid = threadIdx.x;
+  __syncthreads();
+  if (!s_last) return;
+  __threadfence();
+  // last block: sign parity over A, then the outcome (or the constant of its affine form)
   u32 par = 0;
-  for (u32 w = tid; w < K; w += blockDim.x) par ^= (u32)__popcll(R[K + w] & mask[w]) & 1u;
+  const u64 *sgn = SYM ? (sym.sg + (size_t)sym.count * sym.Ks) : (R + K);
+  for (u32 w = tid; w < K; w += blockDim.x) par ^= (u32)__popcll(sgn[w] & mask[w]) & 1u;
   const u64 b = __ballot(par);
-  if ((tid & 63u) == 0) s_par[tid >> 6] = (u32)__popcll(b) & 1u;
+  if (lane == 0) s_px[wave] = (u32)__popcll(b) & 1u;
   __syncthreads();
   if (tid == 0) {
     u32 tot = 0;
-    for (u32 v = 0; v < (blockDim.x >> 6); ++v) tot ^= s_par[v];
-    const u32 e = st->det_acc & 3u;
+    for (u32 v = 0; v < nwaves; ++v) tot ^= s_px[v];
+    const u32 e = atomicAdd(&st->det_acc, 0u) & 3u;
     if (e & 1u) atomicOr(&st->flags, 1u);
-    out_bits[0] = (uint8_t)(tot ^ (e >> 1));
-    // Algorithmic bytes: x and z of every column at each word holding a row of A.
-    stats->n_det += 1;
-    stats->det_bytes += (u64)st->awords * 8ULL * 2ULL * n;
+    const uint8_t outcome = (uint8_t)(tot ^ (e >> 1));
+    if (SYM) {
+      sym.fc[sym.i] = outcome;
+      sym.kind[sym.i] = 0;
+    } else {
+      out_bits[0] = outcome;
+      // Algorithmic bytes: x and z of every column at each word holding a row of A.
+      stats->n_det += 1;
+      stats->det_bytes += (u64)st->awords * 8ULL * 2ULL * n;
+    }
   }
 }
 
@@ -370,44 +455,55 @@ hipError_t launch_pivot(const TabDev &t, u32 q, MeasState *st, u64 *mask, u64 se
   return hipGetLastError();
 }
 
-hipError_t launch_gather(const TabDev &t, MeasState *st, u64 *pivx, u64 *pivz, u32 *cols, hipStream_t s) {
-  hipLaunchKernelGGL(k_gather, dim3(cdiv(t.n, 256)), dim3(256), 0, s, t.X, t.Z, t.R, t.Ls, t.K, t.n, st, pivx, pivz,
-                     cols);
+hipError_t launch_gather(const TabDev &t, MeasState *st, u64 *pivx, u64 *pivz, u32 *cols, const SymCtx *sym,
+                         hipStream_t s) {
+  const u32 colblocks = cdiv(t.n, 256);
+  if (sym) {
+    const u32 vblocks = cdiv(sym->i, 256);
+    hipLaunchKernelGGL(k_gather<true>, dim3(colblocks + vblocks), dim3(256), 0, s, t.X, t.Z, t.R, t.Ls, t.K, t.n, st,
+                       pivx, pivz, cols, *sym);
+  } else {
+    hipLaunchKernelGGL(k_gather<false>, dim3(colblocks), dim3(256), 0, s, t.X, t.Z, t.R, t.Ls, t.K, t.n, st, pivx,
+                       pivz, cols, SymCtx{});
+  }
   return hipGetLastError();
 }
 
 hipError_t launch_rowsum(const TabDev &t, const u64 *mask, const u32 *cols, const MeasState *st, u64 *cnt0,
-                         u64 *cnt1, u32 block, u32 wpt, u32 cpc, u32 max_chunks, hipStream_t s) {
+                         u64 *cnt1, u32 block, u32 wpt, u32 cpc, u32 max_chunks, const SymCtx *sym, hipStream_t s) {
   const u32 tiles = cdiv(t.L, (u64)block * wpt);
-  dim3 grid(tiles, max_chunks);
-  if (wpt == 2)
-    hipLaunchKernelGGL((k_rowsum<2, 4>), grid, dim3(block), 0, s, t.X, t.Z, mask, cols, st, cnt0, cnt1, t.Ls, t.L,
-                       cpc);
+  const u32 vchunks = sym ? cdiv(sym->i, SIGN_COLS_PER_BLOCK) : 0;
+  dim3 grid(tiles, max_chunks + vchunks);
+  const SymCtx sc = sym ? *sym : SymCtx{};
+  if (sym) {
+    if (wpt == 2)
+      hipLaunchKernelGGL((k_rowsum<2, 4, true>), grid, dim3(block), 0, s, t.X, t.Z, mask, cols, st, cnt0, cnt1, t.Ls,
+                         t.L, cpc, max_chunks, sc);
+    else
+      hipLaunchKernelGGL((k_rowsum<1, 4, true>), grid, dim3(block), 0, s, t.X, t.Z, mask, cols, st, cnt0, cnt1, t.Ls,
+                         t.L, cpc, max_chunks, sc);
+  } else {
+    if (wpt == 2)
+      hipLaunchKernelGGL((k_rowsum<2, 4, false>), grid, dim3(block), 0, s, t.X, t.Z, mask, cols, st, cnt0, cnt1,
+                         t.Ls, t.L, cpc, max_chunks, sc);
+    else
+      hipLaunchKernelGGL((k_rowsum<1, 4, false>), grid, dim3(block), 0, s, t.X, t.Z, mask, cols, st, cnt0, cnt1,
+                         t.Ls, t.L, cpc, max_chunks, sc);
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_post(const TabDev &t, u32 q, const u64 *mask, const u64 *pivx, const u64 *pivz, const u64 *cnt0,
+                       const u64 *cnt1, MeasState *st, MeasStats *stats, uint8_t *out_bits, u32 cpc, u32 cpw,
+                       const SymCtx *sym, hipStream_t s) {
+  u32 blocks = std::max(cdiv(std::max(t.L, t.n), 256), cdiv(t.n, cpw));
+  if (sym) blocks = std::max(blocks, cdiv(sym->i + 1, 256));
+  if (sym)
+    hipLaunchKernelGGL(k_post<true>, dim3(blocks), dim3(256), 0, s, t.X, t.Z, t.R, mask, pivx, pivz, cnt0, cnt1, st,
+                       stats, out_bits, t.Ls, t.L, t.K, t.n, q, cpc, cpw, *sym);
   else
-    hipLaunchKernelGGL((k_rowsum<1, 4>), grid, dim3(block), 0, s, t.X, t.Z, mask, cols, st, cnt0, cnt1, t.Ls, t.L,
-                       cpc);
-  return hipGetLastError();
-}
-
-hipError_t launch_finalize(const TabDev &t, u32 q, const u64 *mask, const u64 *pivx, const u64 *pivz,
-                           const u64 *cnt0, const u64 *cnt1, MeasState *st, MeasStats *stats, u32 cpc,
-                           hipStream_t s) {
-  const u32 threads = std::max(t.L, t.n);
-  hipLaunchKernelGGL(k_finalize, dim3(cdiv(threads, 256)), dim3(256), 0, s, t.X, t.Z, t.R, mask, pivx, pivz, cnt0,
-                     cnt1, st, stats, t.Ls, t.L, t.K, t.n, q, cpc);
-  return hipGetLastError();
-}
-
-hipError_t launch_detphase(const TabDev &t, u32 q, const u64 *mask, MeasState *st, u32 block, u32 cols_per_wg,
-                           hipStream_t s) {
-  hipLaunchKernelGGL((k_detphase<2>), dim3(cdiv(t.n, cols_per_wg)), dim3(block), 0, s, t.X, t.Z, mask, st, t.Ls,
-                     t.K, t.n, q, cols_per_wg);
-  return hipGetLastError();
-}
-
-hipError_t launch_detfinal(const TabDev &t, const u64 *mask, MeasState *st, MeasStats *stats, uint8_t *out_bits,
-                           hipStream_t s) {
-  hipLaunchKernelGGL(k_detfinal, dim3(1), dim3(256), 0, s, t.R, mask, st, stats, t.K, t.n, out_bits);
+    hipLaunchKernelGGL(k_post<false>, dim3(blocks), dim3(256), 0, s, t.X, t.Z, t.R, mask, pivx, pivz, cnt0, cnt1, st,
+                       stats, out_bits, t.Ls, t.L, t.K, t.n, q, cpc, cpw, SymCtx{});
   return hipGetLastError();
 }
 

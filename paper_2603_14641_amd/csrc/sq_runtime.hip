@@ -301,7 +301,6 @@ void default_tuning(const Dims &d, sq_tuning *t) {
   t->rowsum_block = d.L >= 1024 ? 256 : 64;
   t->rowsum_wpt = d.L >= 512 ? 2 : 1;
   t->rowsum_cols = 0;   // automatic
-  t->det_block = d.K >= 512 ? 256 : 64;
   t->det_cols = 0;      // automatic
 }
 
@@ -329,7 +328,7 @@ u32 rowsum_cpc(const sq_tableau *T) {
 
 u32 det_cpw(const sq_tableau *T) {
   if (T->tun.det_cols) return T->tun.det_cols;
-  return std::max<u32>(1, cdiv(T->d.n, 4096));
+  return std::max<u32>(1, cdiv(T->d.n, 2048));
 }
 
 hipEvent_t take_event(sq_tableau *T) {
@@ -404,18 +403,17 @@ sq_status measure_one(sq_tableau *T, u32 q, u64 seed, u64 shot, u64 m, uint8_t *
   SQ_TRY(timed(T, SQ_K_PIVOT, [&] {
     return launch_pivot(T->t, q, T->st, T->mask, seed, shot, m, dbits, drand, T->stream);
   }));
-  SQ_TRY(timed(T, SQ_K_GATHER, [&] { return launch_gather(T->t, T->st, T->pivx, T->pivz, T->cols, T->stream); }));
+  SQ_TRY(timed(T, SQ_K_GATHER, [&] {
+    return launch_gather(T->t, T->st, T->pivx, T->pivz, T->cols, nullptr, T->stream);
+  }));
   SQ_TRY(timed(T, SQ_K_ROWSUM, [&] {
     return launch_rowsum(T->t, T->mask, T->cols, T->st, T->cnt0, T->cnt1, T->tun.rowsum_block, T->tun.rowsum_wpt, cpc,
-                         max_chunks, T->stream);
+                         max_chunks, nullptr, T->stream);
   }));
-  SQ_TRY(timed(T, SQ_K_FINAL, [&] {
-    return launch_finalize(T->t, q, T->mask, T->pivx, T->pivz, T->cnt0, T->cnt1, T->st, T->stats, cpc, T->stream);
+  SQ_TRY(timed(T, SQ_K_POST, [&] {
+    return launch_post(T->t, q, T->mask, T->pivx, T->pivz, T->cnt0, T->cnt1, T->st, T->stats, dbits, cpc, det_cpw(T),
+                       nullptr, T->stream);
   }));
-  SQ_TRY(timed(T, SQ_K_DET, [&] {
-    return launch_detphase(T->t, q, T->mask, T->st, T->tun.det_block, det_cpw(T), T->stream);
-  }));
-  SQ_TRY(timed(T, SQ_K_DETFINAL, [&] { return launch_detfinal(T->t, T->mask, T->st, T->stats, dbits, T->stream); }));
   return SQ_OK;
 }
 
@@ -429,7 +427,7 @@ sq_status reset_device(sq_tableau *T) {
 
 sq_status check_tuning(const sq_tuning &t) {
   auto ok_block = [](u32 b) { return b >= 64 && b <= 1024 && b % 64 == 0; };
-  if (!ok_block(t.layer_block) || !ok_block(t.rowsum_block) || !ok_block(t.det_block))
+  if (!ok_block(t.layer_block) || !ok_block(t.rowsum_block))
     return fail(SQ_EINVAL, "block sizes must be multiples of 64 in [64, 1024]");
   if ((t.layer_wpt != 1 && t.layer_wpt != 2) || (t.rowsum_wpt != 1 && t.rowsum_wpt != 2))
     return fail(SQ_EINVAL, "words per thread must be 1 or 2");
@@ -625,24 +623,20 @@ sq_status sq_sample(sq_tableau *T, const uint32_t *qubits, uint32_t count, uint6
     HIP_TRY(launch_sample_init(T->t, sg, Ks, count, T->stream));
     for (u32 i = 0; i < count; ++i) {
       const u32 q = qubits[i];
-      SQ_TRY(timed(T, SQ_K_PIVOT, [&] { return launch_pivot(ts, q, T->st, T->mask, seed, 0, 0, dummy, dummy + 1, T->stream); }));
-      SQ_TRY(timed(T, SQ_K_GATHER, [&] { return launch_gather(ts, T->st, T->pivx, T->pivz, T->cols, T->stream); }));
-      HIP_TRY(launch_gather_signs(sg, T->st, svlist, Ks, i, count, T->stream));
+      SymCtx sym{sg, svlist, kind, fm, fc, Ks, CW, count, i};
+      SQ_TRY(timed(T, SQ_K_PIVOT, [&] {
+        return launch_pivot(ts, q, T->st, T->mask, seed, 0, 0, dummy, dummy + 1, T->stream);
+      }));
+      SQ_TRY(timed(T, SQ_K_GATHER, [&] {
+        return launch_gather(ts, T->st, T->pivx, T->pivz, T->cols, &sym, T->stream);
+      }));
       SQ_TRY(timed(T, SQ_K_ROWSUM, [&] {
         return launch_rowsum(ts, T->mask, T->cols, T->st, T->cnt0, T->cnt1, T->tun.rowsum_block, T->tun.rowsum_wpt,
-                             cpc, max_chunks, T->stream);
+                             cpc, max_chunks, &sym, T->stream);
       }));
-      HIP_TRY(launch_signcols(ts, sg, T->mask, T->st, svlist, Ks, i + 1, T->stream));
-      SQ_TRY(timed(T, SQ_K_FINAL, [&] {
-        return launch_finalize_sym(ts, q, sg + (size_t)count * Ks, T->mask, T->pivx, T->pivz, T->cnt0, T->cnt1, T->st,
-                                   cpc, T->stream);
-      }));
-      HIP_TRY(launch_spvec(sg, T->st, svlist, kind, Ks, i, count, T->stream));
-      SQ_TRY(timed(T, SQ_K_DET, [&] {
-        return launch_detphase(ts, q, T->mask, T->st, T->tun.det_block, det_cpw(T), T->stream);
-      }));
-      SQ_TRY(timed(T, SQ_K_DETFINAL, [&] {
-        return launch_detfinal_sym(ts, sg, T->mask, T->st, kind, fm, fc, Ks, CW, i, count, T->stream);
+      SQ_TRY(timed(T, SQ_K_POST, [&] {
+        return launch_post(ts, q, T->mask, T->pivx, T->pivz, T->cnt0, T->cnt1, T->st, T->stats, dummy, cpc,
+                           det_cpw(T), &sym, T->stream);
       }));
     }
     HIP_TRY(launch_coins(cw, seed, shot_begin, meas_base, shots, count, CW, T->stream));
@@ -1105,7 +1099,6 @@ sq_status sq_set_tuning(sq_tableau *T, const sq_tuning *in) {
   if (in->rowsum_block) t.rowsum_block = in->rowsum_block;
   if (in->rowsum_wpt) t.rowsum_wpt = in->rowsum_wpt;
   if (in->rowsum_cols) t.rowsum_cols = in->rowsum_cols;
-  if (in->det_block) t.det_block = in->det_block;
   if (in->det_cols) t.det_cols = in->det_cols;
   SQ_TRY(check_tuning(t));
   T->tun = t;

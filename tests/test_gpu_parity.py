@@ -15,9 +15,9 @@ from workload import CONFIGS, circuit_ops, iter_circuit
 pytestmark = pytest.mark.gpu
 
 SMALL_TILES = dict(layer_block=64, layer_wpt=1, layer_groups=3, rowsum_block=64, rowsum_wpt=1, rowsum_cols=5,
-                   det_block=64, det_cols=2)
+                   det_cols=2)
 SMALL_TILES_W2 = dict(layer_block=64, layer_wpt=2, layer_groups=7, rowsum_block=128, rowsum_wpt=2, rowsum_cols=3,
-                      det_block=128, det_cols=3)
+                      det_cols=3)
 
 
 @pytest.fixture(scope="module", autouse=True)
