@@ -110,7 +110,10 @@ uint32_t sq_num_qubits(const sq_tableau *t);
 sq_status sq_apply_gates(sq_tableau *t, const sq_op *host_ops, uint64_t count);
 
 /* Measure Z on host_qubits[0..count) in that order (measurement index
- * meas_base + i for the i-th), updating the tableau after each. Writes the
+ * meas_base + i for the i-th), updating the tableau after each. With
+ * tuning.meas_block = k > 1, runs of consecutive random measurements are
+ * applied k at a time in one pass over the tableau (bit-identical to one at a
+ * time; the host reads each block's length, one small copy per block). Writes the
  * outcome bits (0/1) to host_out_bits[0..count) and, if host_out_random is
  * not NULL, 1/0 for random/deterministic outcomes. Blocks until written.
  * Errors: SQ_EINVAL, SQ_ERANGE (qubit >= n), SQ_ESTATE (a device check of
@@ -222,6 +225,7 @@ typedef struct {
   uint64_t n_det;
   uint64_t rowsum_bytes;
   uint64_t det_bytes;
+  uint64_t blocks;        /* blocked passes (each applying several random measurements) */
 } sq_meas_stats;
 sq_status sq_measure_stats(sq_tableau *t, sq_meas_stats *out);
 
@@ -245,6 +249,7 @@ typedef struct {
   uint32_t rowsum_wpt;         /* words per thread in the rowsum kernel */
   uint32_t rowsum_cols;        /* pivot-row columns per workgroup (per chunk) */
   uint32_t det_cols;           /* columns per workgroup of the deterministic-product phase */
+  uint32_t meas_block;         /* sq_measure: random measurements per blocked pass (1 = one at a time, <= 16) */
 } sq_tuning;
 sq_status sq_get_tuning(const sq_tableau *t, sq_tuning *out);
 sq_status sq_set_tuning(sq_tableau *t, const sq_tuning *in);
@@ -258,7 +263,11 @@ enum {
   SQ_K_GATHER = 3,  /* pivot-row gather */
   SQ_K_ROWSUM = 4,  /* rowsum pass */
   SQ_K_POST = 5,    /* random-case finalisation or deterministic product */
-  SQ_K_COUNT = 6
+  SQ_K_BPIVOT = 6,  /* blocked measurements: snapshot and sequential pivot step */
+  SQ_K_BPREP = 7,   /* blocked measurements: pivot rows and their algebra */
+  SQ_K_BPASS = 8,   /* blocked measurements: the streaming pass */
+  SQ_K_BFINAL = 9,  /* blocked measurements: signs and pivot rows */
+  SQ_K_COUNT = 10
 };
 sq_status sq_profile_enable(sq_tableau *t, int on);
 /* Sum of kernel durations (ms) and launch count for one kernel id since the

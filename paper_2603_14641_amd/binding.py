@@ -18,8 +18,10 @@ LIB_PATH = os.path.join(_PKG, "libsq.so")
 # status codes and op types (include/sq.h)
 SQ_OK, SQ_EINVAL, SQ_ENOMEM, SQ_EDEVICE, SQ_ERANGE, SQ_ESTATE = 0, -1, -2, -3, -5, -6
 I, H, S, SDG, X, Y, Z, CX, CZ, MEASURE = 0, 1, 2, 3, 4, 5, 6, 7, 8, 15
-K_LAYER, K_SIGNS, K_PIVOT, K_GATHER, K_ROWSUM, K_POST = range(6)
-KERNEL_NAMES = ["layer", "signs", "pivot", "gather", "rowsum", "post"]
+K_LAYER, K_SIGNS, K_PIVOT, K_GATHER, K_ROWSUM, K_POST, K_BPIVOT, K_BPREP, K_BPASS, K_BFINAL = range(10)
+KERNEL_NAMES = ["layer", "signs", "pivot", "gather", "rowsum", "post",
+                "block_pivot", "block_prep", "block_pass", "block_final"]
+MAX_MEAS_BLOCK = 16
 
 EXPORTED = [
     "sq_last_error", "sq_version", "sq_bytes_required", "sq_create", "sq_destroy", "sq_reset", "sq_sync",
@@ -41,7 +43,7 @@ class SqError(RuntimeError):
 class Tuning(ctypes.Structure):
     _fields_ = [(name, ctypes.c_uint32) for name in (
         "layer_block", "layer_wpt", "layer_groups", "rowsum_block", "rowsum_wpt", "rowsum_cols",
-        "det_cols")]
+        "det_cols", "meas_block")]
 
 
 class BatchItem(ctypes.Structure):
@@ -58,7 +60,8 @@ class BatchOpts(ctypes.Structure):
 
 class MeasStats(ctypes.Structure):
     _fields_ = [("n_random", ctypes.c_uint64), ("n_det", ctypes.c_uint64),
-                ("rowsum_bytes", ctypes.c_uint64), ("det_bytes", ctypes.c_uint64)]
+                ("rowsum_bytes", ctypes.c_uint64), ("det_bytes", ctypes.c_uint64),
+                ("blocks", ctypes.c_uint64)]
 
 
 _lib = None

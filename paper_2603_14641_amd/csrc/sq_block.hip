@@ -1,0 +1,487 @@
+// Blocked random measurements: up to KB consecutive random Z measurements
+// applied in one streaming pass over the tableau, bit-identical to applying
+// them one by one with CHP.
+//
+// Let measurements s = 0..k-1 measure q_s with pivots P_s = S_{p_s} as they
+// stand just before measurement s. A row h that is not D_{p_s} or S_{p_s} of
+// any s ends as C_h h with C_h = P_{s_m} ... P_{s_1} (the pivots that hit it,
+// in order). Whether pivot s hits h is linear over GF(2) in h's bits at the
+// measured columns: b_s = a_s ^ XOR_{s'<s} b_{s'} M[s'][s], where a_s is h's x
+// bit at q_s before the block and M[s'][s] is P_{s'}'s x bit at q_s. The x/z
+// update is then XOR_s b_s P_s. Signs follow from writing a Pauli as
+// i^lam X^x Z^z with lam = 2 r + |x & z| (mod 4), in which products are
+// bilinear: lam(A B) = lam(A) + lam(B) + 2 (z_A . x_B). So
+//   lam(C_h h) = sum_s b_s lam(P_s) + 2 sum_{s<s'} b_s b_s' (z_{P_s'} . x_{P_s})
+//                + lam(h) + 2 XOR_s b_s (z_{P_s} . x_h)   (mod 4),
+// and the new sign is (lam - |x' & z'|) / 2, the difference being even. Per
+// row the pass needs only |x & z| - |x' & z'| (mod 4, over columns where some
+// pivot is not the identity) and the k parities z_{P_s} . x_h: a 2-bit
+// counter and k parity words per row word. D_{p_s} becomes P_s times the later
+// pivots that hit it; S_{p_s} becomes (-1)^coin Z_{q_s}. The block ends before
+// the first deterministic measurement, which then takes the single path.
+#include "sq_device.h"
+
+namespace sq {
+
+// -------------------------------------------------------------- snapshot
+__global__ void k_blk_snap(const u64 *__restrict__ X, u32 Ls, u32 L, BlkArgs a, u64 *__restrict__ snap) {
+  const u32 s = blockIdx.y;
+  const u32 w = blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= a.k || w >= L) return;
+  snap[(size_t)s * Ls + w] = X[(size_t)a.q[s] * Ls + w];
+}
+
+// -------------------------------------------------------------- pivots (one workgroup)
+__global__ __launch_bounds__(1024) void k_blk_pivots(const u64 *__restrict__ snap, u64 *__restrict__ bm, u32 Ls,
+                                                      u32 K, BlkArgs a, BlkState *__restrict__ bs,
+                                                      uint8_t *__restrict__ out_bits, uint8_t *__restrict__ out_rand) {
+  __shared__ u32 s_min, s_k;
+  const u32 tid = threadIdx.x, T = blockDim.x, L = 2 * K;
+  if (tid == 0) s_k = a.k;
+  for (u32 s = 0; s < a.k; ++s) {
+    // column q_s as it stands before measurement s
+    for (u32 w = tid; w < L; w += T) {
+      u64 v = snap[(size_t)s * Ls + w];
+      for (u32 sp = 0; sp < s; ++sp)
+        if ((bs->M[sp] >> s) & 1u) v ^= bm[(size_t)sp * Ls + w];
+      for (u32 sp = 0; sp < s; ++sp)
+        if (w == K + (bs->p[sp] >> 6)) v &= ~(1ULL << (bs->p[sp] & 63u));  // S_{p_s'} is now Z
+      bm[(size_t)s * Ls + w] = v;
+    }
+    if (tid == 0) s_min = 0xFFFFFFFFu;
+    __syncthreads();
+    u32 first = 0xFFFFFFFFu;
+    for (u32 w = tid; w < K; w += T)
+      if (bm[(size_t)s * Ls + K + w] != 0) { first = w; break; }
+    for (int off = 32; off > 0; off >>= 1) first = min(first, (u32)__shfl_xor((int)first, off));
+    if ((tid & 63u) == 0 && first != 0xFFFFFFFFu) atomicMin(&s_min, first);
+    __syncthreads();
+    const u32 wmin = s_min;
+    if (wmin == 0xFFFFFFFFu) {  // deterministic: the block ends here
+      if (tid == 0) s_k = s;
+      __syncthreads();
+      break;
+    }
+    if (tid == 0) {
+      const u32 p = wmin * 64u + (u32)__builtin_ctzll(bm[(size_t)s * Ls + K + wmin]);
+      const u32 wd = p >> 6;
+      const u64 bit = 1ULL << (p & 63u);
+      bs->p[s] = p;
+      // earlier pivots that hit S_p (its bits in their masks, before the clean-up below)
+      u32 hit = 0;
+      for (u32 sp = 0; sp < s; ++sp)
+        if (bm[(size_t)sp * Ls + K + wd] & bit) hit |= 1u << sp;
+      bs->hitS[s] = hit;
+      // x bits of P_s at the later measured columns
+      u32 mrow = 0;
+      for (u32 s2 = s + 1; s2 < a.k; ++s2) {
+        u32 v = (u32)(snap[(size_t)s2 * Ls + K + wd] >> (p & 63u)) & 1u;
+        for (u32 sp = 0; sp < s; ++sp)
+          if ((hit >> sp) & 1u) v ^= (bs->M[sp] >> s2) & 1u;
+        mrow |= v << s2;
+      }
+      bs->M[s] = mrow;
+      // D_p and S_p are not multiplied by P_s
+      bm[(size_t)s * Ls + wd] &= ~bit;
+      bm[(size_t)s * Ls + K + wd] &= ~bit;
+      const u32 c = coin_bit(a.seed, a.shot, a.m0 + s);
+      bs->coin[s] = c;
+      out_rand[s] = 1;
+      out_bits[s] = (uint8_t)c;
+    }
+    __syncthreads();
+  }
+  __syncthreads();
+  const u32 k = s_k;
+  // special rows (D_p, S_p of every pivot of the block) take no part in the
+  // pass; one thread per mask, since pivots can share a word
+  for (u32 s = tid; s < k; s += T) {
+    for (u32 t = 0; t < k; ++t) {
+      const u32 p = bs->p[t];
+      const u64 bit = 1ULL << (p & 63u);
+      bm[(size_t)s * Ls + (p >> 6)] &= ~bit;
+      bm[(size_t)s * Ls + K + (p >> 6)] &= ~bit;
+    }
+  }
+  if (tid == 0) {
+    bs->k = k;
+    // later pivots that hit D_{p_s} (which holds P_s from measurement s on)
+    for (u32 s = 0; s < k; ++s) {
+      u32 hits = 0;
+      for (u32 s2 = s + 1; s2 < k; ++s2) {
+        u32 v = (bs->M[s] >> s2) & 1u;
+        for (u32 s3 = s + 1; s3 < s2; ++s3)
+          if ((hits >> s3) & 1u) v ^= (bs->M[s3] >> s2) & 1u;
+        hits |= v << s2;
+      }
+      bs->dhits[s] = hits;
+    }
+    for (u32 s = 0; s < KB; ++s) {
+      bs->Qz[s] = 0;
+      bs->R0[s] = 0;
+      bs->pc0[s] = 0;
+      bs->pcD[s] = 0;
+    }
+    bs->ncols = 0;
+    bs->done = 0;
+  }
+}
+
+// -------------------------------------------------------------- original pivot rows
+__global__ void k_blk_gather(const u64 *__restrict__ X, const u64 *__restrict__ Z, const u64 *__restrict__ R, u32 Ls,
+                             u32 K, u32 n, BlkState *__restrict__ bs, u64 *__restrict__ p0x, u64 *__restrict__ p0z) {
+  const u32 s = blockIdx.y;
+  if (s >= bs->k) return;
+  const u32 p = bs->p[s];
+  const u32 ws = K + (p >> 6), sh = p & 63u;
+  const u32 j = blockIdx.x * blockDim.x + threadIdx.x;
+  u32 xb = 0, zb = 0;
+  if (j < n) {
+    xb = (u32)(X[(size_t)j * Ls + ws] >> sh) & 1u;
+    zb = (u32)(Z[(size_t)j * Ls + ws] >> sh) & 1u;
+  }
+  const u64 bx = __ballot(xb), bz = __ballot(zb);
+  if ((threadIdx.x & 63u) == 0 && j < n) {
+    p0x[(size_t)s * K + (j >> 6)] = bx;
+    p0z[(size_t)s * K + (j >> 6)] = bz;
+  }
+  if (j == 0) bs->r0[s] = (u32)(R[ws] >> sh) & 1u;
+}
+
+// -------------------------------------------------------------- pivot algebra
+// Thread per 64-column word: evolved pivot rows P_s = S0_{p_s} times the
+// earlier pivots that hit it; pairwise parities z_{P_a} . x_{P_b} (Qz) and
+// z_{P_a} . x_{S0_b} (R0); |x & z| of the original pivot rows and of the final
+// D_{p_s} rows (mod 4); per-column patterns of the pivots' x and z bits. The
+// last block to finish forms lam(P_s) and the final signs of the D_{p_s}.
+__global__ void k_blk_pivalg(const u64 *__restrict__ p0x, const u64 *__restrict__ p0z, u64 *__restrict__ px,
+                             u64 *__restrict__ pz, u32 *__restrict__ patx, u32 *__restrict__ patz, u32 K, u32 n,
+                             BlkState *__restrict__ bs, MeasState *__restrict__ st) {
+  __shared__ u32 s_last;
+  const u32 k = bs->k;
+  const u32 cw = blockIdx.x * blockDim.x + threadIdx.x;
+  const u32 lane = threadIdx.x & 63u;
+  u64 x[KB], z[KB];
+  u32 qz[KB], r0[KB], pc0[KB], pcd[KB];
+#pragma unroll
+  for (u32 s = 0; s < KB; ++s) { x[s] = z[s] = 0; qz[s] = r0[s] = pc0[s] = pcd[s] = 0; }
+  u32 ncols = 0;
+  if (cw < K) {
+#pragma unroll
+    for (u32 s = 0; s < KB; ++s) {
+      if (s >= k) break;
+      u64 vx = p0x[(size_t)s * K + cw], vz = p0z[(size_t)s * K + cw];
+      pc0[s] = (u32)__popcll(vx & vz);
+      const u32 hit = bs->hitS[s];
+#pragma unroll
+      for (u32 sp = 0; sp < KB; ++sp)
+        if (sp < s && ((hit >> sp) & 1u)) { vx ^= x[sp]; vz ^= z[sp]; }
+      x[s] = vx;
+      z[s] = vz;
+      px[(size_t)s * K + cw] = vx;
+      pz[(size_t)s * K + cw] = vz;
+    }
+#pragma unroll
+    for (u32 a = 0; a < KB; ++a) {
+      if (a >= k) break;
+#pragma unroll
+      for (u32 b = 0; b < KB; ++b) {
+        if (b >= k) break;
+        qz[a] |= ((u32)__popcll(z[a] & x[b]) & 1u) << b;
+        r0[a] |= ((u32)__popcll(z[a] & p0x[(size_t)b * K + cw]) & 1u) << b;
+      }
+      // final D_{p_a} row: P_a times its later hits
+      u64 dx = x[a], dz = z[a];
+      const u32 dh = bs->dhits[a];
+#pragma unroll
+      for (u32 s2 = 0; s2 < KB; ++s2)
+        if (s2 < k && ((dh >> s2) & 1u)) { dx ^= x[s2]; dz ^= z[s2]; }
+      pcd[a] = (u32)__popcll(dx & dz);
+    }
+    // per-column patterns (bit s: pivot s has x / z on the column)
+    const u32 jn = min(64u, n - cw * 64u);
+    for (u32 b = 0; b < jn; ++b) {
+      u32 vx = 0, vz = 0;
+#pragma unroll
+      for (u32 s = 0; s < KB; ++s) {
+        vx |= (u32)((x[s] >> b) & 1ULL) << s;
+        vz |= (u32)((z[s] >> b) & 1ULL) << s;
+      }
+      patx[cw * 64u + b] = vx;
+      patz[cw * 64u + b] = vz;
+      ncols += (vx | vz) != 0;
+    }
+  }
+  // wave reductions, then one atomic per wave
+#pragma unroll
+  for (u32 a = 0; a < KB; ++a) {
+    u32 wq = 0, wr = 0;
+#pragma unroll
+    for (u32 b = 0; b < KB; ++b) {
+      wq |= ((u32)__popcll(__ballot((qz[a] >> b) & 1u)) & 1u) << b;
+      wr |= ((u32)__popcll(__ballot((r0[a] >> b) & 1u)) & 1u) << b;
+    }
+    u32 sp0 = pc0[a], spd = pcd[a];
+    for (int off = 32; off > 0; off >>= 1) {
+      sp0 += (u32)__shfl_xor((int)sp0, off);
+      spd += (u32)__shfl_xor((int)spd, off);
+    }
+    if (lane == 0 && a < k) {
+      if (wq) atomicXor(&bs->Qz[a], wq);
+      if (wr) atomicXor(&bs->R0[a], wr);
+      atomicAdd(&bs->pc0[a], sp0);
+      atomicAdd(&bs->pcD[a], spd);
+    }
+  }
+  for (int off = 32; off > 0; off >>= 1) ncols += (u32)__shfl_xor((int)ncols, off);
+  if (lane == 0 && ncols) atomicAdd(&bs->ncols, ncols);
+  __threadfence();
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    s_last = (atomicAdd(&bs->done, 1u) == gridDim.x - 1) ? 1u : 0u;
+  }
+  __syncthreads();
+  if (!s_last || threadIdx.x != 0) return;
+  __threadfence();
+  // lam(P_s): start from the original row, multiply in the earlier pivots that hit it, in order
+  u32 lam[KB];
+  for (u32 s = 0; s < k; ++s) {
+    u32 l = (2u * bs->r0[s] + atomicAdd(&bs->pc0[s], 0u)) & 3u;
+    const u32 hit = bs->hitS[s];
+    u32 used = 0;  // pivots already multiplied in
+    for (u32 sp = 0; sp < s; ++sp) {
+      if (!((hit >> sp) & 1u)) continue;
+      // z_{P_sp} . x_current, x_current = x_{S0_s} ^ XOR_{used} x_{P}
+      u32 par = (atomicAdd(&bs->R0[sp], 0u) >> s) & 1u;
+      const u32 qrow = atomicAdd(&bs->Qz[sp], 0u);
+      par ^= (u32)__popc(qrow & used) & 1u;
+      l = (lam[sp] + l + 2u * par) & 3u;
+      used |= 1u << sp;
+    }
+    lam[s] = l;
+    bs->lam[s] = l;
+  }
+  // final signs of the D_{p_s}: P_s times its later hits, in order
+  u32 flags = 0;
+  for (u32 s = 0; s < k; ++s) {
+    u32 l = lam[s];
+    const u32 dh = bs->dhits[s];
+    u32 used = 1u << s;
+    for (u32 s2 = s + 1; s2 < k; ++s2) {
+      if (!((dh >> s2) & 1u)) continue;
+      const u32 qrow = atomicAdd(&bs->Qz[s2], 0u);
+      const u32 par = (u32)__popc(qrow & used) & 1u;
+      l = (lam[s2] + l + 2u * par) & 3u;
+      used |= 1u << s2;
+    }
+    const u32 e = (l - (atomicAdd(&bs->pcD[s], 0u) & 3u)) & 3u;
+    if (e & 1u) flags |= 1u;
+    bs->dsign[s] = e >> 1;
+  }
+  if (flags) atomicOr(&st->flags, flags);
+}
+
+// -------------------------------------------------------------- the pass
+// Grid (row tiles, column chunks). A thread owns one row word; per column
+// where some pivot is not the identity (patterns from k_blk_pivalg, uniform
+// over the wave): XOR in the masks of the pivots with x (z) on that column,
+// count |x & z| - |x' & z'| (mod 4) and the parities z_{P_s} . x_h.
+__global__ __launch_bounds__(256) void k_blk_pass(u64 *__restrict__ X, u64 *__restrict__ Z,
+                                                  const u64 *__restrict__ bm, const u32 *__restrict__ patx,
+                                                  const u32 *__restrict__ patz, const BlkState *__restrict__ bs,
+                                                  u64 *__restrict__ part, u32 Ls, u32 L, u32 n, u32 cpc) {
+  const u32 k = bs->k;
+  if (k == 0) return;
+  const u32 w = blockIdx.x * blockDim.x + threadIdx.x;
+  if (w >= L) return;
+  const u32 j0 = blockIdx.y * cpc;
+  if (j0 >= n) return;
+  const u32 j1 = min(j0 + cpc, n);
+  u64 b[KB];
+  u64 any = 0;
+#pragma unroll
+  for (u32 s = 0; s < KB; ++s) {
+    b[s] = (s < k) ? bm[(size_t)s * Ls + w] : 0ULL;
+    any |= b[s];
+  }
+  if (any == 0) return;
+  u64 y[KB];
+#pragma unroll
+  for (u32 s = 0; s < KB; ++s) y[s] = 0;
+  u64 d0 = 0, d1 = 0;  // |x & z| - |x' & z'| (mod 4), bit-sliced
+  for (u32 j = j0; j < j1; ++j) {
+    const u32 px = patx[j], pz = patz[j];
+    if ((px | pz) == 0) continue;
+    const size_t o = (size_t)j * Ls + w;
+    const u64 x = X[o], z = Z[o];
+    u64 dx = 0, dz = 0;
+#pragma unroll
+    for (u32 s = 0; s < KB; ++s) {
+      if ((px >> s) & 1u) dx ^= b[s];
+      if ((pz >> s) & 1u) { dz ^= b[s]; y[s] ^= x; }
+    }
+    const u64 x2 = x ^ dx, z2 = z ^ dz;
+    const u64 o1 = x & z, n1 = x2 & z2;
+    const u64 plus = o1 & ~n1, minus = n1 & ~o1;
+    d1 ^= d0 & plus;
+    d0 ^= plus;
+    d0 ^= minus;
+    d1 ^= d0 & minus;
+    if (px) X[o] = x2;
+    if (pz) Z[o] = z2;
+  }
+  const size_t cs = (size_t)blockIdx.y * (2 + KB) * Ls;
+  part[cs + w] = d0;
+  part[cs + Ls + w] = d1;
+#pragma unroll
+  for (u32 s = 0; s < KB; ++s)
+    if (s < k) part[cs + (size_t)(2 + s) * Ls + w] = y[s];
+}
+
+// -------------------------------------------------------------- final
+// Threads t < L: signs of the row word t (hit rows from the lam algebra,
+// special rows from dsign / the coins). Threads t < n: column t's bits of the
+// special rows.
+__global__ void k_blk_final(u64 *__restrict__ X, u64 *__restrict__ Z, u64 *__restrict__ R,
+                            const u64 *__restrict__ bm, const u32 *__restrict__ patx, const u32 *__restrict__ patz,
+                            const u64 *__restrict__ part, const BlkState *__restrict__ bs, BlkArgs a,
+                            MeasState *__restrict__ st, MeasStats *__restrict__ stats, u32 Ls, u32 L, u32 K, u32 n,
+                            u32 nchunks) {
+  const u32 k = bs->k;
+  if (k == 0) return;
+  const u32 t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t < L) {
+    const u32 w = t;
+    u64 b[KB];
+    u64 any = 0;
+#pragma unroll
+    for (u32 s = 0; s < KB; ++s) {
+      b[s] = (s < k) ? bm[(size_t)s * Ls + w] : 0ULL;
+      any |= b[s];
+    }
+    u64 r = R[w];
+    bool touched = false;
+    if (any) {
+      u64 d0 = 0, d1 = 0, y[KB];
+#pragma unroll
+      for (u32 s = 0; s < KB; ++s) y[s] = 0;
+      for (u32 c = 0; c < nchunks; ++c) {
+        const size_t cs = (size_t)c * (2 + KB) * Ls;
+        const u64 a0 = part[cs + w], a1 = part[cs + Ls + w];
+        const u64 carry = d0 & a0;
+        d0 ^= a0;
+        d1 ^= a1 ^ carry;
+#pragma unroll
+        for (u32 s = 0; s < KB; ++s)
+          if (s < k) y[s] ^= part[cs + (size_t)(2 + s) * Ls + w];
+      }
+      // lam = sum_s b_s lam(P_s) + 2 sum_{s<s'} b_s b_s' Qz[s'][s] + 2 r + 2 XOR b_s y_s + d
+      u64 l0 = 0, l1 = 0;
+      for (u32 s = 0; s < k; ++s) {
+        const u32 lp = bs->lam[s];
+        if (lp & 1u) { l1 ^= l0 & b[s]; l0 ^= b[s]; }
+        if (lp & 2u) l1 ^= b[s];
+        const u32 qrow = bs->Qz[s];
+        for (u32 sp = 0; sp < s; ++sp)
+          if ((qrow >> sp) & 1u) l1 ^= b[s] & b[sp];
+        l1 ^= b[s] & y[s];
+      }
+      l1 ^= r;
+      {
+        const u64 carry = l0 & d0;
+        l0 ^= d0;
+        l1 ^= d1 ^ carry;
+      }
+      if (l0 & any) atomicOr(&st->flags, 1u);
+      r = (r & ~any) | (l1 & any);
+      touched = true;
+    }
+    for (u32 s = 0; s < k; ++s) {
+      const u32 p = bs->p[s];
+      const u64 bit = 1ULL << (p & 63u);
+      if (w == (p >> 6)) { r = (r & ~bit) | (bs->dsign[s] ? bit : 0ULL); touched = true; }
+      if (w == K + (p >> 6)) { r = (r & ~bit) | (bs->coin[s] ? bit : 0ULL); touched = true; }
+    }
+    if (touched) R[w] = r;
+    if (t == 0) {
+      stats->n_random += k;
+      stats->blocks += 1;
+    }
+  }
+  if (t < n) {
+    const u32 j = t;
+    const u32 px = patx[j], pz = patz[j];
+    u64 *x = X + (size_t)j * Ls;
+    u64 *z = Z + (size_t)j * Ls;
+    for (u32 s = 0; s < k; ++s) {
+      const u32 p = bs->p[s];
+      const u64 bit = 1ULL << (p & 63u);
+      const u32 dh = bs->dhits[s] | (1u << s);
+      const u32 xb = (u32)__popc(px & dh) & 1u, zb = (u32)__popc(pz & dh) & 1u;
+      const u32 wd = p >> 6, ws = K + wd;
+      x[wd] = (x[wd] & ~bit) | (xb ? bit : 0ULL);
+      z[wd] = (z[wd] & ~bit) | (zb ? bit : 0ULL);
+      x[ws] &= ~bit;
+      z[ws] = (z[ws] & ~bit) | ((j == a.q[s]) ? bit : 0ULL);
+    }
+  }
+}
+
+// Bytes of a block pass, counted by row word: read and write x and z of every
+// supported column for each row word that holds a hit row.
+__global__ void k_blk_bytes(const u64 *__restrict__ bm, const BlkState *__restrict__ bs, MeasStats *stats, u32 Ls,
+                            u32 L) {
+  __shared__ u32 s_cnt;
+  if (threadIdx.x == 0) s_cnt = 0;
+  __syncthreads();
+  const u32 k = bs->k;
+  u32 c = 0;
+  for (u32 w = threadIdx.x; w < L; w += blockDim.x) {
+    u64 any = 0;
+    for (u32 s = 0; s < k; ++s) any |= bm[(size_t)s * Ls + w];
+    c += any != 0;
+  }
+  atomicAdd(&s_cnt, c);
+  __syncthreads();
+  if (threadIdx.x == 0 && k) stats->rowsum_bytes += (u64)s_cnt * 8ULL * 4ULL * bs->ncols;
+}
+
+// -------------------------------------------------------------- launchers
+// Stage 0: snapshot of the measured columns and the sequential pivot step
+// (writes BlkState::k, which the host reads before stage 1).
+hipError_t launch_blk_pivots(const TabDev &t, const BlkArgs &a, const BlkBuffers &b, uint8_t *out_bits,
+                             uint8_t *out_rand, hipStream_t s) {
+  hipLaunchKernelGGL(k_blk_snap, dim3(cdiv(t.L, 256), a.k), dim3(256), 0, s, t.X, t.Ls, t.L, a, b.snap);
+  hipLaunchKernelGGL(k_blk_pivots, dim3(1), dim3(1024), 0, s, b.snap, b.bm, t.Ls, t.K, a, b.bs, out_bits, out_rand);
+  return hipGetLastError();
+}
+
+// Stage 1: pivot rows, their algebra and the byte count.
+hipError_t launch_blk_prep(const TabDev &t, const BlkArgs &a, const BlkBuffers &b, MeasState *st, MeasStats *stats,
+                           hipStream_t s) {
+  hipLaunchKernelGGL(k_blk_gather, dim3(cdiv(t.n, 256), a.k), dim3(256), 0, s, t.X, t.Z, t.R, t.Ls, t.K, t.n, b.bs,
+                     b.p0x, b.p0z);
+  hipLaunchKernelGGL(k_blk_pivalg, dim3(cdiv(t.K, 256)), dim3(256), 0, s, b.p0x, b.p0z, b.px, b.pz, b.patx, b.patz,
+                     t.K, t.n, b.bs, st);
+  hipLaunchKernelGGL(k_blk_bytes, dim3(1), dim3(1024), 0, s, b.bm, b.bs, stats, t.Ls, t.L);
+  return hipGetLastError();
+}
+
+// Stage 2: the streaming pass over the tableau.
+hipError_t launch_blk_pass(const TabDev &t, const BlkBuffers &b, u32 cpc, hipStream_t s) {
+  const u32 nchunks = cdiv(t.n, cpc);
+  hipLaunchKernelGGL(k_blk_pass, dim3(cdiv(t.L, 256), nchunks), dim3(256), 0, s, t.X, t.Z, b.bm, b.patx, b.patz,
+                     b.bs, b.part, t.Ls, t.L, t.n, cpc);
+  return hipGetLastError();
+}
+
+// Stage 3: signs and the special rows.
+hipError_t launch_blk_final(const TabDev &t, const BlkArgs &a, const BlkBuffers &b, MeasState *st, MeasStats *stats,
+                            u32 cpc, hipStream_t s) {
+  const u32 nchunks = cdiv(t.n, cpc);
+  hipLaunchKernelGGL(k_blk_final, dim3(cdiv(std::max(t.L, t.n), 256)), dim3(256), 0, s, t.X, t.Z, t.R, b.bm,
+                     b.patx, b.patz, b.part, b.bs, a, st, stats, t.Ls, t.L, t.K, t.n, nchunks);
+  return hipGetLastError();
+}
+
+}  // namespace sq

@@ -76,8 +76,41 @@ struct SymCtx {
 // Running totals over all measurements of a tableau, for byte accounting.
 struct MeasStats {
   u64 n_random, n_det;
-  u64 rowsum_bytes;   // algorithmic bytes of the rowsum passes (see k_finalize)
+  u64 rowsum_bytes;   // algorithmic bytes of the rowsum passes (single and blocked)
   u64 det_bytes;      // algorithmic bytes of the deterministic-phase passes
+  u64 blocks;         // blocked passes (several random measurements each)
+};
+
+// Blocked random measurements (sq_block.hip): up to KB per pass.
+constexpr u32 KB = 16;
+struct BlkArgs {
+  u32 k;          // measurements offered to the block
+  u32 q[KB];      // their qubits
+  u64 seed, shot, m0;  // coin key and the measurement index of the first
+};
+struct BlkState {
+  u32 k;          // random prefix actually processed (the block ends before a deterministic one)
+  u32 p[KB];      // pivot stabilizer index of each
+  u32 hitS[KB];   // bit s': pivot s' hit S_{p_s} before it became a pivot
+  u32 M[KB];      // bit s2: x of P_s at q_{s2}
+  u32 coin[KB];
+  u32 dhits[KB];  // bit s2: pivot s2 (> s) hits D_{p_s}
+  u32 Qz[KB];     // bit b: z_{P_a} . x_{P_b} (mod 2), row a
+  u32 R0[KB];     // bit b: z_{P_a} . x of the original S_{p_b}
+  u32 pc0[KB];    // |x & z| of the original S_{p_s}
+  u32 pcD[KB];    // |x & z| of the final D_{p_s}
+  u32 r0[KB];     // sign of the original S_{p_s}
+  u32 lam[KB];    // lam(P_s) = 2 r + |x & z| (mod 4)
+  u32 dsign[KB];  // final sign of D_{p_s}
+  u32 ncols;      // columns where some pivot is not the identity
+  u32 done;       // blocks of k_blk_pivalg finished (last-block ticket)
+};
+struct BlkBuffers {
+  u64 *snap, *bm;          // KB * Ls words each: measured columns, hit masks
+  u64 *p0x, *p0z, *px, *pz;  // KB * K words each: original and evolved pivot rows
+  u32 *patx, *patz;        // n each: per column, bit s = pivot s has x (z) there
+  u64 *part;               // chunks * (2 + KB) * Ls partial counters and parities
+  BlkState *bs;
 };
 
 // One circuit of a batched launch (sq_batch.hip): |0...0>, gate passes
@@ -129,6 +162,13 @@ hipError_t launch_coins(u64 *cw, u64 seed, u64 shot_begin, u64 meas_base, u32 sh
 hipError_t launch_eval(const u64 *cw, const uint8_t *kind, const u64 *fm, const uint8_t *fc, u64 *out, u32 shots,
                        u32 count, u32 CW, hipStream_t s);
 hipError_t launch_batch(const BatchItem *items, u32 nitems, u32 *next, u32 block, u32 grid, hipStream_t s);
+hipError_t launch_blk_pivots(const TabDev &t, const BlkArgs &a, const BlkBuffers &b, uint8_t *out_bits,
+                             uint8_t *out_rand, hipStream_t s);
+hipError_t launch_blk_prep(const TabDev &t, const BlkArgs &a, const BlkBuffers &b, MeasState *st, MeasStats *stats,
+                           hipStream_t s);
+hipError_t launch_blk_pass(const TabDev &t, const BlkBuffers &b, u32 cpc, hipStream_t s);
+hipError_t launch_blk_final(const TabDev &t, const BlkArgs &a, const BlkBuffers &b, MeasState *st, MeasStats *stats,
+                            u32 cpc, hipStream_t s);
 hipError_t launch_export_rows(const TabDev &t, const u32 *rows, u32 nrows, u32 W, u64 *ox, u64 *oz, uint8_t *orr,
                               hipStream_t s);
 hipError_t launch_import(const TabDev &t, const u64 *ix, const u64 *iz, const uint8_t *ir, u32 W, hipStream_t s);

@@ -37,6 +37,7 @@ sq_status fail(sq_status code, const char *fmt, ...) {
   } while (0)
 
 constexpr u32 kMaxChunks = 2048;  // per-launch cap on gate-group and column chunks
+constexpr u32 kBlkMaxChunks = 512;  // column chunks of the blocked-measurement pass
 
 inline u32 cdiv(u64 a, u64 b) { return (u32)((a + b - 1) / b); }
 inline u32 round_up(u32 a, u32 b) { return (a + b - 1) / b * b; }
@@ -239,6 +240,9 @@ struct sq_tableau {
   u32 *cols = nullptr;
   MeasState *st = nullptr;
   MeasStats *stats = nullptr;
+  BlkBuffers blk{};
+  u32 blk_cpc = 0;
+  u32 *blk_k_host = nullptr;  // pinned: random-prefix length of the last block
   uint8_t *dev_out = nullptr;
   size_t dev_out_cap = 0;
   Group *dev_groups = nullptr;
@@ -271,8 +275,19 @@ struct sq_program {
 
 namespace {
 
+// Columns per chunk of the blocked pass: about 2048 workgroups in all.
+u32 blk_cpc_of(const Dims &d) {
+  const u32 tiles = cdiv(d.L, 256);
+  const u32 want = std::max<u32>(1, 2048 / tiles);
+  u32 cpc = std::max<u32>(16, cdiv(d.n, want));
+  return std::max<u32>(cpc, cdiv(d.n, kBlkMaxChunks));
+}
+
+constexpr int kLayoutSlots = 22;
+
 size_t layout_words(const Dims &d, size_t *off) {
-  // offsets (in words) of: X, Z, R, mask, pivx, pivz, cnt0, cnt1, sign_part, cols, st, stats
+  // offsets (in words) of: X, Z, R, mask, pivx, pivz, cnt0, cnt1, sign_part, cols, st, stats,
+  // then the blocked-measurement buffers: snap, bm, p0x, p0z, px, pz, patx, patz, part, bs
   size_t o = 0;
   auto take = [&](size_t words) {
     size_t r = o;
@@ -291,6 +306,13 @@ size_t layout_words(const Dims &d, size_t *off) {
   off[9] = take((d.n + 1) / 2);
   off[10] = take(sizeof(MeasState) / 8 + 1);
   off[11] = take(sizeof(MeasStats) / 8 + 1);
+  off[12] = take((size_t)KB * d.Ls);
+  off[13] = take((size_t)KB * d.Ls);
+  for (int i = 14; i < 18; ++i) off[i] = take((size_t)KB * d.K);
+  off[18] = take((d.n + 1) / 2);
+  off[19] = take((d.n + 1) / 2);
+  off[20] = take((size_t)cdiv(d.n, blk_cpc_of(d)) * (2 + KB) * d.Ls);
+  off[21] = take(sizeof(BlkState) / 8 + 1);
   return o;
 }
 
@@ -302,6 +324,7 @@ void default_tuning(const Dims &d, sq_tuning *t) {
   t->rowsum_wpt = d.L >= 512 ? 2 : 1;
   t->rowsum_cols = 0;   // automatic
   t->det_cols = 0;      // automatic
+  t->meas_block = KB;
 }
 
 u32 layer_gpc(const sq_tableau *T, u32 ngroups) {
@@ -417,8 +440,58 @@ sq_status measure_one(sq_tableau *T, u32 q, u64 seed, u64 shot, u64 m, uint8_t *
   return SQ_OK;
 }
 
+// Measurements qubits[i0..i1) (indices meas_base + i), random runs KB at a
+// time through the blocked pass. Each block's length (the random prefix
+// before the first deterministic measurement) is read back before its pass;
+// the deterministic one then takes the single path. Blocks that end at once
+// (deterministic stretches) back off to the single path for 1, 2, 4, ... 64
+// measurements before the next try.
+sq_status measure_range(sq_tableau *T, const uint32_t *qubits, u64 i0, u64 i1, u64 seed, u64 shot, u64 meas_base,
+                        uint8_t *dbits, uint8_t *drand) {
+  const u32 kb = std::min<u32>(T->tun.meas_block, KB);
+  u64 i = i0;
+  u32 single = 0, backoff = 1;
+  while (i < i1) {
+    const u32 want = (u32)std::min<u64>(kb, i1 - i);
+    if (want < 2 || single > 0) {
+      SQ_TRY(measure_one(T, qubits[i], seed, shot, meas_base + i, dbits + i, drand + i));
+      ++i;
+      if (single > 0) --single;
+      continue;
+    }
+    BlkArgs a{};
+    a.k = want;
+    for (u32 s = 0; s < want; ++s) a.q[s] = qubits[i + s];
+    a.seed = seed;
+    a.shot = shot;
+    a.m0 = meas_base + i;
+    SQ_TRY(timed(T, SQ_K_BPIVOT, [&] { return launch_blk_pivots(T->t, a, T->blk, dbits + i, drand + i, T->stream); }));
+    HIP_TRY(hipMemcpyAsync(T->blk_k_host, &T->blk.bs->k, sizeof(u32), hipMemcpyDeviceToHost, T->stream));
+    HIP_TRY(hipStreamSynchronize(T->stream));
+    const u32 k = *T->blk_k_host;
+    if (k > want) return fail(SQ_ESTATE, "blocked measurement: bad block length %u", k);
+    if (k > 0) {
+      SQ_TRY(timed(T, SQ_K_BPREP, [&] { return launch_blk_prep(T->t, a, T->blk, T->st, T->stats, T->stream); }));
+      SQ_TRY(timed(T, SQ_K_BPASS, [&] { return launch_blk_pass(T->t, T->blk, T->blk_cpc, T->stream); }));
+      SQ_TRY(timed(T, SQ_K_BFINAL, [&] {
+        return launch_blk_final(T->t, a, T->blk, T->st, T->stats, T->blk_cpc, T->stream);
+      }));
+      i += k;
+      backoff = 1;
+    } else {
+      single = backoff - 1;
+      backoff = std::min<u32>(2 * backoff, 64);
+    }
+    if (k < want) {  // measurement i is deterministic
+      SQ_TRY(measure_one(T, qubits[i], seed, shot, meas_base + i, dbits + i, drand + i));
+      ++i;
+    }
+  }
+  return SQ_OK;
+}
+
 sq_status reset_device(sq_tableau *T) {
-  size_t off[12];
+  size_t off[kLayoutSlots];
   const size_t words = layout_words(T->d, off);
   HIP_TRY(launch_fill_zero(T->base, words, T->stream));
   HIP_TRY(launch_init_diag(T->t, T->stream));
@@ -431,6 +504,7 @@ sq_status check_tuning(const sq_tuning &t) {
     return fail(SQ_EINVAL, "block sizes must be multiples of 64 in [64, 1024]");
   if ((t.layer_wpt != 1 && t.layer_wpt != 2) || (t.rowsum_wpt != 1 && t.rowsum_wpt != 2))
     return fail(SQ_EINVAL, "words per thread must be 1 or 2");
+  if (t.meas_block < 1 || t.meas_block > KB) return fail(SQ_EINVAL, "meas_block must be in [1, %u]", KB);
   return SQ_OK;
 }
 
@@ -444,7 +518,7 @@ const char *sq_version(void) { return "sq 0.1 (gfx950)"; }
 
 size_t sq_bytes_required(uint32_t n) {
   if (n == 0 || n > SQ_MAX_QUBITS) return 0;
-  size_t off[12];
+  size_t off[kLayoutSlots];
   return layout_words(dims_of(n), off) * 8;
 }
 
@@ -461,12 +535,18 @@ sq_status sq_create(uint32_t n, void *hip_stream, sq_tableau **out) {
   }
   T->stream = (hipStream_t)hip_stream;
   T->d = dims_of(n);
-  size_t off[12];
+  size_t off[kLayoutSlots];
   const size_t words = layout_words(T->d, off);
+  if (hipHostMalloc((void **)&T->blk_k_host, sizeof(u32), hipHostMallocDefault) != hipSuccess) {
+    (void)hipGetLastError();
+    delete T;
+    return fail(SQ_ENOMEM, "pinned host allocation failed");
+  }
   // stream-ordered allocation: no device-wide synchronization, so handles can
   // be created and destroyed while other streams keep working
   if (hipMallocAsync((void **)&T->base, words * 8, T->stream) != hipSuccess) {
     (void)hipGetLastError();
+    (void)hipHostFree(T->blk_k_host);
     delete T;
     return fail(SQ_ENOMEM, "device allocation of %zu bytes failed", words * 8);
   }
@@ -481,6 +561,10 @@ sq_status sq_create(uint32_t n, void *hip_stream, sq_tableau **out) {
   T->cols = reinterpret_cast<u32 *>(b + off[9]);
   T->st = reinterpret_cast<MeasState *>(b + off[10]);
   T->stats = reinterpret_cast<MeasStats *>(b + off[11]);
+  T->blk = BlkBuffers{b + off[12], b + off[13], b + off[14], b + off[15], b + off[16], b + off[17],
+                      reinterpret_cast<u32 *>(b + off[18]), reinterpret_cast<u32 *>(b + off[19]), b + off[20],
+                      reinterpret_cast<BlkState *>(b + off[21])};
+  T->blk_cpc = blk_cpc_of(T->d);
   default_tuning(T->d, &T->tun);
   T->builder.init(n, T->d.L);
   sq_status s = reset_device(T);
@@ -488,6 +572,7 @@ sq_status sq_create(uint32_t n, void *hip_stream, sq_tableau **out) {
   if (s != SQ_OK) {
     (void)hipFreeAsync(T->base, T->stream);
     (void)hipStreamSynchronize(T->stream);
+    (void)hipHostFree(T->blk_k_host);
     delete T;
     return s;
   }
@@ -508,6 +593,7 @@ sq_status sq_destroy(sq_tableau *T) {
   if (T->dev_groups) (void)hipFreeAsync(T->dev_groups, T->stream);
   (void)hipFreeAsync(T->base, T->stream);
   (void)hipStreamSynchronize(T->stream);
+  (void)hipHostFree(T->blk_k_host);
   delete T;
   return SQ_OK;
 }
@@ -570,8 +656,7 @@ sq_status sq_measure(sq_tableau *T, const uint32_t *qubits, uint32_t count, uint
   }
   MeasState before{}, after{};
   HIP_TRY(hipMemcpyAsync(&before, T->st, sizeof(MeasState), hipMemcpyDeviceToHost, T->stream));
-  for (u32 i = 0; i < count; ++i)
-    SQ_TRY(measure_one(T, qubits[i], seed, shot, meas_base + i, T->dev_out + i, T->dev_out + count + i));
+  SQ_TRY(measure_range(T, qubits, 0, count, seed, shot, meas_base, T->dev_out, T->dev_out + count));
   HIP_TRY(hipMemcpyAsync(out_bits, T->dev_out, count, hipMemcpyDeviceToHost, T->stream));
   if (out_random)
     HIP_TRY(hipMemcpyAsync(out_random, T->dev_out + count, count, hipMemcpyDeviceToHost, T->stream));
@@ -984,8 +1069,8 @@ sq_status sq_run(sq_tableau *T, const sq_program *P, uint64_t seed, uint64_t sho
     if (s.kind == 0) {
       SQ_TRY(run_passes(T, P->dev_groups, P->passes, s.first, s.count));
     } else {
-      for (u64 i = s.first; i < s.first + s.count; ++i)
-        SQ_TRY(measure_one(T, P->meas_qubits[i], seed, shot, meas_base + i, dev_out_bits + i, rand_base + i));
+      SQ_TRY(measure_range(T, P->meas_qubits.data(), s.first, s.first + s.count, seed, shot, meas_base,
+                           dev_out_bits, rand_base));
     }
   }
   return SQ_OK;
@@ -1070,6 +1155,7 @@ sq_status sq_measure_stats(sq_tableau *T, sq_meas_stats *out) {
   out->n_det = s.n_det;
   out->rowsum_bytes = s.rowsum_bytes;
   out->det_bytes = s.det_bytes;
+  out->blocks = s.blocks;
   return SQ_OK;
 }
 
@@ -1100,6 +1186,7 @@ sq_status sq_set_tuning(sq_tableau *T, const sq_tuning *in) {
   if (in->rowsum_wpt) t.rowsum_wpt = in->rowsum_wpt;
   if (in->rowsum_cols) t.rowsum_cols = in->rowsum_cols;
   if (in->det_cols) t.det_cols = in->det_cols;
+  if (in->meas_block) t.meas_block = in->meas_block;
   SQ_TRY(check_tuning(t));
   T->tun = t;
   return SQ_OK;

@@ -15,9 +15,10 @@ from workload import CONFIGS, circuit_ops, iter_circuit
 pytestmark = pytest.mark.gpu
 
 SMALL_TILES = dict(layer_block=64, layer_wpt=1, layer_groups=3, rowsum_block=64, rowsum_wpt=1, rowsum_cols=5,
-                   det_cols=2)
+                   det_cols=2, meas_block=1)
 SMALL_TILES_W2 = dict(layer_block=64, layer_wpt=2, layer_groups=7, rowsum_block=128, rowsum_wpt=2, rowsum_cols=3,
-                      det_cols=3)
+                      det_cols=3, meas_block=3)
+SINGLE = dict(meas_block=1)   # one measurement at a time (the default applies runs of up to 16 in one pass)
 
 
 @pytest.fixture(scope="module", autouse=True)
@@ -90,11 +91,62 @@ def test_config2_full():
     st = t.measure_stats()
     assert st.n_random + st.n_det == prog.num_measurements
     assert st.n_random == int(rr.sum())
+    assert st.blocks > 0
+
+
+# ------------------------------------------------------------------ blocked random measurements
+def _measure_sequence(rng, n, count):
+    """Random qubits with repeats: a repeat inside a run is deterministic and
+    ends a block early."""
+    qs = rng.integers(0, n, count)
+    for k in range(0, count - 1, 7):
+        qs[k + 1] = qs[k]
+    return qs
+
+
+@pytest.mark.parametrize("n", [2, 5, 64, 65, 300, 2000])
+@pytest.mark.parametrize("mb", [2, 5, 16])
+def test_blocked_measurements(n, mb):
+    """Runs of random measurements applied up to mb at a time in one pass:
+    outcomes, flags and the whole tableau bit-exact with one-at-a-time CHP."""
+    rng = np.random.default_rng(n * 100 + mb)
+    prep = mixed_program(rng, n, 8, p_meas=0.0)
+    qs = _measure_sequence(rng, n, min(3 * n, 80))
+    meas = np.array([[orc.MEASURE, int(q), 0] for q in qs], dtype=np.uint32)
+    ops = np.concatenate([prep, meas, mixed_program(rng, n, 2, p_meas=0.5)])
+    seed = int(rng.integers(1 << 40))
+    rb, rr, x, z, r, _ = oracle_run(n, ops, seed, shot=2, meas_base=9)
+    t = _tab(n, dict(meas_block=mb))
+    bits, rnd = gpu_run_calls(t, ops, seed, shot=2, meas_base=9)
+    _assert_same(bits, rb, "outcomes")
+    _assert_same(rnd, rr, "random flags")
+    _compare_full(t, (x, z, r))
+    st = t.measure_stats()
+    assert st.n_random == int(rr.sum()) and st.n_det == int((rr == 0).sum())
+    if n >= 64:  # small n can see deterministic measurements first in every block
+        assert st.blocks > 0
+
+
+def test_blocked_pivots_share_words():
+    """n = 40 (one word of rows per half): every pivot of a block sits in the
+    same 64-row word, as do the D rows they overwrite."""
+    n = 40
+    rng = np.random.default_rng(41)
+    ops = np.concatenate([mixed_program(rng, n, 10, p_meas=0.0),
+                          np.array([[orc.MEASURE, q, 0] for q in rng.permutation(n)], dtype=np.uint32)])
+    rb, rr, x, z, r, _ = oracle_run(n, ops, seed=3)
+    assert rr[:16].sum() >= 8
+    t = _tab(n)
+    bits, rnd = gpu_run_calls(t, ops, seed=3)
+    _assert_same(bits, rb, "outcomes")
+    _assert_same(rnd, rr, "random flags")
+    _compare_full(t, (x, z, r))
 
 
 # ------------------------------------------------------------------ tiles, ragged tails, all gate types
 @pytest.mark.parametrize("n", [1, 2, 3, 63, 64, 65, 130, 700, 2500])
-@pytest.mark.parametrize("tuning", [None, SMALL_TILES, SMALL_TILES_W2], ids=["default", "small", "small_w2"])
+@pytest.mark.parametrize("tuning", [None, SINGLE, SMALL_TILES, SMALL_TILES_W2],
+                         ids=["default", "single", "small", "small_w2"])
 def test_mixed_circuits(n, tuning):
     rng = np.random.default_rng(1000 + n)
     layers = 6 if n >= 700 else 12
@@ -225,7 +277,7 @@ def _sampled_rows(n, rng, k_prefix=64, k_rand=32):
     return rows
 
 
-@pytest.mark.parametrize("cfg_id,depth,nmeas", [(3, 40, 16), (4, 100, 16)])
+@pytest.mark.parametrize("cfg_id,depth,nmeas", [(3, 40, 16), (4, 100, 40)])
 def test_full_size_sampled_rows(cfg_id, depth, nmeas):
     """n = 65,536 and 180,000 in the default launch configuration: after
     `depth` generator layers and the first `nmeas` measurements of the final
