@@ -253,20 +253,25 @@ def main():
     kern = {name: t.profile_read(i) for i, name in enumerate(sqb.KERNEL_NAMES)}
     assert kern["layer"][1] > 0
     layer_ms, layer_n = kern["layer"]
-    rowsum_ms, rowsum_n = kern["rowsum"]
-    layer_bytes = pg.gate_bytes / max(pg.num_passes, 1)
-    layer_gbs = layer_bytes / (layer_ms / layer_n * 1e-3) / 1e9
     n_random = st1.n_random
-    rowsum_bytes = st1.rowsum_bytes / max(n_random, 1)
-    rowsum_gbs = rowsum_bytes / (rowsum_ms / max(rowsum_n, 1) * 1e-3) / 1e9 if rowsum_n else 0.0
-    roof_layer = {"kernel": "k_layer", "bound": "hbm", "achieved": round(layer_gbs, 1), "peak": HBM_PEAK_GBS,
-                  "unit": "GB/s", "frac": round(layer_gbs / HBM_PEAK_GBS, 4), "traffic": None,
-                  "bytes_per_launch": int(layer_bytes), "avg_launch_ms": round(layer_ms / layer_n, 4)}
-    roof_rowsum = {"kernel": "k_rowsum", "bound": "hbm", "achieved": round(rowsum_gbs, 1), "peak": HBM_PEAK_GBS,
-                   "unit": "GB/s", "frac": round(rowsum_gbs / HBM_PEAK_GBS, 4), "traffic": None,
-                   "bytes_per_launch": int(rowsum_bytes),
-                   "avg_launch_ms": round(rowsum_ms / max(rowsum_n, 1), 4)}
-    dominant, other = (roof_layer, roof_rowsum) if layer_ms >= rowsum_ms else (roof_rowsum, roof_layer)
+
+    def roof(name, ms, launches, total_bytes):
+        per = total_bytes / max(launches, 1)
+        gbs = per / (ms / launches * 1e-3) / 1e9 if launches else 0.0
+        return {"kernel": name, "bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(gbs / HBM_PEAK_GBS, 4), "traffic": None, "bytes_per_launch": int(per),
+                "avg_launch_ms": round(ms / max(launches, 1), 4), "launches_per_step": launches // args.steps,
+                "ms_per_step": round(ms / args.steps, 3)}
+
+    # The library's byte counters hold one step (each step starts from reset);
+    # the profile holds all timed steps.
+    roofs = [roof("k_layer", layer_ms, layer_n, pg.gate_bytes * args.steps)]
+    if kern["block_pass"][1]:
+        roofs.append(roof("k_blk_pass", *kern["block_pass"], st1.block_bytes * args.steps))
+    if kern["rowsum"][1]:
+        roofs.append(roof("k_rowsum", *kern["rowsum"], st1.rowsum_bytes * args.steps))
+    roofs.sort(key=lambda r: -r["ms_per_step"])
+    dominant, others = roofs[0], roofs[1:]
 
     gates_per_step = int(pg.num_gates)
     result = {
@@ -292,8 +297,9 @@ def main():
         "gate_phase_ms_per_step": gate_ms / args.steps,
         "meas_phase_ms_per_step": meas_ms / args.steps,
         "random_measurements_per_step": int(n_random),
+        "measurement_blocks_per_step": int(st1.blocks),
         "roofline": dominant,
-        "roofline_other": other,
+        "roofline_other": others,
         "kernel_ms": {k: round(v[0], 3) for k, v in kern.items()},
         "kernel_launches": {k: v[1] for k, v in kern.items()},
     }

@@ -226,6 +226,7 @@ typedef struct {
   uint64_t rowsum_bytes;
   uint64_t det_bytes;
   uint64_t blocks;        /* blocked passes (each applying several random measurements) */
+  uint64_t block_bytes;   /* algorithmic bytes of the blocked passes */
 } sq_meas_stats;
 sq_status sq_measure_stats(sq_tableau *t, sq_meas_stats *out);
 

@@ -61,7 +61,7 @@ class BatchOpts(ctypes.Structure):
 class MeasStats(ctypes.Structure):
     _fields_ = [("n_random", ctypes.c_uint64), ("n_det", ctypes.c_uint64),
                 ("rowsum_bytes", ctypes.c_uint64), ("det_bytes", ctypes.c_uint64),
-                ("blocks", ctypes.c_uint64)]
+                ("blocks", ctypes.c_uint64), ("block_bytes", ctypes.c_uint64)]
 
 
 _lib = None

@@ -443,7 +443,7 @@ __global__ void k_blk_bytes(const u64 *__restrict__ bm, const BlkState *__restri
   }
   atomicAdd(&s_cnt, c);
   __syncthreads();
-  if (threadIdx.x == 0 && k) stats->rowsum_bytes += (u64)s_cnt * 8ULL * 4ULL * bs->ncols;
+  if (threadIdx.x == 0 && k) stats->block_bytes += (u64)s_cnt * 8ULL * 4ULL * bs->ncols;
 }
 
 // -------------------------------------------------------------- launchers

@@ -76,9 +76,10 @@ struct SymCtx {
 // Running totals over all measurements of a tableau, for byte accounting.
 struct MeasStats {
   u64 n_random, n_det;
-  u64 rowsum_bytes;   // algorithmic bytes of the rowsum passes (single and blocked)
+  u64 rowsum_bytes;   // algorithmic bytes of the single-measurement rowsum passes
   u64 det_bytes;      // algorithmic bytes of the deterministic-phase passes
   u64 blocks;         // blocked passes (several random measurements each)
+  u64 block_bytes;    // algorithmic bytes of the blocked passes
 };
 
 // Blocked random measurements (sq_block.hip): up to KB per pass.

@@ -1156,6 +1156,7 @@ sq_status sq_measure_stats(sq_tableau *T, sq_meas_stats *out) {
   out->rowsum_bytes = s.rowsum_bytes;
   out->det_bytes = s.det_bytes;
   out->blocks = s.blocks;
+  out->block_bytes = s.block_bytes;
   return SQ_OK;
 }
 
