@@ -27,6 +27,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, AMD public specification
+HBM_SUMMARY = "hbm_counters_n180000_bench.md"  # profiles/ summary of FETCH_SIZE / WRITE_SIZE on this workload
 
 
 def log(msg: str):
@@ -187,6 +188,7 @@ def main():
     import torch
     import paper_2603_14641_amd as sq
     from paper_2603_14641_amd import binding as sqb
+    from paper_2603_14641_amd import profsum
     from workload import CONFIGS
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
@@ -258,8 +260,13 @@ def main():
     def roof(name, ms, launches, total_bytes):
         per = total_bytes / max(launches, 1)
         gbs = per / (ms / launches * 1e-3) / 1e9 if launches else 0.0
+        # HBM bytes per launch from the committed rocprofv3 counter summary of
+        # this workload, or None if that kernel's source changed since
+        traffic = profsum.traffic_per_dispatch(name, HBM_SUMMARY)
         return {"kernel": name, "bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(gbs / HBM_PEAK_GBS, 4), "traffic": None, "bytes_per_launch": int(per),
+                "frac": round(gbs / HBM_PEAK_GBS, 4), "traffic": traffic, "traffic_unit": "bytes per launch",
+                "traffic_over_algorithmic": round(traffic / per, 3) if traffic and per else None,
+                "bytes_per_launch": int(per),
                 "avg_launch_ms": round(ms / max(launches, 1), 4), "launches_per_step": launches // args.steps,
                 "ms_per_step": round(ms / args.steps, 3)}
 
