@@ -172,7 +172,7 @@ def main():
     ap.add_argument("--steps", type=int, default=2)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--layers", type=int, default=1000)
-    ap.add_argument("--meas", type=int, default=500)
+    ap.add_argument("--meas", type=int, default=1000)
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--served-requests", type=int, default=48,

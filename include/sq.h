@@ -183,13 +183,15 @@ uint64_t sq_program_num_gates(const sq_program *p);
 uint64_t sq_program_num_passes(const sq_program *p);
 
 /* Host-only inspection of how a gate sequence is grouped into passes (no
- * device work; usable without a GPU). Writes, per pass, one word with the
- * pass's group count, then three words per group: slot-A qubit (bits 0..23)
- * with changed-column flags xa, za, xb, zb (bits 24..27), slot-B qubit
- * (0xFFFFFFFF for a one-qubit group), and up to 16 4-bit micro-ops, LSB
- * first, 0-terminated (1..6: H, S, S^dagger, X, Y, Z on slot A; 7..12 the
- * same on slot B; 13 CX A->B; 14 CX B->A; 15 CZ). *out_len receives the
- * number of words needed; nothing is written past cap.
+ * device work; usable without a GPU). A pass holds groups on pairwise
+ * disjoint qubit sets, each of at most 8 qubits and 32 micro-ops. Writes, per
+ * pass, one word with its group count, then per group: a header word
+ * (bits 0..3 qubit count nq, bits 4..9 micro-op count m, bits 16..23 and
+ * 24..31 per-slot flags of the x and z columns the group changes), nq words
+ * with the qubit of each slot, and m words with one micro-op each: bits 0..3
+ * the gate (1 H, 2 S, 3 S^dagger, 4 X, 5 Y, 6 Z, 7 CX, 8 CZ), bits 4..7 its
+ * (control) slot, bits 8..11 the target slot of CX / second slot of CZ.
+ * *out_len receives the number of words needed; nothing is written past cap.
  * Errors as sq_apply_gates. */
 sq_status sq_plan_gates(uint32_t n, const sq_op *host_ops, uint64_t count, uint64_t *out, uint64_t cap,
                         uint64_t *out_len);

@@ -358,7 +358,8 @@ def words_to_bits(words: np.ndarray, count: int) -> np.ndarray:
 
 
 def plan_gates(n: int, ops) -> list:
-    """Host-only: the pass plan of a gate sequence as [[(q0word, q1, ops), ...], ...]."""
+    """Host-only: the pass plan of a gate sequence, as a list of passes, each a
+    list of groups (header, qubits, micro-ops); see sq_plan_gates."""
     lib = load()
     a = ops_array(ops)
     need = ctypes.c_uint64(0)
@@ -369,8 +370,14 @@ def plan_gates(n: int, ops) -> list:
     while k < int(need.value):
         cnt = int(buf[k])
         k += 1
-        groups = [(int(buf[k + 3 * g]), int(buf[k + 3 * g + 1]), int(buf[k + 3 * g + 2])) for g in range(cnt)]
-        k += 3 * cnt
+        groups = []
+        for _ in range(cnt):
+            hdr = int(buf[k])
+            nq, nops = hdr & 15, (hdr >> 4) & 63
+            qubits = [int(v) for v in buf[k + 1:k + 1 + nq]]
+            uops = [int(v) for v in buf[k + 1 + nq:k + 1 + nq + nops]]
+            groups.append((hdr, qubits, uops))
+            k += 1 + nq + nops
         passes.append(groups)
     return passes
 

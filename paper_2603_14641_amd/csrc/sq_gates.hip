@@ -4,8 +4,8 @@
 namespace sq {
 
 // ---------------------------------------------------------------------------
-// a2: one fused gate pass. Each group is a short sequence of gates on one or
-// two qubits; groups of a pass act on disjoint qubits, so every (group,
+// a2: one fused gate pass. Each group is a short gate sequence on up to
+// WG_MAXQ qubits; groups of a pass act on disjoint qubits, so every (group,
 // row word) update is independent. The column rules (pre-gate values on the
 // right-hand side) per 64 rows at once:
 //   H:   r ^= x&z;  (x, z) <- (z, x)
@@ -13,83 +13,100 @@ namespace sq {
 //   X:   r ^= z     Y: r ^= x^z     Z: r ^= x
 //   CX(c,t): r ^= x_c & z_t & ~(x_t ^ z_c); x_t ^= x_c; z_c ^= z_t
 //   CZ(a,b): r ^= x_a & x_b & (z_a ^ z_b);  z_a ^= x_b; z_b ^= x_a
-// A thread owns WPT consecutive row words and walks the groups of its
-// chunk, keeping the sign changes in registers; the per-chunk sign words go
+// A thread owns WPT consecutive row words. For each group of its chunk it
+// loads the group's columns into registers, runs the micro-ops (their slots
+// are uniform over the wave, so the dispatch below is a scalar branch and
+// every register index is a constant), and stores the changed columns. Sign
+// changes stay in registers for the whole chunk; the per-chunk sign words go
 // to sign_part and are XOR-reduced by k_sign_reduce.
 template <int WPT>
-__device__ __forceinline__ void run_uops(u64 ops, u64 (&xa)[WPT], u64 (&za)[WPT], u64 (&xb)[WPT], u64 (&zb)[WPT],
-                                         u64 (&s)[WPT]) {
-  for (; ops != 0; ops >>= 4) {
-    switch ((u32)(ops & 15ULL)) {
-      case UOP_H_A:
+struct Cols {
+  u64 x[WG_MAXQ][WPT], z[WG_MAXQ][WPT];
+};
+
+template <int A, int WPT>
+__device__ __forceinline__ void op1(u32 t, Cols<WPT> &c, u64 (&s)[WPT]) {
 #pragma unroll
-        for (int k = 0; k < WPT; ++k) { s[k] ^= xa[k] & za[k]; const u64 t = xa[k]; xa[k] = za[k]; za[k] = t; }
-        break;
-      case UOP_S_A:
-#pragma unroll
-        for (int k = 0; k < WPT; ++k) { s[k] ^= xa[k] & za[k]; za[k] ^= xa[k]; }
-        break;
-      case UOP_SDG_A:
-#pragma unroll
-        for (int k = 0; k < WPT; ++k) { s[k] ^= xa[k] & ~za[k]; za[k] ^= xa[k]; }
-        break;
-      case UOP_X_A:
-#pragma unroll
-        for (int k = 0; k < WPT; ++k) s[k] ^= za[k];
-        break;
-      case UOP_Y_A:
-#pragma unroll
-        for (int k = 0; k < WPT; ++k) s[k] ^= xa[k] ^ za[k];
-        break;
-      case UOP_Z_A:
-#pragma unroll
-        for (int k = 0; k < WPT; ++k) s[k] ^= xa[k];
-        break;
-      case UOP_H_B:
-#pragma unroll
-        for (int k = 0; k < WPT; ++k) { s[k] ^= xb[k] & zb[k]; const u64 t = xb[k]; xb[k] = zb[k]; zb[k] = t; }
-        break;
-      case UOP_S_B:
-#pragma unroll
-        for (int k = 0; k < WPT; ++k) { s[k] ^= xb[k] & zb[k]; zb[k] ^= xb[k]; }
-        break;
-      case UOP_SDG_B:
-#pragma unroll
-        for (int k = 0; k < WPT; ++k) { s[k] ^= xb[k] & ~zb[k]; zb[k] ^= xb[k]; }
-        break;
-      case UOP_X_B:
-#pragma unroll
-        for (int k = 0; k < WPT; ++k) s[k] ^= zb[k];
-        break;
-      case UOP_Y_B:
-#pragma unroll
-        for (int k = 0; k < WPT; ++k) s[k] ^= xb[k] ^ zb[k];
-        break;
-      case UOP_Z_B:
-#pragma unroll
-        for (int k = 0; k < WPT; ++k) s[k] ^= xb[k];
-        break;
-      case UOP_CX_AB:
-#pragma unroll
-        for (int k = 0; k < WPT; ++k) { s[k] ^= xa[k] & zb[k] & ~(xb[k] ^ za[k]); xb[k] ^= xa[k]; za[k] ^= zb[k]; }
-        break;
-      case UOP_CX_BA:
-#pragma unroll
-        for (int k = 0; k < WPT; ++k) { s[k] ^= xb[k] & za[k] & ~(xa[k] ^ zb[k]); xa[k] ^= xb[k]; zb[k] ^= za[k]; }
-        break;
-      case UOP_CZ:
-#pragma unroll
-        for (int k = 0; k < WPT; ++k) { s[k] ^= xa[k] & xb[k] & (za[k] ^ zb[k]); const u64 ta = za[k] ^ xb[k]; zb[k] ^= xa[k]; za[k] = ta; }
-        break;
-      default:
-        break;
+  for (int k = 0; k < WPT; ++k) {
+    u64 &x = c.x[A][k], &z = c.z[A][k];
+    switch (t) {
+      case WOP_H: { s[k] ^= x & z; const u64 v = x; x = z; z = v; } break;
+      case WOP_S: s[k] ^= x & z; z ^= x; break;
+      case WOP_SDG: s[k] ^= x & ~z; z ^= x; break;
+      case WOP_X: s[k] ^= z; break;
+      case WOP_Y: s[k] ^= x ^ z; break;
+      default: s[k] ^= x; break;  // Z
     }
   }
 }
 
-template <int WPT, int B>
-__global__ __launch_bounds__(1024) void k_layer(u64 *__restrict__ X, u64 *__restrict__ Z, u64 *__restrict__ sign_part,
-                                                 const Group *__restrict__ groups, u32 ngroups, u32 gpc, u32 Ls, u32 L) {
+template <int A, int B, int WPT>
+__device__ __forceinline__ void op2(u32 t, Cols<WPT> &c, u64 (&s)[WPT]) {
+  if constexpr (A != B) {
+#pragma unroll
+    for (int k = 0; k < WPT; ++k) {
+      u64 &xa = c.x[A][k], &za = c.z[A][k], &xb = c.x[B][k], &zb = c.z[B][k];
+      if (t == WOP_CX) {
+        s[k] ^= xa & zb & ~(xb ^ za);
+        xb ^= xa;
+        za ^= zb;
+      } else {
+        s[k] ^= xa & xb & (za ^ zb);
+        const u64 ta = za ^ xb;
+        zb ^= xa;
+        za = ta;
+      }
+    }
+  }
+}
+
+template <int A, int WPT>
+__device__ __forceinline__ void op2_row(u32 t, u32 b, Cols<WPT> &c, u64 (&s)[WPT]) {
+  switch (b) {
+    case 0: op2<A, 0>(t, c, s); break;
+    case 1: op2<A, 1>(t, c, s); break;
+    case 2: op2<A, 2>(t, c, s); break;
+    case 3: op2<A, 3>(t, c, s); break;
+    case 4: op2<A, 4>(t, c, s); break;
+    case 5: op2<A, 5>(t, c, s); break;
+    case 6: op2<A, 6>(t, c, s); break;
+    default: op2<A, 7>(t, c, s); break;
+  }
+}
+
+template <int WPT>
+__device__ __forceinline__ void run_op(u32 op, Cols<WPT> &c, u64 (&s)[WPT]) {
+  static_assert(WG_MAXQ == 8, "the slot dispatch below covers 8 slots");
+  const u32 t = op & 15u, a = (op >> 4) & 15u, b = (op >> 8) & 15u;
+  if (t < WOP_CX) {
+    switch (a) {
+      case 0: op1<0>(t, c, s); break;
+      case 1: op1<1>(t, c, s); break;
+      case 2: op1<2>(t, c, s); break;
+      case 3: op1<3>(t, c, s); break;
+      case 4: op1<4>(t, c, s); break;
+      case 5: op1<5>(t, c, s); break;
+      case 6: op1<6>(t, c, s); break;
+      default: op1<7>(t, c, s); break;
+    }
+  } else {
+    switch (a) {
+      case 0: op2_row<0>(t, b, c, s); break;
+      case 1: op2_row<1>(t, b, c, s); break;
+      case 2: op2_row<2>(t, b, c, s); break;
+      case 3: op2_row<3>(t, b, c, s); break;
+      case 4: op2_row<4>(t, b, c, s); break;
+      case 5: op2_row<5>(t, b, c, s); break;
+      case 6: op2_row<6>(t, b, c, s); break;
+      default: op2_row<7>(t, b, c, s); break;
+    }
+  }
+}
+
+template <int WPT>
+__global__ __launch_bounds__(512) void k_layer(u64 *__restrict__ X, u64 *__restrict__ Z, u64 *__restrict__ sign_part,
+                                                const u32 *__restrict__ words, const u32 *__restrict__ offs,
+                                                u32 ngroups, u32 gpc, u32 Ls, u32 L) {
   const u32 w = (blockIdx.x * blockDim.x + threadIdx.x) * WPT;
   if (w >= L) return;
   const u32 g0 = blockIdx.y * gpc;
@@ -97,62 +114,28 @@ __global__ __launch_bounds__(1024) void k_layer(u64 *__restrict__ X, u64 *__rest
   u64 s[WPT];
 #pragma unroll
   for (int k = 0; k < WPT; ++k) s[k] = 0;
-
-  u32 g = g0;
-  for (; g + B <= g1; g += B) {
-    Group G[B];
-    u64 xa[B][WPT], za[B][WPT], xb[B][WPT], zb[B][WPT];
+  Cols<WPT> c;
+  for (u32 g = g0; g < g1; ++g) {
+    const u32 *rec = words + offs[g];
+    const u32 hdr = rec[0];
+    const u32 nq = hdr & 15u, nops = (hdr >> WH_NOPS_SHIFT) & 63u;
 #pragma unroll
-    for (int b = 0; b < B; ++b) G[b] = groups[g + b];
-#pragma unroll
-    for (int b = 0; b < B; ++b) {
-      const size_t ca = (size_t)(G[b].q0 & GQ_MASK) * Ls + w;
-      ldw<WPT>(X + ca, xa[b]);
-      ldw<WPT>(Z + ca, za[b]);
-      if (G[b].q1 != G_SINGLE) {
-        const size_t cb = (size_t)G[b].q1 * Ls + w;
-        ldw<WPT>(X + cb, xb[b]);
-        ldw<WPT>(Z + cb, zb[b]);
-      } else {
-#pragma unroll
-        for (int k = 0; k < WPT; ++k) { xb[b][k] = 0; zb[b][k] = 0; }
+    for (u32 i = 0; i < WG_MAXQ; ++i) {
+      if (i < nq) {
+        const size_t o = (size_t)rec[1 + i] * Ls + w;
+        ldw<WPT>(X + o, c.x[i]);
+        ldw<WPT>(Z + o, c.z[i]);
       }
     }
+    const u32 *ops = rec + 1 + nq;
+    for (u32 j = 0; j < nops; ++j) run_op<WPT>((ops[j >> 1] >> ((j & 1u) * 16u)) & 0xFFFFu, c, s);
 #pragma unroll
-    for (int b = 0; b < B; ++b) {
-      run_uops<WPT>(G[b].ops, xa[b], za[b], xb[b], zb[b], s);
-      const u32 f = G[b].q0;
-      const size_t ca = (size_t)(f & GQ_MASK) * Ls + w;
-      if (f & GD_XA) stw<WPT>(X + ca, xa[b]);
-      if (f & GD_ZA) stw<WPT>(Z + ca, za[b]);
-      if (G[b].q1 != G_SINGLE) {
-        const size_t cb = (size_t)G[b].q1 * Ls + w;
-        if (f & GD_XB) stw<WPT>(X + cb, xb[b]);
-        if (f & GD_ZB) stw<WPT>(Z + cb, zb[b]);
+    for (u32 i = 0; i < WG_MAXQ; ++i) {
+      if (i < nq) {
+        const size_t o = (size_t)rec[1 + i] * Ls + w;
+        if ((hdr >> (WH_DX_SHIFT + i)) & 1u) stw<WPT>(X + o, c.x[i]);
+        if ((hdr >> (WH_DZ_SHIFT + i)) & 1u) stw<WPT>(Z + o, c.z[i]);
       }
-    }
-  }
-  for (; g < g1; ++g) {
-    const Group G = groups[g];
-    u64 xa[WPT], za[WPT], xb[WPT], zb[WPT];
-    const size_t ca = (size_t)(G.q0 & GQ_MASK) * Ls + w;
-    ldw<WPT>(X + ca, xa);
-    ldw<WPT>(Z + ca, za);
-    const bool two = G.q1 != G_SINGLE;
-    const size_t cb = two ? (size_t)G.q1 * Ls + w : 0;
-    if (two) {
-      ldw<WPT>(X + cb, xb);
-      ldw<WPT>(Z + cb, zb);
-    } else {
-#pragma unroll
-      for (int k = 0; k < WPT; ++k) { xb[k] = 0; zb[k] = 0; }
-    }
-    run_uops<WPT>(G.ops, xa, za, xb, zb, s);
-    if (G.q0 & GD_XA) stw<WPT>(X + ca, xa);
-    if (G.q0 & GD_ZA) stw<WPT>(Z + ca, za);
-    if (two) {
-      if (G.q0 & GD_XB) stw<WPT>(X + cb, xb);
-      if (G.q0 & GD_ZB) stw<WPT>(Z + cb, zb);
     }
   }
   stw<WPT>(sign_part + (size_t)blockIdx.y * Ls + w, s);
@@ -167,15 +150,17 @@ __global__ void k_sign_reduce(u64 *__restrict__ R, const u64 *__restrict__ sign_
 }
 
 // Launchers.
-hipError_t launch_layer(const TabDev &t, const Group *groups, u32 ngroups, u32 block, u32 wpt, u32 gpc,
-                        u64 *sign_part, hipStream_t s) {
+hipError_t launch_layer(const TabDev &t, const u32 *words, const u32 *offs, u32 ngroups, u32 block, u32 wpt,
+                        u32 gpc, u64 *sign_part, hipStream_t s) {
   const u32 tiles = cdiv(t.L, (u64)block * wpt);
   const u32 chunks = cdiv(ngroups, gpc);
   dim3 grid(tiles, chunks);
   if (wpt == 2)
-    hipLaunchKernelGGL((k_layer<2, 4>), grid, dim3(block), 0, s, t.X, t.Z, sign_part, groups, ngroups, gpc, t.Ls, t.L);
+    hipLaunchKernelGGL((k_layer<2>), grid, dim3(block), 0, s, t.X, t.Z, sign_part, words, offs, ngroups, gpc, t.Ls,
+                       t.L);
   else
-    hipLaunchKernelGGL((k_layer<1, 4>), grid, dim3(block), 0, s, t.X, t.Z, sign_part, groups, ngroups, gpc, t.Ls, t.L);
+    hipLaunchKernelGGL((k_layer<1>), grid, dim3(block), 0, s, t.X, t.Z, sign_part, words, offs, ngroups, gpc, t.Ls,
+                       t.L);
   return hipGetLastError();
 }
 

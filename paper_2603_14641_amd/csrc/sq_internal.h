@@ -45,6 +45,18 @@ struct Group {
 };
 static_assert(sizeof(Group) == 16, "Group must be 16 bytes");
 
+// Wide gate groups (the tableau gate pass): up to WG_MAXQ qubits and
+// WG_MAXOPS micro-ops per group. A group is a record of u32 words:
+//   word 0: nq (bits 0..3) | nops (bits 4..9) | changed-x flags per slot
+//           (bits 16..23) | changed-z flags per slot (bits 24..31);
+//   words 1..nq: the qubit (column) of each slot;
+//   then the micro-ops, two 16-bit ops per word, low half first.
+// A micro-op is type (bits 0..3) | slot a (bits 4..7) | slot b (bits 8..11);
+// for CX a is the control and b the target.
+constexpr u32 WG_MAXQ = 8, WG_MAXOPS = 32;
+constexpr u32 WH_NOPS_SHIFT = 4, WH_DX_SHIFT = 16, WH_DZ_SHIFT = 24;
+enum : u32 { WOP_H = 1, WOP_S = 2, WOP_SDG = 3, WOP_X = 4, WOP_Y = 5, WOP_Z = 6, WOP_CX = 7, WOP_CZ = 8 };
+
 // Per-measurement device state (one per tableau, reused by every measurement).
 struct MeasState {
   int32_t p;      // pivot stabilizer index, -1 if the outcome is deterministic
@@ -144,8 +156,8 @@ struct LaunchTimer;  // host-side profiling hook (sq_runtime.hip)
 // launch status.
 hipError_t launch_fill_zero(u64 *p, size_t words, hipStream_t s);
 hipError_t launch_init_diag(const TabDev &t, hipStream_t s);
-hipError_t launch_layer(const TabDev &t, const Group *groups, u32 ngroups, u32 block, u32 wpt, u32 gpc,
-                        u64 *sign_part, hipStream_t s);
+hipError_t launch_layer(const TabDev &t, const u32 *words, const u32 *offs, u32 ngroups, u32 block, u32 wpt,
+                        u32 gpc, u64 *sign_part, hipStream_t s);
 hipError_t launch_sign_reduce(const TabDev &t, const u64 *sign_part, u32 nchunks, hipStream_t s);
 hipError_t launch_pivot(const TabDev &t, u32 q, MeasState *st, u64 *mask, u64 seed, u64 shot, u64 m,
                         uint8_t *out_bits, uint8_t *out_rand, hipStream_t s);

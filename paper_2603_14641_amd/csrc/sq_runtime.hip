@@ -13,6 +13,7 @@
 
 #include "../../include/sq.h"
 #include "sq_internal.h"
+#include "sq_plan.h"
 
 using namespace sq;
 
@@ -43,157 +44,6 @@ inline u32 cdiv(u64 a, u64 b) { return (u32)((a + b - 1) / b); }
 inline u32 round_up(u32 a, u32 b) { return (a + b - 1) / b * b; }
 
 bool is_gate(u32 t) { return t <= SQ_CZ; }
-bool is_two_qubit(u32 t) { return t == SQ_CX || t == SQ_CZ; }
-
-// ----------------------------------------------------------------------------
-// Gate-pass compiler: groups a program-order gate sequence into passes of
-// disjoint one- or two-qubit groups (each at most 16 micro-ops). A gate joins
-// the group that already holds its qubits; two single-qubit groups merge when
-// a CX/CZ links them; any other overlap closes the pass. Gates in different
-// groups of a pass act on different qubits and commute, so applying a pass
-// group by group equals applying its gates in program order.
-struct HGroup {
-  u32 qa, qb;
-  u64 ops;
-  u32 nops;
-  bool alive;
-};
-
-u32 dirty_flags(u64 ops) {
-  u32 f = 0;
-  for (; ops; ops >>= 4) {
-    switch ((u32)(ops & 15)) {
-      case UOP_H_A: f |= GD_XA | GD_ZA; break;
-      case UOP_S_A: case UOP_SDG_A: f |= GD_ZA; break;
-      case UOP_H_B: f |= GD_XB | GD_ZB; break;
-      case UOP_S_B: case UOP_SDG_B: f |= GD_ZB; break;
-      case UOP_CX_AB: f |= GD_XB | GD_ZA; break;
-      case UOP_CX_BA: f |= GD_XA | GD_ZB; break;
-      case UOP_CZ: f |= GD_ZA | GD_ZB; break;
-      default: break;
-    }
-  }
-  return f;
-}
-
-u32 one_qubit_uop(u32 type) {
-  switch (type) {
-    case SQ_H: return UOP_H_A;
-    case SQ_S: return UOP_S_A;
-    case SQ_SDG: return UOP_SDG_A;
-    case SQ_X: return UOP_X_A;
-    case SQ_Y: return UOP_Y_A;
-    default: return UOP_Z_A;
-  }
-}
-
-struct PassRange {
-  u64 offset;
-  u32 count;
-  u64 bytes;  // algorithmic bytes of the pass: column reads + changed-column writes
-};
-
-class PassBuilder {
- public:
-  std::vector<Group> groups;
-  std::vector<PassRange> passes;
-
-  void init(u32 n, u32 L) {
-    n_ = n;
-    L_ = L;
-    owner_.assign(n, -1);
-    epoch_of_.assign(n, 0);
-    epoch_ = 1;
-    groups.clear();
-    passes.clear();
-    cur_.clear();
-  }
-
-  void add(u32 type, u32 a, u32 b) {
-    if (type == SQ_I) return;
-    if (!is_two_qubit(type)) {
-      int g = find(a);
-      if (g >= 0 && cur_[g].nops >= 16) { flush(); g = -1; }
-      if (g < 0) g = open(a, G_SINGLE);
-      const u32 code = one_qubit_uop(type) + (cur_[g].qa == a ? 0u : 6u);
-      push(g, code);
-      return;
-    }
-    int ga = find(a), gb = find(b), g;
-    if (ga >= 0 && ga == gb) {
-      g = ga;
-      if (cur_[g].nops >= 16) { flush(); g = open(a, b); }
-    } else {
-      const bool pair_a = ga >= 0 && cur_[ga].qb != G_SINGLE;
-      const bool pair_b = gb >= 0 && cur_[gb].qb != G_SINGLE;
-      const u32 need = (ga >= 0 ? cur_[ga].nops : 0) + (gb >= 0 ? cur_[gb].nops : 0) + 1;
-      if (pair_a || pair_b || need > 16) { flush(); ga = gb = -1; }
-      if (ga < 0 && gb < 0) {
-        g = open(a, b);
-      } else if (gb < 0) {
-        g = ga;
-        cur_[g].qb = b;
-        bind(b, g);
-      } else if (ga < 0) {
-        g = gb;            // b stays slot A, a becomes slot B
-        cur_[g].qb = a;
-        bind(a, g);
-      } else {
-        g = ga;            // merge the single group of b into slot B of a's group
-        cur_[g].qb = b;
-        bind(b, g);
-        const u64 ob = cur_[gb].ops;
-        for (u32 k = 0; k < cur_[gb].nops; ++k) push(g, (u32)((ob >> (4 * k)) & 15) + 6u);
-        cur_[gb].alive = false;
-      }
-    }
-    const bool a_is_A = cur_[g].qa == a;
-    push(g, type == SQ_CZ ? UOP_CZ : (a_is_A ? UOP_CX_AB : UOP_CX_BA));
-  }
-
-  void flush() {
-    const u64 off = groups.size();
-    u64 bytes = 0;
-    for (const HGroup &h : cur_) {
-      if (!h.alive || h.nops == 0) continue;
-      const u32 f = dirty_flags(h.ops);
-      groups.push_back(Group{h.qa | f, h.qb, h.ops});
-      const u32 reads = (h.qb == G_SINGLE) ? 2 : 4;
-      const u32 writes = (u32)__builtin_popcount(f);
-      bytes += (u64)(reads + writes) * L_ * 8ULL;
-    }
-    const u32 cnt = (u32)(groups.size() - off);
-    if (cnt) passes.push_back(PassRange{off, cnt, bytes});
-    cur_.clear();
-    if (++epoch_ == 0) {
-      std::fill(epoch_of_.begin(), epoch_of_.end(), 0u);
-      epoch_ = 1;
-    }
-  }
-
- private:
-  u32 n_ = 0, L_ = 0, epoch_ = 1;
-  std::vector<int32_t> owner_;
-  std::vector<u32> epoch_of_;
-  std::vector<HGroup> cur_;
-
-  int find(u32 q) const { return epoch_of_[q] == epoch_ ? owner_[q] : -1; }
-  void bind(u32 q, int g) {
-    epoch_of_[q] = epoch_;
-    owner_[q] = g;
-  }
-  int open(u32 a, u32 b) {
-    cur_.push_back(HGroup{a, b, 0, 0, true});
-    const int g = (int)cur_.size() - 1;
-    bind(a, g);
-    if (b != G_SINGLE) bind(b, g);
-    return g;
-  }
-  void push(int g, u32 code) {
-    cur_[g].ops |= (u64)code << (4 * cur_[g].nops);
-    cur_[g].nops += 1;
-  }
-};
 
 sq_status validate_ops(u32 n, const sq_op *ops, u64 count, bool allow_measure) {
   if (count && !ops) return fail(SQ_EINVAL, "ops is NULL with count %llu", (unsigned long long)count);
@@ -245,10 +95,12 @@ struct sq_tableau {
   u32 *blk_k_host = nullptr;  // pinned: random-prefix length of the last block
   uint8_t *dev_out = nullptr;
   size_t dev_out_cap = 0;
-  Group *dev_groups = nullptr;
-  size_t dev_groups_cap = 0;
+  u32 *dev_words = nullptr;  // gate-pass records of the last sq_apply_gates call
+  size_t dev_words_cap = 0;
+  u32 *dev_offs = nullptr;
+  size_t dev_offs_cap = 0;
   sq_tuning tun{};
-  PassBuilder builder;
+  WideBuilder builder;
   // profiling
   bool prof = false;
   std::vector<std::pair<hipEvent_t, hipEvent_t>> pending[SQ_K_COUNT];
@@ -261,7 +113,8 @@ struct sq_program {
   int device = 0;
   u32 n = 0;
   Dims d{};
-  Group *dev_groups = nullptr;
+  u32 *dev_words = nullptr;  // gate-pass records and their offsets, device resident
+  u32 *dev_offs = nullptr;
   std::vector<PassRange> passes;
   struct Seg {
     int kind;  // 0 gate passes [first, first+count), 1 measurements [first, first+count)
@@ -405,15 +258,16 @@ sq_status collect_profile(sq_tableau *T) {
     if (s_ != SQ_OK) return s_;      \
   } while (0)
 
-sq_status run_passes(sq_tableau *T, const Group *dev_groups, const std::vector<PassRange> &passes, size_t first,
-                     size_t count) {
+sq_status run_passes(sq_tableau *T, const u32 *dev_words, const u32 *dev_offs, const std::vector<PassRange> &passes,
+                     size_t first, size_t count) {
   for (size_t i = first; i < first + count; ++i) {
     const PassRange &p = passes[i];
     const u32 gpc = layer_gpc(T, p.count);
     const u32 chunks = cdiv(p.count, gpc);
-    const Group *g = dev_groups + p.offset;
+    const u32 *offs = dev_offs + p.offset;
     SQ_TRY(timed(T, SQ_K_LAYER, [&] {
-      return launch_layer(T->t, g, p.count, T->tun.layer_block, T->tun.layer_wpt, gpc, T->sign_part, T->stream);
+      return launch_layer(T->t, dev_words, offs, p.count, T->tun.layer_block, T->tun.layer_wpt, gpc, T->sign_part,
+                          T->stream);
     }));
     SQ_TRY(timed(T, SQ_K_SIGNS, [&] { return launch_sign_reduce(T->t, T->sign_part, chunks, T->stream); }));
   }
@@ -490,6 +344,21 @@ sq_status measure_range(sq_tableau *T, const uint32_t *qubits, u64 i0, u64 i1, u
   return SQ_OK;
 }
 
+// Grow a stream-ordered u32 device buffer of the handle to hold `need` words.
+sq_status ensure_capacity(sq_tableau *T, u32 **buf, size_t *cap, size_t need) {
+  if (need <= *cap) return SQ_OK;
+  if (*buf) (void)hipFreeAsync(*buf, T->stream);
+  *buf = nullptr;
+  *cap = 0;
+  const size_t want = std::max<size_t>(need + need / 4, 4096);
+  if (hipMallocAsync((void **)buf, want * 4, T->stream) != hipSuccess) {
+    (void)hipGetLastError();
+    return fail(SQ_ENOMEM, "device allocation of %zu gate-pass words failed", want);
+  }
+  *cap = want;
+  return SQ_OK;
+}
+
 sq_status reset_device(sq_tableau *T) {
   size_t off[kLayoutSlots];
   const size_t words = layout_words(T->d, off);
@@ -499,9 +368,9 @@ sq_status reset_device(sq_tableau *T) {
 }
 
 sq_status check_tuning(const sq_tuning &t) {
-  auto ok_block = [](u32 b) { return b >= 64 && b <= 1024 && b % 64 == 0; };
-  if (!ok_block(t.layer_block) || !ok_block(t.rowsum_block))
-    return fail(SQ_EINVAL, "block sizes must be multiples of 64 in [64, 1024]");
+  auto ok_block = [](u32 b, u32 hi) { return b >= 64 && b <= hi && b % 64 == 0; };
+  if (!ok_block(t.layer_block, 512) || !ok_block(t.rowsum_block, 1024))
+    return fail(SQ_EINVAL, "block sizes must be multiples of 64 in [64, 512] (gate pass), [64, 1024] (rowsum)");
   if ((t.layer_wpt != 1 && t.layer_wpt != 2) || (t.rowsum_wpt != 1 && t.rowsum_wpt != 2))
     return fail(SQ_EINVAL, "words per thread must be 1 or 2");
   if (t.meas_block < 1 || t.meas_block > KB) return fail(SQ_EINVAL, "meas_block must be in [1, %u]", KB);
@@ -590,7 +459,8 @@ sq_status sq_destroy(sq_tableau *T) {
     }
   for (hipEvent_t e : T->pool) (void)hipEventDestroy(e);
   if (T->dev_out) (void)hipFreeAsync(T->dev_out, T->stream);
-  if (T->dev_groups) (void)hipFreeAsync(T->dev_groups, T->stream);
+  if (T->dev_words) (void)hipFreeAsync(T->dev_words, T->stream);
+  if (T->dev_offs) (void)hipFreeAsync(T->dev_offs, T->stream);
   (void)hipFreeAsync(T->base, T->stream);
   (void)hipStreamSynchronize(T->stream);
   (void)hipHostFree(T->blk_k_host);
@@ -615,25 +485,16 @@ sq_status sq_apply_gates(sq_tableau *T, const sq_op *ops, uint64_t count) {
   if (!T) return fail(SQ_EINVAL, "tableau is NULL");
   SQ_TRY(validate_ops(T->d.n, ops, count, false));
   if (count == 0) return SQ_OK;
-  PassBuilder &pb = T->builder;
+  WideBuilder &pb = T->builder;
   pb.init(T->d.n, T->d.L);
   for (u64 i = 0; i < count; ++i) pb.add(ops[i].type, ops[i].q0, ops[i].q1);
   pb.flush();
-  if (pb.groups.empty()) return SQ_OK;
-  if (pb.groups.size() > T->dev_groups_cap) {
-    if (T->dev_groups) (void)hipFreeAsync(T->dev_groups, T->stream);
-    T->dev_groups = nullptr;
-    T->dev_groups_cap = 0;
-    const size_t cap = std::max<size_t>(pb.groups.size(), 1024);
-    if (hipMallocAsync((void **)&T->dev_groups, cap * sizeof(Group), T->stream) != hipSuccess) {
-      (void)hipGetLastError();
-      return fail(SQ_ENOMEM, "device allocation of %zu gate groups failed", cap);
-    }
-    T->dev_groups_cap = cap;
-  }
-  HIP_TRY(hipMemcpyAsync(T->dev_groups, pb.groups.data(), pb.groups.size() * sizeof(Group), hipMemcpyHostToDevice,
-                         T->stream));
-  return run_passes(T, T->dev_groups, pb.passes, 0, pb.passes.size());
+  if (pb.offs.empty()) return SQ_OK;
+  SQ_TRY(ensure_capacity(T, &T->dev_words, &T->dev_words_cap, pb.words.size()));
+  SQ_TRY(ensure_capacity(T, &T->dev_offs, &T->dev_offs_cap, pb.offs.size()));
+  HIP_TRY(hipMemcpyAsync(T->dev_words, pb.words.data(), pb.words.size() * 4, hipMemcpyHostToDevice, T->stream));
+  HIP_TRY(hipMemcpyAsync(T->dev_offs, pb.offs.data(), pb.offs.size() * 4, hipMemcpyHostToDevice, T->stream));
+  return run_passes(T, T->dev_words, T->dev_offs, pb.passes, 0, pb.passes.size());
 }
 
 sq_status sq_measure(sq_tableau *T, const uint32_t *qubits, uint32_t count, uint64_t seed, uint64_t shot,
@@ -967,7 +828,7 @@ sq_status sq_program_create(uint32_t n, const sq_op *ops, uint64_t count, sq_pro
   (void)hipGetDevice(&P->device);
   P->n = n;
   P->d = dims_of(n);
-  PassBuilder pb;
+  WideBuilder pb;
   pb.init(n, P->d.L);
   u64 i = 0;
   while (i < count) {
@@ -989,17 +850,20 @@ sq_status sq_program_create(uint32_t n, const sq_op *ops, uint64_t count, sq_pro
   }
   P->passes = pb.passes;
   for (const PassRange &r : P->passes) P->gate_bytes += r.bytes;
-  if (!pb.groups.empty()) {
-    if (hipMalloc((void **)&P->dev_groups, pb.groups.size() * sizeof(Group)) != hipSuccess) {
+  if (!pb.offs.empty()) {
+    if (hipMalloc((void **)&P->dev_words, pb.words.size() * 4) != hipSuccess ||
+        hipMalloc((void **)&P->dev_offs, pb.offs.size() * 4) != hipSuccess) {
       (void)hipGetLastError();
+      (void)hipFree(P->dev_words);
       delete P;
-      return fail(SQ_ENOMEM, "device allocation of %zu gate groups failed", pb.groups.size());
+      return fail(SQ_ENOMEM, "device allocation of %zu gate-pass words failed", pb.words.size() + pb.offs.size());
     }
-    if (hipMemcpy(P->dev_groups, pb.groups.data(), pb.groups.size() * sizeof(Group), hipMemcpyHostToDevice) !=
-        hipSuccess) {
-      (void)hipFree(P->dev_groups);
+    if (hipMemcpy(P->dev_words, pb.words.data(), pb.words.size() * 4, hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(P->dev_offs, pb.offs.data(), pb.offs.size() * 4, hipMemcpyHostToDevice) != hipSuccess) {
+      (void)hipFree(P->dev_words);
+      (void)hipFree(P->dev_offs);
       delete P;
-      return fail(SQ_EDEVICE, "upload of gate groups failed");
+      return fail(SQ_EDEVICE, "upload of gate passes failed");
     }
   }
   *out = P;
@@ -1011,7 +875,7 @@ sq_status sq_plan_gates(uint32_t n, const sq_op *ops, uint64_t count, uint64_t *
   if (!out_len || (cap && !out)) return fail(SQ_EINVAL, "NULL argument");
   if (n == 0 || n > SQ_MAX_QUBITS) return fail(SQ_ERANGE, "bad n=%u", n);
   SQ_TRY(validate_ops(n, ops, count, false));
-  PassBuilder pb;
+  WideBuilder pb;
   pb.init(n, dims_of(n).L);
   for (u64 i = 0; i < count; ++i) pb.add(ops[i].type, ops[i].q0, ops[i].q1);
   pb.flush();
@@ -1023,10 +887,11 @@ sq_status sq_plan_gates(uint32_t n, const sq_op *ops, uint64_t count, uint64_t *
   for (const PassRange &r : pb.passes) {
     put(r.count);
     for (u32 g = 0; g < r.count; ++g) {
-      const Group &G = pb.groups[r.offset + g];
-      put(G.q0);
-      put(G.q1);
-      put(G.ops);
+      const u32 *rec = pb.words.data() + pb.offs[r.offset + g];
+      const u32 nq = rec[0] & 15u, nops = (rec[0] >> WH_NOPS_SHIFT) & 63u;
+      put(rec[0]);
+      for (u32 q = 0; q < nq; ++q) put(rec[1 + q]);
+      for (u32 j = 0; j < nops; ++j) put((rec[1 + nq + j / 2] >> ((j & 1u) * 16u)) & 0xFFFFu);
     }
   }
   *out_len = k;
@@ -1035,7 +900,8 @@ sq_status sq_plan_gates(uint32_t n, const sq_op *ops, uint64_t count, uint64_t *
 
 sq_status sq_program_destroy(sq_program *P) {
   if (!P) return SQ_OK;
-  (void)hipFree(P->dev_groups);
+  (void)hipFree(P->dev_words);
+  (void)hipFree(P->dev_offs);
   delete P;
   return SQ_OK;
 }
@@ -1067,7 +933,7 @@ sq_status sq_run(sq_tableau *T, const sq_program *P, uint64_t seed, uint64_t sho
   }
   for (const sq_program::Seg &s : P->segs) {
     if (s.kind == 0) {
-      SQ_TRY(run_passes(T, P->dev_groups, P->passes, s.first, s.count));
+      SQ_TRY(run_passes(T, P->dev_words, P->dev_offs, P->passes, s.first, s.count));
     } else {
       SQ_TRY(measure_range(T, P->meas_qubits.data(), s.first, s.first + s.count, seed, shot, meas_base,
                            dev_out_bits, rand_base));

@@ -56,7 +56,8 @@ def test_version_and_last_error():
 
 
 # ---------------------------------------------------------------- pass compiler
-UOP_1Q = {1: orc.H, 2: orc.S, 3: orc.SDG, 4: orc.X, 5: orc.Y, 6: orc.Z}
+WOP_1Q = {1: orc.H, 2: orc.S, 3: orc.SDG, 4: orc.X, 5: orc.Y, 6: orc.Z}
+MAXQ, MAXOPS = 8, 32
 
 
 def plan_to_gates(plan):
@@ -64,35 +65,49 @@ def plan_to_gates(plan):
     gates = []
     for groups in plan:
         qubits = []
-        for q0w, q1, ops in groups:
-            a = q0w & 0xFFFFFF
-            qubits.append(a)
-            if q1 != 0xFFFFFFFF:
-                qubits.append(q1)
-            while ops:
-                c = ops & 15
-                ops >>= 4
-                if c <= 6:
-                    gates.append([UOP_1Q[c], a, 0])
-                elif c <= 12:
-                    gates.append([UOP_1Q[c - 6], q1, 0])
-                elif c == 13:
-                    gates.append([orc.CX, a, q1])
-                elif c == 14:
-                    gates.append([orc.CX, q1, a])
+        for hdr, qs, uops in groups:
+            qubits += qs
+            for u in uops:
+                t, a, b = u & 15, (u >> 4) & 15, (u >> 8) & 15
+                if t in WOP_1Q:
+                    gates.append([WOP_1Q[t], qs[a], 0])
                 else:
-                    gates.append([orc.CZ, a, q1])
+                    assert a != b
+                    gates.append([orc.CX if t == 7 else orc.CZ, qs[a], qs[b]])
         assert len(set(qubits)) == len(qubits), "groups of a pass must be disjoint"
     return np.array(gates, dtype=np.uint32).reshape(-1, 3)
 
 
-def changed_flags(ops):
-    f = 0
-    while ops:
-        c = ops & 15
-        ops >>= 4
-        f |= {1: 3, 2: 2, 3: 2, 7: 12, 8: 8, 9: 8, 13: 6, 14: 9, 15: 10}.get(c, 0)
-    return f
+def changed_flags(qs, uops):
+    """x and z change flags per slot, from the gate rules: H changes both, S/S^dagger z,
+    CX(c, t) x_t and z_c, CZ both z; X/Y/Z only signs."""
+    dx = dz = 0
+    for u in uops:
+        t, a, b = u & 15, (u >> 4) & 15, (u >> 8) & 15
+        if t == 1:
+            dx |= 1 << a
+            dz |= 1 << a
+        elif t in (2, 3):
+            dz |= 1 << a
+        elif t == 7:
+            dx |= 1 << b
+            dz |= 1 << a
+        elif t == 8:
+            dz |= (1 << a) | (1 << b)
+    return (dx << 16) | (dz << 24)
+
+
+def check_group(hdr, qs, uops):
+    assert 1 <= len(qs) <= MAXQ and 1 <= len(uops) <= MAXOPS
+    assert (hdr & 15) == len(qs) and ((hdr >> 4) & 63) == len(uops)
+    assert (hdr & 0xFFFF0000) == changed_flags(qs, uops)
+    assert len(set(qs)) == len(qs)
+    used = set()
+    for u in uops:
+        used.add((u >> 4) & 15)
+        if (u & 15) >= 7:
+            used.add((u >> 8) & 15)
+    assert used == set(range(len(qs))), "every slot is used and no other"
 
 
 def random_gates(rng, n, count):
@@ -120,8 +135,8 @@ def test_pass_plan_equals_program_order(n, count):
         gates = random_gates(rng, n, count)
         plan = sqb.plan_gates(n, gates)
         for groups in plan:
-            for q0w, q1, ops in groups:
-                assert (q0w >> 24) == changed_flags(ops)
+            for g in groups:
+                check_group(*g)
         flat = plan_to_gates(plan)
         want = tableau_after(n, gates)
         got = tableau_after(n, flat)
@@ -129,22 +144,49 @@ def test_pass_plan_equals_program_order(n, count):
             assert np.array_equal(u, v)
 
 
-def test_plan_of_generator_layer_is_one_pass_per_layer():
-    cfg = workload.CONFIGS[2]
-    ops = workload.circuit_ops(cfg, depth=3, final_measure=False)
+def test_plan_of_generator_layers_spans_several_layers_per_pass():
+    """Groups keep absorbing later layers on their qubits, so a pass covers
+    more than one generator layer and streams fewer columns than one per
+    qubit and layer."""
+    depth = 20
+    cfg = workload.circuits.CircuitConfig("gen4096", 4096, depth, 1, cz=True, mid_measure=False)
+    ops = workload.circuit_ops(cfg, final_measure=False)
     plan = sqb.plan_gates(cfg.n, ops)
-    assert len(plan) == 3
+    assert len(plan) < 0.6 * depth
+    cols = 0
+    for groups in plan:
+        for g in groups:
+            check_group(*g)
+            cols += len(g[1])
+    assert cols < 0.5 * cfg.n * depth
     gates = ops[ops["type"] != workload.GATE_I]
     flat = plan_to_gates(plan)
     assert flat.shape[0] == gates.shape[0]
 
 
 def test_plan_long_single_qubit_runs_split():
-    # 40 gates on one qubit need three groups of at most 16 micro-ops
+    # 40 gates on one qubit need two groups of at most 32 micro-ops
     gates = np.array([[orc.S, 0, 0]] * 40, dtype=np.uint32)
     plan = sqb.plan_gates(1, gates)
-    assert [len(p) for p in plan] == [1, 1, 1]
+    assert [len(p) for p in plan] == [1, 1]
+    assert [len(p[0][2]) for p in plan] == [32, 8]
     assert plan_to_gates(plan).shape[0] == 40
+
+
+def test_plan_cx_chain_caps_group_size():
+    """A CX chain links every qubit: groups stop at 8 qubits and the rest
+    moves to later passes, in order."""
+    n = 30
+    gates = np.array([[orc.CX, q, q + 1] for q in range(n - 1)], dtype=np.uint32)
+    plan = sqb.plan_gates(n, gates)
+    assert len(plan) > 1
+    for groups in plan:
+        for g in groups:
+            check_group(*g)
+    want = tableau_after(n, gates)
+    got = tableau_after(n, plan_to_gates(plan))
+    for u, v in zip(want, got):
+        assert np.array_equal(u, v)
 
 
 @pytest.mark.parametrize("bad,status", [
