@@ -61,8 +61,11 @@ typedef enum {
 /* Operation type codes. Gate records and programs use the same codes. */
 typedef enum {
   SQ_I = 0, SQ_H = 1, SQ_S = 2, SQ_SDG = 3, SQ_X = 4, SQ_Y = 5, SQ_Z = 6,
-  SQ_CX = 7, /* q0 = control, q1 = target */
+  SQ_CX = 7,    /* q0 = control, q1 = target */
   SQ_CZ = 8,
+  SQ_CY = 9,    /* controlled-Y, q0 = control, q1 = target */
+  SQ_SWAP = 10,
+  SQ_ISWAP = 11,
   SQ_MEASURE = 15 /* Z measurement of q0 (programs only) */
 } sq_op_type;
 
@@ -189,8 +192,10 @@ uint64_t sq_program_num_passes(const sq_program *p);
  * (bits 0..3 qubit count nq, bits 4..9 micro-op count m, bits 16..23 and
  * 24..31 per-slot flags of the x and z columns the group changes), nq words
  * with the qubit of each slot, and m words with one micro-op each: bits 0..3
- * the gate (1 H, 2 S, 3 S^dagger, 4 X, 5 Y, 6 Z, 7 CX, 8 CZ), bits 4..7 its
- * (control) slot, bits 8..11 the target slot of CX / second slot of CZ.
+ * the gate (1 H, 2 S, 3 S^dagger, 4 X, 5 Y, 6 Z, 7 CX, 8 CZ, 9 SWAP), bits
+ * 4..7 its (control) slot, bits 8..11 the target slot of CX / other slot of
+ * CZ and SWAP. CY and iSWAP appear as their products (S^dagger, CX, S and
+ * S, S, CZ, SWAP).
  * *out_len receives the number of words needed; nothing is written past cap.
  * Errors as sq_apply_gates. */
 sq_status sq_plan_gates(uint32_t n, const sq_op *host_ops, uint64_t count, uint64_t *out, uint64_t cap,

@@ -28,7 +28,7 @@
 
 enum {
   SQO_I = 0, SQO_H = 1, SQO_S = 2, SQO_SDG = 3, SQO_X = 4, SQO_Y = 5, SQO_Z = 6,
-  SQO_CX = 7, SQO_CZ = 8, SQO_MEASURE = 15
+  SQO_CX = 7, SQO_CZ = 8, SQO_CY = 9, SQO_SWAP = 10, SQO_ISWAP = 11, SQO_MEASURE = 15
 };
 
 typedef struct {
@@ -91,8 +91,25 @@ static inline void putb(uint64_t *v, uint32_t j, int b) {
  * the values before the gate. H, S and CX are the rules printed in the
  * "Tableau Formalism" section; the others follow by conjugation:
  * S^dagger = S^3, X P X flips the sign of Z and Y, Z P Z flips X and Y,
- * Y P Y flips X and Z, and CZ(a,b) = H_b CX(a,b) H_b. */
+ * Y P Y flips X and Z, and CZ(a,b) = H_b CX(a,b) H_b. The remaining gates of
+ * the paper's gate set are products of these, conjugated factor by factor in
+ * time order: CY(a,b) = S_b CX(a,b) S_b^dagger (S^dagger first),
+ * iSWAP(a,b) = SWAP CZ (S_a S_b) (the S gates first); SWAP exchanges the two
+ * qubits' bits and leaves the sign. */
 static void gate_on_row(uint64_t *x, uint64_t *z, uint8_t *r, uint32_t type, uint32_t a, uint32_t b) {
+  if (type == SQO_CY) {
+    gate_on_row(x, z, r, SQO_SDG, b, 0);
+    gate_on_row(x, z, r, SQO_CX, a, b);
+    gate_on_row(x, z, r, SQO_S, b, 0);
+    return;
+  }
+  if (type == SQO_ISWAP) {
+    gate_on_row(x, z, r, SQO_S, a, 0);
+    gate_on_row(x, z, r, SQO_S, b, 0);
+    gate_on_row(x, z, r, SQO_CZ, a, b);
+    gate_on_row(x, z, r, SQO_SWAP, a, b);
+    return;
+  }
   int xa = getb(x, a), za = getb(z, a);
   switch (type) {
     case SQO_H:
@@ -129,6 +146,14 @@ static void gate_on_row(uint64_t *x, uint64_t *z, uint8_t *r, uint32_t type, uin
       *r ^= (uint8_t)(xa & xb & (za ^ zb));
       putb(z, a, za ^ xb);
       putb(z, b, zb ^ xa);
+      break;
+    }
+    case SQO_SWAP: {
+      int xb = getb(x, b), zb = getb(z, b);
+      putb(x, a, xb);
+      putb(z, a, zb);
+      putb(x, b, xa);
+      putb(z, b, za);
       break;
     }
     default:

@@ -19,7 +19,8 @@ _SRC = os.path.join(_HERE, "chp_oracle.c")
 _LIB = os.path.join(_HERE, "libsq_oracle.so")
 
 # Operation type codes (records of three uint32: type, q0, q1).
-I, H, S, SDG, X, Y, Z, CX, CZ, MEASURE = 0, 1, 2, 3, 4, 5, 6, 7, 8, 15
+I, H, S, SDG, X, Y, Z, CX, CZ, CY, SWAP, ISWAP, MEASURE = 0, 1, 2, 3, 4, 5, 6, 7, 8, 9, 10, 11, 15
+TWO_QUBIT = (CX, CZ, CY, SWAP, ISWAP)
 
 
 def build_oracle(src: str = _SRC, out: str = _LIB, extra_flags: Sequence[str] = ()) -> str:

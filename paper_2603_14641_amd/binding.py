@@ -17,7 +17,7 @@ LIB_PATH = os.path.join(_PKG, "libsq.so")
 
 # status codes and op types (include/sq.h)
 SQ_OK, SQ_EINVAL, SQ_ENOMEM, SQ_EDEVICE, SQ_ERANGE, SQ_ESTATE = 0, -1, -2, -3, -5, -6
-I, H, S, SDG, X, Y, Z, CX, CZ, MEASURE = 0, 1, 2, 3, 4, 5, 6, 7, 8, 15
+I, H, S, SDG, X, Y, Z, CX, CZ, CY, SWAP, ISWAP, MEASURE = 0, 1, 2, 3, 4, 5, 6, 7, 8, 9, 10, 11, 15
 K_LAYER, K_SIGNS, K_PIVOT, K_GATHER, K_ROWSUM, K_POST, K_BPIVOT, K_BPREP, K_BPASS, K_BFINAL = range(10)
 KERNEL_NAMES = ["layer", "signs", "pivot", "gather", "rowsum", "post",
                 "block_pivot", "block_prep", "block_pass", "block_final"]

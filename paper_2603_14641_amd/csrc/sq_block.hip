@@ -31,100 +31,167 @@ __global__ void k_blk_snap(const u64 *__restrict__ X, u32 Ls, u32 L, BlkArgs a, 
   snap[(size_t)s * Ls + w] = X[(size_t)a.q[s] * Ls + w];
 }
 
-// -------------------------------------------------------------- pivots (one workgroup)
-__global__ __launch_bounds__(1024) void k_blk_pivots(const u64 *__restrict__ snap, u64 *__restrict__ bm, u32 Ls,
-                                                      u32 K, BlkArgs a, BlkState *__restrict__ bs,
-                                                      uint8_t *__restrict__ out_bits, uint8_t *__restrict__ out_rand) {
-  __shared__ u32 s_min, s_k;
-  const u32 tid = threadIdx.x, T = blockDim.x, L = 2 * K;
-  if (tid == 0) s_k = a.k;
-  for (u32 s = 0; s < a.k; ++s) {
-    // column q_s as it stands before measurement s
-    for (u32 w = tid; w < L; w += T) {
-      u64 v = snap[(size_t)s * Ls + w];
-      for (u32 sp = 0; sp < s; ++sp)
-        if ((bs->M[sp] >> s) & 1u) v ^= bm[(size_t)sp * Ls + w];
-      for (u32 sp = 0; sp < s; ++sp)
-        if (w == K + (bs->p[sp] >> 6)) v &= ~(1ULL << (bs->p[sp] & 63u));  // S_{p_s'} is now Z
-      bm[(size_t)s * Ls + w] = v;
+// -------------------------------------------------------------- pivots (one wave)
+// Sequential over the measurements of the block, but only the pivot search
+// is: lane l owns stabilizer word 64t + l of tile t, so a lane only ever
+// reads words it wrote itself and the wave needs no barrier. For step s the
+// stabilizer half of column q_s as it stands before measurement s is
+//   snap_s ^ XOR_{s' < s, M[s'][s] = 1} (hit mask of s'),
+// with the rows S_{p_s'} (now Z_{q_s'}, no x) cleared; tiles are computed
+// lazily, in order, for every earlier step first. A block ends before its
+// first deterministic measurement (no stabilizer word is nonzero).
+__global__ __launch_bounds__(64) void k_blk_pivots(const u64 *__restrict__ snap, u64 *__restrict__ bm, u32 Ls,
+                                                    u32 K, BlkArgs a, BlkState *__restrict__ bs,
+                                                    uint8_t *__restrict__ out_bits, uint8_t *__restrict__ out_rand) {
+  const u32 lane = threadIdx.x;
+  const u32 ntiles = (K + 63u) / 64u;
+  u32 done[KB];   // tiles computed per step (uniform)
+  u32 piv[KB];    // pivot of each decided step
+  u32 mrow[KB];   // M[s]: bit s2 = x of P_s at q_{s2}
+#pragma unroll
+  for (u32 s = 0; s < KB; ++s) { done[s] = 0; piv[s] = 0; mrow[s] = 0; }
+  // stabilizer word w of step s (w = 64 * tile + lane), stored in bm's S half
+  auto tile_word = [&](u32 s, u32 t) -> u64 {
+    const u32 w = t * 64u + lane;
+    if (w >= K) return 0ULL;
+    u64 v = snap[(size_t)s * Ls + K + w];
+    for (u32 sp = 0; sp < s; ++sp) {
+      if ((mrow[sp] >> s) & 1u) v ^= bm[(size_t)sp * Ls + K + w];
+      if ((piv[sp] >> 6) == w) v &= ~(1ULL << (piv[sp] & 63u));  // S_{p_s'} is Z now
     }
-    if (tid == 0) s_min = 0xFFFFFFFFu;
-    __syncthreads();
-    u32 first = 0xFFFFFFFFu;
-    for (u32 w = tid; w < K; w += T)
-      if (bm[(size_t)s * Ls + K + w] != 0) { first = w; break; }
-    for (int off = 32; off > 0; off >>= 1) first = min(first, (u32)__shfl_xor((int)first, off));
-    if ((tid & 63u) == 0 && first != 0xFFFFFFFFu) atomicMin(&s_min, first);
-    __syncthreads();
-    const u32 wmin = s_min;
+    return v;
+  };
+  u32 k = a.k;
+  for (u32 s = 0; s < a.k; ++s) {
+    u32 wmin = 0xFFFFFFFFu;
+    u64 vmin = 0;
+    for (u32 t = 0; t < ntiles; ++t) {
+      // earlier steps first (their pivots are known, so their own bits are cleared too)
+      for (u32 sp = 0; sp < s; ++sp) {
+        while (done[sp] <= t) {
+          const u32 tt = done[sp];
+          u64 v = tile_word(sp, tt);
+          const u32 w = tt * 64u + lane;
+          if ((piv[sp] >> 6) == w) v &= ~(1ULL << (piv[sp] & 63u));
+          if (w < K) bm[(size_t)sp * Ls + K + w] = v;
+          done[sp] = tt + 1;
+        }
+      }
+      const u64 v = tile_word(s, t);
+      const u32 w = t * 64u + lane;
+      if (w < K) bm[(size_t)s * Ls + K + w] = v;
+      done[s] = t + 1;
+      const u64 nz = __ballot(v != 0);
+      if (nz) {
+        const u32 l = (u32)__builtin_ctzll(nz);
+        wmin = t * 64u + l;
+        vmin = __shfl(v, (int)l);
+        break;
+      }
+    }
     if (wmin == 0xFFFFFFFFu) {  // deterministic: the block ends here
-      if (tid == 0) s_k = s;
-      __syncthreads();
+      k = s;
       break;
     }
-    if (tid == 0) {
-      const u32 p = wmin * 64u + (u32)__builtin_ctzll(bm[(size_t)s * Ls + K + wmin]);
-      const u32 wd = p >> 6;
-      const u64 bit = 1ULL << (p & 63u);
-      bs->p[s] = p;
-      // earlier pivots that hit S_p (its bits in their masks, before the clean-up below)
-      u32 hit = 0;
+    const u32 p = wmin * 64u + (u32)__builtin_ctzll(vmin);
+    const u32 pl = wmin & 63u;
+    const u64 bit = 1ULL << (p & 63u);
+    // earlier pivots that hit S_p (lane pl holds word wmin of every earlier step)
+    u32 hit = 0;
+    for (u32 sp = 0; sp < s; ++sp) {
+      const u64 b = lane == pl ? bm[(size_t)sp * Ls + K + wmin] : 0ULL;
+      if (__ballot((b & bit) != 0)) hit |= 1u << sp;
+    }
+    // x bits of P_s at the later measured columns, one lane per later step
+    u32 mine = 0;
+    if (lane > s && lane < a.k) {
+      u32 v = (u32)(snap[(size_t)lane * Ls + K + wmin] >> (p & 63u)) & 1u;
       for (u32 sp = 0; sp < s; ++sp)
-        if (bm[(size_t)sp * Ls + K + wd] & bit) hit |= 1u << sp;
+        if ((hit >> sp) & 1u) v ^= (mrow[sp] >> lane) & 1u;
+      mine = v;
+    }
+    const u64 mb = __ballot(mine != 0);
+    piv[s] = p;
+    mrow[s] = (u32)mb;
+    // S_p itself is not multiplied by P_s
+    if (lane == pl) bm[(size_t)s * Ls + K + wmin] = vmin & ~bit;
+    if (lane == 0) {
+      bs->p[s] = p;
       bs->hitS[s] = hit;
-      // x bits of P_s at the later measured columns
-      u32 mrow = 0;
-      for (u32 s2 = s + 1; s2 < a.k; ++s2) {
-        u32 v = (u32)(snap[(size_t)s2 * Ls + K + wd] >> (p & 63u)) & 1u;
-        for (u32 sp = 0; sp < s; ++sp)
-          if ((hit >> sp) & 1u) v ^= (bs->M[sp] >> s2) & 1u;
-        mrow |= v << s2;
-      }
-      bs->M[s] = mrow;
-      // D_p and S_p are not multiplied by P_s
-      bm[(size_t)s * Ls + wd] &= ~bit;
-      bm[(size_t)s * Ls + K + wd] &= ~bit;
+      bs->M[s] = (u32)mb;
       const u32 c = coin_bit(a.seed, a.shot, a.m0 + s);
       bs->coin[s] = c;
       out_rand[s] = 1;
       out_bits[s] = (uint8_t)c;
     }
-    __syncthreads();
   }
-  __syncthreads();
-  const u32 k = s_k;
-  // special rows (D_p, S_p of every pivot of the block) take no part in the
-  // pass; one thread per mask, since pivots can share a word
-  for (u32 s = tid; s < k; s += T) {
-    for (u32 t = 0; t < k; ++t) {
-      const u32 p = bs->p[t];
-      const u64 bit = 1ULL << (p & 63u);
-      bm[(size_t)s * Ls + (p >> 6)] &= ~bit;
-      bm[(size_t)s * Ls + K + (p >> 6)] &= ~bit;
+  if (lane != 0) return;
+  bs->k = k;
+  // later pivots that hit D_{p_s} (which holds P_s from measurement s on)
+  for (u32 s = 0; s < k; ++s) {
+    u32 hits = 0;
+    for (u32 s2 = s + 1; s2 < k; ++s2) {
+      u32 v = (mrow[s] >> s2) & 1u;
+      for (u32 s3 = s + 1; s3 < s2; ++s3)
+        if ((hits >> s3) & 1u) v ^= (mrow[s3] >> s2) & 1u;
+      hits |= v << s2;
+    }
+    bs->dhits[s] = hits;
+  }
+  for (u32 s = 0; s < KB; ++s) {
+    bs->Qz[s] = 0;
+    bs->R0[s] = 0;
+    bs->pc0[s] = 0;
+    bs->pcD[s] = 0;
+  }
+  bs->ncols = 0;
+  bs->done = 0;
+  // group the pivots by row word (pivots of a block usually share one or two)
+  u32 nw = 0;
+  for (u32 s = 0; s < k; ++s) {
+    const u32 wd = piv[s] >> 6;
+    u32 i = 0;
+    while (i < nw && bs->word[i] != wd) ++i;
+    if (i == nw) {
+      bs->word[nw] = wd;
+      bs->wmem[nw] = 0;
+      ++nw;
+    }
+    bs->wmem[i] |= 1u << s;
+  }
+  bs->nwords = nw;
+}
+
+// -------------------------------------------------------------- hit masks
+// Thread per row word: bit h of mask s says pivot s multiplies row h. For
+// every row outside the special ones the recurrence
+//   b_s = a_s ^ XOR_{s' < s} b_{s'} M[s'][s]
+// holds; the special rows (D_p and S_p of every pivot) take no part in the
+// pass and are cleared.
+__global__ void k_blk_masks(const u64 *__restrict__ snap, u64 *__restrict__ bm, const BlkState *__restrict__ bs,
+                            u32 Ls, u32 L, u32 K) {
+  const u32 k = bs->k;
+  const u32 w = blockIdx.x * blockDim.x + threadIdx.x;
+  if (w >= L || k == 0) return;
+  u64 special = 0;
+  const u32 hw = w < K ? w : w - K;
+  for (u32 t = 0; t < k; ++t)
+    if ((bs->p[t] >> 6) == hw) special |= 1ULL << (bs->p[t] & 63u);
+  u64 b[KB];
+#pragma unroll
+  for (u32 s = 0; s < KB; ++s) {
+    b[s] = 0;
+    if (s < k) {
+      u64 v = snap[(size_t)s * Ls + w];
+#pragma unroll
+      for (u32 sp = 0; sp < KB; ++sp)
+        if (sp < s && ((bs->M[sp] >> s) & 1u)) v ^= b[sp];
+      b[s] = v;
     }
   }
-  if (tid == 0) {
-    bs->k = k;
-    // later pivots that hit D_{p_s} (which holds P_s from measurement s on)
-    for (u32 s = 0; s < k; ++s) {
-      u32 hits = 0;
-      for (u32 s2 = s + 1; s2 < k; ++s2) {
-        u32 v = (bs->M[s] >> s2) & 1u;
-        for (u32 s3 = s + 1; s3 < s2; ++s3)
-          if ((hits >> s3) & 1u) v ^= (bs->M[s3] >> s2) & 1u;
-        hits |= v << s2;
-      }
-      bs->dhits[s] = hits;
-    }
-    for (u32 s = 0; s < KB; ++s) {
-      bs->Qz[s] = 0;
-      bs->R0[s] = 0;
-      bs->pc0[s] = 0;
-      bs->pcD[s] = 0;
-    }
-    bs->ncols = 0;
-    bs->done = 0;
-  }
+#pragma unroll
+  for (u32 s = 0; s < KB; ++s)
+    if (s < k) bm[(size_t)s * Ls + w] = b[s] & ~special;
 }
 
 // -------------------------------------------------------------- original pivot rows
@@ -409,20 +476,29 @@ __global__ void k_blk_final(u64 *__restrict__ X, u64 *__restrict__ Z, u64 *__res
     }
   }
   if (t < n) {
+    // column t of the special rows, one read-modify-write per distinct word:
+    // D_{p_s} = P_s times its later hits, S_{p_s} = Z_{q_s}
     const u32 j = t;
     const u32 px = patx[j], pz = patz[j];
     u64 *x = X + (size_t)j * Ls;
     u64 *z = Z + (size_t)j * Ls;
-    for (u32 s = 0; s < k; ++s) {
-      const u32 p = bs->p[s];
-      const u64 bit = 1ULL << (p & 63u);
-      const u32 dh = bs->dhits[s] | (1u << s);
-      const u32 xb = (u32)__popc(px & dh) & 1u, zb = (u32)__popc(pz & dh) & 1u;
-      const u32 wd = p >> 6, ws = K + wd;
-      x[wd] = (x[wd] & ~bit) | (xb ? bit : 0ULL);
-      z[wd] = (z[wd] & ~bit) | (zb ? bit : 0ULL);
-      x[ws] &= ~bit;
-      z[ws] = (z[ws] & ~bit) | ((j == a.q[s]) ? bit : 0ULL);
+    const u32 nw = bs->nwords;
+    for (u32 i = 0; i < nw; ++i) {
+      const u32 wd = bs->word[i], mem = bs->wmem[i];
+      u64 mask = 0, xd = 0, zd = 0, zs = 0;
+      for (u32 m = mem; m; m &= m - 1) {
+        const u32 s = (u32)__builtin_ctz(m);
+        const u64 bit = 1ULL << (bs->p[s] & 63u);
+        const u32 dh = bs->dhits[s] | (1u << s);
+        mask |= bit;
+        if (__popc(px & dh) & 1) xd |= bit;
+        if (__popc(pz & dh) & 1) zd |= bit;
+        if (j == a.q[s]) zs |= bit;
+      }
+      x[wd] = (x[wd] & ~mask) | xd;
+      z[wd] = (z[wd] & ~mask) | zd;
+      x[K + wd] &= ~mask;
+      z[K + wd] = (z[K + wd] & ~mask) | zs;
     }
   }
 }
@@ -452,13 +528,14 @@ __global__ void k_blk_bytes(const u64 *__restrict__ bm, const BlkState *__restri
 hipError_t launch_blk_pivots(const TabDev &t, const BlkArgs &a, const BlkBuffers &b, uint8_t *out_bits,
                              uint8_t *out_rand, hipStream_t s) {
   hipLaunchKernelGGL(k_blk_snap, dim3(cdiv(t.L, 256), a.k), dim3(256), 0, s, t.X, t.Ls, t.L, a, b.snap);
-  hipLaunchKernelGGL(k_blk_pivots, dim3(1), dim3(1024), 0, s, b.snap, b.bm, t.Ls, t.K, a, b.bs, out_bits, out_rand);
+  hipLaunchKernelGGL(k_blk_pivots, dim3(1), dim3(64), 0, s, b.snap, b.bm, t.Ls, t.K, a, b.bs, out_bits, out_rand);
   return hipGetLastError();
 }
 
 // Stage 1: pivot rows, their algebra and the byte count.
 hipError_t launch_blk_prep(const TabDev &t, const BlkArgs &a, const BlkBuffers &b, MeasState *st, MeasStats *stats,
                            hipStream_t s) {
+  hipLaunchKernelGGL(k_blk_masks, dim3(cdiv(t.L, 256)), dim3(256), 0, s, b.snap, b.bm, b.bs, t.Ls, t.L, t.K);
   hipLaunchKernelGGL(k_blk_gather, dim3(cdiv(t.n, 256), a.k), dim3(256), 0, s, t.X, t.Z, t.R, t.Ls, t.K, t.n, b.bs,
                      b.p0x, b.p0z);
   hipLaunchKernelGGL(k_blk_pivalg, dim3(cdiv(t.K, 256)), dim3(256), 0, s, b.p0x, b.p0z, b.px, b.pz, b.patx, b.patz,

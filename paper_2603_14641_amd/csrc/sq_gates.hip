@@ -13,6 +13,8 @@ namespace sq {
 //   X:   r ^= z     Y: r ^= x^z     Z: r ^= x
 //   CX(c,t): r ^= x_c & z_t & ~(x_t ^ z_c); x_t ^= x_c; z_c ^= z_t
 //   CZ(a,b): r ^= x_a & x_b & (z_a ^ z_b);  z_a ^= x_b; z_b ^= x_a
+//   SWAP(a,b): exchange the two columns (sign unchanged)
+// (CY and iSWAP arrive as products of these.)
 // A thread owns WPT consecutive row words. For each group of its chunk it
 // loads the group's columns into registers, runs the micro-ops (their slots
 // are uniform over the wave, so the dispatch below is a scalar branch and
@@ -50,6 +52,12 @@ __device__ __forceinline__ void op2(u32 t, Cols<WPT> &c, u64 (&s)[WPT]) {
         s[k] ^= xa & zb & ~(xb ^ za);
         xb ^= xa;
         za ^= zb;
+      } else if (t == WOP_SWAP) {
+        const u64 tx = xa, tz = za;
+        xa = xb;
+        za = zb;
+        xb = tx;
+        zb = tz;
       } else {
         s[k] ^= xa & xb & (za ^ zb);
         const u64 ta = za ^ xb;
@@ -104,6 +112,39 @@ __device__ __forceinline__ void run_op(u32 op, Cols<WPT> &c, u64 (&s)[WPT]) {
 }
 
 template <int WPT>
+__device__ __forceinline__ void load_group(const u32 *rec, const u64 *__restrict__ X, const u64 *__restrict__ Z,
+                                           u32 Ls, u32 w, Cols<WPT> &c) {
+  const u32 nq = rec[0] & 15u;
+#pragma unroll
+  for (u32 i = 0; i < WG_MAXQ; ++i) {
+    if (i < nq) {
+      const size_t o = (size_t)rec[1 + i] * Ls + w;
+      ldw<WPT>(X + o, c.x[i]);
+      ldw<WPT>(Z + o, c.z[i]);
+    }
+  }
+}
+
+template <int WPT>
+__device__ __forceinline__ void finish_group(const u32 *rec, u64 *__restrict__ X, u64 *__restrict__ Z, u32 Ls, u32 w,
+                                             Cols<WPT> &c, u64 (&s)[WPT]) {
+  const u32 hdr = rec[0];
+  const u32 nq = hdr & 15u, nops = (hdr >> WH_NOPS_SHIFT) & 63u;
+  const u32 *ops = rec + 1 + nq;
+  for (u32 j = 0; j < nops; ++j) run_op<WPT>((ops[j >> 1] >> ((j & 1u) * 16u)) & 0xFFFFu, c, s);
+#pragma unroll
+  for (u32 i = 0; i < WG_MAXQ; ++i) {
+    if (i < nq) {
+      const size_t o = (size_t)rec[1 + i] * Ls + w;
+      if ((hdr >> (WH_DX_SHIFT + i)) & 1u) stw<WPT>(X + o, c.x[i]);
+      if ((hdr >> (WH_DZ_SHIFT + i)) & 1u) stw<WPT>(Z + o, c.z[i]);
+    }
+  }
+}
+
+// B groups are loaded before the first is computed, so a wave keeps the
+// columns of B groups in flight.
+template <int WPT, int B>
 __global__ __launch_bounds__(512) void k_layer(u64 *__restrict__ X, u64 *__restrict__ Z, u64 *__restrict__ sign_part,
                                                 const u32 *__restrict__ words, const u32 *__restrict__ offs,
                                                 u32 ngroups, u32 gpc, u32 Ls, u32 L) {
@@ -114,29 +155,17 @@ __global__ __launch_bounds__(512) void k_layer(u64 *__restrict__ X, u64 *__restr
   u64 s[WPT];
 #pragma unroll
   for (int k = 0; k < WPT; ++k) s[k] = 0;
-  Cols<WPT> c;
-  for (u32 g = g0; g < g1; ++g) {
-    const u32 *rec = words + offs[g];
-    const u32 hdr = rec[0];
-    const u32 nq = hdr & 15u, nops = (hdr >> WH_NOPS_SHIFT) & 63u;
+  Cols<WPT> c[B];
+  for (u32 g = g0; g < g1; g += B) {
+    const u32 *rec[B];
 #pragma unroll
-    for (u32 i = 0; i < WG_MAXQ; ++i) {
-      if (i < nq) {
-        const size_t o = (size_t)rec[1 + i] * Ls + w;
-        ldw<WPT>(X + o, c.x[i]);
-        ldw<WPT>(Z + o, c.z[i]);
-      }
+    for (int b = 0; b < B; ++b) {
+      rec[b] = g + b < g1 ? words + offs[g + b] : nullptr;
+      if (rec[b]) load_group<WPT>(rec[b], X, Z, Ls, w, c[b]);
     }
-    const u32 *ops = rec + 1 + nq;
-    for (u32 j = 0; j < nops; ++j) run_op<WPT>((ops[j >> 1] >> ((j & 1u) * 16u)) & 0xFFFFu, c, s);
 #pragma unroll
-    for (u32 i = 0; i < WG_MAXQ; ++i) {
-      if (i < nq) {
-        const size_t o = (size_t)rec[1 + i] * Ls + w;
-        if ((hdr >> (WH_DX_SHIFT + i)) & 1u) stw<WPT>(X + o, c.x[i]);
-        if ((hdr >> (WH_DZ_SHIFT + i)) & 1u) stw<WPT>(Z + o, c.z[i]);
-      }
-    }
+    for (int b = 0; b < B; ++b)
+      if (rec[b]) finish_group<WPT>(rec[b], X, Z, Ls, w, c[b], s);
   }
   stw<WPT>(sign_part + (size_t)blockIdx.y * Ls + w, s);
 }
@@ -156,10 +185,10 @@ hipError_t launch_layer(const TabDev &t, const u32 *words, const u32 *offs, u32 
   const u32 chunks = cdiv(ngroups, gpc);
   dim3 grid(tiles, chunks);
   if (wpt == 2)
-    hipLaunchKernelGGL((k_layer<2>), grid, dim3(block), 0, s, t.X, t.Z, sign_part, words, offs, ngroups, gpc, t.Ls,
+    hipLaunchKernelGGL((k_layer<2, 1>), grid, dim3(block), 0, s, t.X, t.Z, sign_part, words, offs, ngroups, gpc, t.Ls,
                        t.L);
   else
-    hipLaunchKernelGGL((k_layer<1>), grid, dim3(block), 0, s, t.X, t.Z, sign_part, words, offs, ngroups, gpc, t.Ls,
+    hipLaunchKernelGGL((k_layer<1, 2>), grid, dim3(block), 0, s, t.X, t.Z, sign_part, words, offs, ngroups, gpc, t.Ls,
                        t.L);
   return hipGetLastError();
 }

@@ -55,7 +55,9 @@ static_assert(sizeof(Group) == 16, "Group must be 16 bytes");
 // for CX a is the control and b the target.
 constexpr u32 WG_MAXQ = 8, WG_MAXOPS = 32;
 constexpr u32 WH_NOPS_SHIFT = 4, WH_DX_SHIFT = 16, WH_DZ_SHIFT = 24;
-enum : u32 { WOP_H = 1, WOP_S = 2, WOP_SDG = 3, WOP_X = 4, WOP_Y = 5, WOP_Z = 6, WOP_CX = 7, WOP_CZ = 8 };
+enum : u32 {
+  WOP_H = 1, WOP_S = 2, WOP_SDG = 3, WOP_X = 4, WOP_Y = 5, WOP_Z = 6, WOP_CX = 7, WOP_CZ = 8, WOP_SWAP = 9
+};
 
 // Per-measurement device state (one per tableau, reused by every measurement).
 struct MeasState {
@@ -117,6 +119,9 @@ struct BlkState {
   u32 dsign[KB];  // final sign of D_{p_s}
   u32 ncols;      // columns where some pivot is not the identity
   u32 done;       // blocks of k_blk_pivalg finished (last-block ticket)
+  u32 nwords;     // distinct row words (within a half) holding the pivots
+  u32 word[KB];   // those words
+  u32 wmem[KB];   // bit s: pivot s lies in word[i]
 };
 struct BlkBuffers {
   u64 *snap, *bm;          // KB * Ls words each: measured columns, hit masks

@@ -24,7 +24,9 @@
 
 namespace sq {
 
-inline bool is_two_qubit(u32 t) { return t == SQ_CX || t == SQ_CZ; }
+inline bool is_two_qubit(u32 t) {
+  return t == SQ_CX || t == SQ_CZ || t == SQ_CY || t == SQ_SWAP || t == SQ_ISWAP;
+}
 
 struct PassRange {
   u64 offset;  // first group (index into the group list or the offset table)
@@ -42,6 +44,7 @@ inline u32 wide_type(u32 sq_type) {
     case SQ_Y: return WOP_Y;
     case SQ_Z: return WOP_Z;
     case SQ_CX: return WOP_CX;
+    case SQ_SWAP: return WOP_SWAP;
     default: return WOP_CZ;
   }
 }
@@ -68,6 +71,21 @@ class WideBuilder {
 
   void add(u32 type, u32 a, u32 b) {
     if (type == SQ_I) return;
+    // products of the native rules, in time order: CY(a,b) = S_b CX(a,b)
+    // S_b^dagger, iSWAP(a,b) = SWAP CZ (S_a S_b)
+    if (type == SQ_CY) {
+      add(SQ_SDG, b, 0);
+      add(SQ_CX, a, b);
+      add(SQ_S, b, 0);
+      return;
+    }
+    if (type == SQ_ISWAP) {
+      add(SQ_S, a, 0);
+      add(SQ_S, b, 0);
+      add(SQ_CZ, a, b);
+      add(SQ_SWAP, a, b);
+      return;
+    }
     const bool two = is_two_qubit(type);
     int64_t p = std::max<int64_t>(front_[a], lo_);
     if (two) p = std::max<int64_t>(p, front_[b]);
@@ -160,6 +178,7 @@ class WideBuilder {
         case WOP_S: case WOP_SDG: dz |= 1u << a; break;
         case WOP_CX: dx |= 1u << b; dz |= 1u << a; break;
         case WOP_CZ: dz |= (1u << a) | (1u << b); break;
+        case WOP_SWAP: dx |= (1u << a) | (1u << b); dz |= (1u << a) | (1u << b); break;
         default: break;  // X, Y, Z change signs only
       }
     }
@@ -241,6 +260,26 @@ class PassBuilder {
 
   void add(u32 type, u32 a, u32 b) {
     if (type == SQ_I) return;
+    // CY, SWAP, iSWAP as products of the pair micro-ops, in time order
+    if (type == SQ_CY) {
+      add(SQ_SDG, b, 0);
+      add(SQ_CX, a, b);
+      add(SQ_S, b, 0);
+      return;
+    }
+    if (type == SQ_SWAP) {
+      add(SQ_CX, a, b);
+      add(SQ_CX, b, a);
+      add(SQ_CX, a, b);
+      return;
+    }
+    if (type == SQ_ISWAP) {
+      add(SQ_S, a, 0);
+      add(SQ_S, b, 0);
+      add(SQ_CZ, a, b);
+      add(SQ_SWAP, a, b);
+      return;
+    }
     if (!is_two_qubit(type)) {
       int g = find(a);
       if (g >= 0 && cur_[g].nops >= 16) { flush(); g = -1; }

@@ -43,7 +43,7 @@ constexpr u32 kBlkMaxChunks = 512;  // column chunks of the blocked-measurement 
 inline u32 cdiv(u64 a, u64 b) { return (u32)((a + b - 1) / b); }
 inline u32 round_up(u32 a, u32 b) { return (a + b - 1) / b * b; }
 
-bool is_gate(u32 t) { return t <= SQ_CZ; }
+bool is_gate(u32 t) { return t <= SQ_ISWAP; }
 
 sq_status validate_ops(u32 n, const sq_op *ops, u64 count, bool allow_measure) {
   if (count && !ops) return fail(SQ_EINVAL, "ops is NULL with count %llu", (unsigned long long)count);
@@ -184,7 +184,9 @@ u32 layer_gpc(const sq_tableau *T, u32 ngroups) {
   const u32 tiles = cdiv(T->d.L, (u64)T->tun.layer_block * T->tun.layer_wpt);
   u32 gpc = T->tun.layer_groups;
   if (gpc == 0) {
-    const u32 want_chunks = std::max<u32>(1, 2048 / tiles);
+    // about 6,000 workgroups: several rounds over the chip, so the last
+    // round's tail is short (measured on the MI355X at n = 180,000)
+    const u32 want_chunks = std::max<u32>(1, 6144 / tiles);
     gpc = std::max<u32>(16, cdiv(ngroups, want_chunks));
   }
   gpc = std::max<u32>(gpc, cdiv(ngroups, kMaxChunks));

@@ -9,9 +9,10 @@ from oracle import oracle as orc
 ONE_Q = np.array([orc.I, orc.H, orc.S, orc.SDG, orc.X, orc.Y, orc.Z], dtype=np.uint32)
 
 
-def mixed_program(rng, n, layers, p_meas=0.2, cz=True):
+def mixed_program(rng, n, layers, p_meas=0.2, cz=True, extra=False):
     """Layers of random one-qubit gates (all types), random disjoint CX/CZ
-    pairs, then a random (unsorted) set of measured qubits."""
+    pairs (with extra=True also CY, SWAP and iSWAP), then a random (unsorted)
+    set of measured qubits."""
     ops = []
     for _ in range(layers):
         kinds = ONE_Q[rng.integers(0, ONE_Q.size, n)]
@@ -21,7 +22,10 @@ def mixed_program(rng, n, layers, p_meas=0.2, cz=True):
         for k in range(n // 2):
             u = rng.random()
             a, b = int(perm[2 * k]), int(perm[2 * k + 1])
-            if u < 0.45:
+            if extra:
+                if u < 0.8:
+                    ops.append([[orc.CX, orc.CZ, orc.CY, orc.SWAP, orc.ISWAP][int(u / 0.16)], a, b])
+            elif u < 0.45:
                 ops.append([orc.CX, a, b])
             elif cz and u < 0.65:
                 ops.append([orc.CZ, a, b])

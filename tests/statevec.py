@@ -25,6 +25,19 @@ for _c in (0, 1):
     for _t in (0, 1):
         CXM[_c + 2 * (_t ^ _c), _c + 2 * _t] = 1
 CZM = np.diag([1, 1, 1, -1]).astype(complex)
+# controlled-Y: Y on the target when the control is 1 (Y|0> = i|1>, Y|1> = -i|0>)
+CYM = np.zeros((4, 4), dtype=complex)
+CYM[0, 0] = CYM[2, 2] = 1
+CYM[3, 1] = 1j
+CYM[1, 3] = -1j
+# SWAP: |a b> -> |b a>; iSWAP: |01> -> i|10>, |10> -> i|01>
+SWAPM = np.zeros((4, 4), dtype=complex)
+ISWAPM = np.zeros((4, 4), dtype=complex)
+for _a in (0, 1):
+    for _b in (0, 1):
+        SWAPM[_b + 2 * _a, _a + 2 * _b] = 1
+        ISWAPM[_b + 2 * _a, _a + 2 * _b] = 1 if _a == _b else 1j
+TWO_QUBIT = {7: CXM, 8: CZM, 9: CYM, 10: SWAPM, 11: ISWAPM}
 
 PAULI_BY_BITS = {(0, 0): I2, (1, 0): PX, (0, 1): PZ, (1, 1): PY}
 LETTER_BY_BITS = {(0, 0): "I", (1, 0): "X", (0, 1): "Z", (1, 1): "Y"}
@@ -108,10 +121,8 @@ def apply_gate(psi: np.ndarray, n: int, typ: int, a: int, b: int = 0) -> np.ndar
         return psi
     if typ in ONE_QUBIT:
         return apply_1q(psi, n, ONE_QUBIT[typ], a)
-    if typ == 7:
-        return apply_2q(psi, n, CXM, a, b)
-    if typ == 8:
-        return apply_2q(psi, n, CZM, a, b)
+    if typ in TWO_QUBIT:
+        return apply_2q(psi, n, TWO_QUBIT[typ], a, b)
     raise ValueError(typ)
 
 

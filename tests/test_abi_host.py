@@ -34,10 +34,11 @@ def test_library_exports_every_declared_symbol():
 def test_type_codes_agree():
     text = open(HEADER).read()
     codes = dict((k, int(v)) for k, v in re.findall(r"\b(SQ_[A-Z]+) = (\d+)", text))
-    for name in ["I", "H", "S", "SDG", "X", "Y", "Z", "CX", "CZ", "MEASURE"]:
+    for name in ["I", "H", "S", "SDG", "X", "Y", "Z", "CX", "CZ", "CY", "SWAP", "ISWAP", "MEASURE"]:
         assert codes["SQ_" + name] == getattr(sqb, name) == getattr(orc, name)
     assert workload.GATE_CX == sqb.CX and workload.GATE_CZ == sqb.CZ and workload.OP_MEASURE == sqb.MEASURE
     assert workload.GATE_SDG == sqb.SDG and workload.GATE_Y == sqb.Y
+    assert (workload.GATE_CY, workload.GATE_SWAP, workload.GATE_ISWAP) == (sqb.CY, sqb.SWAP, sqb.ISWAP)
 
 
 def test_bytes_required():
@@ -73,7 +74,7 @@ def plan_to_gates(plan):
                     gates.append([WOP_1Q[t], qs[a], 0])
                 else:
                     assert a != b
-                    gates.append([orc.CX if t == 7 else orc.CZ, qs[a], qs[b]])
+                    gates.append([{7: orc.CX, 8: orc.CZ, 9: orc.SWAP}[t], qs[a], qs[b]])
         assert len(set(qubits)) == len(qubits), "groups of a pass must be disjoint"
     return np.array(gates, dtype=np.uint32).reshape(-1, 3)
 
@@ -94,6 +95,9 @@ def changed_flags(qs, uops):
             dz |= 1 << a
         elif t == 8:
             dz |= (1 << a) | (1 << b)
+        elif t == 9:
+            dx |= (1 << a) | (1 << b)
+            dz |= (1 << a) | (1 << b)
     return (dx << 16) | (dz << 24)
 
 
@@ -113,8 +117,8 @@ def check_group(hdr, qs, uops):
 def random_gates(rng, n, count):
     out = []
     for _ in range(count):
-        t = int(rng.integers(0, 9 if n > 1 else 7))
-        if t in (orc.CX, orc.CZ):
+        t = int(rng.integers(0, 12 if n > 1 else 7))
+        if t in orc.TWO_QUBIT:
             a, b = rng.choice(n, 2, replace=False)
             out.append([t, int(a), int(b)])
         else:

@@ -84,6 +84,25 @@ def test_batch_equals_plain_and_oracle(block):
                 assert np.array_equal(g[s], w), f"request {k} shot {s} differs from the oracle"
 
 
+def test_batch_all_gate_types():
+    """Batched circuits with CY, SWAP and iSWAP (pair micro-op products) against the oracle."""
+    from paper_2603_14641_amd import batch_sample
+    rng = np.random.default_rng(77)
+    reqs = []
+    for i in range(16):
+        n = int(rng.integers(2, 70))
+        ops = mixed_program(rng, n, int(rng.integers(2, 10)), p_meas=0.0, extra=True)
+        qubits = [int(q) for q in rng.permutation(n)]
+        reqs.append(dict(n=n, ops=ops, qubits=qubits, shots=int(rng.integers(1, 20)), seed=i, shot_begin=0,
+                         meas_base=0))
+    got = batch_sample(reqs, block=256)
+    for k, (req, g) in enumerate(zip(reqs, got)):
+        ow = oracle_words(req, range(req["shots"]))
+        for s, w in ow.items():
+            assert np.array_equal(g[s], w), f"request {k} shot {s} differs from the oracle"
+        assert np.array_equal(g, plain(req))
+
+
 def test_batch_routes_large_items_to_single_path():
     from paper_2603_14641_amd import batch_sample
     rng = np.random.default_rng(9)

@@ -160,6 +160,23 @@ def test_mixed_circuits(n, tuning):
     _compare_full(t, (x, z, r))
 
 
+@pytest.mark.parametrize("n", [2, 5, 64, 65, 300, 1500])
+@pytest.mark.parametrize("tuning", [None, SMALL_TILES], ids=["default", "small"])
+def test_all_gate_types(n, tuning):
+    """CY, SWAP and iSWAP beside the other gates (the GPU applies them as
+    products of its micro-ops, the oracle by its own rules)."""
+    rng = np.random.default_rng(5000 + n)
+    ops = mixed_program(rng, n, 8 if n >= 300 else 14, p_meas=0.15 if n > 2 else 0.4, extra=True)
+    assert np.isin(ops[:, 0], [orc.CY, orc.SWAP, orc.ISWAP]).any() or n < 4
+    seed = int(rng.integers(1 << 40))
+    rb, rr, x, z, r, _ = oracle_run(n, ops, seed, shot=1, meas_base=3)
+    t = _tab(n, tuning)
+    bits, rnd = gpu_run_calls(t, ops, seed, shot=1, meas_base=3)
+    _assert_same(bits, rb, "outcomes")
+    _assert_same(rnd, rr, "random flags")
+    _compare_full(t, (x, z, r))
+
+
 def test_program_and_calls_agree_with_oracle_many_small():
     """200 small circuits with dense measurement (many deterministic outcomes)."""
     from paper_2603_14641_amd import Program

@@ -41,6 +41,13 @@ MUTANTS = {
                         "if (!getb(ROWX(t, (uint32_t)t->local[n + i]), q)) continue;"),
     "philox 9 rounds": ("round < 10", "round < 9"),
     "coin from word 1": ("return (int)(out[0] & 1);", "return (int)(out[1] & 1);"),
+    "SWAP keeps z_a": ("      putb(z, a, zb);\n", ""),
+    "CY S order": ("    gate_on_row(x, z, r, SQO_SDG, b, 0);\n    gate_on_row(x, z, r, SQO_CX, a, b);\n"
+                   "    gate_on_row(x, z, r, SQO_S, b, 0);",
+                   "    gate_on_row(x, z, r, SQO_S, b, 0);\n    gate_on_row(x, z, r, SQO_CX, a, b);\n"
+                   "    gate_on_row(x, z, r, SQO_SDG, b, 0);"),
+    "iSWAP drops S_b": ("    gate_on_row(x, z, r, SQO_S, b, 0);\n    gate_on_row(x, z, r, SQO_CZ, a, b);",
+                        "    gate_on_row(x, z, r, SQO_CZ, a, b);"),
 }
 
 
@@ -50,8 +57,8 @@ def _program(rng, n, length, p_meas):
         if rng.random() < p_meas:
             ops.append([orc.MEASURE, int(rng.integers(n)), 0])
             continue
-        t = int(rng.integers(1, 9))
-        if t in (orc.CX, orc.CZ):
+        t = int(rng.integers(1, 12))
+        if t in orc.TWO_QUBIT:
             a, b = rng.choice(n, 2, replace=False)
             ops.append([t, int(a), int(b)])
         else:
@@ -74,8 +81,8 @@ def pin_philox(lib):
 
 def pin_gates(lib):
     n = 2
-    for typ in range(1, 9):
-        placements = [(0, 1), (1, 0)] if typ in (orc.CX, orc.CZ) else [(0, 0), (1, 0)]
+    for typ in range(1, 12):
+        placements = [(0, 1), (1, 0)] if typ in orc.TWO_QUBIT else [(0, 0), (1, 0)]
         for a, b in placements:
             u = sv.gate_unitary(n, typ, a, b)
             for code in range(16):
@@ -160,7 +167,30 @@ def pin_measure_update(lib):
         done += 1
 
 
-PINS = [pin_philox, pin_gates, pin_state_vector, pin_measure_update]
+def pin_rowsum(lib):
+    """rowsum(h, i) of random commuting rows equals the matrix product P_i P_h."""
+    rng = np.random.default_rng(29)
+    n = 3
+    checked = 0
+    while checked < 200:
+        t = orc.Tableau(n, lib=lib)
+        x, z, r = t.rows_array()
+        x[:, 0] = rng.integers(0, 8, 2 * n).astype(np.uint64)
+        z[:, 0] = rng.integers(0, 8, 2 * n).astype(np.uint64)
+        r[:] = rng.integers(0, 2, 2 * n).astype(np.uint8)
+        t.set_rows(x, z, r)
+        h, i = (int(v) for v in rng.choice(2 * n, 2, replace=False))
+        ph = sv.row_matrix(x[h], z[h], int(r[h]), n)
+        pi = sv.row_matrix(x[i], z[i], int(r[i]), n)
+        if not np.allclose(ph @ pi, pi @ ph):
+            continue
+        t.rowsum(h, i)
+        x2, z2, r2 = t.rows_array()
+        assert np.allclose(sv.row_matrix(x2[h], z2[h], int(r2[h]), n), pi @ ph)
+        checked += 1
+
+
+PINS = [pin_philox, pin_gates, pin_state_vector, pin_measure_update, pin_rowsum]
 
 
 def test_unmutated_oracle_passes_compact_pins():

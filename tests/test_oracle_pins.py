@@ -17,7 +17,7 @@ from oracle import oracle as orc
 
 GOLDEN = os.path.join(os.path.dirname(__file__), "golden", "paper_examples.json")
 NAME_TO_TYPE = {"H": orc.H, "S": orc.S, "SDG": orc.SDG, "X": orc.X, "Y": orc.Y, "Z": orc.Z,
-                "CX": orc.CX, "CZ": orc.CZ}
+                "CX": orc.CX, "CZ": orc.CZ, "CY": orc.CY, "SWAP": orc.SWAP, "ISWAP": orc.ISWAP}
 
 
 def ops_of(*gates):
@@ -100,12 +100,12 @@ def _set_single_row(t, n, xbits, zbits, sign):
     t.set_rows(x, z, r)
 
 
-@pytest.mark.parametrize("gate", ["H", "S", "SDG", "X", "Y", "Z", "CX", "CZ"])
+@pytest.mark.parametrize("gate", ["H", "S", "SDG", "X", "Y", "Z", "CX", "CZ", "CY", "SWAP", "ISWAP"])
 def test_gate_rules_against_conjugation(gate):
     """Every Pauli P (with sign) on 2 qubits must map to U P U^dagger."""
     n = 2
     typ = NAME_TO_TYPE[gate]
-    placements = [(0, 1), (1, 0)] if typ in (orc.CX, orc.CZ) else [(0, 0), (1, 0)]
+    placements = [(0, 1), (1, 0)] if typ in orc.TWO_QUBIT else [(0, 0), (1, 0)]
     for a, b in placements:
         u = sv.gate_unitary(n, typ, a, b)
         for code in range(16):
@@ -163,14 +163,14 @@ def test_paper_product_state_plus01():
 
 
 # ---------------------------------------------------------------- brute force
-def _random_program(rng, n, length, p_meas=0.15, gates=(1, 2, 3, 4, 5, 6, 7, 8)):
+def _random_program(rng, n, length, p_meas=0.15, gates=(1, 2, 3, 4, 5, 6, 7, 8, 9, 10, 11)):
     ops = []
     for _ in range(length):
         if rng.random() < p_meas:
             ops.append([orc.MEASURE, int(rng.integers(n)), 0])
             continue
         t = int(rng.choice(gates))
-        if t in (orc.CX, orc.CZ):
+        if t in orc.TWO_QUBIT:
             if n < 2:
                 continue
             a, b = rng.choice(n, 2, replace=False)
@@ -357,6 +357,13 @@ def test_gate_identities_on_tableaux():
             ([[orc.CZ, a, b]], [[orc.H, b, 0], [orc.CX, a, b], [orc.H, b, 0]]),
             ([[orc.CZ, a, b]], [[orc.CZ, b, a]]),
             ([[orc.Y, a, 0]], [[orc.Z, a, 0], [orc.X, a, 0]]),
+            # SWAP as three CX; SWAP and iSWAP are symmetric; iSWAP^2 = Z_a Z_b;
+            # CY = S_b CX S_b^dagger
+            ([[orc.SWAP, a, b]], [[orc.CX, a, b], [orc.CX, b, a], [orc.CX, a, b]]),
+            ([[orc.SWAP, a, b]], [[orc.SWAP, b, a]]),
+            ([[orc.ISWAP, a, b]], [[orc.ISWAP, b, a]]),
+            ([[orc.ISWAP, a, b]] * 2, [[orc.Z, a, 0], [orc.Z, b, 0]]),
+            ([[orc.CY, a, b]], [[orc.SDG, b, 0], [orc.CX, a, b], [orc.S, b, 0]]),
         ]
         for lhs, rhs in same:
             ta = _tableau_after(n, prefix + lhs)

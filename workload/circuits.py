@@ -41,6 +41,9 @@ GATE_Y = 5
 GATE_Z = 6
 GATE_CX = 7
 GATE_CZ = 8
+GATE_CY = 9
+GATE_SWAP = 10
+GATE_ISWAP = 11
 OP_MEASURE = 15
 
 OP_DTYPE = np.dtype([("type", "<u4"), ("q0", "<u4"), ("q1", "<u4")])
