@@ -185,6 +185,22 @@ uint64_t sq_program_num_gates(const sq_program *p);
 /* Number of fused gate passes the program launches. */
 uint64_t sq_program_num_passes(const sq_program *p);
 
+/* Read an OpenQASM 2.0 circuit (host only, no device work) into operation
+ * records for sq_program_create / sq_apply_gates. Accepted: the version line,
+ * include lines (ignored), qreg/creg declarations, the gates id, x, y, z, h,
+ * s, sdg, cx (and CX), cy, cz, swap, iswap on qubits or whole registers
+ * (broadcast over registers of equal size), parameterless gate definitions
+ * built from these (expanded at each call; a definition of a known gate name
+ * keeps the built-in), measure (qubit or whole register; outcomes come in
+ * program order, the classical target is not recorded), barrier (ignored)
+ * and // comments. Qubits of several registers are numbered in declaration
+ * order. text: len bytes, not necessarily NUL-terminated. Writes up to cap
+ * records to host_ops, the number of records to *count and the qubit count
+ * to *n (call with cap = 0 to size the buffer).
+ * Errors: SQ_EINVAL for anything else (parameters, reset, if, opaque, U,
+ * unknown names, bad indices, syntax), with the line in sq_last_error(). */
+sq_status sq_qasm_parse(const char *text, size_t len, sq_op *host_ops, uint64_t cap, uint64_t *count, uint32_t *n);
+
 /* Host-only inspection of how a gate sequence is grouped into passes (no
  * device work; usable without a GPU). A pass holds groups on pairwise
  * disjoint qubit sets, each of at most 8 qubits and 32 micro-ops. Writes, per

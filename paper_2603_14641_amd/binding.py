@@ -31,6 +31,7 @@ EXPORTED = [
     "sq_plan_gates",
     "sq_run", "sq_export_rows", "sq_export", "sq_import", "sq_measure_stats", "sq_error_flags",
     "sq_get_tuning", "sq_set_tuning", "sq_profile_enable", "sq_profile_read", "sq_profile_reset",
+    "sq_qasm_parse",
 ]
 
 
@@ -105,6 +106,7 @@ def load(path: str = LIB_PATH):
         "sq_program_num_passes": (u64, [vp]),
         "sq_program_gate_bytes": (u64, [vp]),
         "sq_plan_gates": (i32, [u32, vp, u64, vp, u64, ctypes.POINTER(u64)]),
+        "sq_qasm_parse": (i32, [ctypes.c_char_p, ctypes.c_size_t, vp, u64, ctypes.POINTER(u64), ctypes.POINTER(u32)]),
         "sq_run": (i32, [vp, vp, u64, u64, u64, vp, vp]),
         "sq_export_rows": (i32, [vp, vp, u32, vp, vp, vp]),
         "sq_export": (i32, [vp, vp, vp, vp]),
@@ -380,6 +382,18 @@ def plan_gates(n: int, ops) -> list:
             k += 1 + nq + nops
         passes.append(groups)
     return passes
+
+
+def parse_qasm(text) -> Tuple[int, np.ndarray]:
+    """Host-only: an OpenQASM 2.0 circuit as (qubit count, (k, 3) uint32 op records)."""
+    lib = load()
+    data = text.encode() if isinstance(text, str) else bytes(text)
+    count, n = ctypes.c_uint64(0), ctypes.c_uint32(0)
+    _check(lib.sq_qasm_parse(data, len(data), None, 0, ctypes.byref(count), ctypes.byref(n)))
+    out = np.zeros((max(int(count.value), 1), 3), dtype=np.uint32)
+    _check(lib.sq_qasm_parse(data, len(data), out.ctypes.data, int(count.value), ctypes.byref(count),
+                             ctypes.byref(n)))
+    return int(n.value), out[:int(count.value)]
 
 
 def bytes_required(n: int) -> int:

@@ -131,7 +131,16 @@ __device__ __forceinline__ void finish_group(const u32 *rec, u64 *__restrict__ X
   const u32 hdr = rec[0];
   const u32 nq = hdr & 15u, nops = (hdr >> WH_NOPS_SHIFT) & 63u;
   const u32 *ops = rec + 1 + nq;
-  for (u32 j = 0; j < nops; ++j) run_op<WPT>((ops[j >> 1] >> ((j & 1u) * 16u)) & 0xFFFFu, c, s);
+  // two micro-ops per word; the next word's scalar load is issued before
+  // the current word's ops run, so its latency is hidden
+  const u32 nw = (nops + 1u) >> 1;
+  u32 cur = ops[0];
+  for (u32 i = 0; i < nw; ++i) {
+    const u32 nxt = (i + 1 < nw) ? ops[i + 1] : 0u;
+    run_op<WPT>(cur & 0xFFFFu, c, s);
+    if (2 * i + 1 < nops) run_op<WPT>(cur >> 16, c, s);
+    cur = nxt;
+  }
 #pragma unroll
   for (u32 i = 0; i < WG_MAXQ; ++i) {
     if (i < nq) {
@@ -143,7 +152,8 @@ __device__ __forceinline__ void finish_group(const u32 *rec, u64 *__restrict__ X
 }
 
 // B groups are loaded before the first is computed, so a wave keeps the
-// columns of B groups in flight.
+// columns of B groups in flight (B = 1 in use: with B = 2 the compiler moves
+// the column arrays to scratch memory).
 template <int WPT, int B>
 __global__ __launch_bounds__(512) void k_layer(u64 *__restrict__ X, u64 *__restrict__ Z, u64 *__restrict__ sign_part,
                                                 const u32 *__restrict__ words, const u32 *__restrict__ offs,
@@ -188,7 +198,7 @@ hipError_t launch_layer(const TabDev &t, const u32 *words, const u32 *offs, u32 
     hipLaunchKernelGGL((k_layer<2, 1>), grid, dim3(block), 0, s, t.X, t.Z, sign_part, words, offs, ngroups, gpc, t.Ls,
                        t.L);
   else
-    hipLaunchKernelGGL((k_layer<1, 2>), grid, dim3(block), 0, s, t.X, t.Z, sign_part, words, offs, ngroups, gpc, t.Ls,
+    hipLaunchKernelGGL((k_layer<1, 1>), grid, dim3(block), 0, s, t.X, t.Z, sign_part, words, offs, ngroups, gpc, t.Ls,
                        t.L);
   return hipGetLastError();
 }

@@ -31,6 +31,14 @@ sq_status fail(sq_status code, const char *fmt, ...) {
   return code;
 }
 
+}  // namespace
+
+// Lets the other host files of the library (the OpenQASM reader) report
+// through sq_last_error.
+void sq_set_error_message(const char *msg) { g_err = msg ? msg : ""; }
+
+namespace {
+
 #define HIP_TRY(expr)                                                                        \
   do {                                                                                       \
     hipError_t e_ = (expr);                                                                  \
