@@ -84,16 +84,34 @@ def _per_kernel(path: str, counter: str) -> Dict[str, list]:
     return vals
 
 
+def calibration(path: str, counter: str) -> float:
+    """Counter value of the 1 GiB calibration copy: bench.py --copy-calibration
+    runs three such copies before any other work, so they are the run's first
+    three large copy dispatches; they must agree within 1%."""
+    rows = []
+    with open(path, newline="") as f:
+        for row in csv.DictReader(f):
+            if row["Counter_Name"] == counter and short_name(row["Kernel_Name"]) == COPY_KERNEL \
+                    and int(row["Grid_Size"]) >= 65536:
+                rows.append((int(row["Dispatch_Id"]), float(row["Counter_Value"])))
+    rows.sort()
+    if len(rows) < 3:
+        raise SystemExit("no calibration copies in the run (pass --copy-calibration to bench.py)")
+    vals = [v for _, v in rows[:3]]
+    if max(vals) > 1.01 * min(vals):
+        raise SystemExit(f"calibration copies disagree: {vals}")
+    return sum(vals) / 3
+
+
 def hbm_summary(fetch_csv: str, write_csv: str, title: str, command: str) -> str:
     fetch = _per_kernel(fetch_csv, "FETCH_SIZE")
     write = _per_kernel(write_csv, "WRITE_SIZE")
-    if COPY_KERNEL not in fetch or COPY_KERNEL not in write:
-        raise SystemExit("no calibration copy in the runs (pass --copy-calibration to bench.py)")
-    f_cal = COPY_KIB / max(fetch[COPY_KERNEL])
-    w_cal = COPY_KIB / max(write[COPY_KERNEL])
+    f_raw, w_raw = calibration(fetch_csv, "FETCH_SIZE"), calibration(write_csv, "WRITE_SIZE")
+    f_cal = COPY_KIB / f_raw
+    w_cal = COPY_KIB / w_raw
     lines = [f"# {title}", "", "Commands (one counter per run):", "", "```", command, "```", "",
-             f"Calibration: the plain 1 GiB device copy (`{COPY_KERNEL}`) reads FETCH_SIZE = "
-             f"{max(fetch[COPY_KERNEL]):.1f} KiB and WRITE_SIZE = {max(write[COPY_KERNEL]):.1f} KiB for "
+             f"Calibration: the plain 1 GiB device copy (`{COPY_KERNEL}`, the run's first three copies) reads "
+             f"FETCH_SIZE = {f_raw:.1f} KiB and WRITE_SIZE = {w_raw:.1f} KiB for "
              f"{COPY_KIB} KiB moved each way, so FETCH_SIZE is scaled by {f_cal:.4f} and WRITE_SIZE by "
              f"{w_cal:.4f}.", "",
              "| Kernel | Dispatches | FETCH_SIZE avg (KiB) | WRITE_SIZE avg (KiB) | scaled read (GB) | "

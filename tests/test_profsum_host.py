@@ -14,7 +14,8 @@ def _csv(path, counter, rows):
         w = csv.writer(f)
         w.writerow(HDR)
         for i, (name, val) in enumerate(rows):
-            w.writerow([i, i, "Agent 1", 1, 1, 1, 64, 1, name, 64, 0, 0, 8, 0, 16, counter, val, 0, 1])
+            grid = 131072 if "copyBuffer" in name else 64
+            w.writerow([i, i, "Agent 1", 1, 1, 1, grid, 1, name, 64, 0, 0, 8, 0, 16, counter, val, 0, 1])
 
 
 def test_short_name():
@@ -26,9 +27,11 @@ def test_hbm_scaling_and_staleness(tmp_path):
     layer = "void sq::k_layer<2, 4>(unsigned long long*, unsigned int)"
     fetch = tmp_path / "f.csv"
     write = tmp_path / "w.csv"
-    # the copy moves 1 GiB each way but FETCH_SIZE reads half of it: factor 2
-    _csv(fetch, "FETCH_SIZE", [("__amd_rocclr_copyBuffer", 524288.0), (layer, 100.0), (layer, 300.0)])
-    _csv(write, "WRITE_SIZE", [("__amd_rocclr_copyBuffer", 1048576.0), (layer, 50.0), (layer, 50.0)])
+    # the copy moves 1 GiB each way but FETCH_SIZE reads half of it: factor 2;
+    # a later, larger copy (4 GiB) must not be taken for the calibration
+    cp = "__amd_rocclr_copyBuffer"
+    _csv(fetch, "FETCH_SIZE", [(cp, 524288.0)] * 3 + [(layer, 100.0), (layer, 300.0), (cp, 2097152.0)])
+    _csv(write, "WRITE_SIZE", [(cp, 1048576.0)] * 3 + [(layer, 50.0), (layer, 50.0), (cp, 4194304.0)])
     text = profsum.hbm_summary(str(fetch), str(write), "t", "cmd")
     summ = tmp_path / "s.md"
     summ.write_text(text)
