@@ -405,6 +405,38 @@ __global__ __launch_bounds__(256) void k_blk_pass(u64 *__restrict__ X, u64 *__re
     if (s < k) part[cs + (size_t)(2 + s) * Ls + w] = y[s];
 }
 
+// -------------------------------------------------------------- chunk reduction
+// Thread per (row word, field): field 0 adds the 2-bit counters of all
+// chunks (mod 4), field 1 + s XORs the parity words of pivot s. The result
+// goes to chunk 0's slots.
+__global__ void k_blk_reduce(u64 *__restrict__ part, const u64 *__restrict__ bm, const BlkState *__restrict__ bs,
+                             u32 Ls, u32 L, u32 nchunks) {
+  const u32 k = bs->k;
+  const u32 w = blockIdx.x * blockDim.x + threadIdx.x;
+  const u32 f = blockIdx.y;
+  if (w >= L || f > k) return;
+  u64 any = 0;
+  for (u32 s = 0; s < k; ++s) any |= bm[(size_t)s * Ls + w];
+  if (any == 0) return;  // k_blk_pass wrote nothing for this row word
+  const size_t stride = (size_t)(2 + KB) * Ls;
+  if (f == 0) {
+    u64 d0 = 0, d1 = 0;
+    for (u32 c = 0; c < nchunks; ++c) {
+      const u64 a0 = part[c * stride + w], a1 = part[c * stride + Ls + w];
+      const u64 carry = d0 & a0;
+      d0 ^= a0;
+      d1 ^= a1 ^ carry;
+    }
+    part[w] = d0;
+    part[Ls + w] = d1;
+  } else {
+    const size_t o = (size_t)(1 + f) * Ls + w;
+    u64 y = 0;
+    for (u32 c = 0; c < nchunks; ++c) y ^= part[c * stride + o];
+    part[o] = y;
+  }
+}
+
 // -------------------------------------------------------------- final
 // Threads t < L: signs of the row word t (hit rows from the lam algebra,
 // special rows from dsign / the coins). Threads t < n: column t's bits of the
@@ -412,8 +444,7 @@ __global__ __launch_bounds__(256) void k_blk_pass(u64 *__restrict__ X, u64 *__re
 __global__ void k_blk_final(u64 *__restrict__ X, u64 *__restrict__ Z, u64 *__restrict__ R,
                             const u64 *__restrict__ bm, const u32 *__restrict__ patx, const u32 *__restrict__ patz,
                             const u64 *__restrict__ part, const BlkState *__restrict__ bs, BlkArgs a,
-                            MeasState *__restrict__ st, MeasStats *__restrict__ stats, u32 Ls, u32 L, u32 K, u32 n,
-                            u32 nchunks) {
+                            MeasState *__restrict__ st, MeasStats *__restrict__ stats, u32 Ls, u32 L, u32 K, u32 n) {
   const u32 k = bs->k;
   if (k == 0) return;
   const u32 t = blockIdx.x * blockDim.x + threadIdx.x;
@@ -429,19 +460,11 @@ __global__ void k_blk_final(u64 *__restrict__ X, u64 *__restrict__ Z, u64 *__res
     u64 r = R[w];
     bool touched = false;
     if (any) {
-      u64 d0 = 0, d1 = 0, y[KB];
+      // chunk sums reduced by k_blk_reduce into chunk 0's slots
+      const u64 d0 = part[w], d1 = part[Ls + w];
+      u64 y[KB];
 #pragma unroll
-      for (u32 s = 0; s < KB; ++s) y[s] = 0;
-      for (u32 c = 0; c < nchunks; ++c) {
-        const size_t cs = (size_t)c * (2 + KB) * Ls;
-        const u64 a0 = part[cs + w], a1 = part[cs + Ls + w];
-        const u64 carry = d0 & a0;
-        d0 ^= a0;
-        d1 ^= a1 ^ carry;
-#pragma unroll
-        for (u32 s = 0; s < KB; ++s)
-          if (s < k) y[s] ^= part[cs + (size_t)(2 + s) * Ls + w];
-      }
+      for (u32 s = 0; s < KB; ++s) y[s] = s < k ? part[(size_t)(2 + s) * Ls + w] : 0ULL;
       // lam = sum_s b_s lam(P_s) + 2 sum_{s<s'} b_s b_s' Qz[s'][s] + 2 r + 2 XOR b_s y_s + d
       u64 l0 = 0, l1 = 0;
       for (u32 s = 0; s < k; ++s) {
@@ -552,12 +575,14 @@ hipError_t launch_blk_pass(const TabDev &t, const BlkBuffers &b, u32 cpc, hipStr
   return hipGetLastError();
 }
 
-// Stage 3: signs and the special rows.
+// Stage 3: chunk reduction, signs and the special rows.
 hipError_t launch_blk_final(const TabDev &t, const BlkArgs &a, const BlkBuffers &b, MeasState *st, MeasStats *stats,
                             u32 cpc, hipStream_t s) {
   const u32 nchunks = cdiv(t.n, cpc);
+  hipLaunchKernelGGL(k_blk_reduce, dim3(cdiv(t.L, 256), 1 + a.k), dim3(256), 0, s, b.part, b.bm, b.bs, t.Ls, t.L,
+                     nchunks);
   hipLaunchKernelGGL(k_blk_final, dim3(cdiv(std::max(t.L, t.n), 256)), dim3(256), 0, s, t.X, t.Z, t.R, b.bm,
-                     b.patx, b.patz, b.part, b.bs, a, st, stats, t.Ls, t.L, t.K, t.n, nchunks);
+                     b.patx, b.patz, b.part, b.bs, a, st, stats, t.Ls, t.L, t.K, t.n);
   return hipGetLastError();
 }
 

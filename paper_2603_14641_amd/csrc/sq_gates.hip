@@ -180,12 +180,15 @@ __global__ __launch_bounds__(512) void k_layer(u64 *__restrict__ X, u64 *__restr
   stw<WPT>(sign_part + (size_t)blockIdx.y * Ls + w, s);
 }
 
+// Grid (row tiles, slices): slice y XORs the partials of chunks y, y + S,
+// y + 2S, ... and folds them into R with one 64-bit atomic XOR (the order of
+// the XORs does not matter).
 __global__ void k_sign_reduce(u64 *__restrict__ R, const u64 *__restrict__ sign_part, u32 nchunks, u32 Ls, u32 L) {
   const u32 w = blockIdx.x * blockDim.x + threadIdx.x;
   if (w >= L) return;
   u64 acc = 0;
-  for (u32 c = 0; c < nchunks; ++c) acc ^= sign_part[(size_t)c * Ls + w];
-  R[w] ^= acc;
+  for (u32 c = blockIdx.y; c < nchunks; c += gridDim.y) acc ^= sign_part[(size_t)c * Ls + w];
+  if (acc) atomicXor(&R[w], acc);
 }
 
 // Launchers.
@@ -204,7 +207,9 @@ hipError_t launch_layer(const TabDev &t, const u32 *words, const u32 *offs, u32 
 }
 
 hipError_t launch_sign_reduce(const TabDev &t, const u64 *sign_part, u32 nchunks, hipStream_t s) {
-  hipLaunchKernelGGL(k_sign_reduce, dim3(cdiv(t.L, 256)), dim3(256), 0, s, t.R, sign_part, nchunks, t.Ls, t.L);
+  const u32 slices = std::min<u32>(std::max<u32>(nchunks, 1), 64);
+  hipLaunchKernelGGL(k_sign_reduce, dim3(cdiv(t.L, 256), slices), dim3(256), 0, s, t.R, sign_part, nchunks, t.Ls,
+                     t.L);
   return hipGetLastError();
 }
 
