@@ -169,8 +169,8 @@ typedef struct {
 typedef struct {
   uint32_t block;        /* threads per workgroup of the batched kernel (multiple of 64, <= 512; 0 = automatic) */
   uint32_t grid;         /* workgroups of the persistent launch (0 = automatic) */
-  uint32_t max_batch_n;  /* larger circuits take the single-tableau path (0 = automatic) */
-  uint32_t streams;      /* concurrent streams (host worker threads) for those (0 = automatic) */
+  uint32_t max_batch_n;  /* larger circuits take the single-tableau path (0 = automatic: 1024) */
+  uint32_t streams;      /* concurrent streams (host worker threads) for those (0 = automatic: 8) */
 } sq_batch_opts;
 
 sq_status sq_batch_sample(const sq_batch_item *items, uint32_t nitems, const sq_batch_opts *opts, void *hip_stream);

@@ -33,7 +33,7 @@ ROWSUM_CANDIDATES = [
 ]
 BATCH_CANDIDATES = [
     dict(block=b, max_batch_n=m, streams=s)
-    for b in (128, 256) for m in (1024, 2048, 4096) for s in (4,)
+    for b in (128, 256) for m in (256, 512, 1024, 2048) for s in (4, 8)
 ]
 
 

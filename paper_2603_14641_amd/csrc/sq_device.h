@@ -63,4 +63,10 @@ __device__ __forceinline__ void stw(u64 *p, const u64 (&v)[WPT]) {
 
 static inline u32 cdiv(u64 a, u64 b) { return (u32)((a + b - 1) / b); }
 
+// 64-bit xor-shuffle across the wave, as two 32-bit shuffles.
+__device__ __forceinline__ u64 shfl_xor_u64(u64 v, int off) {
+  const u32 lo = (u32)__shfl_xor((int)(u32)v, off), hi = (u32)__shfl_xor((int)(u32)(v >> 32), off);
+  return ((u64)hi << 32) | lo;
+}
+
 }  // namespace sq

@@ -296,32 +296,46 @@ __global__ __launch_bounds__(256) void k_post(u64 *__restrict__ X, u64 *__restri
       stats->n_random += 1;
       stats->rowsum_bytes += (u64)st->mwords * 8ULL * (2ULL * st->ncols + st->nx + st->nz);
     }
+    // Sign words: one wave per row word; lanes sum the chunks' 2-bit
+    // counters over a stride of 64 chunks, then a butterfly adds the lanes'
+    // counters (bit-sliced, mod 4).
     const u32 nsign = SYM ? K : L;
-    if (t < nsign) {
-      const u32 w = SYM ? K + t : t;  // row word
+    const u32 gw = blockIdx.x * nwaves + wave;
+    if (gw < nsign) {
+      const u32 w = SYM ? K + gw : gw;  // row word
       const u64 m = mask[w];
       const bool own = SYM ? (w == ws) : (w == wd || w == ws);
-      if (m != 0 || own) {
-        u64 r = SYM ? sym.sg[(size_t)sym.count * sym.Ks + t] : R[w];
+      if (m != 0 || own) {  // uniform over the wave
+        u64 s0 = 0, s1 = 0;
         if (m != 0) {
           const u32 nch = (st->ncols + cpc - 1) / cpc;
-          u64 s0 = 0, s1 = 0;
-          for (u32 c = 0; c < nch; ++c) {
+          for (u32 c = lane; c < nch; c += 64u) {
             const u64 b0 = cnt0[(size_t)c * Ls + w], b1 = cnt1[(size_t)c * Ls + w];
             const u64 carry = s0 & b0;
             s0 ^= b0;
             s1 ^= b1 ^ carry;
           }
-          if (s0 & m) atomicOr(&st->flags, 1u);
-          r ^= m & (s1 ^ (rp ? ~0ULL : 0ULL));
+          for (int off = 32; off > 0; off >>= 1) {
+            const u64 o0 = shfl_xor_u64(s0, off), o1 = shfl_xor_u64(s1, off);
+            const u64 carry = s0 & o0;
+            s0 ^= o0;
+            s1 ^= o1 ^ carry;
+          }
         }
-        if (SYM) {
-          if (w == ws) r &= ~bit;
-          sym.sg[(size_t)sym.count * sym.Ks + t] = r;
-        } else {
-          if (w == wd) r = (r & ~bit) | (rp ? bit : 0ULL);
-          if (w == ws) r = (r & ~bit) | (st->coin ? bit : 0ULL);
-          R[w] = r;
+        if (lane == 0) {
+          u64 r = SYM ? sym.sg[(size_t)sym.count * sym.Ks + gw] : R[w];
+          if (m != 0) {
+            if (s0 & m) atomicOr(&st->flags, 1u);
+            r ^= m & (s1 ^ (rp ? ~0ULL : 0ULL));
+          }
+          if (SYM) {
+            if (w == ws) r &= ~bit;
+            sym.sg[(size_t)sym.count * sym.Ks + gw] = r;
+          } else {
+            if (w == wd) r = (r & ~bit) | (rp ? bit : 0ULL);
+            if (w == ws) r = (r & ~bit) | (st->coin ? bit : 0ULL);
+            R[w] = r;
+          }
         }
       }
     }
@@ -398,15 +412,38 @@ __global__ __launch_bounds__(256) void k_post(u64 *__restrict__ X, u64 *__restri
     if (carry_x != 0u || carry_z != (u32)(j == q)) bad = 1;
   }
   if (SYM) {
-    // coin coefficients of the outcome's affine form: v = t < i
-    const u32 v = t;
-    u32 par = 0;
-    if (v < sym.i) {
-      const u64 *c = sym.sg + (size_t)v * sym.Ks;
-      for (u32 w = 0; w < K; ++w) par ^= (u32)__popcll(c[w] & mask[w]) & 1u;
+    // Coin coefficients of the outcome's affine form: bit v of F_i is the
+    // parity of sign column v over the rows in A (v < i). Block b builds
+    // word b (columns 64b .. 64b+63); each wave takes 64 / nwaves columns and
+    // reads a column's words lane by lane (coalesced).
+    // (k_post runs with 256 threads: 4 waves of 16 columns; a lane loads its
+    // word of all 16 columns before using any, so a wave waits about K / 64
+    // memory round trips, not 16 times that)
+    constexpr u32 PER = 16;
+    __shared__ u64 s_fw;
+    if (tid == 0) s_fw = 0;
+    __syncthreads();
+    const u32 vbase = blockIdx.x * 64u;
+    const u32 v0 = vbase + wave * PER;
+    if (v0 < sym.i) {
+      u32 par[PER];
+#pragma unroll
+      for (u32 k = 0; k < PER; ++k) par[k] = 0;
+      for (u32 w = lane; w < K; w += 64u) {
+        const u64 m = mask[w];
+        u64 c[PER];
+#pragma unroll
+        for (u32 k = 0; k < PER; ++k) c[k] = (v0 + k < sym.i) ? sym.sg[(size_t)(v0 + k) * sym.Ks + w] : 0ULL;
+#pragma unroll
+        for (u32 k = 0; k < PER; ++k) par[k] ^= (u32)__popcll(c[k] & m) & 1u;
+      }
+      u64 bits = 0;
+#pragma unroll
+      for (u32 k = 0; k < PER; ++k) bits |= (u64)((u32)__popcll(__ballot(par[k])) & 1u) << k;
+      if (lane == 0 && bits) atomicOr(&s_fw, bits << (v0 & 63u));
     }
-    const u64 bb = __ballot(par);
-    if (lane == 0 && v <= sym.i) sym.fm[(size_t)sym.i * sym.CW + (v >> 6)] = bb;
+    __syncthreads();
+    if (tid == 0 && vbase <= sym.i) sym.fm[(size_t)sym.i * sym.CW + blockIdx.x] = s_fw;
   }
   for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off);
   if (lane == 0) s_acc[wave] = acc;
@@ -496,8 +533,10 @@ hipError_t launch_rowsum(const TabDev &t, const u64 *mask, const u32 *cols, cons
 hipError_t launch_post(const TabDev &t, u32 q, const u64 *mask, const u64 *pivx, const u64 *pivz, const u64 *cnt0,
                        const u64 *cnt1, MeasState *st, MeasStats *stats, uint8_t *out_bits, u32 cpc, u32 cpw,
                        const SymCtx *sym, hipStream_t s) {
-  u32 blocks = std::max(cdiv(std::max(t.L, t.n), 256), cdiv(t.n, cpw));
-  if (sym) blocks = std::max(blocks, cdiv(sym->i + 1, 256));
+  // roles: a wave per sign word (4 per block), a thread per column, a block per
+  // deterministic column range (and per affine-form word on the sampling path)
+  u32 blocks = std::max(std::max(cdiv(t.L, 4), cdiv(t.n, 256)), cdiv(t.n, cpw));
+  if (sym) blocks = std::max(blocks, cdiv(sym->i + 1, 64));  // one affine-form word per block
   if (sym)
     hipLaunchKernelGGL(k_post<true>, dim3(blocks), dim3(256), 0, s, t.X, t.Z, t.R, mask, pivx, pivz, cnt0, cnt1, st,
                        stats, out_bits, t.Ls, t.L, t.K, t.n, q, cpc, cpw, *sym);

@@ -630,7 +630,11 @@ sq_status sq_batch_sample(const sq_batch_item *items, uint32_t nitems, const sq_
   if (!items) return fail(SQ_EINVAL, "items is NULL");
   hipStream_t stream = (hipStream_t)hip_stream;
   u32 block = opts && opts->block ? opts->block : 256;
-  u32 max_n = opts && opts->max_batch_n ? opts->max_batch_n : 4096;
+  // Automatic: one workgroup per circuit pays off up to about a thousand
+  // qubits; larger circuits finish sooner on the whole GPU (measured on the
+  // MI355X on the batched/served mix: 1024 qubits and 8 streams 2.2 s, 4096
+  // qubits 6.9 s).
+  u32 max_n = opts && opts->max_batch_n ? opts->max_batch_n : 1024;
   if (block % 64 || block < 64 || block > 512) return fail(SQ_EINVAL, "batch block must be a multiple of 64 in [64, 512]");
   max_n = std::min(max_n, kBatchMaxN);
   for (u32 k = 0; k < nitems; ++k) {
@@ -660,7 +664,7 @@ sq_status sq_batch_sample(const sq_batch_item *items, uint32_t nitems, const sq_
   // Large items: single-tableau path, several at once on worker threads with
   // their own (default-priority) streams, overlapping each other's launch
   // latency and the batched launch below.
-  const u32 nworkers = std::min<u32>((u32)large.size(), opts && opts->streams ? opts->streams : 4);
+  const u32 nworkers = std::min<u32>((u32)large.size(), opts && opts->streams ? opts->streams : 8);
   std::vector<sq_status> wstatus(nworkers, SQ_OK);
   std::vector<std::string> werr(nworkers);
   std::vector<std::thread> workers;

@@ -329,6 +329,36 @@ def test_full_size_sampled_rows(cfg_id, depth, nmeas):
     assert not r2.any()
 
 
+@pytest.mark.slow
+def test_config3_full_depth_sampled_rows():
+    """n = 65,536 at its full depth (1000 generator layers, 72 M gates, in
+    the default launch configuration), then the first 16 measurements of the
+    final sweep: outcomes and 56 sampled rows against the row-subset oracle."""
+    from paper_2603_14641_amd import Program
+    cfg = CONFIGS[3]
+    n, nmeas = cfg.n, 16
+    rng = np.random.default_rng(33)
+    rows = sorted(set(list(range(n, n + 32)) + list(range(0, 8))
+                      + [int(v) for v in rng.choice(np.arange(8, 2 * n), 16, replace=False)]))
+    ops = circuit_ops(cfg, final_measure=False)
+    assert int(np.count_nonzero(ops["type"] == orc.MEASURE)) == 0
+    meas = np.array([[orc.MEASURE, q, 0] for q in range(nmeas)], dtype=np.uint32)
+    allops = np.concatenate([np.stack([ops["type"], ops["q0"], ops["q1"]], 1).astype(np.uint32), meas])
+    sub = orc.Tableau(n, rows=rows)
+    rb, rr, _ = sub.run(allops, seed=cfg.seed, shot=0)
+    assert rb.size == nmeas, "a pivot fell outside the sampled stabilizer prefix"
+    t = _tab(n)
+    bits, rnd = t.run_to_host(Program(n, allops), seed=cfg.seed, shot=0)
+    _assert_same(bits, rb, "outcomes")
+    _assert_same(rnd, rr, "random flags")
+    x, z, r = t.export_rows(rows)
+    sx, sz, sr = sub.rows_array()
+    _assert_same(x, sx, "sampled x rows")
+    _assert_same(z, sz, "sampled z rows")
+    _assert_same(r, sr, "sampled signs")
+    assert t.error_flags() == 0
+
+
 def test_layer_then_inverse_is_identity_at_180k():
     """Any size: a generator layer followed by its inverse restores |0...0> exactly, signs included."""
     cfg = CONFIGS[4]
