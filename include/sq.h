@@ -273,7 +273,7 @@ typedef struct {
   uint32_t rowsum_wpt;         /* words per thread in the rowsum kernel */
   uint32_t rowsum_cols;        /* pivot-row columns per workgroup (per chunk) */
   uint32_t det_cols;           /* columns per workgroup of the deterministic-product phase */
-  uint32_t meas_block;         /* sq_measure: random measurements per blocked pass (1 = one at a time, <= 16) */
+  uint32_t meas_block;         /* sq_measure: random measurements per blocked pass (1 = one at a time, <= 32) */
 } sq_tuning;
 sq_status sq_get_tuning(const sq_tableau *t, sq_tuning *out);
 sq_status sq_set_tuning(sq_tableau *t, const sq_tuning *in);

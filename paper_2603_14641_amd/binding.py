@@ -21,7 +21,7 @@ I, H, S, SDG, X, Y, Z, CX, CZ, CY, SWAP, ISWAP, MEASURE = 0, 1, 2, 3, 4, 5, 6, 7
 K_LAYER, K_SIGNS, K_PIVOT, K_GATHER, K_ROWSUM, K_POST, K_BPIVOT, K_BPREP, K_BPASS, K_BFINAL = range(10)
 KERNEL_NAMES = ["layer", "signs", "pivot", "gather", "rowsum", "post",
                 "block_pivot", "block_prep", "block_pass", "block_final"]
-MAX_MEAS_BLOCK = 16
+MAX_MEAS_BLOCK = 32
 
 EXPORTED = [
     "sq_last_error", "sq_version", "sq_bytes_required", "sq_create", "sq_destroy", "sq_reset", "sq_sync",

@@ -13,10 +13,12 @@
 // bilinear: lam(A B) = lam(A) + lam(B) + 2 (z_A . x_B). So
 //   lam(C_h h) = sum_s b_s lam(P_s) + 2 sum_{s<s'} b_s b_s' (z_{P_s'} . x_{P_s})
 //                + lam(h) + 2 XOR_s b_s (z_{P_s} . x_h)   (mod 4),
-// and the new sign is (lam - |x' & z'|) / 2, the difference being even. Per
-// row the pass needs only |x & z| - |x' & z'| (mod 4, over columns where some
-// pivot is not the identity) and the k parities z_{P_s} . x_h: a 2-bit
-// counter and k parity words per row word. D_{p_s} becomes P_s times the later
+// and the new sign is (lam - |x' & z'|) / 2, the difference being even. The
+// last term is z_{C_h} . x_h, and per column j the bit z_{C_h}(j) =
+// XOR_s b_s z_{P_s}(j) is exactly the z update the pass applies there, so it
+// is the XOR over columns of (z update & x). Per row word the pass keeps
+// |x & z| - |x' & z'| (mod 4, over columns where some pivot is not the
+// identity) as a 2-bit counter and that one parity word. D_{p_s} becomes P_s times the later
 // pivots that hit it; S_{p_s} becomes (-1)^coin Z_{q_s}. The block ends before
 // the first deterministic measurement, which then takes the single path.
 #include "sq_device.h"
@@ -31,28 +33,38 @@ __global__ void k_blk_snap(const u64 *__restrict__ X, u32 Ls, u32 L, BlkArgs a, 
   snap[(size_t)s * Ls + w] = X[(size_t)a.q[s] * Ls + w];
 }
 
-// -------------------------------------------------------------- pivots (one wave)
-// Sequential over the measurements of the block, but only the pivot search
-// is: lane l owns stabilizer word 64t + l of tile t, so a lane only ever
-// reads words it wrote itself and the wave needs no barrier. For step s the
+// -------------------------------------------------------------- pivots (one workgroup)
+// Sequential over the measurements of the block; within a step the
+// stabilizer words are spread over the workgroup's waves. For step s the
 // stabilizer half of column q_s as it stands before measurement s is
 //   snap_s ^ XOR_{s' < s, M[s'][s] = 1} (hit mask of s'),
-// with the rows S_{p_s'} (now Z_{q_s'}, no x) cleared; tiles are computed
-// lazily, in order, for every earlier step first. A block ends before its
-// first deterministic measurement (no stabilizer word is nonzero).
-__global__ __launch_bounds__(64) void k_blk_pivots(const u64 *__restrict__ snap, u64 *__restrict__ bm, u32 Ls,
-                                                    u32 K, BlkArgs a, BlkState *__restrict__ bs,
-                                                    uint8_t *__restrict__ out_bits, uint8_t *__restrict__ out_rand) {
-  const u32 lane = threadIdx.x;
+// with the rows S_{p_s'} (now Z_{q_s'}, no x) cleared. Words come in tiles of
+// 64; wave v owns the tiles t = v mod PW_WAVES and lane l word 64t + l, so a
+// lane only ever reads words it wrote itself. Each wave computes its tiles
+// lazily, in order (for every earlier step first), and stops at its first
+// nonzero tile; the smallest such word over the waves holds the pivot. A
+// block ends before its first deterministic measurement (no nonzero word).
+constexpr u32 PW_WAVES = 16;
+
+__global__ __launch_bounds__(64 * PW_WAVES) void k_blk_pivots(const u64 *__restrict__ snap, u64 *__restrict__ bm,
+                                                               u32 Ls, u32 K, BlkArgs a, BlkState *__restrict__ bs,
+                                                               uint8_t *__restrict__ out_bits,
+                                                               uint8_t *__restrict__ out_rand) {
+  __shared__ u32 s_wmin, s_hit;
+  __shared__ u64 s_vmin;
+  // uniform per-step state in LDS (indexed by step, which is not a
+  // compile-time constant); done[] is per wave and written by its lane 0
+  __shared__ u32 piv[KB];              // pivot of each decided step
+  __shared__ u32 mrow[KB];             // M[s]: bit s2 = x of P_s at q_{s2}
+  __shared__ u32 sdone[PW_WAVES][KB];  // tiles of each wave computed per step
+  const u32 tid = threadIdx.x, lane = tid & 63u, wave = tid >> 6;
   const u32 ntiles = (K + 63u) / 64u;
-  u32 done[KB];   // tiles computed per step (uniform)
-  u32 piv[KB];    // pivot of each decided step
-  u32 mrow[KB];   // M[s]: bit s2 = x of P_s at q_{s2}
-#pragma unroll
-  for (u32 s = 0; s < KB; ++s) { done[s] = 0; piv[s] = 0; mrow[s] = 0; }
-  // stabilizer word w of step s (w = 64 * tile + lane), stored in bm's S half
-  auto tile_word = [&](u32 s, u32 t) -> u64 {
-    const u32 w = t * 64u + lane;
+  u32 *done = sdone[wave];
+  if (tid < KB) { piv[tid] = 0; mrow[tid] = 0; }
+  if (lane < KB) done[lane] = 0;
+  __syncthreads();
+  auto word_of = [&](u32 j) { return (j * PW_WAVES + wave) * 64u + lane; };  // local tile j
+  auto tile_word = [&](u32 s, u32 w) -> u64 {
     if (w >= K) return 0ULL;
     u64 v = snap[(size_t)s * Ls + K + w];
     for (u32 sp = 0; sp < s; ++sp) {
@@ -61,71 +73,80 @@ __global__ __launch_bounds__(64) void k_blk_pivots(const u64 *__restrict__ snap,
     }
     return v;
   };
+  const u32 myt = ntiles > wave ? (ntiles - wave + PW_WAVES - 1) / PW_WAVES : 0;  // tiles of this wave
   u32 k = a.k;
   for (u32 s = 0; s < a.k; ++s) {
-    u32 wmin = 0xFFFFFFFFu;
-    u64 vmin = 0;
-    for (u32 t = 0; t < ntiles; ++t) {
+    if (tid == 0) s_wmin = 0xFFFFFFFFu;
+    __syncthreads();
+    for (u32 j = 0; j < myt; ++j) {
       // earlier steps first (their pivots are known, so their own bits are cleared too)
       for (u32 sp = 0; sp < s; ++sp) {
-        while (done[sp] <= t) {
-          const u32 tt = done[sp];
-          u64 v = tile_word(sp, tt);
-          const u32 w = tt * 64u + lane;
+        for (u32 d = done[sp]; d <= j; ++d) {
+          const u32 w = word_of(d);
+          u64 v = tile_word(sp, w);
           if ((piv[sp] >> 6) == w) v &= ~(1ULL << (piv[sp] & 63u));
           if (w < K) bm[(size_t)sp * Ls + K + w] = v;
-          done[sp] = tt + 1;
         }
+        if (lane == 0 && done[sp] <= j) done[sp] = j + 1;
       }
-      const u64 v = tile_word(s, t);
-      const u32 w = t * 64u + lane;
+      const u32 w = word_of(j);
+      const u64 v = tile_word(s, w);
       if (w < K) bm[(size_t)s * Ls + K + w] = v;
-      done[s] = t + 1;
+      if (lane == 0) done[s] = j + 1;
       const u64 nz = __ballot(v != 0);
-      if (nz) {
-        const u32 l = (u32)__builtin_ctzll(nz);
-        wmin = t * 64u + l;
-        vmin = __shfl(v, (int)l);
+      if (nz) {  // uniform over the wave
+        if (lane == (u32)__builtin_ctzll(nz)) atomicMin(&s_wmin, w);
         break;
       }
     }
+    __syncthreads();
+    const u32 wmin = s_wmin;
     if (wmin == 0xFFFFFFFFu) {  // deterministic: the block ends here
       k = s;
       break;
     }
-    const u32 p = wmin * 64u + (u32)__builtin_ctzll(vmin);
-    const u32 pl = wmin & 63u;
-    const u64 bit = 1ULL << (p & 63u);
-    // earlier pivots that hit S_p (lane pl holds word wmin of every earlier step)
-    u32 hit = 0;
-    for (u32 sp = 0; sp < s; ++sp) {
-      const u64 b = lane == pl ? bm[(size_t)sp * Ls + K + wmin] : 0ULL;
-      if (__ballot((b & bit) != 0)) hit |= 1u << sp;
+    const u32 owner = (wmin >> 6) % PW_WAVES, pl = wmin & 63u;
+    // the owning lane holds word wmin of this and every earlier step
+    if (wave == owner && lane == pl) {
+      const u64 vmin = bm[(size_t)s * Ls + K + wmin];
+      const u64 bit = 1ULL << (u32)__builtin_ctzll(vmin);
+      u32 hit = 0;  // earlier pivots that hit S_p
+      for (u32 sp = 0; sp < s; ++sp)
+        if (bm[(size_t)sp * Ls + K + wmin] & bit) hit |= 1u << sp;
+      bm[(size_t)s * Ls + K + wmin] = vmin & ~bit;  // S_p is not multiplied by P_s
+      s_vmin = vmin;
+      s_hit = hit;
     }
-    // x bits of P_s at the later measured columns, one lane per later step
+    __syncthreads();
+    const u64 vmin = s_vmin;
+    const u32 hit = s_hit;
+    const u32 p = wmin * 64u + (u32)__builtin_ctzll(vmin);
+    // x bits of P_s at the later measured columns (wave 0, one lane per later step)
     u32 mine = 0;
-    if (lane > s && lane < a.k) {
+    if (wave == 0 && lane > s && lane < a.k) {
       u32 v = (u32)(snap[(size_t)lane * Ls + K + wmin] >> (p & 63u)) & 1u;
       for (u32 sp = 0; sp < s; ++sp)
         if ((hit >> sp) & 1u) v ^= (mrow[sp] >> lane) & 1u;
       mine = v;
     }
     const u64 mb = __ballot(mine != 0);
-    piv[s] = p;
-    mrow[s] = (u32)mb;
-    // S_p itself is not multiplied by P_s
-    if (lane == pl) bm[(size_t)s * Ls + K + wmin] = vmin & ~bit;
-    if (lane == 0) {
+    if (wave == 0 && lane == 0) {
+      piv[s] = p;
+      mrow[s] = (u32)mb;
+    }
+    __syncthreads();
+    if (tid == 0) {
       bs->p[s] = p;
       bs->hitS[s] = hit;
-      bs->M[s] = (u32)mb;
+      bs->M[s] = mrow[s];
       const u32 c = coin_bit(a.seed, a.shot, a.m0 + s);
       bs->coin[s] = c;
       out_rand[s] = 1;
       out_bits[s] = (uint8_t)c;
     }
+    __syncthreads();  // s_wmin and s_hit are rewritten by the next step
   }
-  if (lane != 0) return;
+  if (tid != 0) return;
   bs->k = k;
   // later pivots that hit D_{p_s} (which holds P_s from measurement s on)
   for (u32 s = 0; s < k; ++s) {
@@ -195,123 +216,110 @@ __global__ void k_blk_masks(const u64 *__restrict__ snap, u64 *__restrict__ bm, 
 }
 
 // -------------------------------------------------------------- original pivot rows
+// Thread per column: the x and z words of the pivots' stabilizer words (one
+// read each per distinct word, usually one or two per block), then one wave
+// ballot per pivot packs its bits of 64 columns.
 __global__ void k_blk_gather(const u64 *__restrict__ X, const u64 *__restrict__ Z, const u64 *__restrict__ R, u32 Ls,
                              u32 K, u32 n, BlkState *__restrict__ bs, u64 *__restrict__ p0x, u64 *__restrict__ p0z) {
-  const u32 s = blockIdx.y;
-  if (s >= bs->k) return;
-  const u32 p = bs->p[s];
-  const u32 ws = K + (p >> 6), sh = p & 63u;
+  const u32 nw = bs->nwords;
   const u32 j = blockIdx.x * blockDim.x + threadIdx.x;
-  u32 xb = 0, zb = 0;
-  if (j < n) {
-    xb = (u32)(X[(size_t)j * Ls + ws] >> sh) & 1u;
-    zb = (u32)(Z[(size_t)j * Ls + ws] >> sh) & 1u;
+  for (u32 i = 0; i < nw; ++i) {
+    const u32 ws = K + bs->word[i];
+    u64 xw = 0, zw = 0;
+    if (j < n) {
+      xw = X[(size_t)j * Ls + ws];
+      zw = Z[(size_t)j * Ls + ws];
+    }
+    for (u32 m = bs->wmem[i]; m; m &= m - 1) {
+      const u32 s = (u32)__builtin_ctz(m);
+      const u32 sh = bs->p[s] & 63u;
+      const u64 bx = __ballot((xw >> sh) & 1u), bz = __ballot((zw >> sh) & 1u);
+      if ((threadIdx.x & 63u) == 0 && j < n) {
+        p0x[(size_t)s * K + (j >> 6)] = bx;
+        p0z[(size_t)s * K + (j >> 6)] = bz;
+      }
+      if (j == 0) bs->r0[s] = (u32)(R[ws] >> sh) & 1u;
+    }
   }
-  const u64 bx = __ballot(xb), bz = __ballot(zb);
-  if ((threadIdx.x & 63u) == 0 && j < n) {
-    p0x[(size_t)s * K + (j >> 6)] = bx;
-    p0z[(size_t)s * K + (j >> 6)] = bz;
-  }
-  if (j == 0) bs->r0[s] = (u32)(R[ws] >> sh) & 1u;
 }
 
 // -------------------------------------------------------------- pivot algebra
-// Thread per 64-column word: evolved pivot rows P_s = S0_{p_s} times the
-// earlier pivots that hit it; pairwise parities z_{P_a} . x_{P_b} (Qz) and
-// z_{P_a} . x_{S0_b} (R0); |x & z| of the original pivot rows and of the final
-// D_{p_s} rows (mod 4); per-column patterns of the pivots' x and z bits. The
-// last block to finish forms lam(P_s) and the final signs of the D_{p_s}.
-__global__ void k_blk_pivalg(const u64 *__restrict__ p0x, const u64 *__restrict__ p0z, u64 *__restrict__ px,
-                             u64 *__restrict__ pz, u32 *__restrict__ patx, u32 *__restrict__ patz, u32 K, u32 n,
-                             BlkState *__restrict__ bs, MeasState *__restrict__ st) {
-  __shared__ u32 s_last;
+// (1) Thread per 64-column word: the evolved pivot rows P_s = S0_{p_s} times
+// the earlier pivots that hit it, in order, and |x & z| of each original
+// pivot row (summed per pivot).
+__global__ void k_blk_evolve(const u64 *__restrict__ p0x, const u64 *__restrict__ p0z, u64 *__restrict__ px,
+                             u64 *__restrict__ pz, u32 K, BlkState *__restrict__ bs) {
   const u32 k = bs->k;
   const u32 cw = blockIdx.x * blockDim.x + threadIdx.x;
   const u32 lane = threadIdx.x & 63u;
-  u64 x[KB], z[KB];
-  u32 qz[KB], r0[KB], pc0[KB], pcd[KB];
-#pragma unroll
-  for (u32 s = 0; s < KB; ++s) { x[s] = z[s] = 0; qz[s] = r0[s] = pc0[s] = pcd[s] = 0; }
-  u32 ncols = 0;
-  if (cw < K) {
-#pragma unroll
-    for (u32 s = 0; s < KB; ++s) {
-      if (s >= k) break;
-      u64 vx = p0x[(size_t)s * K + cw], vz = p0z[(size_t)s * K + cw];
-      pc0[s] = (u32)__popcll(vx & vz);
-      const u32 hit = bs->hitS[s];
-#pragma unroll
-      for (u32 sp = 0; sp < KB; ++sp)
-        if (sp < s && ((hit >> sp) & 1u)) { vx ^= x[sp]; vz ^= z[sp]; }
-      x[s] = vx;
-      z[s] = vz;
+  for (u32 s = 0; s < k; ++s) {
+    u64 vx = 0, vz = 0;
+    u32 pc = 0;
+    if (cw < K) {
+      vx = p0x[(size_t)s * K + cw];
+      vz = p0z[(size_t)s * K + cw];
+      pc = (u32)__popcll(vx & vz);
+      for (u32 m = bs->hitS[s]; m; m &= m - 1) {  // earlier pivots (own writes of this thread)
+        const u32 sp = (u32)__builtin_ctz(m);
+        vx ^= px[(size_t)sp * K + cw];
+        vz ^= pz[(size_t)sp * K + cw];
+      }
       px[(size_t)s * K + cw] = vx;
       pz[(size_t)s * K + cw] = vz;
     }
-#pragma unroll
-    for (u32 a = 0; a < KB; ++a) {
-      if (a >= k) break;
-#pragma unroll
-      for (u32 b = 0; b < KB; ++b) {
-        if (b >= k) break;
-        qz[a] |= ((u32)__popcll(z[a] & x[b]) & 1u) << b;
-        r0[a] |= ((u32)__popcll(z[a] & p0x[(size_t)b * K + cw]) & 1u) << b;
-      }
-      // final D_{p_a} row: P_a times its later hits
-      u64 dx = x[a], dz = z[a];
-      const u32 dh = bs->dhits[a];
-#pragma unroll
-      for (u32 s2 = 0; s2 < KB; ++s2)
-        if (s2 < k && ((dh >> s2) & 1u)) { dx ^= x[s2]; dz ^= z[s2]; }
-      pcd[a] = (u32)__popcll(dx & dz);
-    }
-    // per-column patterns (bit s: pivot s has x / z on the column)
-    const u32 jn = min(64u, n - cw * 64u);
-    for (u32 b = 0; b < jn; ++b) {
-      u32 vx = 0, vz = 0;
-#pragma unroll
-      for (u32 s = 0; s < KB; ++s) {
-        vx |= (u32)((x[s] >> b) & 1ULL) << s;
-        vz |= (u32)((z[s] >> b) & 1ULL) << s;
-      }
-      patx[cw * 64u + b] = vx;
-      patz[cw * 64u + b] = vz;
-      ncols += (vx | vz) != 0;
-    }
+    for (int off = 32; off > 0; off >>= 1) pc += (u32)__shfl_xor((int)pc, off);
+    if (lane == 0 && pc) atomicAdd(&bs->pc0[s], pc);
   }
-  // wave reductions, then one atomic per wave
-#pragma unroll
-  for (u32 a = 0; a < KB; ++a) {
+}
+
+// (2) Thread per (64-column word, pivot a): bits b of z_{P_a} . x_{P_b} (Qz)
+// and of z_{P_a} . x_{S0_b} (R0), and |x & z| of the final D_{p_a} (P_a times
+// its later hits). The last block to finish forms lam(P_s) and the final
+// signs of the D_{p_s}.
+__global__ void k_blk_pairs(const u64 *__restrict__ p0x, const u64 *__restrict__ px, const u64 *__restrict__ pz,
+                            u32 K, BlkState *__restrict__ bs, MeasState *__restrict__ st) {
+  __shared__ u32 s_last;
+  __shared__ u32 lam[KB];
+  const u32 k = bs->k;
+  const u32 a = blockIdx.y;
+  const u32 cw = blockIdx.x * blockDim.x + threadIdx.x;
+  const u32 lane = threadIdx.x & 63u;
+  if (a < k) {
+    u32 qz = 0, r0 = 0, pcd = 0;
+    if (cw < K) {
+      const u64 za = pz[(size_t)a * K + cw];
+      for (u32 b = 0; b < k; ++b) {
+        qz |= ((u32)__popcll(za & px[(size_t)b * K + cw]) & 1u) << b;
+        r0 |= ((u32)__popcll(za & p0x[(size_t)b * K + cw]) & 1u) << b;
+      }
+      u64 dx = px[(size_t)a * K + cw], dz = za;
+      for (u32 m = bs->dhits[a]; m; m &= m - 1) {
+        const u32 s2 = (u32)__builtin_ctz(m);
+        dx ^= px[(size_t)s2 * K + cw];
+        dz ^= pz[(size_t)s2 * K + cw];
+      }
+      pcd = (u32)__popcll(dx & dz);
+    }
+    // wave reductions: parities by ballot, counts by shuffles
     u32 wq = 0, wr = 0;
-#pragma unroll
-    for (u32 b = 0; b < KB; ++b) {
-      wq |= ((u32)__popcll(__ballot((qz[a] >> b) & 1u)) & 1u) << b;
-      wr |= ((u32)__popcll(__ballot((r0[a] >> b) & 1u)) & 1u) << b;
+    for (u32 b = 0; b < k; ++b) {
+      wq |= ((u32)__popcll(__ballot((qz >> b) & 1u)) & 1u) << b;
+      wr |= ((u32)__popcll(__ballot((r0 >> b) & 1u)) & 1u) << b;
     }
-    u32 sp0 = pc0[a], spd = pcd[a];
-    for (int off = 32; off > 0; off >>= 1) {
-      sp0 += (u32)__shfl_xor((int)sp0, off);
-      spd += (u32)__shfl_xor((int)spd, off);
-    }
-    if (lane == 0 && a < k) {
+    for (int off = 32; off > 0; off >>= 1) pcd += (u32)__shfl_xor((int)pcd, off);
+    if (lane == 0) {
       if (wq) atomicXor(&bs->Qz[a], wq);
       if (wr) atomicXor(&bs->R0[a], wr);
-      atomicAdd(&bs->pc0[a], sp0);
-      atomicAdd(&bs->pcD[a], spd);
+      if (pcd) atomicAdd(&bs->pcD[a], pcd);
     }
   }
-  for (int off = 32; off > 0; off >>= 1) ncols += (u32)__shfl_xor((int)ncols, off);
-  if (lane == 0 && ncols) atomicAdd(&bs->ncols, ncols);
   __threadfence();
   __syncthreads();
-  if (threadIdx.x == 0) {
-    s_last = (atomicAdd(&bs->done, 1u) == gridDim.x - 1) ? 1u : 0u;
-  }
+  if (threadIdx.x == 0) s_last = (atomicAdd(&bs->done, 1u) == gridDim.x * gridDim.y - 1) ? 1u : 0u;
   __syncthreads();
   if (!s_last || threadIdx.x != 0) return;
   __threadfence();
   // lam(P_s): start from the original row, multiply in the earlier pivots that hit it, in order
-  u32 lam[KB];
   for (u32 s = 0; s < k; ++s) {
     u32 l = (2u * bs->r0[s] + atomicAdd(&bs->pc0[s], 0u)) & 3u;
     const u32 hit = bs->hitS[s];
@@ -320,8 +328,7 @@ __global__ void k_blk_pivalg(const u64 *__restrict__ p0x, const u64 *__restrict_
       if (!((hit >> sp) & 1u)) continue;
       // z_{P_sp} . x_current, x_current = x_{S0_s} ^ XOR_{used} x_{P}
       u32 par = (atomicAdd(&bs->R0[sp], 0u) >> s) & 1u;
-      const u32 qrow = atomicAdd(&bs->Qz[sp], 0u);
-      par ^= (u32)__popc(qrow & used) & 1u;
+      par ^= (u32)__popc(atomicAdd(&bs->Qz[sp], 0u) & used) & 1u;
       l = (lam[sp] + l + 2u * par) & 3u;
       used |= 1u << sp;
     }
@@ -336,8 +343,7 @@ __global__ void k_blk_pivalg(const u64 *__restrict__ p0x, const u64 *__restrict_
     u32 used = 1u << s;
     for (u32 s2 = s + 1; s2 < k; ++s2) {
       if (!((dh >> s2) & 1u)) continue;
-      const u32 qrow = atomicAdd(&bs->Qz[s2], 0u);
-      const u32 par = (u32)__popc(qrow & used) & 1u;
+      const u32 par = (u32)__popc(atomicAdd(&bs->Qz[s2], 0u) & used) & 1u;
       l = (lam[s2] + l + 2u * par) & 3u;
       used |= 1u << s2;
     }
@@ -348,9 +354,29 @@ __global__ void k_blk_pivalg(const u64 *__restrict__ p0x, const u64 *__restrict_
   if (flags) atomicOr(&st->flags, flags);
 }
 
+// (3) Thread per column: bit s of patx / patz = pivot s has x / z there;
+// columns where some pivot is not the identity are counted.
+__global__ void k_blk_patterns(const u64 *__restrict__ px, const u64 *__restrict__ pz, u32 *__restrict__ patx,
+                               u32 *__restrict__ patz, u32 K, u32 n, BlkState *__restrict__ bs) {
+  const u32 k = bs->k;
+  const u32 j = blockIdx.x * blockDim.x + threadIdx.x;
+  u32 vx = 0, vz = 0;
+  if (j < n) {
+    const u32 cw = j >> 6, sh = j & 63u;
+    for (u32 s = 0; s < k; ++s) {
+      vx |= (u32)((px[(size_t)s * K + cw] >> sh) & 1ULL) << s;
+      vz |= (u32)((pz[(size_t)s * K + cw] >> sh) & 1ULL) << s;
+    }
+    patx[j] = vx;
+    patz[j] = vz;
+  }
+  const u32 c = (u32)__popcll(__ballot((vx | vz) != 0));
+  if ((threadIdx.x & 63u) == 0 && c) atomicAdd(&bs->ncols, c);
+}
+
 // -------------------------------------------------------------- the pass
 // Grid (row tiles, column chunks). A thread owns one row word; per column
-// where some pivot is not the identity (patterns from k_blk_pivalg, uniform
+// where some pivot is not the identity (patterns from k_blk_patterns, uniform
 // over the wave): XOR in the masks of the pivots with x (z) on that column,
 // count |x & z| - |x' & z'| (mod 4) and the parities z_{P_s} . x_h.
 __global__ __launch_bounds__(256) void k_blk_pass(u64 *__restrict__ X, u64 *__restrict__ Z,
@@ -372,9 +398,7 @@ __global__ __launch_bounds__(256) void k_blk_pass(u64 *__restrict__ X, u64 *__re
     any |= b[s];
   }
   if (any == 0) return;
-  u64 y[KB];
-#pragma unroll
-  for (u32 s = 0; s < KB; ++s) y[s] = 0;
+  u64 yy = 0;          // z_{C_h} . x_h per row: XOR over columns of dz & x
   u64 d0 = 0, d1 = 0;  // |x & z| - |x' & z'| (mod 4), bit-sliced
   for (u32 j = j0; j < j1; ++j) {
     const u32 px = patx[j], pz = patz[j];
@@ -385,8 +409,9 @@ __global__ __launch_bounds__(256) void k_blk_pass(u64 *__restrict__ X, u64 *__re
 #pragma unroll
     for (u32 s = 0; s < KB; ++s) {
       if ((px >> s) & 1u) dx ^= b[s];
-      if ((pz >> s) & 1u) { dz ^= b[s]; y[s] ^= x; }
+      if ((pz >> s) & 1u) dz ^= b[s];
     }
+    yy ^= dz & x;
     const u64 x2 = x ^ dx, z2 = z ^ dz;
     const u64 o1 = x & z, n1 = x2 & z2;
     const u64 plus = o1 & ~n1, minus = n1 & ~o1;
@@ -397,28 +422,26 @@ __global__ __launch_bounds__(256) void k_blk_pass(u64 *__restrict__ X, u64 *__re
     if (px) X[o] = x2;
     if (pz) Z[o] = z2;
   }
-  const size_t cs = (size_t)blockIdx.y * (2 + KB) * Ls;
+  const size_t cs = (size_t)blockIdx.y * BLK_PART * Ls;
   part[cs + w] = d0;
   part[cs + Ls + w] = d1;
-#pragma unroll
-  for (u32 s = 0; s < KB; ++s)
-    if (s < k) part[cs + (size_t)(2 + s) * Ls + w] = y[s];
+  part[cs + 2 * (size_t)Ls + w] = yy;
 }
 
 // -------------------------------------------------------------- chunk reduction
 // Thread per (row word, field): field 0 adds the 2-bit counters of all
-// chunks (mod 4), field 1 + s XORs the parity words of pivot s. The result
-// goes to chunk 0's slots.
+// chunks (mod 4), field 1 XORs their parity words. The result goes to chunk
+// 0's slots.
 __global__ void k_blk_reduce(u64 *__restrict__ part, const u64 *__restrict__ bm, const BlkState *__restrict__ bs,
                              u32 Ls, u32 L, u32 nchunks) {
   const u32 k = bs->k;
   const u32 w = blockIdx.x * blockDim.x + threadIdx.x;
   const u32 f = blockIdx.y;
-  if (w >= L || f > k) return;
+  if (w >= L) return;
   u64 any = 0;
   for (u32 s = 0; s < k; ++s) any |= bm[(size_t)s * Ls + w];
   if (any == 0) return;  // k_blk_pass wrote nothing for this row word
-  const size_t stride = (size_t)(2 + KB) * Ls;
+  const size_t stride = (size_t)BLK_PART * Ls;
   if (f == 0) {
     u64 d0 = 0, d1 = 0;
     for (u32 c = 0; c < nchunks; ++c) {
@@ -430,7 +453,7 @@ __global__ void k_blk_reduce(u64 *__restrict__ part, const u64 *__restrict__ bm,
     part[w] = d0;
     part[Ls + w] = d1;
   } else {
-    const size_t o = (size_t)(1 + f) * Ls + w;
+    const size_t o = 2 * (size_t)Ls + w;
     u64 y = 0;
     for (u32 c = 0; c < nchunks; ++c) y ^= part[c * stride + o];
     part[o] = y;
@@ -438,91 +461,96 @@ __global__ void k_blk_reduce(u64 *__restrict__ part, const u64 *__restrict__ bm,
 }
 
 // -------------------------------------------------------------- final
-// Threads t < L: signs of the row word t (hit rows from the lam algebra,
-// special rows from dsign / the coins). Threads t < n: column t's bits of the
-// special rows.
-__global__ void k_blk_final(u64 *__restrict__ X, u64 *__restrict__ Z, u64 *__restrict__ R,
-                            const u64 *__restrict__ bm, const u32 *__restrict__ patx, const u32 *__restrict__ patz,
-                            const u64 *__restrict__ part, const BlkState *__restrict__ bs, BlkArgs a,
-                            MeasState *__restrict__ st, MeasStats *__restrict__ stats, u32 Ls, u32 L, u32 K, u32 n) {
+// Thread per row word (blocks of BLK_SIGN_T): new signs of the hit rows from
+// the lam algebra, then the special rows' signs (dsign, the coins). The hit
+// masks are staged in LDS, where they can be indexed by pivot.
+constexpr u32 BLK_SIGN_T = 128;
+
+__global__ __launch_bounds__(BLK_SIGN_T) void k_blk_signs(u64 *__restrict__ R, const u64 *__restrict__ bm,
+                                                           const u64 *__restrict__ part,
+                                                           const BlkState *__restrict__ bs,
+                                                           MeasState *__restrict__ st, MeasStats *__restrict__ stats,
+                                                           u32 Ls, u32 L, u32 K) {
+  __shared__ u64 sb[KB][BLK_SIGN_T];
   const u32 k = bs->k;
   if (k == 0) return;
-  const u32 t = blockIdx.x * blockDim.x + threadIdx.x;
-  if (t < L) {
-    const u32 w = t;
-    u64 b[KB];
-    u64 any = 0;
-#pragma unroll
-    for (u32 s = 0; s < KB; ++s) {
-      b[s] = (s < k) ? bm[(size_t)s * Ls + w] : 0ULL;
-      any |= b[s];
-    }
-    u64 r = R[w];
-    bool touched = false;
-    if (any) {
-      // chunk sums reduced by k_blk_reduce into chunk 0's slots
-      const u64 d0 = part[w], d1 = part[Ls + w];
-      u64 y[KB];
-#pragma unroll
-      for (u32 s = 0; s < KB; ++s) y[s] = s < k ? part[(size_t)(2 + s) * Ls + w] : 0ULL;
-      // lam = sum_s b_s lam(P_s) + 2 sum_{s<s'} b_s b_s' Qz[s'][s] + 2 r + 2 XOR b_s y_s + d
-      u64 l0 = 0, l1 = 0;
-      for (u32 s = 0; s < k; ++s) {
-        const u32 lp = bs->lam[s];
-        if (lp & 1u) { l1 ^= l0 & b[s]; l0 ^= b[s]; }
-        if (lp & 2u) l1 ^= b[s];
-        const u32 qrow = bs->Qz[s];
-        for (u32 sp = 0; sp < s; ++sp)
-          if ((qrow >> sp) & 1u) l1 ^= b[s] & b[sp];
-        l1 ^= b[s] & y[s];
-      }
-      l1 ^= r;
-      {
-        const u64 carry = l0 & d0;
-        l0 ^= d0;
-        l1 ^= d1 ^ carry;
-      }
-      if (l0 & any) atomicOr(&st->flags, 1u);
-      r = (r & ~any) | (l1 & any);
-      touched = true;
-    }
-    for (u32 s = 0; s < k; ++s) {
-      const u32 p = bs->p[s];
-      const u64 bit = 1ULL << (p & 63u);
-      if (w == (p >> 6)) { r = (r & ~bit) | (bs->dsign[s] ? bit : 0ULL); touched = true; }
-      if (w == K + (p >> 6)) { r = (r & ~bit) | (bs->coin[s] ? bit : 0ULL); touched = true; }
-    }
-    if (touched) R[w] = r;
-    if (t == 0) {
-      stats->n_random += k;
-      stats->blocks += 1;
-    }
+  const u32 tid = threadIdx.x;
+  const u32 w = blockIdx.x * blockDim.x + tid;
+  if (w >= L) return;
+  u64 any = 0;
+  for (u32 s = 0; s < k; ++s) {
+    const u64 v = bm[(size_t)s * Ls + w];
+    sb[s][tid] = v;  // each thread reads back only its own column of sb
+    any |= v;
   }
-  if (t < n) {
-    // column t of the special rows, one read-modify-write per distinct word:
-    // D_{p_s} = P_s times its later hits, S_{p_s} = Z_{q_s}
-    const u32 j = t;
-    const u32 px = patx[j], pz = patz[j];
-    u64 *x = X + (size_t)j * Ls;
-    u64 *z = Z + (size_t)j * Ls;
-    const u32 nw = bs->nwords;
-    for (u32 i = 0; i < nw; ++i) {
-      const u32 wd = bs->word[i], mem = bs->wmem[i];
-      u64 mask = 0, xd = 0, zd = 0, zs = 0;
-      for (u32 m = mem; m; m &= m - 1) {
-        const u32 s = (u32)__builtin_ctz(m);
-        const u64 bit = 1ULL << (bs->p[s] & 63u);
-        const u32 dh = bs->dhits[s] | (1u << s);
-        mask |= bit;
-        if (__popc(px & dh) & 1) xd |= bit;
-        if (__popc(pz & dh) & 1) zd |= bit;
-        if (j == a.q[s]) zs |= bit;
-      }
-      x[wd] = (x[wd] & ~mask) | xd;
-      z[wd] = (z[wd] & ~mask) | zd;
-      x[K + wd] &= ~mask;
-      z[K + wd] = (z[K + wd] & ~mask) | zs;
+  u64 r = R[w];
+  bool touched = false;
+  if (any) {
+    // chunk sums reduced by k_blk_reduce into chunk 0's slots
+    const u64 d0 = part[w], d1 = part[Ls + w], yy = part[2 * (size_t)Ls + w];
+    // lam = sum_s b_s lam(P_s) + 2 sum_{s<s'} b_s b_s' Qz[s'][s] + 2 r + 2 (z_{C_h} . x_h) + d
+    u64 l0 = 0, l1 = 0;
+    for (u32 s = 0; s < k; ++s) {
+      const u64 bsv = sb[s][tid];
+      const u32 lp = bs->lam[s];
+      if (lp & 1u) { l1 ^= l0 & bsv; l0 ^= bsv; }
+      if (lp & 2u) l1 ^= bsv;
+      u64 acc = 0;  // XOR of the earlier masks selected by row s of Qz
+      for (u32 m = bs->Qz[s] & ((1u << s) - 1u); m; m &= m - 1) acc ^= sb[__builtin_ctz(m)][tid];
+      l1 ^= bsv & acc;
     }
+    l1 ^= r ^ yy;
+    {
+      const u64 carry = l0 & d0;
+      l0 ^= d0;
+      l1 ^= d1 ^ carry;
+    }
+    if (l0 & any) atomicOr(&st->flags, 1u);
+    r = (r & ~any) | (l1 & any);
+    touched = true;
+  }
+  for (u32 s = 0; s < k; ++s) {
+    const u32 p = bs->p[s];
+    const u64 bit = 1ULL << (p & 63u);
+    if (w == (p >> 6)) { r = (r & ~bit) | (bs->dsign[s] ? bit : 0ULL); touched = true; }
+    if (w == K + (p >> 6)) { r = (r & ~bit) | (bs->coin[s] ? bit : 0ULL); touched = true; }
+  }
+  if (touched) R[w] = r;
+  if (w == 0) {
+    stats->n_random += k;
+    stats->blocks += 1;
+  }
+}
+
+// Thread per column: the column's bits of the special rows, one
+// read-modify-write per distinct row word holding pivots: D_{p_s} = P_s times
+// its later hits, S_{p_s} = Z_{q_s}.
+__global__ void k_blk_special(u64 *__restrict__ X, u64 *__restrict__ Z, const u32 *__restrict__ patx,
+                              const u32 *__restrict__ patz, const BlkState *__restrict__ bs, BlkArgs a, u32 Ls, u32 K,
+                              u32 n) {
+  const u32 k = bs->k;
+  const u32 j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k == 0 || j >= n) return;
+  const u32 px = patx[j], pz = patz[j];
+  u64 *x = X + (size_t)j * Ls;
+  u64 *z = Z + (size_t)j * Ls;
+  const u32 nw = bs->nwords;
+  for (u32 i = 0; i < nw; ++i) {
+    const u32 wd = bs->word[i], mem = bs->wmem[i];
+    u64 mask = 0, xd = 0, zd = 0, zs = 0;
+    for (u32 m = mem; m; m &= m - 1) {
+      const u32 s = (u32)__builtin_ctz(m);
+      const u64 bit = 1ULL << (bs->p[s] & 63u);
+      const u32 dh = bs->dhits[s] | (1u << s);
+      mask |= bit;
+      if (__popc(px & dh) & 1) xd |= bit;
+      if (__popc(pz & dh) & 1) zd |= bit;
+      if (j == a.q[s]) zs |= bit;
+    }
+    x[wd] = (x[wd] & ~mask) | xd;
+    z[wd] = (z[wd] & ~mask) | zd;
+    x[K + wd] &= ~mask;
+    z[K + wd] = (z[K + wd] & ~mask) | zs;
   }
 }
 
@@ -551,7 +579,8 @@ __global__ void k_blk_bytes(const u64 *__restrict__ bm, const BlkState *__restri
 hipError_t launch_blk_pivots(const TabDev &t, const BlkArgs &a, const BlkBuffers &b, uint8_t *out_bits,
                              uint8_t *out_rand, hipStream_t s) {
   hipLaunchKernelGGL(k_blk_snap, dim3(cdiv(t.L, 256), a.k), dim3(256), 0, s, t.X, t.Ls, t.L, a, b.snap);
-  hipLaunchKernelGGL(k_blk_pivots, dim3(1), dim3(64), 0, s, b.snap, b.bm, t.Ls, t.K, a, b.bs, out_bits, out_rand);
+  hipLaunchKernelGGL(k_blk_pivots, dim3(1), dim3(64 * PW_WAVES), 0, s, b.snap, b.bm, t.Ls, t.K, a, b.bs, out_bits,
+                     out_rand);
   return hipGetLastError();
 }
 
@@ -559,10 +588,12 @@ hipError_t launch_blk_pivots(const TabDev &t, const BlkArgs &a, const BlkBuffers
 hipError_t launch_blk_prep(const TabDev &t, const BlkArgs &a, const BlkBuffers &b, MeasState *st, MeasStats *stats,
                            hipStream_t s) {
   hipLaunchKernelGGL(k_blk_masks, dim3(cdiv(t.L, 256)), dim3(256), 0, s, b.snap, b.bm, b.bs, t.Ls, t.L, t.K);
-  hipLaunchKernelGGL(k_blk_gather, dim3(cdiv(t.n, 256), a.k), dim3(256), 0, s, t.X, t.Z, t.R, t.Ls, t.K, t.n, b.bs,
-                     b.p0x, b.p0z);
-  hipLaunchKernelGGL(k_blk_pivalg, dim3(cdiv(t.K, 256)), dim3(256), 0, s, b.p0x, b.p0z, b.px, b.pz, b.patx, b.patz,
-                     t.K, t.n, b.bs, st);
+  hipLaunchKernelGGL(k_blk_gather, dim3(cdiv(t.n, 256)), dim3(256), 0, s, t.X, t.Z, t.R, t.Ls, t.K, t.n, b.bs, b.p0x,
+                     b.p0z);
+  hipLaunchKernelGGL(k_blk_evolve, dim3(cdiv(t.K, 64)), dim3(64), 0, s, b.p0x, b.p0z, b.px, b.pz, t.K, b.bs);
+  hipLaunchKernelGGL(k_blk_pairs, dim3(cdiv(t.K, 64), a.k), dim3(64), 0, s, b.p0x, b.px, b.pz, t.K, b.bs, st);
+  hipLaunchKernelGGL(k_blk_patterns, dim3(cdiv(t.n, 256)), dim3(256), 0, s, b.px, b.pz, b.patx, b.patz, t.K, t.n,
+                     b.bs);
   hipLaunchKernelGGL(k_blk_bytes, dim3(1), dim3(1024), 0, s, b.bm, b.bs, stats, t.Ls, t.L);
   return hipGetLastError();
 }
@@ -579,10 +610,12 @@ hipError_t launch_blk_pass(const TabDev &t, const BlkBuffers &b, u32 cpc, hipStr
 hipError_t launch_blk_final(const TabDev &t, const BlkArgs &a, const BlkBuffers &b, MeasState *st, MeasStats *stats,
                             u32 cpc, hipStream_t s) {
   const u32 nchunks = cdiv(t.n, cpc);
-  hipLaunchKernelGGL(k_blk_reduce, dim3(cdiv(t.L, 256), 1 + a.k), dim3(256), 0, s, b.part, b.bm, b.bs, t.Ls, t.L,
+  hipLaunchKernelGGL(k_blk_reduce, dim3(cdiv(t.L, 256), 2), dim3(256), 0, s, b.part, b.bm, b.bs, t.Ls, t.L,
                      nchunks);
-  hipLaunchKernelGGL(k_blk_final, dim3(cdiv(std::max(t.L, t.n), 256)), dim3(256), 0, s, t.X, t.Z, t.R, b.bm,
-                     b.patx, b.patz, b.part, b.bs, a, st, stats, t.Ls, t.L, t.K, t.n);
+  hipLaunchKernelGGL(k_blk_signs, dim3(cdiv(t.L, BLK_SIGN_T)), dim3(BLK_SIGN_T), 0, s, t.R, b.bm, b.part, b.bs, st,
+                     stats, t.Ls, t.L, t.K);
+  hipLaunchKernelGGL(k_blk_special, dim3(cdiv(t.n, 256)), dim3(256), 0, s, t.X, t.Z, b.patx, b.patz, b.bs, a, t.Ls,
+                     t.K, t.n);
   return hipGetLastError();
 }
 

@@ -97,7 +97,8 @@ struct MeasStats {
 };
 
 // Blocked random measurements (sq_block.hip): up to KB per pass.
-constexpr u32 KB = 16;
+constexpr u32 KB = 32;
+constexpr u32 BLK_PART = 3;  // partial words per (chunk, row word): counter bits 0, 1 and the parity
 struct BlkArgs {
   u32 k;          // measurements offered to the block
   u32 q[KB];      // their qubits
@@ -127,7 +128,7 @@ struct BlkBuffers {
   u64 *snap, *bm;          // KB * Ls words each: measured columns, hit masks
   u64 *p0x, *p0z, *px, *pz;  // KB * K words each: original and evolved pivot rows
   u32 *patx, *patz;        // n each: per column, bit s = pivot s has x (z) there
-  u64 *part;               // chunks * (2 + KB) * Ls partial counters and parities
+  u64 *part;               // chunks * BLK_PART * Ls partial counters and parities
   BlkState *bs;
 };
 

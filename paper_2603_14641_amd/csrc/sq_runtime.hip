@@ -172,7 +172,7 @@ size_t layout_words(const Dims &d, size_t *off) {
   for (int i = 14; i < 18; ++i) off[i] = take((size_t)KB * d.K);
   off[18] = take((d.n + 1) / 2);
   off[19] = take((d.n + 1) / 2);
-  off[20] = take((size_t)cdiv(d.n, blk_cpc_of(d)) * (2 + KB) * d.Ls);
+  off[20] = take((size_t)cdiv(d.n, blk_cpc_of(d)) * BLK_PART * d.Ls);
   off[21] = take(sizeof(BlkState) / 8 + 1);
   return o;
 }

@@ -18,7 +18,7 @@ SMALL_TILES = dict(layer_block=64, layer_wpt=1, layer_groups=3, rowsum_block=64,
                    det_cols=2, meas_block=1)
 SMALL_TILES_W2 = dict(layer_block=64, layer_wpt=2, layer_groups=7, rowsum_block=128, rowsum_wpt=2, rowsum_cols=3,
                       det_cols=3, meas_block=3)
-SINGLE = dict(meas_block=1)   # one measurement at a time (the default applies runs of up to 16 in one pass)
+SINGLE = dict(meas_block=1)   # one measurement at a time (the default applies runs of up to 32 in one pass)
 
 
 @pytest.fixture(scope="module", autouse=True)
@@ -105,7 +105,7 @@ def _measure_sequence(rng, n, count):
 
 
 @pytest.mark.parametrize("n", [2, 5, 64, 65, 300, 2000])
-@pytest.mark.parametrize("mb", [2, 5, 16])
+@pytest.mark.parametrize("mb", [2, 5, 16, 32])
 def test_blocked_measurements(n, mb):
     """Runs of random measurements applied up to mb at a time in one pass:
     outcomes, flags and the whole tableau bit-exact with one-at-a-time CHP."""
