@@ -402,3 +402,63 @@ int sqo_num_threads(void) {
   return 1;
 #endif
 }
+
+/* ------------------------------------------------------------------ */
+/* Pauli-frame sampling ("Sampling" section, Algorithm alg:sampling), one
+ * shot at a time. A shot's frame is a Pauli row (x and z bits over the n
+ * qubits); gates conjugate it with the same rules as a tableau row (its sign
+ * is not used). The frame starts with x = 0 and z drawn at random; measuring
+ * qubit q records x_q and draws z_q afresh. The outcome of measurement i in
+ * shot s is the reference sample's outcome i XOR the recorded x_q (the
+ * paper records the frame bit alone; the reference XOR is this build's
+ * reading, which makes the outcome a sample of the circuit).
+ *
+ * Random bit of shot s for event e: bit (s mod 64) of output word 0 of
+ * Philox4x64-10 with key (seed, 2^63 + floor(s / 64)) and counter
+ * (e, 0, 0, 0); events 0..n-1 initialise z of each qubit, event n + i
+ * re-draws z after measurement i. (The top key bit keeps these draws apart
+ * from the measurement coins, keyed (seed, shot).)
+ *
+ * ops: count records (type, q0, q1) with type SQO_MEASURE for measurements;
+ * ref: one byte per measurement; out: shots x W words, W = ceil(M / 64),
+ * bit i of shot s at out[s * W + i / 64]. Returns M, or -1 on bad input. */
+int sqo_frame_bit(uint64_t seed, uint64_t s, uint64_t e) {
+  uint64_t ctr[4] = {e, 0, 0, 0}, key[2] = {seed, (1ULL << 63) + (s >> 6)}, out[4];
+  sqo_philox4x64_10(ctr, key, out);
+  return (int)((out[0] >> (s & 63)) & 1);
+}
+
+int64_t sqo_frame_sample(uint32_t n, const uint32_t *ops, uint64_t count, const uint8_t *ref, uint64_t seed,
+                         uint32_t shots, uint64_t *out) {
+  if (n == 0) return -1;
+  uint64_t M = 0;
+  for (uint64_t o = 0; o < count; ++o) {
+    if (ops[3 * o] == SQO_MEASURE) ++M;
+    if (ops[3 * o + 1] >= n) return -1;
+  }
+  const uint64_t W = (M + 63) / 64;
+  const uint32_t nw = (n + 63) / 64;
+  #pragma omp parallel for schedule(dynamic, 16)
+  for (long s = 0; s < (long)shots; ++s) {
+    uint64_t *x = (uint64_t *)calloc(nw, 8), *z = (uint64_t *)calloc(nw, 8);
+    uint64_t *o_s = out + (size_t)s * W;
+    for (uint64_t w = 0; w < W; ++w) o_s[w] = 0;
+    for (uint32_t q = 0; q < n; ++q) putb(z, q, sqo_frame_bit(seed, (uint64_t)s, q));
+    uint64_t i = 0;
+    for (uint64_t o = 0; o < count; ++o) {
+      const uint32_t t = ops[3 * o], a = ops[3 * o + 1], b = ops[3 * o + 2];
+      if (t == SQO_MEASURE) {
+        const int bit = (int)(ref[i] & 1) ^ getb(x, a);
+        if (bit) o_s[i >> 6] |= 1ULL << (i & 63);
+        putb(z, a, sqo_frame_bit(seed, (uint64_t)s, (uint64_t)n + i));
+        ++i;
+      } else {
+        uint8_t sign = 0;
+        gate_on_row(x, z, &sign, t, a, b);
+      }
+    }
+    free(x);
+    free(z);
+  }
+  return (int64_t)M;
+}

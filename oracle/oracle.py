@@ -64,6 +64,10 @@ def _bind(lib):
     lib.sqo_philox4x64_10.argtypes = [vp, vp, vp]
     lib.sqo_coin.restype = ctypes.c_int
     lib.sqo_coin.argtypes = [u64, u64, u64]
+    lib.sqo_frame_bit.restype = ctypes.c_int
+    lib.sqo_frame_bit.argtypes = [u64, u64, u64]
+    lib.sqo_frame_sample.restype = i64
+    lib.sqo_frame_sample.argtypes = [u32, vp, u64, vp, u64, u32, vp]
     lib.sqo_g.restype = ctypes.c_int
     lib.sqo_g.argtypes = [ctypes.c_int] * 4
     lib.sqo_gsum_word.restype = ctypes.c_int
@@ -180,6 +184,28 @@ def philox4x64_10(ctr: Sequence[int], key: Sequence[int]) -> np.ndarray:
 
 def coin(seed: int, shot: int, m: int) -> int:
     return int(load().sqo_coin(seed, shot, m))
+
+
+def frame_bit(seed: int, shot: int, event: int, lib=None) -> int:
+    """Random bit of a shot for one frame event (see sqo_frame_sample)."""
+    return int((lib or load()).sqo_frame_bit(seed, shot, event))
+
+
+def frame_sample(n: int, ops, ref, seed: int, shots: int, lib=None) -> np.ndarray:
+    """Pauli-frame samples (shots x ceil(M/64) words) of a program against a
+    reference outcome vector ref (one 0/1 per measurement)."""
+    lib = lib or load()
+    a = np.ascontiguousarray(np.asarray(ops, dtype=np.uint32).reshape(-1, 3))
+    m = int(np.count_nonzero(a[:, 0] == MEASURE))
+    r = np.ascontiguousarray(np.asarray(ref, dtype=np.uint8).reshape(-1))
+    if r.size != m:
+        raise ValueError(f"reference has {r.size} outcomes, program measures {m}")
+    W = max((m + 63) // 64, 1)
+    out = np.zeros((max(shots, 1), W), dtype=np.uint64)
+    got = lib.sqo_frame_sample(n, a.ctypes.data, a.shape[0], r.ctypes.data, seed, shots, out.ctypes.data)
+    if got < 0:
+        raise ValueError("bad program")
+    return out[:shots, :(m + 63) // 64]
 
 
 def num_threads() -> int:

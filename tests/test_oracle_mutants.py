@@ -46,6 +46,10 @@ MUTANTS = {
                    "    gate_on_row(x, z, r, SQO_S, b, 0);",
                    "    gate_on_row(x, z, r, SQO_S, b, 0);\n    gate_on_row(x, z, r, SQO_CX, a, b);\n"
                    "    gate_on_row(x, z, r, SQO_SDG, b, 0);"),
+    "frames start at z = 0": ("    for (uint32_t q = 0; q < n; ++q) putb(z, q, sqo_frame_bit(seed, (uint64_t)s, q));\n", ""),
+    "frames keep z after measuring": ("        putb(z, a, sqo_frame_bit(seed, (uint64_t)s, (uint64_t)n + i));\n", ""),
+    "frames record z": ("const int bit = (int)(ref[i] & 1) ^ getb(x, a);", "const int bit = (int)(ref[i] & 1) ^ getb(z, a);"),
+    "frames drop the reference": ("const int bit = (int)(ref[i] & 1) ^ getb(x, a);", "const int bit = getb(x, a);"),
     "iSWAP drops S_b": ("    gate_on_row(x, z, r, SQO_S, b, 0);\n    gate_on_row(x, z, r, SQO_CZ, a, b);",
                         "    gate_on_row(x, z, r, SQO_CZ, a, b);"),
 }
@@ -190,7 +194,29 @@ def pin_rowsum(lib):
         checked += 1
 
 
-PINS = [pin_philox, pin_gates, pin_state_vector, pin_measure_update, pin_rowsum]
+def pin_frames(lib):
+    """Frame samples lie in the support of the exact outcome distribution and
+    match its frequencies (compact form of test_oracle_frames)."""
+    from test_oracle_frames import _program, _strings, exact_distribution
+    rng = np.random.default_rng(31)
+    shots = 3000
+    for n in (2, 3, 4):
+        for trial in range(3):
+            ops = _program(rng, n, 14, 0.25)
+            m = int(np.count_nonzero(ops[:, 0] == orc.MEASURE))
+            dist = exact_distribution(n, ops)
+            ref, _, _ = orc.Tableau(n, lib=lib).run(ops, seed=trial, shot=0)
+            got = _strings(orc.frame_sample(n, ops, ref, seed=50 + trial, shots=shots, lib=lib), m)
+            counts = {}
+            for g in got:
+                assert g in dist
+                counts[g] = counts.get(g, 0) + 1
+            for g, p in dist.items():
+                sd = np.sqrt(shots * max(p * (1 - p), 0.0))
+                assert abs(counts.get(g, 0) - shots * p) <= 5 * sd + 1
+
+
+PINS = [pin_philox, pin_gates, pin_state_vector, pin_measure_update, pin_rowsum, pin_frames]
 
 
 def test_unmutated_oracle_passes_compact_pins():
