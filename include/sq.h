@@ -185,6 +185,24 @@ uint64_t sq_program_num_gates(const sq_program *p);
 /* Number of fused gate passes the program launches. */
 uint64_t sq_program_num_passes(const sq_program *p);
 
+/* Many-shot sampling by Pauli frames (the paper's sampling mode): shots of
+ * program p (gates and measurements from |0...0>) without a tableau per shot.
+ * host_ref holds one reference outcome (0 or 1) per measurement of p, e.g.
+ * the outcomes sq_run gives for some seed and shot. Per shot a frame (x and z
+ * bits over the qubits) starts at x = 0 with z drawn at random and is
+ * conjugated by every gate; measuring qubit q gives host_ref[i] XOR x_q and
+ * draws z_q afresh. Random words: Philox4x64-10, key (seed, 2^63 + w) and
+ * counter (e, 0, 0, 0), bit b for shot 64 w + b; event e = q initialises
+ * z_q, e = n + i re-draws it after measurement i. The outcomes follow the
+ * circuit's distribution (each shot a sample) but are not the per-shot CHP
+ * outcomes of sq_sample. Output: host_out[s * W + i/64] bit i%64,
+ * W = ceil(M/64), bits past M zero. Runs on hip_stream (NULL = default) in
+ * stream-ordered scratch (about 2 n * ceil(shots/64) words of frames plus
+ * records); blocks. Errors: SQ_EINVAL (NULL, reference not 0/1, program of
+ * another device), SQ_ENOMEM, SQ_EDEVICE. */
+sq_status sq_frame_sample(const sq_program *p, const uint8_t *host_ref, uint64_t seed, uint32_t shots,
+                          uint64_t *host_out, void *hip_stream);
+
 /* Read an OpenQASM 2.0 circuit (host only, no device work) into operation
  * records for sq_program_create / sq_apply_gates. Accepted: the version line,
  * include lines (ignored), qreg/creg declarations, the gates id, x, y, z, h,

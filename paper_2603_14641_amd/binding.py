@@ -31,7 +31,7 @@ EXPORTED = [
     "sq_plan_gates",
     "sq_run", "sq_export_rows", "sq_export", "sq_import", "sq_measure_stats", "sq_error_flags",
     "sq_get_tuning", "sq_set_tuning", "sq_profile_enable", "sq_profile_read", "sq_profile_reset",
-    "sq_qasm_parse",
+    "sq_qasm_parse", "sq_frame_sample",
 ]
 
 
@@ -107,6 +107,7 @@ def load(path: str = LIB_PATH):
         "sq_program_gate_bytes": (u64, [vp]),
         "sq_plan_gates": (i32, [u32, vp, u64, vp, u64, ctypes.POINTER(u64)]),
         "sq_qasm_parse": (i32, [ctypes.c_char_p, ctypes.c_size_t, vp, u64, ctypes.POINTER(u64), ctypes.POINTER(u32)]),
+        "sq_frame_sample": (i32, [vp, vp, u64, u32, vp, vp]),
         "sq_run": (i32, [vp, vp, u64, u64, u64, vp, vp]),
         "sq_export_rows": (i32, [vp, vp, u32, vp, vp, vp]),
         "sq_export": (i32, [vp, vp, vp, vp]),
@@ -162,6 +163,27 @@ class Program:
         self.num_gates = int(self.lib.sq_program_num_gates(h))
         self.num_passes = int(self.lib.sq_program_num_passes(h))
         self.gate_bytes = int(self.lib.sq_program_gate_bytes(h))
+
+    def frame_sample(self, shots: int, seed: int = 0, ref=None, ref_seed: Optional[int] = None,
+                     stream=None) -> np.ndarray:
+        """Pauli-frame samples (shots x ceil(M/64) uint64 words, sq_frame_sample).
+        ref: one 0/1 per measurement; by default the program's CHP outcomes
+        for (ref_seed or seed, shot 0) on a fresh tableau."""
+        m = self.num_measurements
+        if ref is None:
+            t = Tableau(self.n, stream=stream)
+            try:
+                ref, _ = t.run_to_host(self, seed=seed if ref_seed is None else ref_seed, shot=0)
+            finally:
+                t.close()
+        r = np.ascontiguousarray(np.asarray(ref, dtype=np.uint8).reshape(-1))
+        if r.size != m:
+            raise ValueError(f"reference has {r.size} outcomes, program measures {m}")
+        W = (m + 63) // 64
+        out = np.zeros((max(int(shots), 1), max(W, 1)), dtype=np.uint64)
+        _check(self.lib.sq_frame_sample(self.h, r.ctypes.data, int(seed), int(shots), out.ctypes.data,
+                                        _stream_ptr(stream)))
+        return out[:int(shots), :W]
 
     def close(self):
         if getattr(self, "h", None):

@@ -188,6 +188,10 @@ hipError_t launch_blk_prep(const TabDev &t, const BlkArgs &a, const BlkBuffers &
 hipError_t launch_blk_pass(const TabDev &t, const BlkBuffers &b, u32 cpc, hipStream_t s);
 hipError_t launch_blk_final(const TabDev &t, const BlkArgs &a, const BlkBuffers &b, MeasState *st, MeasStats *stats,
                             u32 cpc, hipStream_t s);
+hipError_t launch_frame_init(u64 *Fx, u64 *Fz, u32 n, u32 Lf, u32 Ls, u64 seed, hipStream_t s);
+hipError_t launch_frame_measure(const u64 *Fx, u64 *Fz, const u32 *qubits, u32 count, u64 m0, const uint8_t *ref,
+                                u64 *rec, u32 n, u32 Lf, u32 Ls, u64 seed, hipStream_t s);
+hipError_t launch_frame_transpose(const u64 *rec, u64 *out, u64 M, u32 W, u32 Lf, u32 shots, hipStream_t s);
 hipError_t launch_export_rows(const TabDev &t, const u32 *rows, u32 nrows, u32 W, u64 *ox, u64 *oz, uint8_t *orr,
                               hipStream_t s);
 hipError_t launch_import(const TabDev &t, const u64 *ix, const u64 *iz, const uint8_t *ir, u32 W, hipStream_t s);

@@ -956,6 +956,68 @@ sq_status sq_run(sq_tableau *T, const sq_program *P, uint64_t seed, uint64_t sho
   return SQ_OK;
 }
 
+sq_status sq_frame_sample(const sq_program *P, const uint8_t *host_ref, uint64_t seed, uint32_t shots,
+                          uint64_t *host_out, void *hip_stream) {
+  if (!P) return fail(SQ_EINVAL, "program is NULL");
+  if (shots == 0) return SQ_OK;
+  const u64 M = P->meas_qubits.size();
+  if (M && (!host_ref || !host_out)) return fail(SQ_EINVAL, "host_ref/host_out is NULL");
+  for (u64 i = 0; i < M; ++i)
+    if (host_ref[i] > 1) return fail(SQ_EINVAL, "reference outcome %llu is %u, not 0 or 1", (unsigned long long)i,
+                                     host_ref[i]);
+  if (M == 0) return SQ_OK;
+  int dev = 0;
+  HIP_TRY(hipGetDevice(&dev));
+  if (dev != P->device) return fail(SQ_EINVAL, "program lives on device %d, current device is %d", P->device, dev);
+  hipStream_t st = (hipStream_t)hip_stream;
+  const u32 n = P->n, Lf = cdiv(shots, 64), Ls = round_up(Lf, 16), W = cdiv(M, 64);
+  const u32 block = Lf >= 1024 ? 256 : 64, wpt = Lf >= 512 ? 2 : 1;
+  const u32 tiles = cdiv(Lf, (u64)block * wpt);
+  // workspace: Fx | Fz | dummy signs | sign partials | records | output | qubits | reference
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    size_t r = off;
+    off += (bytes + 255) / 256 * 256;
+    return r;
+  };
+  const size_t o_fx = take((size_t)n * Ls * 8), o_fz = take((size_t)n * Ls * 8), o_r = take((size_t)Ls * 8);
+  const size_t o_sp = take((size_t)kMaxChunks * Ls * 8), o_rec = take((size_t)M * Lf * 8);
+  const size_t o_out = take((size_t)shots * W * 8), o_q = take(M * 4), o_ref = take(M);
+  char *ws = nullptr;
+  if (hipMallocAsync((void **)&ws, off, st) != hipSuccess) {
+    (void)hipGetLastError();
+    return fail(SQ_ENOMEM, "device allocation of %zu bytes failed", off);
+  }
+  auto release = [&]() { (void)hipFreeAsync(ws, st); };
+  u64 *Fx = (u64 *)(ws + o_fx), *Fz = (u64 *)(ws + o_fz), *rec = (u64 *)(ws + o_rec), *dout = (u64 *)(ws + o_out);
+  u32 *dq = (u32 *)(ws + o_q);
+  uint8_t *dref = (uint8_t *)(ws + o_ref);
+  const TabDev ft{Fx, Fz, (u64 *)(ws + o_r), n, cdiv(Lf, 2), Lf, Ls};
+  hipError_t e = hipMemcpyAsync(dq, P->meas_qubits.data(), M * 4, hipMemcpyHostToDevice, st);
+  if (e == hipSuccess) e = hipMemcpyAsync(dref, host_ref, M, hipMemcpyHostToDevice, st);
+  if (e == hipSuccess) e = launch_frame_init(Fx, Fz, n, Lf, Ls, seed, st);
+  for (const sq_program::Seg &sg : P->segs) {
+    if (e != hipSuccess) break;
+    if (sg.kind == 0) {
+      for (u64 i = sg.first; i < sg.first + sg.count && e == hipSuccess; ++i) {
+        const PassRange &p = P->passes[i];
+        const u32 want = std::max<u32>(1, 6144 / tiles);
+        const u32 gpc = std::max<u32>(std::max<u32>(16, cdiv(p.count, want)), cdiv(p.count, kMaxChunks));
+        // frame signs are not used: the partials are written and left
+        e = launch_layer(ft, P->dev_words, P->dev_offs + p.offset, p.count, block, wpt, gpc, (u64 *)(ws + o_sp), st);
+      }
+    } else {
+      e = launch_frame_measure(Fx, Fz, dq, (u32)sg.count, sg.first, dref, rec, n, Lf, Ls, seed, st);
+    }
+  }
+  if (e == hipSuccess) e = launch_frame_transpose(rec, dout, M, W, Lf, shots, st);
+  if (e == hipSuccess) e = hipMemcpyAsync(host_out, dout, (size_t)shots * W * 8, hipMemcpyDeviceToHost, st);
+  release();
+  if (e == hipSuccess) e = hipStreamSynchronize(st);
+  if (e != hipSuccess) return fail(SQ_EDEVICE, "frame sampling: %s", hipGetErrorString(e));
+  return SQ_OK;
+}
+
 sq_status sq_export_rows(sq_tableau *T, const uint32_t *rows, uint32_t nrows, uint64_t *hx, uint64_t *hz,
                          uint8_t *hr) {
   if (!T) return fail(SQ_EINVAL, "tableau is NULL");
