@@ -36,6 +36,7 @@ KERNEL_SOURCES = {
     "k_blk_": "sq_block.hip",
     "k_sample_init": "sq_sample.hip", "k_coins": "sq_sample.hip", "k_eval": "sq_sample.hip",
     "k_batch": "sq_batch.hip",
+    "k_frame_": "sq_frames.hip",
     "k_fill_zero": "sq_io.hip", "k_init_diag": "sq_io.hip", "k_export_rows": "sq_io.hip", "k_import": "sq_io.hip",
 }
 COMMON = ("sq_device.h", "sq_internal.h")
