@@ -554,6 +554,81 @@ __global__ void k_blk_special(u64 *__restrict__ X, u64 *__restrict__ Z, const u3
   }
 }
 
+// -------------------------------------------------------------- symbolic signs (sampling sweep)
+// With stabilizer signs kept as affine forms in the coins (sign column v =
+// coefficient of coin v, column `count` = the constant), a block acts on the
+// forms linearly. With every original sign set to 0 the block's algebra gives
+// a constant c(h) per hit row (k_blk_signs writes it when run on a zeroed sign
+// word array); the sign-dependent part is
+//   r'(h) = r(h) ^ XOR_s b_s(h) Lin(P_s),  Lin(P_s) = r(S0_{p_s}) ^ XOR_{s' hits s} Lin(P_{s'}),
+// and S_{p_s} becomes Z_{q_s} with its own coin (column m0 + s) as sign.
+
+// Thread t <= m0: sign column v = t (t < m0) or the constant (t = m0); bit s
+// of svt[t] = coefficient of column v in Lin(P_s).
+__global__ void k_blk_sv_prep(const u64 *__restrict__ sg, u32 Ks, u32 count, u32 m0,
+                              const BlkState *__restrict__ bs, u32 *__restrict__ svt) {
+  const u32 t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t > m0) return;
+  const u32 v = t < m0 ? t : count;
+  const u32 k = bs->k, nw = bs->nwords;
+  u32 s0 = 0;  // coefficients of the original pivot rows
+  for (u32 i = 0; i < nw; ++i) {
+    const u64 wv = sg[(size_t)v * Ks + bs->word[i]];
+    for (u32 m = bs->wmem[i]; m; m &= m - 1) {
+      const u32 s = (u32)__builtin_ctz(m);
+      if ((wv >> (bs->p[s] & 63u)) & 1ULL) s0 |= 1u << s;
+    }
+  }
+  u32 lin = 0;
+  for (u32 s = 0; s < k; ++s) lin |= ((((s0 >> s) & 1u) ^ ((u32)__popc(lin & bs->hitS[s]) & 1u)) << s);
+  svt[t] = lin;
+}
+
+// Grid (stabilizer-word tiles, column chunks of SV_CHUNK): thread per
+// stabilizer word, looping over the chunk's columns t in [0, m0 + k]: t < m0
+// coin columns, m0 <= t < m0 + k this block's coins, t = m0 + k the constant.
+constexpr u32 SV_CHUNK = 64;
+
+__global__ __launch_bounds__(64) void k_blk_sv_update(u64 *__restrict__ sg, u32 Ks, u32 count, u32 m0,
+                                                       const BlkState *__restrict__ bs, const u64 *__restrict__ bm,
+                                                       const u32 *__restrict__ svt, const u64 *__restrict__ cvec,
+                                                       u32 Ls, u32 K) {
+  const u32 k = bs->k;
+  const u32 w = blockIdx.x * blockDim.x + threadIdx.x;  // stabilizer row word
+  if (k == 0 || w >= K) return;
+  u64 b[KB];
+#pragma unroll
+  for (u32 s = 0; s < KB; ++s) b[s] = s < k ? bm[(size_t)s * Ls + K + w] : 0ULL;
+  u64 smask = 0;  // rows S_{p_s} in this word
+  for (u32 s = 0; s < k; ++s)
+    if ((bs->p[s] >> 6) == w) smask |= 1ULL << (bs->p[s] & 63u);
+  const u32 tlo = blockIdx.y * SV_CHUNK, thi = min(tlo + SV_CHUNK, m0 + k + 1);
+  for (u32 t = tlo; t < thi; ++t) {
+    const bool own = t >= m0 && t < m0 + k;  // a coin of this block
+    const u32 v = t < m0 + k ? t : count;
+    const size_t o = (size_t)v * Ks + w;
+    u64 val = sg[o];
+    if (!own) {
+      const u32 lin = svt[t < m0 ? t : m0];
+      u64 acc = 0;
+#pragma unroll
+      for (u32 s = 0; s < KB; ++s)
+        if ((lin >> s) & 1u) acc ^= b[s];
+      val ^= acc;
+      if (v == count) val ^= cvec[K + w];
+    }
+    if (smask) {
+      u64 set = 0;
+      if (own) {
+        const u32 p = bs->p[t - m0];
+        if ((p >> 6) == w) set = 1ULL << (p & 63u);
+      }
+      val = (val & ~smask) | set;
+    }
+    sg[o] = val;
+  }
+}
+
 // Bytes of a block pass, counted by row word: read and write x and z of every
 // supported column for each row word that holds a hit row.
 __global__ void k_blk_bytes(const u64 *__restrict__ bm, const BlkState *__restrict__ bs, MeasStats *stats, u32 Ls,
@@ -616,6 +691,16 @@ hipError_t launch_blk_final(const TabDev &t, const BlkArgs &a, const BlkBuffers 
                      stats, t.Ls, t.L, t.K);
   hipLaunchKernelGGL(k_blk_special, dim3(cdiv(t.n, 256)), dim3(256), 0, s, t.X, t.Z, b.patx, b.patz, b.bs, a, t.Ls,
                      t.K, t.n);
+  return hipGetLastError();
+}
+
+// Symbolic signs after a block whose pass and special rows are done; cvec
+// holds the constants c(h) (the block ran with it as its zeroed sign array).
+hipError_t launch_blk_sv(u64 *sg, u32 Ks, u32 count, u32 m0, u32 kmax, const BlkBuffers &b, u32 *svt,
+                         const u64 *cvec, u32 Ls, u32 K, hipStream_t s) {
+  hipLaunchKernelGGL(k_blk_sv_prep, dim3(cdiv(m0 + 1, 256)), dim3(256), 0, s, sg, Ks, count, m0, b.bs, svt);
+  hipLaunchKernelGGL(k_blk_sv_update, dim3(cdiv(K, 64), cdiv(m0 + kmax + 1, SV_CHUNK)), dim3(64), 0, s, sg, Ks, count,
+                     m0, b.bs, b.bm, svt, cvec, Ls, K);
   return hipGetLastError();
 }
 

@@ -548,7 +548,8 @@ sq_status sq_sample(sq_tableau *T, const uint32_t *qubits, uint32_t count, uint6
   const Dims &d = T->d;
   const u32 Ks = round_up(d.K, 16);
   const u32 CW = cdiv(count, 64);
-  // workspace: X, Z copies | sign columns | Fm | cw | out | svlist | kind | fc | dummy
+  // workspace: X, Z copies | sign columns | Fm | cw | out | svlist | kind | fc | dummy |
+  // blocked sweep: constants c(h) | pivot coefficients per column | outcome and stats sinks
   size_t off = 0;
   auto take = [&](size_t bytes) {
     size_t r = off;
@@ -559,6 +560,8 @@ sq_status sq_sample(sq_tableau *T, const uint32_t *qubits, uint32_t count, uint6
   const size_t o_sg = take((size_t)(count + 1) * Ks * 8), o_fm = take((size_t)count * CW * 8);
   const size_t o_cw = take((size_t)shots * CW * 8), o_out = take((size_t)shots * CW * 8);
   const size_t o_sv = take((size_t)(count + 1) * 4), o_kind = take(count), o_fc = take(count), o_dummy = take(2);
+  const size_t o_cvec = take((size_t)d.Ls * 8), o_svt = take((size_t)(count + 1) * 4), o_bits = take(KB);
+  const size_t o_stats = take(sizeof(MeasStats));
   uint8_t *ws = nullptr;
   if (hipMallocAsync((void **)&ws, off, T->stream) != hipSuccess) {
     (void)hipGetLastError();
@@ -568,6 +571,12 @@ sq_status sq_sample(sq_tableau *T, const uint32_t *qubits, uint32_t count, uint6
   u32 *svlist = (u32 *)(ws + o_sv);
   uint8_t *kind = ws + o_kind, *fc = ws + o_fc, *dummy = ws + o_dummy;
   TabDev ts{(u64 *)(ws + o_x), (u64 *)(ws + o_z), T->t.R, d.n, d.K, d.L, d.Ls};
+  // the blocked kernels run with a zeroed sign array (they then produce the
+  // constants c(h)); the real signs live in the sign columns
+  u64 *cvec = (u64 *)(ws + o_cvec);
+  u32 *svt = (u32 *)(ws + o_svt);
+  MeasStats *sstats = (MeasStats *)(ws + o_stats);
+  TabDev tb{ts.X, ts.Z, cvec, d.n, d.K, d.L, d.Ls};
   const u32 cpc = rowsum_cpc(T);
   const u32 max_chunks = cdiv(d.n, cpc);
   MeasState before{}, after{};
@@ -577,7 +586,7 @@ sq_status sq_sample(sq_tableau *T, const uint32_t *qubits, uint32_t count, uint6
     HIP_TRY(hipMemcpyAsync(ts.X, T->t.X, (size_t)d.n * d.Ls * 8, hipMemcpyDeviceToDevice, T->stream));
     HIP_TRY(hipMemcpyAsync(ts.Z, T->t.Z, (size_t)d.n * d.Ls * 8, hipMemcpyDeviceToDevice, T->stream));
     HIP_TRY(launch_sample_init(T->t, sg, Ks, count, T->stream));
-    for (u32 i = 0; i < count; ++i) {
+    auto single = [&](u32 i) -> sq_status {
       const u32 q = qubits[i];
       SymCtx sym{sg, svlist, kind, fm, fc, Ks, CW, count, i};
       SQ_TRY(timed(T, SQ_K_PIVOT, [&] {
@@ -594,6 +603,50 @@ sq_status sq_sample(sq_tableau *T, const uint32_t *qubits, uint32_t count, uint6
         return launch_post(ts, q, T->mask, T->pivx, T->pivz, T->cnt0, T->cnt1, T->st, T->stats, dummy, cpc,
                            det_cpw(T), &sym, T->stream);
       }));
+      return SQ_OK;
+    };
+    // runs of random measurements up to meas_block at a time (as in
+    // measure_range), the deterministic ones one by one
+    const u32 kb = std::min<u32>(T->tun.meas_block, KB);
+    u32 i = 0, single_left = 0, backoff = 1;
+    while (i < count) {
+      const u32 want = std::min<u32>(kb, count - i);
+      if (want < 2 || single_left > 0) {
+        SQ_TRY(single(i));
+        ++i;
+        if (single_left > 0) --single_left;
+        continue;
+      }
+      BlkArgs a{};
+      a.k = want;
+      for (u32 s2 = 0; s2 < want; ++s2) a.q[s2] = qubits[i + s2];
+      a.seed = seed;
+      a.m0 = i;
+      HIP_TRY(launch_fill_zero(cvec, d.Ls, T->stream));
+      SQ_TRY(timed(T, SQ_K_BPIVOT, [&] {
+        return launch_blk_pivots(tb, a, T->blk, ws + o_bits, kind + i, T->stream);
+      }));
+      HIP_TRY(hipMemcpyAsync(T->blk_k_host, &T->blk.bs->k, sizeof(u32), hipMemcpyDeviceToHost, T->stream));
+      HIP_TRY(hipStreamSynchronize(T->stream));
+      const u32 k = *T->blk_k_host;
+      if (k > want) return fail(SQ_ESTATE, "blocked sampling sweep: bad block length %u", k);
+      if (k > 0) {
+        SQ_TRY(timed(T, SQ_K_BPREP, [&] { return launch_blk_prep(tb, a, T->blk, T->st, sstats, T->stream); }));
+        SQ_TRY(timed(T, SQ_K_BPASS, [&] { return launch_blk_pass(tb, T->blk, T->blk_cpc, T->stream); }));
+        SQ_TRY(timed(T, SQ_K_BFINAL, [&] {
+          return launch_blk_final(tb, a, T->blk, T->st, sstats, T->blk_cpc, T->stream);
+        }));
+        HIP_TRY(launch_blk_sv(sg, Ks, count, i, want, T->blk, svt, cvec, d.Ls, d.K, T->stream));
+        i += k;
+        backoff = 1;
+      } else {
+        single_left = backoff - 1;
+        backoff = std::min<u32>(2 * backoff, 64);
+      }
+      if (k < want) {  // measurement i is deterministic
+        SQ_TRY(single(i));
+        ++i;
+      }
     }
     HIP_TRY(launch_coins(cw, seed, shot_begin, meas_base, shots, count, CW, T->stream));
     HIP_TRY(launch_eval(cw, kind, fm, fc, dout, shots, count, CW, T->stream));

@@ -70,6 +70,38 @@ def test_sample_all_qubits(n):
            meas_base=int(rng.integers(1000)))
 
 
+@pytest.mark.parametrize("mb", [1, 2, 32])
+def test_sample_block_sizes_agree_with_oracle(mb):
+    """The sampling sweep with 1 (one at a time), 2 and 32 random measurements
+    per pass; n = 1500, every qubit, with deterministic ones mixed in."""
+    n = 1500
+    rng = np.random.default_rng(4242)
+    ref = orc.Tableau(n)
+    ref.run(mixed_program(rng, n, 6, p_meas=0.05), seed=8)
+    t = _gpu_from_oracle(ref)
+    t.set_tuning(meas_block=mb)
+    qs = list(rng.permutation(n)) + list(range(0, n, 97))
+    _check(t, ref, qs, seed=5, shot_begin=11, shots=6, meas_base=2)
+
+
+def test_sample_blocked_equals_single_at_4000():
+    """n = 4000: the blocked sweep gives the one-at-a-time sweep's bits for 300 shots."""
+    from paper_2603_14641_amd import Program, Tableau
+    n = 4000
+    rng = np.random.default_rng(77)
+    prog = Program(n, mixed_program(rng, n, 10, p_meas=0.02))
+    outs = []
+    for mb in (1, 32):
+        t = Tableau(n)
+        t.set_tuning(meas_block=mb)
+        t.run_to_host(prog, seed=1, shot=0)
+        qs = list(rng.permutation(n)) if mb == 1 else qs_keep
+        qs_keep = qs
+        outs.append(t.sample_bits(qs, 300, seed=9, shot_begin=0, meas_base=0))
+        t.close()
+    assert np.array_equal(outs[0], outs[1])
+
+
 @pytest.mark.parametrize("n", [3, 40, 130])
 def test_sample_unordered_with_repeats(n):
     """Random order, repeated qubits (re-measurements are deterministic with
