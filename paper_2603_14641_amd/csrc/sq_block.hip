@@ -39,45 +39,57 @@ __global__ void k_blk_snap(const u64 *__restrict__ X, u32 Ls, u32 L, BlkArgs a, 
 // stabilizer half of column q_s as it stands before measurement s is
 //   snap_s ^ XOR_{s' < s, M[s'][s] = 1} (hit mask of s'),
 // with the rows S_{p_s'} (now Z_{q_s'}, no x) cleared. Words come in tiles of
-// 64; wave v owns the tiles t = v mod PW_WAVES and lane l word 64t + l, so a
+// 64; wave v owns the tiles t = v mod (waves) and lane l word 64t + l, so a
 // lane only ever reads words it wrote itself. Each wave computes its tiles
 // lazily, in order (for every earlier step first), and stops at its first
 // nonzero tile; the smallest such word over the waves holds the pivot. A
 // block ends before its first deterministic measurement (no nonzero word).
+// The lane that owns the pivot word does the step's bookkeeping, so a step
+// costs two barriers; the per-pivot outputs are written once at the end.
 constexpr u32 PW_WAVES = 16;
 
 __global__ __launch_bounds__(64 * PW_WAVES) void k_blk_pivots(const u64 *__restrict__ snap, u64 *__restrict__ bm,
                                                                u32 Ls, u32 K, BlkArgs a, BlkState *__restrict__ bs,
                                                                uint8_t *__restrict__ out_bits,
                                                                uint8_t *__restrict__ out_rand) {
-  __shared__ u32 s_wmin, s_hit;
-  __shared__ u64 s_vmin;
-  // uniform per-step state in LDS (indexed by step, which is not a
-  // compile-time constant); done[] is per wave and written by its lane 0
+  __shared__ u32 s_wmin[2];  // double-buffered: step s uses s_wmin[s & 1]
+  // per-step state in LDS (indexed by step, which is not a compile-time
+  // constant); done[] is per wave and written by its lane 0
   __shared__ u32 piv[KB];              // pivot of each decided step
   __shared__ u32 mrow[KB];             // M[s]: bit s2 = x of P_s at q_{s2}
+  __shared__ u32 mcol[KB];             // bit s' of mcol[s] = M[s'][s]
+  __shared__ u32 hits[KB];             // earlier pivots that hit S_{p_s}
   __shared__ u32 sdone[PW_WAVES][KB];  // tiles of each wave computed per step
-  const u32 tid = threadIdx.x, lane = tid & 63u, wave = tid >> 6;
+  const u32 tid = threadIdx.x, lane = tid & 63u, wave = tid >> 6, nwv = blockDim.x >> 6;
   const u32 ntiles = (K + 63u) / 64u;
   u32 *done = sdone[wave];
-  if (tid < KB) { piv[tid] = 0; mrow[tid] = 0; }
+  if (tid < KB) { piv[tid] = 0; mrow[tid] = 0; mcol[tid] = 0; hits[tid] = 0; }
+  if (tid < 2) s_wmin[tid] = 0xFFFFFFFFu;
   if (lane < KB) done[lane] = 0;
   __syncthreads();
-  auto word_of = [&](u32 j) { return (j * PW_WAVES + wave) * 64u + lane; };  // local tile j
+  auto word_of = [&](u32 j) { return (j * nwv + wave) * 64u + lane; };  // local tile j
   auto tile_word = [&](u32 s, u32 w) -> u64 {
     if (w >= K) return 0ULL;
+    const u64 *col = bm + K + w;
     u64 v = snap[(size_t)s * Ls + K + w];
-    for (u32 sp = 0; sp < s; ++sp) {
-      if ((mrow[sp] >> s) & 1u) v ^= bm[(size_t)sp * Ls + K + w];
-      if ((piv[sp] >> 6) == w) v &= ~(1ULL << (piv[sp] & 63u));  // S_{p_s'} is Z now
+    const u32 sel = mcol[s] & ((1u << s) - 1u);
+    // every row is loaded (rows the step does not use are masked), so the
+    // loads are independent and in flight together
+#pragma unroll
+    for (u32 sp = 0; sp < KB; ++sp) {
+      const u64 b = col[(size_t)sp * Ls];
+      v ^= ((sel >> sp) & 1u) ? b : 0ULL;
+    }
+#pragma unroll
+    for (u32 sp = 0; sp < KB; ++sp) {
+      const u32 pv = piv[sp];
+      if (sp < s && (pv >> 6) == w) v &= ~(1ULL << (pv & 63u));  // S_{p_s'} is Z now
     }
     return v;
   };
-  const u32 myt = ntiles > wave ? (ntiles - wave + PW_WAVES - 1) / PW_WAVES : 0;  // tiles of this wave
+  const u32 myt = ntiles > wave ? (ntiles - wave + nwv - 1) / nwv : 0;  // tiles of this wave
   u32 k = a.k;
   for (u32 s = 0; s < a.k; ++s) {
-    if (tid == 0) s_wmin = 0xFFFFFFFFu;
-    __syncthreads();
     for (u32 j = 0; j < myt; ++j) {
       // earlier steps first (their pivots are known, so their own bits are cleared too)
       for (u32 sp = 0; sp < s; ++sp) {
@@ -95,92 +107,87 @@ __global__ __launch_bounds__(64 * PW_WAVES) void k_blk_pivots(const u64 *__restr
       if (lane == 0) done[s] = j + 1;
       const u64 nz = __ballot(v != 0);
       if (nz) {  // uniform over the wave
-        if (lane == (u32)__builtin_ctzll(nz)) atomicMin(&s_wmin, w);
+        if (lane == (u32)__builtin_ctzll(nz)) atomicMin(&s_wmin[s & 1u], w);
         break;
       }
     }
     __syncthreads();
-    const u32 wmin = s_wmin;
+    const u32 wmin = s_wmin[s & 1u];
     if (wmin == 0xFFFFFFFFu) {  // deterministic: the block ends here
       k = s;
       break;
     }
-    const u32 owner = (wmin >> 6) % PW_WAVES, pl = wmin & 63u;
+    if (tid == 0) s_wmin[(s + 1) & 1u] = 0xFFFFFFFFu;  // its last reader passed the barrier above
     // the owning lane holds word wmin of this and every earlier step
-    if (wave == owner && lane == pl) {
-      const u64 vmin = bm[(size_t)s * Ls + K + wmin];
-      const u64 bit = 1ULL << (u32)__builtin_ctzll(vmin);
+    if (wave == (wmin >> 6) % nwv && lane == (wmin & 63u)) {
+      u64 *col = bm + K + wmin;
+      const u64 vmin = col[(size_t)s * Ls];
+      const u32 pb = (u32)__builtin_ctzll(vmin);
+      const u64 bit = 1ULL << pb;
       u32 hit = 0;  // earlier pivots that hit S_p
-      for (u32 sp = 0; sp < s; ++sp)
-        if (bm[(size_t)sp * Ls + K + wmin] & bit) hit |= 1u << sp;
-      bm[(size_t)s * Ls + K + wmin] = vmin & ~bit;  // S_p is not multiplied by P_s
-      s_vmin = vmin;
-      s_hit = hit;
+#pragma unroll
+      for (u32 sp = 0; sp < KB; ++sp) hit |= ((col[(size_t)sp * Ls] & bit) ? 1u : 0u) << sp;
+      hit &= (1u << s) - 1u;
+      col[(size_t)s * Ls] = vmin & ~bit;  // S_p is not multiplied by P_s
+      // x bits of P_s at the later measured columns: the snapshot's bit at p
+      // plus the earlier pivots that hit S_p (M is known for those)
+      const u64 *sc = snap + K + wmin;
+      u32 mb = 0;
+#pragma unroll
+      for (u32 s2 = 0; s2 < KB; ++s2)
+        mb |= (((u32)(sc[(size_t)s2 * Ls] >> pb) ^ (u32)__popc(hit & mcol[s2])) & 1u) << s2;
+      const u32 later = ~((2u << s) - 1u) & (a.k >= KB ? 0xFFFFFFFFu : (1u << a.k) - 1u);
+      mb &= later;
+      piv[s] = wmin * 64u + pb;
+      mrow[s] = mb;
+      hits[s] = hit;
+#pragma unroll
+      for (u32 s2 = 0; s2 < KB; ++s2)
+        if ((mb >> s2) & 1u) mcol[s2] |= 1u << s;
     }
     __syncthreads();
-    const u64 vmin = s_vmin;
-    const u32 hit = s_hit;
-    const u32 p = wmin * 64u + (u32)__builtin_ctzll(vmin);
-    // x bits of P_s at the later measured columns (wave 0, one lane per later step)
-    u32 mine = 0;
-    if (wave == 0 && lane > s && lane < a.k) {
-      u32 v = (u32)(snap[(size_t)lane * Ls + K + wmin] >> (p & 63u)) & 1u;
-      for (u32 sp = 0; sp < s; ++sp)
-        if ((hit >> sp) & 1u) v ^= (mrow[sp] >> lane) & 1u;
-      mine = v;
-    }
-    const u64 mb = __ballot(mine != 0);
-    if (wave == 0 && lane == 0) {
-      piv[s] = p;
-      mrow[s] = (u32)mb;
-    }
-    __syncthreads();
-    if (tid == 0) {
-      bs->p[s] = p;
-      bs->hitS[s] = hit;
-      bs->M[s] = mrow[s];
-      const u32 c = coin_bit(a.seed, a.shot, a.m0 + s);
-      bs->coin[s] = c;
-      out_rand[s] = 1;
-      out_bits[s] = (uint8_t)c;
-    }
-    __syncthreads();  // s_wmin and s_hit are rewritten by the next step
   }
-  if (tid != 0) return;
-  bs->k = k;
-  // later pivots that hit D_{p_s} (which holds P_s from measurement s on)
-  for (u32 s = 0; s < k; ++s) {
-    u32 hits = 0;
-    for (u32 s2 = s + 1; s2 < k; ++s2) {
-      u32 v = (mrow[s] >> s2) & 1u;
-      for (u32 s3 = s + 1; s3 < s2; ++s3)
-        if ((hits >> s3) & 1u) v ^= (mrow[s3] >> s2) & 1u;
-      hits |= v << s2;
-    }
-    bs->dhits[s] = hits;
+  if (wave != 0) return;
+  // one lane per decided pivot
+  const u32 s = lane;
+  const bool on = s < k;
+  if (on) {
+    const u32 c = coin_bit(a.seed, a.shot, a.m0 + s);
+    bs->p[s] = piv[s];
+    bs->hitS[s] = hits[s];
+    bs->M[s] = mrow[s];
+    bs->coin[s] = c;
+    out_rand[s] = 1;
+    out_bits[s] = (uint8_t)c;
+    // later pivots that hit D_{p_s} (which holds P_s from measurement s on)
+    u32 h = 0;
+    for (u32 s2 = s + 1; s2 < k; ++s2) h |= (((mrow[s] >> s2) ^ (u32)__popc(h & mcol[s2])) & 1u) << s2;
+    bs->dhits[s] = h;
   }
-  for (u32 s = 0; s < KB; ++s) {
+  if (s < KB) {
     bs->Qz[s] = 0;
     bs->R0[s] = 0;
     bs->pc0[s] = 0;
     bs->pcD[s] = 0;
   }
-  bs->ncols = 0;
-  bs->done = 0;
-  // group the pivots by row word (pivots of a block usually share one or two)
-  u32 nw = 0;
-  for (u32 s = 0; s < k; ++s) {
-    const u32 wd = piv[s] >> 6;
-    u32 i = 0;
-    while (i < nw && bs->word[i] != wd) ++i;
-    if (i == nw) {
-      bs->word[nw] = wd;
-      bs->wmem[nw] = 0;
-      ++nw;
-    }
-    bs->wmem[i] |= 1u << s;
+  // group the pivots by row word (pivots of a block usually share one or two),
+  // words numbered in order of first use
+  const u32 wd = on ? piv[s] >> 6 : 0xFFFFFFFFu;
+  u32 same = 0;  // pivots on this lane's word
+  for (u32 s2 = 0; s2 < k; ++s2) same |= ((u32)__shfl((int)wd, (int)s2) == wd ? 1u : 0u) << s2;
+  const bool first = on && (same & ((1u << s) - 1u)) == 0;
+  const u64 fb = __ballot(first);
+  if (first) {
+    const u32 i = (u32)__popcll(fb & ((1ULL << s) - 1ULL));
+    bs->word[i] = wd;
+    bs->wmem[i] = same;
   }
-  bs->nwords = nw;
+  if (lane == 0) {
+    bs->k = k;
+    bs->nwords = (u32)__popcll(fb);
+    bs->ncols = 0;
+    bs->done = 0;
+  }
 }
 
 // -------------------------------------------------------------- hit masks
@@ -246,40 +253,49 @@ __global__ void k_blk_gather(const u64 *__restrict__ X, const u64 *__restrict__ 
 // -------------------------------------------------------------- pivot algebra
 // (1) Thread per 64-column word: the evolved pivot rows P_s = S0_{p_s} times
 // the earlier pivots that hit it, in order, and |x & z| of each original
-// pivot row (summed per pivot).
-__global__ void k_blk_evolve(const u64 *__restrict__ p0x, const u64 *__restrict__ p0z, u64 *__restrict__ px,
-                             u64 *__restrict__ pz, u32 K, BlkState *__restrict__ bs) {
+// pivot row (summed per pivot). All rows stay in registers.
+__global__ __launch_bounds__(64) void k_blk_evolve(const u64 *__restrict__ p0x, const u64 *__restrict__ p0z,
+                                                   u64 *__restrict__ px, u64 *__restrict__ pz, u32 K,
+                                                   BlkState *__restrict__ bs) {
   const u32 k = bs->k;
   const u32 cw = blockIdx.x * blockDim.x + threadIdx.x;
   const u32 lane = threadIdx.x & 63u;
-  for (u32 s = 0; s < k; ++s) {
-    u64 vx = 0, vz = 0;
-    u32 pc = 0;
-    if (cw < K) {
-      vx = p0x[(size_t)s * K + cw];
-      vz = p0z[(size_t)s * K + cw];
-      pc = (u32)__popcll(vx & vz);
-      for (u32 m = bs->hitS[s]; m; m &= m - 1) {  // earlier pivots (own writes of this thread)
-        const u32 sp = (u32)__builtin_ctz(m);
-        vx ^= px[(size_t)sp * K + cw];
-        vz ^= pz[(size_t)sp * K + cw];
-      }
-      px[(size_t)s * K + cw] = vx;
-      pz[(size_t)s * K + cw] = vz;
+  const bool in = cw < K;
+  u64 vx[KB], vz[KB];
+#pragma unroll
+  for (u32 s = 0; s < KB; ++s) {  // rows past k are allocated; their values are not used
+    vx[s] = in ? p0x[(size_t)s * K + cw] : 0ULL;
+    vz[s] = in ? p0z[(size_t)s * K + cw] : 0ULL;
+  }
+#pragma unroll
+  for (u32 s = 0; s < KB; ++s) {
+    u32 pc = (u32)__popcll(vx[s] & vz[s]);
+    const u32 h = s < k ? bs->hitS[s] : 0u;
+#pragma unroll
+    for (u32 sp = 0; sp < s; ++sp) {
+      const u64 m = 0ULL - (u64)((h >> sp) & 1u);
+      vx[s] ^= vx[sp] & m;
+      vz[s] ^= vz[sp] & m;
     }
-    for (int off = 32; off > 0; off >>= 1) pc += (u32)__shfl_xor((int)pc, off);
-    if (lane == 0 && pc) atomicAdd(&bs->pc0[s], pc);
+    if (s < k) {
+      if (in) {
+        px[(size_t)s * K + cw] = vx[s];
+        pz[(size_t)s * K + cw] = vz[s];
+      }
+      for (int off = 32; off > 0; off >>= 1) pc += (u32)__shfl_xor((int)pc, off);
+      if (lane == 0 && pc) atomicAdd(&bs->pc0[s], pc);
+    }
   }
 }
 
 // (2) Thread per (64-column word, pivot a): bits b of z_{P_a} . x_{P_b} (Qz)
 // and of z_{P_a} . x_{S0_b} (R0), and |x & z| of the final D_{p_a} (P_a times
-// its later hits). The last block to finish forms lam(P_s) and the final
-// signs of the D_{p_s}.
-__global__ void k_blk_pairs(const u64 *__restrict__ p0x, const u64 *__restrict__ px, const u64 *__restrict__ pz,
-                            u32 K, BlkState *__restrict__ bs, MeasState *__restrict__ st) {
+// its later hits). The last block to finish (one wave, a lane per pivot)
+// forms lam(P_s) and the final signs of the D_{p_s}.
+__global__ __launch_bounds__(64) void k_blk_pairs(const u64 *__restrict__ p0x, const u64 *__restrict__ px,
+                                                  const u64 *__restrict__ pz, u32 K, BlkState *__restrict__ bs,
+                                                  MeasState *__restrict__ st) {
   __shared__ u32 s_last;
-  __shared__ u32 lam[KB];
   const u32 k = bs->k;
   const u32 a = blockIdx.y;
   const u32 cw = blockIdx.x * blockDim.x + threadIdx.x;
@@ -317,41 +333,50 @@ __global__ void k_blk_pairs(const u64 *__restrict__ p0x, const u64 *__restrict__
   __syncthreads();
   if (threadIdx.x == 0) s_last = (atomicAdd(&bs->done, 1u) == gridDim.x * gridDim.y - 1) ? 1u : 0u;
   __syncthreads();
-  if (!s_last || threadIdx.x != 0) return;
+  if (!s_last) return;
   __threadfence();
-  // lam(P_s): start from the original row, multiply in the earlier pivots that hit it, in order
-  for (u32 s = 0; s < k; ++s) {
-    u32 l = (2u * bs->r0[s] + atomicAdd(&bs->pc0[s], 0u)) & 3u;
-    const u32 hit = bs->hitS[s];
-    u32 used = 0;  // pivots already multiplied in
-    for (u32 sp = 0; sp < s; ++sp) {
-      if (!((hit >> sp) & 1u)) continue;
-      // z_{P_sp} . x_current, x_current = x_{S0_s} ^ XOR_{used} x_{P}
-      u32 par = (atomicAdd(&bs->R0[sp], 0u) >> s) & 1u;
-      par ^= (u32)__popc(atomicAdd(&bs->Qz[sp], 0u) & used) & 1u;
-      l = (lam[sp] + l + 2u * par) & 3u;
-      used |= 1u << sp;
+  // lane s holds pivot s's sums (atomic reads see every block's updates)
+  const u32 s = lane;
+  const bool on = s < k;
+  u32 base = 0, qs = 0, rs = 0, pd = 0, hs = 0, dh = 0;
+  if (on) {
+    base = 2u * bs->r0[s] + atomicAdd(&bs->pc0[s], 0u);
+    qs = atomicAdd(&bs->Qz[s], 0u);
+    rs = atomicAdd(&bs->R0[s], 0u);
+    pd = atomicAdd(&bs->pcD[s], 0u);
+    hs = bs->hitS[s];
+    dh = bs->dhits[s];
+  }
+  // lam(P_t): the original row times the earlier pivots sp that hit it, in
+  // order; each factor adds lam(P_sp) + 2 (z_{P_sp} . x of the partial
+  // product), whose x is x_{S0_t} ^ XOR of the factors before sp
+  u32 lam = 0;
+  for (u32 t = 0; t < k; ++t) {
+    const u32 ht = (u32)__shfl((int)hs, (int)t);
+    u32 term = 0;
+    if (s < t && ((ht >> s) & 1u)) {  // hits of t are earlier pivots
+      const u32 par = ((rs >> t) ^ (u32)__popc(qs & ht & ((1u << s) - 1u))) & 1u;
+      term = (lam + 2u * par) & 3u;
     }
-    lam[s] = l;
-    bs->lam[s] = l;
+    const u32 sum = (u32)__popcll(__ballot(term & 1u)) + 2u * (u32)__popcll(__ballot((term >> 1) & 1u));
+    const u32 bt = (u32)__shfl((int)base, (int)t);
+    if (s == t) lam = (bt + sum) & 3u;
   }
   // final signs of the D_{p_s}: P_s times its later hits, in order
-  u32 flags = 0;
-  for (u32 s = 0; s < k; ++s) {
-    u32 l = lam[s];
-    const u32 dh = bs->dhits[s];
-    u32 used = 1u << s;
-    for (u32 s2 = s + 1; s2 < k; ++s2) {
-      if (!((dh >> s2) & 1u)) continue;
-      const u32 par = (u32)__popc(atomicAdd(&bs->Qz[s2], 0u) & used) & 1u;
-      l = (lam[s2] + l + 2u * par) & 3u;
+  u32 l = lam, used = 1u << (s & 31u);
+  for (u32 s2 = 0; s2 < k; ++s2) {
+    const u32 q2 = (u32)__shfl((int)qs, (int)s2), l2 = (u32)__shfl((int)lam, (int)s2);
+    if (on && ((dh >> s2) & 1u)) {  // dh holds only pivots after s
+      l = (l2 + l + 2u * ((u32)__popc(q2 & used) & 1u)) & 3u;
       used |= 1u << s2;
     }
-    const u32 e = (l - (atomicAdd(&bs->pcD[s], 0u) & 3u)) & 3u;
-    if (e & 1u) flags |= 1u;
+  }
+  const u32 e = (l - (pd & 3u)) & 3u;
+  if (on) {
+    bs->lam[s] = lam;
     bs->dsign[s] = e >> 1;
   }
-  if (flags) atomicOr(&st->flags, flags);
+  if (__ballot(on && (e & 1u)) && lane == 0) atomicOr(&st->flags, 1u);
 }
 
 // (3) Thread per column: bit s of patx / patz = pivot s has x / z there;
@@ -429,34 +454,44 @@ __global__ __launch_bounds__(256) void k_blk_pass(u64 *__restrict__ X, u64 *__re
 }
 
 // -------------------------------------------------------------- chunk reduction
-// Thread per (row word, field): field 0 adds the 2-bit counters of all
-// chunks (mod 4), field 1 XORs their parity words. The result goes to chunk
-// 0's slots.
+// A wave per (row word, field): lanes take every 64th chunk, then a butterfly
+// combines them. Field 0 adds the 2-bit counters (mod 4), field 1 XORs the
+// parity words. The result goes to chunk 0's slots.
 __global__ void k_blk_reduce(u64 *__restrict__ part, const u64 *__restrict__ bm, const BlkState *__restrict__ bs,
                              u32 Ls, u32 L, u32 nchunks) {
   const u32 k = bs->k;
-  const u32 w = blockIdx.x * blockDim.x + threadIdx.x;
+  const u32 lane = threadIdx.x & 63u;
+  const u32 w = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
   const u32 f = blockIdx.y;
-  if (w >= L) return;
+  if (w >= L) return;  // uniform over the wave
   u64 any = 0;
   for (u32 s = 0; s < k; ++s) any |= bm[(size_t)s * Ls + w];
   if (any == 0) return;  // k_blk_pass wrote nothing for this row word
   const size_t stride = (size_t)BLK_PART * Ls;
   if (f == 0) {
     u64 d0 = 0, d1 = 0;
-    for (u32 c = 0; c < nchunks; ++c) {
+    for (u32 c = lane; c < nchunks; c += 64u) {
       const u64 a0 = part[c * stride + w], a1 = part[c * stride + Ls + w];
       const u64 carry = d0 & a0;
       d0 ^= a0;
       d1 ^= a1 ^ carry;
     }
-    part[w] = d0;
-    part[Ls + w] = d1;
+    for (int off = 32; off > 0; off >>= 1) {
+      const u64 o0 = shfl_xor_u64(d0, off), o1 = shfl_xor_u64(d1, off);
+      const u64 carry = d0 & o0;
+      d0 ^= o0;
+      d1 ^= o1 ^ carry;
+    }
+    if (lane == 0) {
+      part[w] = d0;
+      part[Ls + w] = d1;
+    }
   } else {
     const size_t o = 2 * (size_t)Ls + w;
     u64 y = 0;
-    for (u32 c = 0; c < nchunks; ++c) y ^= part[c * stride + o];
-    part[o] = y;
+    for (u32 c = lane; c < nchunks; c += 64u) y ^= part[c * stride + o];
+    for (int off = 32; off > 0; off >>= 1) y ^= shfl_xor_u64(y, off);
+    if (lane == 0) part[o] = y;
   }
 }
 
@@ -654,7 +689,8 @@ __global__ void k_blk_bytes(const u64 *__restrict__ bm, const BlkState *__restri
 hipError_t launch_blk_pivots(const TabDev &t, const BlkArgs &a, const BlkBuffers &b, uint8_t *out_bits,
                              uint8_t *out_rand, hipStream_t s) {
   hipLaunchKernelGGL(k_blk_snap, dim3(cdiv(t.L, 256), a.k), dim3(256), 0, s, t.X, t.Ls, t.L, a, b.snap);
-  hipLaunchKernelGGL(k_blk_pivots, dim3(1), dim3(64 * PW_WAVES), 0, s, b.snap, b.bm, t.Ls, t.K, a, b.bs, out_bits,
+  const u32 waves = std::max<u32>(1, std::min<u32>(PW_WAVES, cdiv(t.K, 64)));
+  hipLaunchKernelGGL(k_blk_pivots, dim3(1), dim3(64 * waves), 0, s, b.snap, b.bm, t.Ls, t.K, a, b.bs, out_bits,
                      out_rand);
   return hipGetLastError();
 }
@@ -685,8 +721,7 @@ hipError_t launch_blk_pass(const TabDev &t, const BlkBuffers &b, u32 cpc, hipStr
 hipError_t launch_blk_final(const TabDev &t, const BlkArgs &a, const BlkBuffers &b, MeasState *st, MeasStats *stats,
                             u32 cpc, hipStream_t s) {
   const u32 nchunks = cdiv(t.n, cpc);
-  hipLaunchKernelGGL(k_blk_reduce, dim3(cdiv(t.L, 256), 2), dim3(256), 0, s, b.part, b.bm, b.bs, t.Ls, t.L,
-                     nchunks);
+  hipLaunchKernelGGL(k_blk_reduce, dim3(cdiv(t.L, 4), 2), dim3(256), 0, s, b.part, b.bm, b.bs, t.Ls, t.L, nchunks);
   hipLaunchKernelGGL(k_blk_signs, dim3(cdiv(t.L, BLK_SIGN_T)), dim3(BLK_SIGN_T), 0, s, t.R, b.bm, b.part, b.bs, st,
                      stats, t.Ls, t.L, t.K);
   hipLaunchKernelGGL(k_blk_special, dim3(cdiv(t.n, 256)), dim3(256), 0, s, t.X, t.Z, b.patx, b.patz, b.bs, a, t.Ls,
