@@ -292,7 +292,11 @@ typedef struct {
   uint32_t rowsum_cols;        /* pivot-row columns per workgroup (per chunk) */
   uint32_t det_cols;           /* columns per workgroup of the deterministic-product phase */
   uint32_t meas_block;         /* sq_measure: random measurements per blocked pass (1 = one at a time, <= 32) */
+  uint32_t pivot_waves;        /* blocked pivot search: SQ_PIVOT_AUTO (default: registers when the stabilizer
+                                  half has at most 512 words, else tiles over up to 16 waves), or 1..16 =
+                                  tiles, computed lazily, over that many waves */
 } sq_tuning;
+#define SQ_PIVOT_AUTO 255u
 sq_status sq_get_tuning(const sq_tableau *t, sq_tuning *out);
 sq_status sq_set_tuning(sq_tableau *t, const sq_tuning *in);
 

@@ -22,6 +22,7 @@ K_LAYER, K_SIGNS, K_PIVOT, K_GATHER, K_ROWSUM, K_POST, K_BPIVOT, K_BPREP, K_BPAS
 KERNEL_NAMES = ["layer", "signs", "pivot", "gather", "rowsum", "post",
                 "block_pivot", "block_prep", "block_pass", "block_final"]
 MAX_MEAS_BLOCK = 32
+PIVOT_AUTO = 255         # sq_tuning.pivot_waves: choose the pivot search automatically
 
 EXPORTED = [
     "sq_last_error", "sq_version", "sq_bytes_required", "sq_create", "sq_destroy", "sq_reset", "sq_sync",
@@ -44,7 +45,7 @@ class SqError(RuntimeError):
 class Tuning(ctypes.Structure):
     _fields_ = [(name, ctypes.c_uint32) for name in (
         "layer_block", "layer_wpt", "layer_groups", "rowsum_block", "rowsum_wpt", "rowsum_cols",
-        "det_cols", "meas_block")]
+        "det_cols", "meas_block", "pivot_waves")]
 
 
 class BatchItem(ctypes.Structure):

@@ -48,6 +48,55 @@ __global__ void k_blk_snap(const u64 *__restrict__ X, u32 Ls, u32 L, BlkArgs a, 
 // costs two barriers; the per-pivot outputs are written once at the end.
 constexpr u32 PW_WAVES = 16;
 
+// The per-pivot outputs of a block, by wave 0 of the pivot kernels (lane s
+// for pivot s): positions, hit sets, M, the coins and outcome bytes, the
+// later pivots that hit each D_{p_s}, zeroed sums for the pivot algebra, and
+// the pivots grouped by row word.
+__device__ void pivots_finish(u32 lane, u32 k, const u32 *piv, const u32 *mrow, const u32 *mcol, const u32 *hits,
+                              const BlkArgs &a, BlkState *__restrict__ bs, uint8_t *__restrict__ out_bits,
+                              uint8_t *__restrict__ out_rand) {
+  const u32 s = lane;
+  const bool on = s < k;
+  if (on) {
+    const u32 c = coin_bit(a.seed, a.shot, a.m0 + s);
+    bs->p[s] = piv[s];
+    bs->hitS[s] = hits[s];
+    bs->M[s] = mrow[s];
+    bs->coin[s] = c;
+    out_rand[s] = 1;
+    out_bits[s] = (uint8_t)c;
+    // later pivots that hit D_{p_s} (which holds P_s from measurement s on)
+    u32 h = 0;
+    for (u32 s2 = s + 1; s2 < k; ++s2) h |= (((mrow[s] >> s2) ^ (u32)__popc(h & mcol[s2])) & 1u) << s2;
+    bs->dhits[s] = h;
+  }
+  if (s < KB) {
+    bs->Qz[s] = 0;
+    bs->R0[s] = 0;
+    bs->pc0[s] = 0;
+    bs->pcD[s] = 0;
+  }
+  // group the pivots by row word (pivots of a block usually share one or two),
+  // words numbered in order of first use
+  const u32 wd = on ? piv[s] >> 6 : 0xFFFFFFFFu;
+  u32 same = 0;  // pivots on this lane's word
+  for (u32 s2 = 0; s2 < k; ++s2) same |= ((u32)__shfl((int)wd, (int)s2) == wd ? 1u : 0u) << s2;
+  const bool first = on && (same & ((1u << s) - 1u)) == 0;
+  const u64 fb = __ballot(first);
+  if (first) {
+    const u32 i = (u32)__popcll(fb & ((1ULL << s) - 1ULL));
+    bs->word[i] = wd;
+    bs->wmem[i] = same;
+  }
+  if (lane == 0) {
+    bs->k = k;
+    bs->nwords = (u32)__popcll(fb);
+    bs->ncols = 0;
+    bs->done = 0;
+  }
+}
+
+
 __global__ __launch_bounds__(64 * PW_WAVES) void k_blk_pivots(const u64 *__restrict__ snap, u64 *__restrict__ bm,
                                                                u32 Ls, u32 K, BlkArgs a, BlkState *__restrict__ bs,
                                                                uint8_t *__restrict__ out_bits,
@@ -90,21 +139,27 @@ __global__ __launch_bounds__(64 * PW_WAVES) void k_blk_pivots(const u64 *__restr
   const u32 myt = ntiles > wave ? (ntiles - wave + nwv - 1) / nwv : 0;  // tiles of this wave
   u32 k = a.k;
   for (u32 s = 0; s < a.k; ++s) {
+    u64 vlast = 0;  // this lane's word of step s in the last tile the wave computed
     for (u32 j = 0; j < myt; ++j) {
-      // earlier steps first (their pivots are known, so their own bits are cleared too)
-      for (u32 sp = 0; sp < s; ++sp) {
-        for (u32 d = done[sp]; d <= j; ++d) {
-          const u32 w = word_of(d);
-          u64 v = tile_word(sp, w);
-          if ((piv[sp] >> 6) == w) v &= ~(1ULL << (piv[sp] & 63u));
-          if (w < K) bm[(size_t)sp * Ls + K + w] = v;
+      // earlier steps first (their pivots are known, so their own bits are
+      // cleared too); done[] never increases with the step, so done[s - 1]
+      // tells whether any earlier step lacks tile j
+      if (s > 0 && done[s - 1] <= j) {
+        for (u32 sp = 0; sp < s; ++sp) {
+          for (u32 d = done[sp]; d <= j; ++d) {
+            const u32 w = word_of(d);
+            u64 v = tile_word(sp, w);
+            if ((piv[sp] >> 6) == w) v &= ~(1ULL << (piv[sp] & 63u));
+            if (w < K) bm[(size_t)sp * Ls + K + w] = v;
+          }
+          if (lane == 0 && done[sp] <= j) done[sp] = j + 1;
         }
-        if (lane == 0 && done[sp] <= j) done[sp] = j + 1;
       }
       const u32 w = word_of(j);
       const u64 v = tile_word(s, w);
       if (w < K) bm[(size_t)s * Ls + K + w] = v;
       if (lane == 0) done[s] = j + 1;
+      vlast = v;
       const u64 nz = __ballot(v != 0);
       if (nz) {  // uniform over the wave
         if (lane == (u32)__builtin_ctzll(nz)) atomicMin(&s_wmin[s & 1u], w);
@@ -118,76 +173,107 @@ __global__ __launch_bounds__(64 * PW_WAVES) void k_blk_pivots(const u64 *__restr
       break;
     }
     if (tid == 0) s_wmin[(s + 1) & 1u] = 0xFFFFFFFFu;  // its last reader passed the barrier above
-    // the owning lane holds word wmin of this and every earlier step
-    if (wave == (wmin >> 6) % nwv && lane == (wmin & 63u)) {
-      u64 *col = bm + K + wmin;
-      const u64 vmin = col[(size_t)s * Ls];
+    // the owning wave (the one whose last tile holds word wmin) does the
+    // step's bookkeeping, one lane per step
+    if (wave == (wmin >> 6) % nwv) {
+      const u32 pl = wmin & 63u;
+      const u64 vmin = shfl_u64(vlast, (int)pl);
       const u32 pb = (u32)__builtin_ctzll(vmin);
       const u64 bit = 1ULL << pb;
-      u32 hit = 0;  // earlier pivots that hit S_p
-#pragma unroll
-      for (u32 sp = 0; sp < KB; ++sp) hit |= ((col[(size_t)sp * Ls] & bit) ? 1u : 0u) << sp;
-      hit &= (1u << s) - 1u;
-      col[(size_t)s * Ls] = vmin & ~bit;  // S_p is not multiplied by P_s
-      // x bits of P_s at the later measured columns: the snapshot's bit at p
-      // plus the earlier pivots that hit S_p (M is known for those)
-      const u64 *sc = snap + K + wmin;
-      u32 mb = 0;
-#pragma unroll
-      for (u32 s2 = 0; s2 < KB; ++s2)
-        mb |= (((u32)(sc[(size_t)s2 * Ls] >> pb) ^ (u32)__popc(hit & mcol[s2])) & 1u) << s2;
-      const u32 later = ~((2u << s) - 1u) & (a.k >= KB ? 0xFFFFFFFFu : (1u << a.k) - 1u);
-      mb &= later;
-      piv[s] = wmin * 64u + pb;
-      mrow[s] = mb;
-      hits[s] = hit;
-#pragma unroll
-      for (u32 s2 = 0; s2 < KB; ++s2)
-        if ((mb >> s2) & 1u) mcol[s2] |= 1u << s;
+      // rows of earlier steps at word wmin (written before the barrier) and
+      // the snapshot of every measured column there
+      const u64 hv = lane < s ? bm[(size_t)lane * Ls + K + wmin] : 0ULL;
+      const u64 sv = lane < a.k ? snap[(size_t)lane * Ls + K + wmin] : 0ULL;
+      const u32 hit = (u32)__ballot((hv & bit) != 0);  // earlier pivots that hit S_p
+      // x bit of P_s at the later measured column q_lane: the snapshot's bit
+      // at p plus the earlier pivots that hit S_p (M is known for those)
+      const bool later = lane > s && lane < a.k;
+      const bool mine = later && ((((u32)(sv >> pb)) ^ (u32)__popc(hit & mcol[lane & (KB - 1u)])) & 1u);
+      const u32 mb = (u32)__ballot(mine);
+      if (lane == pl) bm[(size_t)s * Ls + K + wmin] = vmin & ~bit;  // S_p is not multiplied by P_s
+      if (mine) mcol[lane] |= 1u << s;
+      if (lane == 0) {
+        piv[s] = wmin * 64u + pb;
+        mrow[s] = mb;
+        hits[s] = hit;
+      }
     }
     __syncthreads();
   }
-  if (wave != 0) return;
-  // one lane per decided pivot
-  const u32 s = lane;
-  const bool on = s < k;
-  if (on) {
-    const u32 c = coin_bit(a.seed, a.shot, a.m0 + s);
-    bs->p[s] = piv[s];
-    bs->hitS[s] = hits[s];
-    bs->M[s] = mrow[s];
-    bs->coin[s] = c;
-    out_rand[s] = 1;
-    out_bits[s] = (uint8_t)c;
-    // later pivots that hit D_{p_s} (which holds P_s from measurement s on)
-    u32 h = 0;
-    for (u32 s2 = s + 1; s2 < k; ++s2) h |= (((mrow[s] >> s2) ^ (u32)__popc(h & mcol[s2])) & 1u) << s2;
-    bs->dhits[s] = h;
+  if (wave == 0) pivots_finish(lane, k, piv, mrow, mcol, hits, a, bs, out_bits, out_rand);
+}
+
+// Small tableaux (at most PR_WAVES tiles of 64 stabilizer words): lane l
+// owns word l and keeps its rows of every step and its snapshot words in
+// registers, so a step touches LDS only. Every word is evaluated at every
+// step (the recurrence above, with the step loop unrolled so that rows are
+// indexed by constants); the pivots already found in a lane's word are left
+// out of its search, and the pivot's owner lane does the step's bookkeeping.
+constexpr u32 PR_WAVES = 8;
+
+__global__ __launch_bounds__(64 * PR_WAVES) void k_blk_pivots_reg(const u64 *__restrict__ snap, u32 Ls, u32 K,
+                                                                  BlkArgs a, BlkState *__restrict__ bs,
+                                                                  uint8_t *__restrict__ out_bits,
+                                                                  uint8_t *__restrict__ out_rand) {
+  __shared__ u32 s_wmin[2];  // double-buffered: step s uses s_wmin[s & 1]
+  __shared__ u32 piv[KB], mrow[KB], mcol[KB], hits[KB];
+  const u32 tid = threadIdx.x, lane = tid & 63u, wave = tid >> 6;
+  const u32 w = tid;  // this lane's stabilizer word
+  const bool in = w < K;
+  if (tid < KB) { piv[tid] = 0; mrow[tid] = 0; mcol[tid] = 0; hits[tid] = 0; }
+  if (tid < 2) s_wmin[tid] = 0xFFFFFFFFu;
+  u64 sn[KB], rv[KB];
+#pragma unroll
+  for (u32 s = 0; s < KB; ++s) {  // rows past a.k are allocated; they are masked out below
+    sn[s] = in ? snap[(size_t)s * Ls + K + w] : 0ULL;
+    rv[s] = 0;
   }
-  if (s < KB) {
-    bs->Qz[s] = 0;
-    bs->R0[s] = 0;
-    bs->pc0[s] = 0;
-    bs->pcD[s] = 0;
+  u64 spec = 0;  // pivots found in this word so far (rows S_{p_s'}: Z now, no x)
+  const u32 kall = a.k >= KB ? 0xFFFFFFFFu : (1u << a.k) - 1u;
+  u32 k = a.k;
+  __syncthreads();
+#pragma unroll
+  for (u32 s = 0; s < KB; ++s) {
+    if (s < k) {  // uniform
+      const u32 sel = __builtin_amdgcn_readfirstlane(mcol[s]);  // M[s'][s] of the earlier steps
+      u64 v = sn[s];
+#pragma unroll
+      for (u32 sp = 0; sp < s; ++sp)
+        if ((sel >> sp) & 1u) v ^= rv[sp];
+      rv[s] = v;
+      const u64 vc = v & ~spec;
+      const u64 nz = __ballot(vc != 0);
+      if (nz && lane == (u32)__builtin_ctzll(nz)) atomicMin(&s_wmin[s & 1u], w);
+      __syncthreads();
+      const u32 wmin = s_wmin[s & 1u];
+      if (wmin == 0xFFFFFFFFu) {  // deterministic: the block ends here
+        k = s;
+      } else {
+        if (tid == 0) s_wmin[(s + 1) & 1u] = 0xFFFFFFFFu;  // its last reader passed the barrier above
+        if (w == wmin) {
+          const u32 pb = (u32)__builtin_ctzll(vc);
+          spec |= 1ULL << pb;
+          u32 hit = 0;  // earlier pivots that hit S_p
+#pragma unroll
+          for (u32 sp = 0; sp < s; ++sp) hit |= (u32)((rv[sp] >> pb) & 1ULL) << sp;
+          // x bits of P_s at the later measured columns
+          u32 mb = 0;
+#pragma unroll
+          for (u32 s2 = s + 1; s2 < KB; ++s2)
+            mb |= ((((u32)(sn[s2] >> pb)) ^ (u32)__popc(hit & mcol[s2])) & 1u) << s2;
+          mb &= kall;
+          piv[s] = wmin * 64u + pb;
+          mrow[s] = mb;
+          hits[s] = hit;
+#pragma unroll
+          for (u32 s2 = s + 1; s2 < KB; ++s2)
+            if ((mb >> s2) & 1u) atomicOr(&mcol[s2], 1u << s);
+        }
+        __syncthreads();
+      }
+    }
   }
-  // group the pivots by row word (pivots of a block usually share one or two),
-  // words numbered in order of first use
-  const u32 wd = on ? piv[s] >> 6 : 0xFFFFFFFFu;
-  u32 same = 0;  // pivots on this lane's word
-  for (u32 s2 = 0; s2 < k; ++s2) same |= ((u32)__shfl((int)wd, (int)s2) == wd ? 1u : 0u) << s2;
-  const bool first = on && (same & ((1u << s) - 1u)) == 0;
-  const u64 fb = __ballot(first);
-  if (first) {
-    const u32 i = (u32)__popcll(fb & ((1ULL << s) - 1ULL));
-    bs->word[i] = wd;
-    bs->wmem[i] = same;
-  }
-  if (lane == 0) {
-    bs->k = k;
-    bs->nwords = (u32)__popcll(fb);
-    bs->ncols = 0;
-    bs->done = 0;
-  }
+  if (wave == 0) pivots_finish(lane, k, piv, mrow, mcol, hits, a, bs, out_bits, out_rand);
 }
 
 // -------------------------------------------------------------- hit masks
@@ -207,14 +293,13 @@ __global__ void k_blk_masks(const u64 *__restrict__ snap, u64 *__restrict__ bm, 
     if ((bs->p[t] >> 6) == hw) special |= 1ULL << (bs->p[t] & 63u);
   u64 b[KB];
 #pragma unroll
-  for (u32 s = 0; s < KB; ++s) {
-    b[s] = 0;
-    if (s < k) {
-      u64 v = snap[(size_t)s * Ls + w];
+  for (u32 s = 0; s < KB; ++s) b[s] = snap[(size_t)s * Ls + w];  // rows past k are allocated, not used
 #pragma unroll
-      for (u32 sp = 0; sp < KB; ++sp)
-        if (sp < s && ((bs->M[sp] >> s) & 1u)) v ^= b[sp];
-      b[s] = v;
+  for (u32 s = 0; s < KB; ++s) {
+    if (s < k) {
+#pragma unroll
+      for (u32 sp = 0; sp < s; ++sp)
+        if ((bs->M[sp] >> s) & 1u) b[s] ^= b[sp];
     }
   }
 #pragma unroll
@@ -498,7 +583,9 @@ __global__ void k_blk_reduce(u64 *__restrict__ part, const u64 *__restrict__ bm,
 // -------------------------------------------------------------- final
 // Thread per row word (blocks of BLK_SIGN_T): new signs of the hit rows from
 // the lam algebra, then the special rows' signs (dsign, the coins). The hit
-// masks are staged in LDS, where they can be indexed by pivot.
+// masks stay in registers (the pivot conditions are uniform). The block's
+// byte count (x and z of every supported column, read and written, for each
+// row word holding a hit row) is added here too.
 constexpr u32 BLK_SIGN_T = 128;
 
 __global__ __launch_bounds__(BLK_SIGN_T) void k_blk_signs(u64 *__restrict__ R, const u64 *__restrict__ bm,
@@ -506,18 +593,20 @@ __global__ __launch_bounds__(BLK_SIGN_T) void k_blk_signs(u64 *__restrict__ R, c
                                                            const BlkState *__restrict__ bs,
                                                            MeasState *__restrict__ st, MeasStats *__restrict__ stats,
                                                            u32 Ls, u32 L, u32 K) {
-  __shared__ u64 sb[KB][BLK_SIGN_T];
   const u32 k = bs->k;
   if (k == 0) return;
-  const u32 tid = threadIdx.x;
-  const u32 w = blockIdx.x * blockDim.x + tid;
-  if (w >= L) return;
+  const u32 w = blockIdx.x * blockDim.x + threadIdx.x;
+  const bool in = w < L;
+  u64 b[KB];
+#pragma unroll
+  for (u32 s = 0; s < KB; ++s) b[s] = in ? bm[(size_t)s * Ls + w] : 0ULL;  // rows past k: not used
   u64 any = 0;
-  for (u32 s = 0; s < k; ++s) {
-    const u64 v = bm[(size_t)s * Ls + w];
-    sb[s][tid] = v;  // each thread reads back only its own column of sb
-    any |= v;
-  }
+#pragma unroll
+  for (u32 s = 0; s < KB; ++s)
+    if (s < k) any |= b[s];
+  const u32 nhit = (u32)__popcll(__ballot(any != 0));
+  if ((threadIdx.x & 63u) == 0 && nhit) atomicAdd(&stats->block_bytes, (u64)nhit * 8ULL * 4ULL * bs->ncols);
+  if (!in) return;
   u64 r = R[w];
   bool touched = false;
   if (any) {
@@ -525,14 +614,18 @@ __global__ __launch_bounds__(BLK_SIGN_T) void k_blk_signs(u64 *__restrict__ R, c
     const u64 d0 = part[w], d1 = part[Ls + w], yy = part[2 * (size_t)Ls + w];
     // lam = sum_s b_s lam(P_s) + 2 sum_{s<s'} b_s b_s' Qz[s'][s] + 2 r + 2 (z_{C_h} . x_h) + d
     u64 l0 = 0, l1 = 0;
-    for (u32 s = 0; s < k; ++s) {
-      const u64 bsv = sb[s][tid];
-      const u32 lp = bs->lam[s];
-      if (lp & 1u) { l1 ^= l0 & bsv; l0 ^= bsv; }
-      if (lp & 2u) l1 ^= bsv;
-      u64 acc = 0;  // XOR of the earlier masks selected by row s of Qz
-      for (u32 m = bs->Qz[s] & ((1u << s) - 1u); m; m &= m - 1) acc ^= sb[__builtin_ctz(m)][tid];
-      l1 ^= bsv & acc;
+#pragma unroll
+    for (u32 s = 0; s < KB; ++s) {
+      if (s < k) {
+        const u32 lp = bs->lam[s], q = bs->Qz[s];
+        if (lp & 1u) { l1 ^= l0 & b[s]; l0 ^= b[s]; }
+        if (lp & 2u) l1 ^= b[s];
+        u64 acc = 0;  // XOR of the earlier masks selected by row s of Qz
+#pragma unroll
+        for (u32 sp = 0; sp < s; ++sp)
+          if ((q >> sp) & 1u) acc ^= b[sp];
+        l1 ^= b[s] & acc;
+      }
     }
     l1 ^= r ^ yy;
     {
@@ -622,7 +715,7 @@ __global__ void k_blk_sv_prep(const u64 *__restrict__ sg, u32 Ks, u32 count, u32
 // Grid (stabilizer-word tiles, column chunks of SV_CHUNK): thread per
 // stabilizer word, looping over the chunk's columns t in [0, m0 + k]: t < m0
 // coin columns, m0 <= t < m0 + k this block's coins, t = m0 + k the constant.
-constexpr u32 SV_CHUNK = 64;
+constexpr u32 SV_CHUNK = 16, SV_GROUP = 16;
 
 __global__ __launch_bounds__(64) void k_blk_sv_update(u64 *__restrict__ sg, u32 Ks, u32 count, u32 m0,
                                                        const BlkState *__restrict__ bs, const u64 *__restrict__ bm,
@@ -638,60 +731,57 @@ __global__ __launch_bounds__(64) void k_blk_sv_update(u64 *__restrict__ sg, u32 
   for (u32 s = 0; s < k; ++s)
     if ((bs->p[s] >> 6) == w) smask |= 1ULL << (bs->p[s] & 63u);
   const u32 tlo = blockIdx.y * SV_CHUNK, thi = min(tlo + SV_CHUNK, m0 + k + 1);
-  for (u32 t = tlo; t < thi; ++t) {
-    const bool own = t >= m0 && t < m0 + k;  // a coin of this block
-    const u32 v = t < m0 + k ? t : count;
-    const size_t o = (size_t)v * Ks + w;
-    u64 val = sg[o];
-    if (!own) {
-      const u32 lin = svt[t < m0 ? t : m0];
-      u64 acc = 0;
+  // columns in groups of SV_GROUP: the group's loads are in flight together
+  for (u32 t0 = tlo; t0 < thi; t0 += SV_GROUP) {
+    u64 val[SV_GROUP];
 #pragma unroll
-      for (u32 s = 0; s < KB; ++s)
-        if ((lin >> s) & 1u) acc ^= b[s];
-      val ^= acc;
-      if (v == count) val ^= cvec[K + w];
+    for (u32 i = 0; i < SV_GROUP; ++i) {
+      const u32 t = t0 + i;
+      const u32 v = t < m0 + k ? t : count;
+      val[i] = t < thi ? sg[(size_t)v * Ks + w] : 0ULL;
     }
-    if (smask) {
-      u64 set = 0;
-      if (own) {
-        const u32 p = bs->p[t - m0];
-        if ((p >> 6) == w) set = 1ULL << (p & 63u);
+#pragma unroll
+    for (u32 i = 0; i < SV_GROUP; ++i) {
+      const u32 t = t0 + i;
+      if (t >= thi) continue;
+      const bool own = t >= m0 && t < m0 + k;  // a coin of this block
+      const u32 v = t < m0 + k ? t : count;
+      u64 x = val[i];
+      if (!own) {
+        const u32 lin = svt[t < m0 ? t : m0];
+        u64 acc = 0;
+#pragma unroll
+        for (u32 s = 0; s < KB; ++s)
+          if ((lin >> s) & 1u) acc ^= b[s];
+        x ^= acc;
+        if (v == count) x ^= cvec[K + w];
       }
-      val = (val & ~smask) | set;
+      if (smask) {
+        u64 set = 0;
+        if (own) {
+          const u32 p = bs->p[t - m0];
+          if ((p >> 6) == w) set = 1ULL << (p & 63u);
+        }
+        x = (x & ~smask) | set;
+      }
+      sg[(size_t)v * Ks + w] = x;
     }
-    sg[o] = val;
   }
-}
-
-// Bytes of a block pass, counted by row word: read and write x and z of every
-// supported column for each row word that holds a hit row.
-__global__ void k_blk_bytes(const u64 *__restrict__ bm, const BlkState *__restrict__ bs, MeasStats *stats, u32 Ls,
-                            u32 L) {
-  __shared__ u32 s_cnt;
-  if (threadIdx.x == 0) s_cnt = 0;
-  __syncthreads();
-  const u32 k = bs->k;
-  u32 c = 0;
-  for (u32 w = threadIdx.x; w < L; w += blockDim.x) {
-    u64 any = 0;
-    for (u32 s = 0; s < k; ++s) any |= bm[(size_t)s * Ls + w];
-    c += any != 0;
-  }
-  atomicAdd(&s_cnt, c);
-  __syncthreads();
-  if (threadIdx.x == 0 && k) stats->block_bytes += (u64)s_cnt * 8ULL * 4ULL * bs->ncols;
 }
 
 // -------------------------------------------------------------- launchers
 // Stage 0: snapshot of the measured columns and the sequential pivot step
 // (writes BlkState::k, which the host reads before stage 1).
 hipError_t launch_blk_pivots(const TabDev &t, const BlkArgs &a, const BlkBuffers &b, uint8_t *out_bits,
-                             uint8_t *out_rand, hipStream_t s) {
+                             uint8_t *out_rand, u32 waves, hipStream_t s) {
   hipLaunchKernelGGL(k_blk_snap, dim3(cdiv(t.L, 256), a.k), dim3(256), 0, s, t.X, t.Ls, t.L, a, b.snap);
-  const u32 waves = std::max<u32>(1, std::min<u32>(PW_WAVES, cdiv(t.K, 64)));
-  hipLaunchKernelGGL(k_blk_pivots, dim3(1), dim3(64 * waves), 0, s, b.snap, b.bm, t.Ls, t.K, a, b.bs, out_bits,
-                     out_rand);
+  const u32 tiles = std::max<u32>(1, cdiv(t.K, 64));
+  if (waves == PIVOT_AUTO && tiles <= PR_WAVES)
+    hipLaunchKernelGGL(k_blk_pivots_reg, dim3(1), dim3(64 * tiles), 0, s, b.snap, t.Ls, t.K, a, b.bs, out_bits,
+                       out_rand);
+  else
+    hipLaunchKernelGGL(k_blk_pivots, dim3(1), dim3(64 * std::min<u32>({PW_WAVES, tiles, waves})), 0, s, b.snap,
+                       b.bm, t.Ls, t.K, a, b.bs, out_bits, out_rand);
   return hipGetLastError();
 }
 
@@ -705,7 +795,6 @@ hipError_t launch_blk_prep(const TabDev &t, const BlkArgs &a, const BlkBuffers &
   hipLaunchKernelGGL(k_blk_pairs, dim3(cdiv(t.K, 64), a.k), dim3(64), 0, s, b.p0x, b.px, b.pz, t.K, b.bs, st);
   hipLaunchKernelGGL(k_blk_patterns, dim3(cdiv(t.n, 256)), dim3(256), 0, s, b.px, b.pz, b.patx, b.patz, t.K, t.n,
                      b.bs);
-  hipLaunchKernelGGL(k_blk_bytes, dim3(1), dim3(1024), 0, s, b.bm, b.bs, stats, t.Ls, t.L);
   return hipGetLastError();
 }
 

@@ -69,4 +69,10 @@ __device__ __forceinline__ u64 shfl_xor_u64(u64 v, int off) {
   return ((u64)hi << 32) | lo;
 }
 
+// 64-bit broadcast of lane src's value, as two 32-bit shuffles.
+__device__ __forceinline__ u64 shfl_u64(u64 v, int src) {
+  const u32 lo = (u32)__shfl((int)(u32)v, src), hi = (u32)__shfl((int)(u32)(v >> 32), src);
+  return ((u64)hi << 32) | lo;
+}
+
 }  // namespace sq

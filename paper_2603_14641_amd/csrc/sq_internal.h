@@ -181,8 +181,11 @@ hipError_t launch_coins(u64 *cw, u64 seed, u64 shot_begin, u64 meas_base, u32 sh
 hipError_t launch_eval(const u64 *cw, const uint8_t *kind, const u64 *fm, const uint8_t *fc, u64 *out, u32 shots,
                        u32 count, u32 CW, hipStream_t s);
 hipError_t launch_batch(const BatchItem *items, u32 nitems, u32 *next, u32 block, u32 grid, hipStream_t s);
+// waves: PIVOT_AUTO (the C-ABI's SQ_PIVOT_AUTO), or 1..16 for the tiled search
+// with that many waves
+constexpr u32 PIVOT_AUTO = 255;
 hipError_t launch_blk_pivots(const TabDev &t, const BlkArgs &a, const BlkBuffers &b, uint8_t *out_bits,
-                             uint8_t *out_rand, hipStream_t s);
+                             uint8_t *out_rand, u32 waves, hipStream_t s);
 hipError_t launch_blk_prep(const TabDev &t, const BlkArgs &a, const BlkBuffers &b, MeasState *st, MeasStats *stats,
                            hipStream_t s);
 hipError_t launch_blk_pass(const TabDev &t, const BlkBuffers &b, u32 cpc, hipStream_t s);

@@ -137,6 +137,8 @@ struct sq_program {
 namespace {
 
 // Columns per chunk of the blocked pass: about 2048 workgroups in all.
+static_assert(SQ_PIVOT_AUTO == PIVOT_AUTO, "pivot_waves sentinel");
+
 u32 blk_cpc_of(const Dims &d) {
   const u32 tiles = cdiv(d.L, 256);
   const u32 want = std::max<u32>(1, 2048 / tiles);
@@ -186,6 +188,7 @@ void default_tuning(const Dims &d, sq_tuning *t) {
   t->rowsum_cols = 0;   // automatic
   t->det_cols = 0;      // automatic
   t->meas_block = KB;
+  t->pivot_waves = SQ_PIVOT_AUTO;
 }
 
 u32 layer_gpc(const sq_tableau *T, u32 ngroups) {
@@ -329,7 +332,7 @@ sq_status measure_range(sq_tableau *T, const uint32_t *qubits, u64 i0, u64 i1, u
     a.seed = seed;
     a.shot = shot;
     a.m0 = meas_base + i;
-    SQ_TRY(timed(T, SQ_K_BPIVOT, [&] { return launch_blk_pivots(T->t, a, T->blk, dbits + i, drand + i, T->stream); }));
+    SQ_TRY(timed(T, SQ_K_BPIVOT, [&] { return launch_blk_pivots(T->t, a, T->blk, dbits + i, drand + i, T->tun.pivot_waves, T->stream); }));
     HIP_TRY(hipMemcpyAsync(T->blk_k_host, &T->blk.bs->k, sizeof(u32), hipMemcpyDeviceToHost, T->stream));
     HIP_TRY(hipStreamSynchronize(T->stream));
     const u32 k = *T->blk_k_host;
@@ -384,6 +387,8 @@ sq_status check_tuning(const sq_tuning &t) {
   if ((t.layer_wpt != 1 && t.layer_wpt != 2) || (t.rowsum_wpt != 1 && t.rowsum_wpt != 2))
     return fail(SQ_EINVAL, "words per thread must be 1 or 2");
   if (t.meas_block < 1 || t.meas_block > KB) return fail(SQ_EINVAL, "meas_block must be in [1, %u]", KB);
+  if (t.pivot_waves != SQ_PIVOT_AUTO && (t.pivot_waves < 1 || t.pivot_waves > 16))
+    return fail(SQ_EINVAL, "pivot_waves must be in [1, 16] or SQ_PIVOT_AUTO");
   return SQ_OK;
 }
 
@@ -624,7 +629,7 @@ sq_status sq_sample(sq_tableau *T, const uint32_t *qubits, uint32_t count, uint6
       a.m0 = i;
       HIP_TRY(launch_fill_zero(cvec, d.Ls, T->stream));
       SQ_TRY(timed(T, SQ_K_BPIVOT, [&] {
-        return launch_blk_pivots(tb, a, T->blk, ws + o_bits, kind + i, T->stream);
+        return launch_blk_pivots(tb, a, T->blk, ws + o_bits, kind + i, T->tun.pivot_waves, T->stream);
       }));
       HIP_TRY(hipMemcpyAsync(T->blk_k_host, &T->blk.bs->k, sizeof(u32), hipMemcpyDeviceToHost, T->stream));
       HIP_TRY(hipStreamSynchronize(T->stream));
@@ -1183,6 +1188,7 @@ sq_status sq_set_tuning(sq_tableau *T, const sq_tuning *in) {
   if (in->rowsum_cols) t.rowsum_cols = in->rowsum_cols;
   if (in->det_cols) t.det_cols = in->det_cols;
   if (in->meas_block) t.meas_block = in->meas_block;
+  if (in->pivot_waves) t.pivot_waves = in->pivot_waves;
   SQ_TRY(check_tuning(t));
   T->tun = t;
   return SQ_OK;

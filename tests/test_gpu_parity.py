@@ -127,6 +127,54 @@ def test_blocked_measurements(n, mb):
         assert st.blocks > 0
 
 
+def _deep_pivot_program(rng, n, lo, hi0, count):
+    """Superpositions on qubits [0, lo) and [hi0, n) only: measuring a high
+    qubit finds its pivot among stabilizer rows >= hi0 (later 64-word tiles),
+    a low one in the first word, an untouched one nothing (deterministic,
+    which ends a block). The measured qubits mix all three."""
+    hi = np.arange(hi0, n)
+    ops = [[orc.H, int(q), 0] for q in hi] + [[orc.H, q, 0] for q in range(lo)]
+    perm = rng.permutation(hi)
+    ops += [[orc.CX, int(a), int(b)] for a, b in zip(perm[::2], perm[1::2])]
+    ops += [[orc.S, int(q), 0] for q in rng.choice(hi, hi.size // 4, replace=False)]
+    ops += [[orc.CX, a, a + 1] for a in range(0, lo - 1, 2)]
+    qs = []
+    for _ in range(count):
+        u = rng.random()
+        if u < 0.55:
+            qs.append(int(rng.choice(hi)))
+        elif u < 0.9:
+            qs.append(int(rng.integers(0, lo)))
+        else:
+            qs.append(int(rng.integers(lo, hi0)))
+    ops += [[orc.MEASURE, q, 0] for q in qs]
+    return np.array(ops, dtype=np.uint32)
+
+
+@pytest.mark.parametrize("n,hi0", [(5000, 4100), (20000, 16500)])
+@pytest.mark.parametrize("pw", ["auto", 1, 2, 16])
+def test_blocked_deep_pivots(n, hi0, pw):
+    """Pivots spread over several 64-word tiles of the stabilizer half, for
+    both pivot searches: registers (automatic at these sizes) and the lazy
+    tiled one with 1, 2 or 16 waves (a wave owning several tiles computes
+    later tiles of earlier steps on demand). Outcomes, flags and the whole
+    tableau bit-exact with one-at-a-time CHP."""
+    rng = np.random.default_rng(n + (0 if pw == "auto" else pw))
+    ops = _deep_pivot_program(rng, n, 40, hi0, 96)
+    seed = int(rng.integers(1 << 40))
+    rb, rr, x, z, r, _ = oracle_run(n, ops, seed, shot=1)
+    assert rr.sum() >= 40 and (rr == 0).sum() >= 8
+    tun = dict(meas_block=32)
+    if pw != "auto":
+        tun["pivot_waves"] = pw
+    t = _tab(n, tun)
+    bits, rnd = gpu_run_calls(t, ops, seed, shot=1)
+    _assert_same(bits, rb, "outcomes")
+    _assert_same(rnd, rr, "random flags")
+    _compare_full(t, (x, z, r))
+    assert t.measure_stats().blocks > 0
+
+
 def test_blocked_pivots_share_words():
     """n = 40 (one word of rows per half): every pivot of a block sits in the
     same 64-row word, as do the D rows they overwrite."""
@@ -247,6 +295,10 @@ def test_empty_calls_and_errors_leave_state_unchanged():
             t.apply_gates(np.array(bad, dtype=np.uint32))
     with pytest.raises(SqError):
         t.measure([0, n])
+    for bad in (dict(pivot_waves=17), dict(meas_block=33), dict(layer_block=96)):
+        with pytest.raises(SqError):
+            t.set_tuning(**bad)
+    assert t.tuning().pivot_waves == 255   # automatic, unchanged by the rejected calls
     after = t.export()
     for u, v in zip(before, after):
         _assert_same(u, v, "state after rejected calls")
