@@ -25,20 +25,13 @@
 
 namespace sq {
 
-// -------------------------------------------------------------- snapshot
-__global__ void k_blk_snap(const u64 *__restrict__ X, u32 Ls, u32 L, BlkArgs a, u64 *__restrict__ snap) {
-  const u32 s = blockIdx.y;
-  const u32 w = blockIdx.x * blockDim.x + threadIdx.x;
-  if (s >= a.k || w >= L) return;
-  snap[(size_t)s * Ls + w] = X[(size_t)a.q[s] * Ls + w];
-}
-
 // -------------------------------------------------------------- pivots (one workgroup)
 // Sequential over the measurements of the block; within a step the
 // stabilizer words are spread over the workgroup's waves. For step s the
 // stabilizer half of column q_s as it stands before measurement s is
-//   snap_s ^ XOR_{s' < s, M[s'][s] = 1} (hit mask of s'),
-// with the rows S_{p_s'} (now Z_{q_s'}, no x) cleared. Words come in tiles of
+//   X_{q_s} ^ XOR_{s' < s, M[s'][s] = 1} (hit mask of s'),
+// with X as it stands before the block (nothing writes X until the pass) and
+// the rows S_{p_s'} (now Z_{q_s'}, no x) cleared. Words come in tiles of
 // 64; wave v owns the tiles t = v mod (waves) and lane l word 64t + l, so a
 // lane only ever reads words it wrote itself. Each wave computes its tiles
 // lazily, in order (for every earlier step first), and stops at its first
@@ -97,7 +90,7 @@ __device__ void pivots_finish(u32 lane, u32 k, const u32 *piv, const u32 *mrow, 
 }
 
 
-__global__ __launch_bounds__(64 * PW_WAVES) void k_blk_pivots(const u64 *__restrict__ snap, u64 *__restrict__ bm,
+__global__ __launch_bounds__(64 * PW_WAVES) void k_blk_pivots(const u64 *__restrict__ X, u64 *__restrict__ bm,
                                                                u32 Ls, u32 K, BlkArgs a, BlkState *__restrict__ bs,
                                                                uint8_t *__restrict__ out_bits,
                                                                uint8_t *__restrict__ out_rand) {
@@ -109,18 +102,22 @@ __global__ __launch_bounds__(64 * PW_WAVES) void k_blk_pivots(const u64 *__restr
   __shared__ u32 mcol[KB];             // bit s' of mcol[s] = M[s'][s]
   __shared__ u32 hits[KB];             // earlier pivots that hit S_{p_s}
   __shared__ u32 sdone[PW_WAVES][KB];  // tiles of each wave computed per step
+  __shared__ u32 sq[KB];               // measured qubits (step s reads column q_s of X)
   const u32 tid = threadIdx.x, lane = tid & 63u, wave = tid >> 6, nwv = blockDim.x >> 6;
   const u32 ntiles = (K + 63u) / 64u;
   u32 *done = sdone[wave];
   if (tid < KB) { piv[tid] = 0; mrow[tid] = 0; mcol[tid] = 0; hits[tid] = 0; }
   if (tid < 2) s_wmin[tid] = 0xFFFFFFFFu;
+#pragma unroll
+  for (u32 s = 0; s < KB; ++s)
+    if (tid == s) sq[s] = s < a.k ? a.q[s] : 0u;
   if (lane < KB) done[lane] = 0;
   __syncthreads();
   auto word_of = [&](u32 j) { return (j * nwv + wave) * 64u + lane; };  // local tile j
   auto tile_word = [&](u32 s, u32 w) -> u64 {
     if (w >= K) return 0ULL;
     const u64 *col = bm + K + w;
-    u64 v = snap[(size_t)s * Ls + K + w];
+    u64 v = X[(size_t)sq[s] * Ls + K + w];
     const u32 sel = mcol[s] & ((1u << s) - 1u);
     // every row is loaded (rows the step does not use are masked), so the
     // loads are independent and in flight together
@@ -181,12 +178,12 @@ __global__ __launch_bounds__(64 * PW_WAVES) void k_blk_pivots(const u64 *__restr
       const u32 pb = (u32)__builtin_ctzll(vmin);
       const u64 bit = 1ULL << pb;
       // rows of earlier steps at word wmin (written before the barrier) and
-      // the snapshot of every measured column there
+      // every measured column of X there
       const u64 hv = lane < s ? bm[(size_t)lane * Ls + K + wmin] : 0ULL;
-      const u64 sv = lane < a.k ? snap[(size_t)lane * Ls + K + wmin] : 0ULL;
+      const u64 sv = lane < a.k ? X[(size_t)sq[lane] * Ls + K + wmin] : 0ULL;
       const u32 hit = (u32)__ballot((hv & bit) != 0);  // earlier pivots that hit S_p
-      // x bit of P_s at the later measured column q_lane: the snapshot's bit
-      // at p plus the earlier pivots that hit S_p (M is known for those)
+      // x bit of P_s at the later measured column q_lane: X's bit at p plus
+      // the earlier pivots that hit S_p (M is known for those)
       const bool later = lane > s && lane < a.k;
       const bool mine = later && ((((u32)(sv >> pb)) ^ (u32)__popc(hit & mcol[lane & (KB - 1u)])) & 1u);
       const u32 mb = (u32)__ballot(mine);
@@ -204,14 +201,14 @@ __global__ __launch_bounds__(64 * PW_WAVES) void k_blk_pivots(const u64 *__restr
 }
 
 // Small tableaux (at most PR_WAVES tiles of 64 stabilizer words): lane l
-// owns word l and keeps its rows of every step and its snapshot words in
-// registers, so a step touches LDS only. Every word is evaluated at every
+// owns word l and keeps its rows of every step and its words of the
+// measured columns in registers, so a step touches LDS only. Every word is evaluated at every
 // step (the recurrence above, with the step loop unrolled so that rows are
 // indexed by constants); the pivots already found in a lane's word are left
 // out of its search, and the pivot's owner lane does the step's bookkeeping.
 constexpr u32 PR_WAVES = 8;
 
-__global__ __launch_bounds__(64 * PR_WAVES) void k_blk_pivots_reg(const u64 *__restrict__ snap, u32 Ls, u32 K,
+__global__ __launch_bounds__(64 * PR_WAVES) void k_blk_pivots_reg(const u64 *__restrict__ X, u32 Ls, u32 K,
                                                                   BlkArgs a, BlkState *__restrict__ bs,
                                                                   uint8_t *__restrict__ out_bits,
                                                                   uint8_t *__restrict__ out_rand) {
@@ -224,8 +221,8 @@ __global__ __launch_bounds__(64 * PR_WAVES) void k_blk_pivots_reg(const u64 *__r
   if (tid < 2) s_wmin[tid] = 0xFFFFFFFFu;
   u64 sn[KB], rv[KB];
 #pragma unroll
-  for (u32 s = 0; s < KB; ++s) {  // rows past a.k are allocated; they are masked out below
-    sn[s] = in ? snap[(size_t)s * Ls + K + w] : 0ULL;
+  for (u32 s = 0; s < KB; ++s) {  // steps past a.k are masked out below
+    sn[s] = in && s < a.k ? X[(size_t)a.q[s] * Ls + K + w] : 0ULL;
     rv[s] = 0;
   }
   u64 spec = 0;  // pivots found in this word so far (rows S_{p_s'}: Z now, no x)
@@ -282,8 +279,8 @@ __global__ __launch_bounds__(64 * PR_WAVES) void k_blk_pivots_reg(const u64 *__r
 //   b_s = a_s ^ XOR_{s' < s} b_{s'} M[s'][s]
 // holds; the special rows (D_p and S_p of every pivot) take no part in the
 // pass and are cleared.
-__global__ void k_blk_masks(const u64 *__restrict__ snap, u64 *__restrict__ bm, const BlkState *__restrict__ bs,
-                            u32 Ls, u32 L, u32 K) {
+__global__ void k_blk_masks(const u64 *__restrict__ X, u64 *__restrict__ bm, const BlkState *__restrict__ bs,
+                            BlkArgs a, u32 Ls, u32 L, u32 K) {
   const u32 k = bs->k;
   const u32 w = blockIdx.x * blockDim.x + threadIdx.x;
   if (w >= L || k == 0) return;
@@ -293,7 +290,7 @@ __global__ void k_blk_masks(const u64 *__restrict__ snap, u64 *__restrict__ bm, 
     if ((bs->p[t] >> 6) == hw) special |= 1ULL << (bs->p[t] & 63u);
   u64 b[KB];
 #pragma unroll
-  for (u32 s = 0; s < KB; ++s) b[s] = snap[(size_t)s * Ls + w];  // rows past k are allocated, not used
+  for (u32 s = 0; s < KB; ++s) b[s] = s < k ? X[(size_t)a.q[s] * Ls + w] : 0ULL;
 #pragma unroll
   for (u32 s = 0; s < KB; ++s) {
     if (s < k) {
@@ -307,130 +304,162 @@ __global__ void k_blk_masks(const u64 *__restrict__ snap, u64 *__restrict__ bm, 
     if (s < k) bm[(size_t)s * Ls + w] = b[s] & ~special;
 }
 
-// -------------------------------------------------------------- original pivot rows
-// Thread per column: the x and z words of the pivots' stabilizer words (one
-// read each per distinct word, usually one or two per block), then one wave
-// ballot per pivot packs its bits of 64 columns.
-__global__ void k_blk_gather(const u64 *__restrict__ X, const u64 *__restrict__ Z, const u64 *__restrict__ R, u32 Ls,
-                             u32 K, u32 n, BlkState *__restrict__ bs, u64 *__restrict__ p0x, u64 *__restrict__ p0z) {
+// -------------------------------------------------------------- pivot rows and their algebra
+// Grid cdiv(n, ROWS_T): thread per column j, wave per 64-column word cw.
+// (1) The original pivot rows' bits at the wave's columns: one read of x and
+// z per distinct stabilizer word holding pivots, a ballot per pivot.
+// (2) The evolved pivot rows P_s = S0_{p_s} times the earlier pivots that hit
+// it, in order (uniform over the wave). (3) The column patterns: bit s of
+// patx[j] / patz[j] = P_s has x / z at j; columns where some P_s is not the
+// identity are counted. (4) The word's share of the pair products, lane a
+// for pivot a: bits b of z_{P_a} . x_{P_b} (Qz) and of z_{P_a} . x_{S0_b}
+// (R0), |x & z| of the final D_{p_a} (P_a times its later hits) and of the
+// original row S0_{p_a}, the counts mod 4. The last block to finish sums the
+// shares over words and forms lam(P_s) and the final signs of the D_{p_s}.
+constexpr u32 ROWS_T = 256;
+constexpr u32 ROWS_W = ROWS_T / 64;  // waves per block
+
+__global__ __launch_bounds__(ROWS_T) void k_blk_rows(const u64 *__restrict__ X, const u64 *__restrict__ Z,
+                                                     const u64 *__restrict__ R, u32 Ls, u32 K, u32 n,
+                                                     BlkState *__restrict__ bs, u32 *__restrict__ patx,
+                                                     u32 *__restrict__ patz, u32 *__restrict__ wpart,
+                                                     MeasState *__restrict__ st) {
+  __shared__ u64 s0x[ROWS_W][KB], s0z[ROWS_W][KB], sx[ROWS_W][KB], sz[ROWS_W][KB];
+  __shared__ u32 red[4][ROWS_W][KB];
+  __shared__ u32 s_last;
+  const u32 k = bs->k;
+  const u32 tid = threadIdx.x, lane = tid & 63u, wv = tid >> 6;
+  const u32 j = blockIdx.x * ROWS_T + tid;
+  const u32 cw = j >> 6;  // uniform over the wave
+  // (1) original rows, into LDS (rows past k stay zero)
+  if (lane < KB) {
+    s0x[wv][lane] = 0;
+    s0z[wv][lane] = 0;
+  }
   const u32 nw = bs->nwords;
-  const u32 j = blockIdx.x * blockDim.x + threadIdx.x;
   for (u32 i = 0; i < nw; ++i) {
-    const u32 ws = K + bs->word[i];
+    const u32 ws = K + bs->word[i], mem = bs->wmem[i];
     u64 xw = 0, zw = 0;
     if (j < n) {
       xw = X[(size_t)j * Ls + ws];
       zw = Z[(size_t)j * Ls + ws];
     }
-    for (u32 m = bs->wmem[i]; m; m &= m - 1) {
-      const u32 s = (u32)__builtin_ctz(m);
-      const u32 sh = bs->p[s] & 63u;
-      const u64 bx = __ballot((xw >> sh) & 1u), bz = __ballot((zw >> sh) & 1u);
-      if ((threadIdx.x & 63u) == 0 && j < n) {
-        p0x[(size_t)s * K + (j >> 6)] = bx;
-        p0z[(size_t)s * K + (j >> 6)] = bz;
+#pragma unroll
+    for (u32 s = 0; s < KB; ++s) {
+      if ((mem >> s) & 1u) {  // uniform
+        const u32 sh = bs->p[s] & 63u;
+        const u64 bx = __ballot((xw >> sh) & 1u), bz = __ballot((zw >> sh) & 1u);
+        if (lane == 0) {
+          s0x[wv][s] = bx;
+          s0z[wv][s] = bz;
+        }
+        if (j == 0) bs->r0[s] = (u32)(R[ws] >> sh) & 1u;
       }
-      if (j == 0) bs->r0[s] = (u32)(R[ws] >> sh) & 1u;
     }
   }
-}
-
-// -------------------------------------------------------------- pivot algebra
-// (1) Thread per 64-column word: the evolved pivot rows P_s = S0_{p_s} times
-// the earlier pivots that hit it, in order, and |x & z| of each original
-// pivot row (summed per pivot). All rows stay in registers.
-__global__ __launch_bounds__(64) void k_blk_evolve(const u64 *__restrict__ p0x, const u64 *__restrict__ p0z,
-                                                   u64 *__restrict__ px, u64 *__restrict__ pz, u32 K,
-                                                   BlkState *__restrict__ bs) {
-  const u32 k = bs->k;
-  const u32 cw = blockIdx.x * blockDim.x + threadIdx.x;
-  const u32 lane = threadIdx.x & 63u;
-  const bool in = cw < K;
+  __syncthreads();
+  // (2) evolved rows
   u64 vx[KB], vz[KB];
 #pragma unroll
-  for (u32 s = 0; s < KB; ++s) {  // rows past k are allocated; their values are not used
-    vx[s] = in ? p0x[(size_t)s * K + cw] : 0ULL;
-    vz[s] = in ? p0z[(size_t)s * K + cw] : 0ULL;
-  }
-#pragma unroll
   for (u32 s = 0; s < KB; ++s) {
-    u32 pc = (u32)__popcll(vx[s] & vz[s]);
     const u32 h = s < k ? bs->hitS[s] : 0u;
+    u64 ax = s0x[wv][s], az = s0z[wv][s];
 #pragma unroll
     for (u32 sp = 0; sp < s; ++sp) {
       const u64 m = 0ULL - (u64)((h >> sp) & 1u);
-      vx[s] ^= vx[sp] & m;
-      vz[s] ^= vz[sp] & m;
+      ax ^= vx[sp] & m;
+      az ^= vz[sp] & m;
     }
-    if (s < k) {
-      if (in) {
-        px[(size_t)s * K + cw] = vx[s];
-        pz[(size_t)s * K + cw] = vz[s];
-      }
-      for (int off = 32; off > 0; off >>= 1) pc += (u32)__shfl_xor((int)pc, off);
-      if (lane == 0 && pc) atomicAdd(&bs->pc0[s], pc);
+    vx[s] = ax;
+    vz[s] = az;
+  }
+  // (3) patterns (rows past k are zero)
+  u32 px = 0, pz = 0;
+#pragma unroll
+  for (u32 s = 0; s < KB; ++s) {
+    px |= (u32)((vx[s] >> lane) & 1ULL) << s;
+    pz |= (u32)((vz[s] >> lane) & 1ULL) << s;
+  }
+  if (j < n) {
+    patx[j] = px;
+    patz[j] = pz;
+  }
+  const u32 c = (u32)__popcll(__ballot(j < n && (px | pz) != 0));
+  if (lane == 0 && c) atomicAdd(&bs->ncols, c);
+  // (4) pair shares, lane a for pivot a
+  if (lane == 0) {
+#pragma unroll
+    for (u32 s = 0; s < KB; ++s) {
+      sx[wv][s] = vx[s];
+      sz[wv][s] = vz[s];
     }
   }
-}
-
-// (2) Thread per (64-column word, pivot a): bits b of z_{P_a} . x_{P_b} (Qz)
-// and of z_{P_a} . x_{S0_b} (R0), and |x & z| of the final D_{p_a} (P_a times
-// its later hits). The last block to finish (one wave, a lane per pivot)
-// forms lam(P_s) and the final signs of the D_{p_s}.
-__global__ __launch_bounds__(64) void k_blk_pairs(const u64 *__restrict__ p0x, const u64 *__restrict__ px,
-                                                  const u64 *__restrict__ pz, u32 K, BlkState *__restrict__ bs,
-                                                  MeasState *__restrict__ st) {
-  __shared__ u32 s_last;
-  const u32 k = bs->k;
-  const u32 a = blockIdx.y;
-  const u32 cw = blockIdx.x * blockDim.x + threadIdx.x;
-  const u32 lane = threadIdx.x & 63u;
-  if (a < k) {
-    u32 qz = 0, r0 = 0, pcd = 0;
-    if (cw < K) {
-      const u64 za = pz[(size_t)a * K + cw];
-      for (u32 b = 0; b < k; ++b) {
-        qz |= ((u32)__popcll(za & px[(size_t)b * K + cw]) & 1u) << b;
-        r0 |= ((u32)__popcll(za & p0x[(size_t)b * K + cw]) & 1u) << b;
-      }
-      u64 dx = px[(size_t)a * K + cw], dz = za;
-      for (u32 m = bs->dhits[a]; m; m &= m - 1) {
-        const u32 s2 = (u32)__builtin_ctz(m);
-        dx ^= px[(size_t)s2 * K + cw];
-        dz ^= pz[(size_t)s2 * K + cw];
-      }
-      pcd = (u32)__popcll(dx & dz);
+  __syncthreads();
+  if (lane < KB && cw < K) {
+    const u32 a = lane;
+    const u64 za = sz[wv][a];
+    u32 qz = 0, r0 = 0;
+#pragma unroll
+    for (u32 b = 0; b < KB; ++b) {
+      qz |= ((u32)__popcll(za & sx[wv][b]) & 1u) << b;
+      r0 |= ((u32)__popcll(za & s0x[wv][b]) & 1u) << b;
     }
-    // wave reductions: parities by ballot, counts by shuffles
-    u32 wq = 0, wr = 0;
-    for (u32 b = 0; b < k; ++b) {
-      wq |= ((u32)__popcll(__ballot((qz >> b) & 1u)) & 1u) << b;
-      wr |= ((u32)__popcll(__ballot((r0 >> b) & 1u)) & 1u) << b;
+    const u32 dh = a < k ? bs->dhits[a] : 0u;
+    u64 dx = sx[wv][a], dz = za;
+#pragma unroll
+    for (u32 b = 0; b < KB; ++b) {
+      const u64 m = 0ULL - (u64)((dh >> b) & 1u);
+      dx ^= sx[wv][b] & m;
+      dz ^= sz[wv][b] & m;
     }
-    for (int off = 32; off > 0; off >>= 1) pcd += (u32)__shfl_xor((int)pcd, off);
-    if (lane == 0) {
-      if (wq) atomicXor(&bs->Qz[a], wq);
-      if (wr) atomicXor(&bs->R0[a], wr);
-      if (pcd) atomicAdd(&bs->pcD[a], pcd);
-    }
+    u32 *wp = wpart + (size_t)cw * 4u * KB;
+    wp[a] = qz;
+    wp[KB + a] = r0;
+    wp[2 * KB + a] = (u32)__popcll(dx & dz) & 3u;
+    wp[3 * KB + a] = (u32)__popcll(s0x[wv][a] & s0z[wv][a]) & 3u;
   }
   __threadfence();
   __syncthreads();
-  if (threadIdx.x == 0) s_last = (atomicAdd(&bs->done, 1u) == gridDim.x * gridDim.y - 1) ? 1u : 0u;
+  if (tid == 0) s_last = (atomicAdd(&bs->done, 1u) == gridDim.x - 1) ? 1u : 0u;
   __syncthreads();
   if (!s_last) return;
   __threadfence();
-  // lane s holds pivot s's sums (atomic reads see every block's updates)
+  // sums over words: lane a of wave g takes the words g, g + ROWS_W, ...
+  {
+    const u32 a = lane & (KB - 1u), g = wv;
+    u32 q = 0, r = 0, d = 0, p0 = 0;
+    if (lane < KB) {
+      for (u32 w = g; w < K; w += ROWS_W) {
+        const u32 *wp = wpart + (size_t)w * 4u * KB;
+        q ^= wp[a];
+        r ^= wp[KB + a];
+        d += wp[2 * KB + a];
+        p0 += wp[3 * KB + a];
+      }
+      red[0][g][a] = q;
+      red[1][g][a] = r;
+      red[2][g][a] = d;
+      red[3][g][a] = p0;
+    }
+  }
+  __syncthreads();
+  if (wv != 0) return;
   const u32 s = lane;
   const bool on = s < k;
-  u32 base = 0, qs = 0, rs = 0, pd = 0, hs = 0, dh = 0;
+  u32 qs = 0, rs = 0, pd = 0, base = 0, hs = 0, dh = 0;
   if (on) {
-    base = 2u * bs->r0[s] + atomicAdd(&bs->pc0[s], 0u);
-    qs = atomicAdd(&bs->Qz[s], 0u);
-    rs = atomicAdd(&bs->R0[s], 0u);
-    pd = atomicAdd(&bs->pcD[s], 0u);
+    u32 p0 = 0;
+#pragma unroll
+    for (u32 g = 0; g < ROWS_W; ++g) {
+      qs ^= red[0][g][s];
+      rs ^= red[1][g][s];
+      pd += red[2][g][s];
+      p0 += red[3][g][s];
+    }
+    base = 2u * bs->r0[s] + p0;
     hs = bs->hitS[s];
     dh = bs->dhits[s];
+    bs->Qz[s] = qs;
   }
   // lam(P_t): the original row times the earlier pivots sp that hit it, in
   // order; each factor adds lam(P_sp) + 2 (z_{P_sp} . x of the partial
@@ -464,29 +493,9 @@ __global__ __launch_bounds__(64) void k_blk_pairs(const u64 *__restrict__ p0x, c
   if (__ballot(on && (e & 1u)) && lane == 0) atomicOr(&st->flags, 1u);
 }
 
-// (3) Thread per column: bit s of patx / patz = pivot s has x / z there;
-// columns where some pivot is not the identity are counted.
-__global__ void k_blk_patterns(const u64 *__restrict__ px, const u64 *__restrict__ pz, u32 *__restrict__ patx,
-                               u32 *__restrict__ patz, u32 K, u32 n, BlkState *__restrict__ bs) {
-  const u32 k = bs->k;
-  const u32 j = blockIdx.x * blockDim.x + threadIdx.x;
-  u32 vx = 0, vz = 0;
-  if (j < n) {
-    const u32 cw = j >> 6, sh = j & 63u;
-    for (u32 s = 0; s < k; ++s) {
-      vx |= (u32)((px[(size_t)s * K + cw] >> sh) & 1ULL) << s;
-      vz |= (u32)((pz[(size_t)s * K + cw] >> sh) & 1ULL) << s;
-    }
-    patx[j] = vx;
-    patz[j] = vz;
-  }
-  const u32 c = (u32)__popcll(__ballot((vx | vz) != 0));
-  if ((threadIdx.x & 63u) == 0 && c) atomicAdd(&bs->ncols, c);
-}
-
 // -------------------------------------------------------------- the pass
 // Grid (row tiles, column chunks). A thread owns one row word; per column
-// where some pivot is not the identity (patterns from k_blk_patterns, uniform
+// where some pivot is not the identity (patterns from k_blk_rows, uniform
 // over the wave): XOR in the masks of the pivots with x (z) on that column,
 // count |x & z| - |x' & z'| (mod 4) and the parities z_{P_s} . x_h.
 __global__ __launch_bounds__(256) void k_blk_pass(u64 *__restrict__ X, u64 *__restrict__ Z,
@@ -517,9 +526,9 @@ __global__ __launch_bounds__(256) void k_blk_pass(u64 *__restrict__ X, u64 *__re
     const u64 x = X[o], z = Z[o];
     u64 dx = 0, dz = 0;
 #pragma unroll
-    for (u32 s = 0; s < KB; ++s) {
-      if ((px >> s) & 1u) dx ^= b[s];
-      if ((pz >> s) & 1u) dz ^= b[s];
+    for (u32 s = 0; s < KB; ++s) {  // all-ones / zero masks from the uniform patterns
+      dx = xor_and(dx, b[s], 0u - ((px >> s) & 1u));
+      dz = xor_and(dz, b[s], 0u - ((pz >> s) & 1u));
     }
     yy ^= dz & x;
     const u64 x2 = x ^ dx, z2 = z ^ dz;
@@ -751,8 +760,7 @@ __global__ __launch_bounds__(64) void k_blk_sv_update(u64 *__restrict__ sg, u32 
         const u32 lin = svt[t < m0 ? t : m0];
         u64 acc = 0;
 #pragma unroll
-        for (u32 s = 0; s < KB; ++s)
-          if ((lin >> s) & 1u) acc ^= b[s];
+        for (u32 s = 0; s < KB; ++s) acc = xor_and(acc, b[s], 0u - ((lin >> s) & 1u));
         x ^= acc;
         if (v == count) x ^= cvec[K + w];
       }
@@ -770,17 +778,16 @@ __global__ __launch_bounds__(64) void k_blk_sv_update(u64 *__restrict__ sg, u32 
 }
 
 // -------------------------------------------------------------- launchers
-// Stage 0: snapshot of the measured columns and the sequential pivot step
-// (writes BlkState::k, which the host reads before stage 1).
+// Stage 0: the sequential pivot step (writes BlkState::k, which the host
+// reads before stage 1).
 hipError_t launch_blk_pivots(const TabDev &t, const BlkArgs &a, const BlkBuffers &b, uint8_t *out_bits,
                              uint8_t *out_rand, u32 waves, hipStream_t s) {
-  hipLaunchKernelGGL(k_blk_snap, dim3(cdiv(t.L, 256), a.k), dim3(256), 0, s, t.X, t.Ls, t.L, a, b.snap);
   const u32 tiles = std::max<u32>(1, cdiv(t.K, 64));
   if (waves == PIVOT_AUTO && tiles <= PR_WAVES)
-    hipLaunchKernelGGL(k_blk_pivots_reg, dim3(1), dim3(64 * tiles), 0, s, b.snap, t.Ls, t.K, a, b.bs, out_bits,
+    hipLaunchKernelGGL(k_blk_pivots_reg, dim3(1), dim3(64 * tiles), 0, s, t.X, t.Ls, t.K, a, b.bs, out_bits,
                        out_rand);
   else
-    hipLaunchKernelGGL(k_blk_pivots, dim3(1), dim3(64 * std::min<u32>({PW_WAVES, tiles, waves})), 0, s, b.snap,
+    hipLaunchKernelGGL(k_blk_pivots, dim3(1), dim3(64 * std::min<u32>({PW_WAVES, tiles, waves})), 0, s, t.X,
                        b.bm, t.Ls, t.K, a, b.bs, out_bits, out_rand);
   return hipGetLastError();
 }
@@ -788,13 +795,9 @@ hipError_t launch_blk_pivots(const TabDev &t, const BlkArgs &a, const BlkBuffers
 // Stage 1: pivot rows, their algebra and the byte count.
 hipError_t launch_blk_prep(const TabDev &t, const BlkArgs &a, const BlkBuffers &b, MeasState *st, MeasStats *stats,
                            hipStream_t s) {
-  hipLaunchKernelGGL(k_blk_masks, dim3(cdiv(t.L, 256)), dim3(256), 0, s, b.snap, b.bm, b.bs, t.Ls, t.L, t.K);
-  hipLaunchKernelGGL(k_blk_gather, dim3(cdiv(t.n, 256)), dim3(256), 0, s, t.X, t.Z, t.R, t.Ls, t.K, t.n, b.bs, b.p0x,
-                     b.p0z);
-  hipLaunchKernelGGL(k_blk_evolve, dim3(cdiv(t.K, 64)), dim3(64), 0, s, b.p0x, b.p0z, b.px, b.pz, t.K, b.bs);
-  hipLaunchKernelGGL(k_blk_pairs, dim3(cdiv(t.K, 64), a.k), dim3(64), 0, s, b.p0x, b.px, b.pz, t.K, b.bs, st);
-  hipLaunchKernelGGL(k_blk_patterns, dim3(cdiv(t.n, 256)), dim3(256), 0, s, b.px, b.pz, b.patx, b.patz, t.K, t.n,
-                     b.bs);
+  hipLaunchKernelGGL(k_blk_masks, dim3(cdiv(t.L, 256)), dim3(256), 0, s, t.X, b.bm, b.bs, a, t.Ls, t.L, t.K);
+  hipLaunchKernelGGL(k_blk_rows, dim3(cdiv(t.n, ROWS_T)), dim3(ROWS_T), 0, s, t.X, t.Z, t.R, t.Ls, t.K, t.n, b.bs,
+                     b.patx, b.patz, b.wpart, st);
   return hipGetLastError();
 }
 

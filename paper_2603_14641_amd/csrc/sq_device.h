@@ -69,6 +69,16 @@ __device__ __forceinline__ u64 shfl_xor_u64(u64 v, int off) {
   return ((u64)hi << 32) | lo;
 }
 
+// a ^ (b & m) with a 32-bit mask m applied to both halves, one v_bitop3_b32
+// per half. The immediate is the truth table: the function evaluated on the
+// bit patterns 0xF0, 0xCC, 0xAA standing for the first, second and third
+// operand (0xF0 ^ (0xCC & 0xAA) = 0x78).
+__device__ __forceinline__ u64 xor_and(u64 a, u64 b, u32 m) {
+  const u32 lo = __builtin_amdgcn_bitop3_b32((u32)a, (u32)b, m, 0x78);
+  const u32 hi = __builtin_amdgcn_bitop3_b32((u32)(a >> 32), (u32)(b >> 32), m, 0x78);
+  return ((u64)hi << 32) | lo;
+}
+
 // 64-bit broadcast of lane src's value, as two 32-bit shuffles.
 __device__ __forceinline__ u64 shfl_u64(u64 v, int src) {
   const u32 lo = (u32)__shfl((int)(u32)v, src), hi = (u32)__shfl((int)(u32)(v >> 32), src);

@@ -125,8 +125,8 @@ struct BlkState {
   u32 wmem[KB];   // bit s: pivot s lies in word[i]
 };
 struct BlkBuffers {
-  u64 *snap, *bm;          // KB * Ls words each: measured columns, hit masks
-  u64 *p0x, *p0z, *px, *pz;  // KB * K words each: original and evolved pivot rows
+  u64 *bm;                 // KB * Ls words: hit masks
+  u32 *wpart;              // K * 4 * KB: per 64-column word, its share of the pivot algebra
   u32 *patx, *patz;        // n each: per column, bit s = pivot s has x (z) there
   u64 *part;               // chunks * BLK_PART * Ls partial counters and parities
   BlkState *bs;

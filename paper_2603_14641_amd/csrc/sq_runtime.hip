@@ -146,11 +146,11 @@ u32 blk_cpc_of(const Dims &d) {
   return std::max<u32>(cpc, cdiv(d.n, kBlkMaxChunks));
 }
 
-constexpr int kLayoutSlots = 22;
+constexpr int kLayoutSlots = 18;
 
 size_t layout_words(const Dims &d, size_t *off) {
   // offsets (in words) of: X, Z, R, mask, pivx, pivz, cnt0, cnt1, sign_part, cols, st, stats,
-  // then the blocked-measurement buffers: snap, bm, p0x, p0z, px, pz, patx, patz, part, bs
+  // then the blocked-measurement buffers: bm, wpart, patx, patz, part, bs
   size_t o = 0;
   auto take = [&](size_t words) {
     size_t r = o;
@@ -170,12 +170,11 @@ size_t layout_words(const Dims &d, size_t *off) {
   off[10] = take(sizeof(MeasState) / 8 + 1);
   off[11] = take(sizeof(MeasStats) / 8 + 1);
   off[12] = take((size_t)KB * d.Ls);
-  off[13] = take((size_t)KB * d.Ls);
-  for (int i = 14; i < 18; ++i) off[i] = take((size_t)KB * d.K);
-  off[18] = take((d.n + 1) / 2);
-  off[19] = take((d.n + 1) / 2);
-  off[20] = take((size_t)cdiv(d.n, blk_cpc_of(d)) * BLK_PART * d.Ls);
-  off[21] = take(sizeof(BlkState) / 8 + 1);
+  off[13] = take((size_t)2 * KB * d.K);  // 4 * KB u32 per word
+  off[14] = take((d.n + 1) / 2);
+  off[15] = take((d.n + 1) / 2);
+  off[16] = take((size_t)cdiv(d.n, blk_cpc_of(d)) * BLK_PART * d.Ls);
+  off[17] = take(sizeof(BlkState) / 8 + 1);
   return o;
 }
 
@@ -445,9 +444,8 @@ sq_status sq_create(uint32_t n, void *hip_stream, sq_tableau **out) {
   T->cols = reinterpret_cast<u32 *>(b + off[9]);
   T->st = reinterpret_cast<MeasState *>(b + off[10]);
   T->stats = reinterpret_cast<MeasStats *>(b + off[11]);
-  T->blk = BlkBuffers{b + off[12], b + off[13], b + off[14], b + off[15], b + off[16], b + off[17],
-                      reinterpret_cast<u32 *>(b + off[18]), reinterpret_cast<u32 *>(b + off[19]), b + off[20],
-                      reinterpret_cast<BlkState *>(b + off[21])};
+  T->blk = BlkBuffers{b + off[12], reinterpret_cast<u32 *>(b + off[13]), reinterpret_cast<u32 *>(b + off[14]),
+                      reinterpret_cast<u32 *>(b + off[15]), b + off[16], reinterpret_cast<BlkState *>(b + off[17])};
   T->blk_cpc = blk_cpc_of(T->d);
   default_tuning(T->d, &T->tun);
   T->builder.init(n, T->d.L);
