@@ -15,8 +15,10 @@
 //   and up to 16 4-bit micro-ops; any other overlap closes the pass.
 #pragma once
 #include <algorithm>
+#include <atomic>
 #include <cstdint>
 #include <deque>
+#include <thread>
 #include <vector>
 
 #include "../../include/sq.h"
@@ -205,6 +207,72 @@ class WideBuilder {
     ++lo_;
   }
 };
+
+// Gate lists of at least 2 kPlanChunk ops are compiled in chunks of
+// kPlanChunk ops, on helper threads: the passes of consecutive chunks,
+// concatenated, apply the gates in program order (gates at the start of a
+// chunk just cannot join the previous chunk's open passes, about one extra
+// pass per boundary). Chunk boundaries depend on the op count only, so the
+// plan does not depend on how many threads were free.
+constexpr u64 kPlanChunk = 1ull << 19;
+constexpr int kPlanMaxHelpers = 15;  // helper threads over all callers at once
+inline std::atomic<int> g_plan_helpers{0};
+
+inline void plan_chunked(u32 n, u32 L, const sq_op *ops, u64 count, WideBuilder &out) {
+  const u64 nch = (count + kPlanChunk - 1) / kPlanChunk;
+  std::vector<WideBuilder> part(nch);
+  std::atomic<u64> next{0};
+  auto work = [&]() {
+    for (;;) {
+      const u64 c = next.fetch_add(1);
+      if (c >= nch) break;
+      const u64 lo = c * kPlanChunk, hi = std::min<u64>(count, lo + kPlanChunk);
+      WideBuilder &b = part[c];
+      b.init(n, L);
+      for (u64 i = lo; i < hi; ++i) b.add(ops[i].type, ops[i].q0, ops[i].q1);
+      b.flush();
+    }
+  };
+  const int hw = std::max(1, (int)std::thread::hardware_concurrency());
+  const int cap = std::min(kPlanMaxHelpers, hw - 1);
+  const int want = (int)std::min<u64>(nch - 1, 7);
+  int got = 0;
+  while (got < want) {
+    int cur = g_plan_helpers.load();
+    if (cur >= cap) break;
+    if (g_plan_helpers.compare_exchange_weak(cur, cur + 1)) ++got;
+  }
+  std::vector<std::thread> helpers;
+  for (int i = 0; i < got; ++i) helpers.emplace_back(work);
+  work();
+  for (std::thread &t : helpers) t.join();
+  g_plan_helpers -= got;
+  out.words.clear();
+  out.offs.clear();
+  out.passes.clear();
+  for (const WideBuilder &b : part) {
+    const u32 wbase = (u32)out.words.size();
+    const u64 obase = out.offs.size();
+    out.words.insert(out.words.end(), b.words.begin(), b.words.end());
+    for (u32 o : b.offs) out.offs.push_back(o + wbase);
+    for (PassRange r : b.passes) {
+      r.offset += obase;
+      out.passes.push_back(r);
+    }
+  }
+}
+
+// The plan of a host gate list (gates only): one builder, or chunks on
+// helper threads for long lists.
+inline void plan_gate_list(u32 n, u32 L, const sq_op *ops, u64 count, WideBuilder &out) {
+  if (count >= 2 * kPlanChunk) {
+    plan_chunked(n, L, ops, count, out);
+    return;
+  }
+  out.init(n, L);
+  for (u64 i = 0; i < count; ++i) out.add(ops[i].type, ops[i].q0, ops[i].q1);
+  out.flush();
+}
 
 // ============================================================== pair groups
 struct HGroup {

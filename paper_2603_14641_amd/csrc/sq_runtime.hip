@@ -499,9 +499,7 @@ sq_status sq_apply_gates(sq_tableau *T, const sq_op *ops, uint64_t count) {
   SQ_TRY(validate_ops(T->d.n, ops, count, false));
   if (count == 0) return SQ_OK;
   WideBuilder &pb = T->builder;
-  pb.init(T->d.n, T->d.L);
-  for (u64 i = 0; i < count; ++i) pb.add(ops[i].type, ops[i].q0, ops[i].q1);
-  pb.flush();
+  plan_gate_list(T->d.n, T->d.L, ops, count, pb);
   if (pb.offs.empty()) return SQ_OK;
   SQ_TRY(ensure_capacity(T, &T->dev_words, &T->dev_words_cap, pb.words.size()));
   SQ_TRY(ensure_capacity(T, &T->dev_offs, &T->dev_offs_cap, pb.offs.size()));
@@ -946,9 +944,7 @@ sq_status sq_plan_gates(uint32_t n, const sq_op *ops, uint64_t count, uint64_t *
   if (n == 0 || n > SQ_MAX_QUBITS) return fail(SQ_ERANGE, "bad n=%u", n);
   SQ_TRY(validate_ops(n, ops, count, false));
   WideBuilder pb;
-  pb.init(n, dims_of(n).L);
-  for (u64 i = 0; i < count; ++i) pb.add(ops[i].type, ops[i].q0, ops[i].q1);
-  pb.flush();
+  plan_gate_list(n, dims_of(n).L, ops, count, pb);
   u64 k = 0;
   auto put = [&](u64 v) {
     if (k < cap) out[k] = v;

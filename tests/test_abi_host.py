@@ -148,6 +148,28 @@ def test_pass_plan_equals_program_order(n, count):
             assert np.array_equal(u, v)
 
 
+def test_chunked_plan_equals_program_order():
+    """Gate lists of 2^20 ops or more are compiled in chunks of 2^19 ops on
+    helper threads; the concatenated plan must still apply the gates in
+    program order (here three chunks, every gate type, n = 12)."""
+    rng = np.random.default_rng(77)
+    n, count = 12, (1 << 20) + 12345
+    t = rng.integers(0, 12, count).astype(np.uint32)
+    a = rng.integers(0, n, count).astype(np.uint32)
+    b = ((a + 1 + rng.integers(0, n - 1, count)) % n).astype(np.uint32)
+    two = np.isin(t, orc.TWO_QUBIT)
+    gates = np.stack([t, a, np.where(two, b, 0)], 1).astype(np.uint32)
+    plan = sqb.plan_gates(n, gates)
+    for groups in plan[::97]:
+        for g in groups:
+            check_group(*g)
+    flat = plan_to_gates(plan)
+    want = tableau_after(n, gates)
+    got = tableau_after(n, flat)
+    for u, v in zip(want, got):
+        assert np.array_equal(u, v)
+
+
 def test_plan_of_generator_layers_spans_several_layers_per_pass():
     """Groups keep absorbing later layers on their qubits, so a pass covers
     more than one generator layer and streams fewer columns than one per

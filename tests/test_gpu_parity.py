@@ -411,6 +411,35 @@ def test_config3_full_depth_sampled_rows():
     assert t.error_flags() == 0
 
 
+def test_long_gate_list_compiled_in_chunks():
+    """2^20 + 777 gates of every type through sq_apply_gates, which compiles
+    lists this long in chunks on helper threads: 96 sampled rows against the
+    oracle holding only those rows, and the whole tableau against the same
+    gates run as a program (one builder)."""
+    from paper_2603_14641_amd import Program
+    n = 3000
+    rng = np.random.default_rng(123)
+    count = (1 << 20) + 777
+    t = rng.integers(0, 12, count)
+    a = rng.integers(0, n, count)
+    b = (a + 1 + rng.integers(0, n - 1, count)) % n
+    ops = np.stack([t, a, np.where(np.isin(t, orc.TWO_QUBIT), b, 0)], 1).astype(np.uint32)
+    rows = sorted(int(v) for v in rng.choice(2 * n, 96, replace=False))
+    sub = orc.Tableau(n, rows=rows)
+    sub.run(ops)
+    t1 = _tab(n)
+    t1.apply_gates(ops)
+    x, z, r = t1.export_rows(rows)
+    sx, sz, sr = sub.rows_array()
+    _assert_same(x, sx, "sampled x rows")
+    _assert_same(z, sz, "sampled z rows")
+    _assert_same(r, sr, "sampled signs")
+    t2 = _tab(n)
+    t2.run_to_host(Program(n, ops), seed=0, shot=0)
+    for u, v, what in zip(t1.export(), t2.export(), ("x", "z", "signs")):
+        _assert_same(u, v, f"{what}: chunked list vs program")
+
+
 def test_layer_then_inverse_is_identity_at_180k():
     """Any size: a generator layer followed by its inverse restores |0...0> exactly, signs included."""
     cfg = CONFIGS[4]
