@@ -222,7 +222,10 @@ __global__ __launch_bounds__(64 * PR_WAVES) void k_blk_pivots_reg(const u64 *__r
   u64 sn[KB], rv[KB];
 #pragma unroll
   for (u32 s = 0; s < KB; ++s) {  // steps past a.k are masked out below
-    sn[s] = in && s < a.k ? X[(size_t)a.q[s] * Ls + K + w] : 0ULL;
+    // every load issued (steps past a.k read column q_0 and are masked), so
+    // that none waits behind a branch
+    const u64 v = in ? X[(size_t)(s < a.k ? a.q[s] : a.q[0]) * Ls + K + w] : 0ULL;
+    sn[s] = s < a.k ? v : 0ULL;
     rv[s] = 0;
   }
   u64 spec = 0;  // pivots found in this word so far (rows S_{p_s'}: Z now, no x)
@@ -235,8 +238,7 @@ __global__ __launch_bounds__(64 * PR_WAVES) void k_blk_pivots_reg(const u64 *__r
       const u32 sel = __builtin_amdgcn_readfirstlane(mcol[s]);  // M[s'][s] of the earlier steps
       u64 v = sn[s];
 #pragma unroll
-      for (u32 sp = 0; sp < s; ++sp)
-        if ((sel >> sp) & 1u) v ^= rv[sp];
+      for (u32 sp = 0; sp < s; ++sp) v = xor_and(v, rv[sp], 0u - ((sel >> sp) & 1u));
       rv[s] = v;
       const u64 vc = v & ~spec;
       const u64 nz = __ballot(vc != 0);
@@ -247,24 +249,29 @@ __global__ __launch_bounds__(64 * PR_WAVES) void k_blk_pivots_reg(const u64 *__r
         k = s;
       } else {
         if (tid == 0) s_wmin[(s + 1) & 1u] = 0xFFFFFFFFu;  // its last reader passed the barrier above
-        if (w == wmin) {
-          const u32 pb = (u32)__builtin_ctzll(vc);
-          spec |= 1ULL << pb;
-          u32 hit = 0;  // earlier pivots that hit S_p
+        if (wave == (wmin >> 6)) {  // the owner wave; lane pl owns word wmin
+          const u32 pl = wmin & 63u;
+          const u32 pb = (u32)__builtin_ctzll(shfl_u64(vc, (int)pl));
+          // every lane takes bit pb of its rows and measured columns; lane pl's
+          // are row p's: the earlier pivots that hit S_p, and X's bits at p
+          u32 hv = 0, sv = 0;
 #pragma unroll
-          for (u32 sp = 0; sp < s; ++sp) hit |= (u32)((rv[sp] >> pb) & 1ULL) << sp;
-          // x bits of P_s at the later measured columns
-          u32 mb = 0;
+          for (u32 sp = 0; sp < s; ++sp) hv |= (u32)((rv[sp] >> pb) & 1ULL) << sp;
 #pragma unroll
-          for (u32 s2 = s + 1; s2 < KB; ++s2)
-            mb |= ((((u32)(sn[s2] >> pb)) ^ (u32)__popc(hit & mcol[s2])) & 1u) << s2;
-          mb &= kall;
-          piv[s] = wmin * 64u + pb;
-          mrow[s] = mb;
-          hits[s] = hit;
-#pragma unroll
-          for (u32 s2 = s + 1; s2 < KB; ++s2)
-            if ((mb >> s2) & 1u) atomicOr(&mcol[s2], 1u << s);
+          for (u32 s2 = s + 1; s2 < KB; ++s2) sv |= (u32)((sn[s2] >> pb) & 1ULL) << s2;
+          const u32 hit = (u32)__shfl((int)hv, (int)pl), snb = (u32)__shfl((int)sv, (int)pl);
+          // lane s2 > s: x bit of P_s at q_{s2} (the earlier pivots that hit S_p
+          // add their own, known for those)
+          const bool mine = lane > s && ((kall >> (lane & 31u)) & 1u) && lane < KB &&
+                            (((snb >> lane) ^ (u32)__popc(hit & mcol[lane & (KB - 1u)])) & 1u);
+          const u32 mb = (u32)__ballot(mine);
+          if (mine) mcol[lane] |= 1u << s;
+          if (lane == pl) spec |= 1ULL << pb;
+          if (lane == 0) {
+            piv[s] = wmin * 64u + pb;
+            mrow[s] = mb;
+            hits[s] = hit;
+          }
         }
         __syncthreads();
       }
@@ -290,7 +297,10 @@ __global__ void k_blk_masks(const u64 *__restrict__ X, u64 *__restrict__ bm, con
     if ((bs->p[t] >> 6) == hw) special |= 1ULL << (bs->p[t] & 63u);
   u64 b[KB];
 #pragma unroll
-  for (u32 s = 0; s < KB; ++s) b[s] = s < k ? X[(size_t)a.q[s] * Ls + w] : 0ULL;
+  for (u32 s = 0; s < KB; ++s) {  // all loads issued (past k: column q_0, masked)
+    const u64 v = X[(size_t)(s < k ? a.q[s] : a.q[0]) * Ls + w];
+    b[s] = s < k ? v : 0ULL;
+  }
 #pragma unroll
   for (u32 s = 0; s < KB; ++s) {
     if (s < k) {
@@ -314,8 +324,9 @@ __global__ void k_blk_masks(const u64 *__restrict__ X, u64 *__restrict__ bm, con
 // identity are counted. (4) The word's share of the pair products, lane a
 // for pivot a: bits b of z_{P_a} . x_{P_b} (Qz) and of z_{P_a} . x_{S0_b}
 // (R0), |x & z| of the final D_{p_a} (P_a times its later hits) and of the
-// original row S0_{p_a}, the counts mod 4. The last block to finish sums the
-// shares over words and forms lam(P_s) and the final signs of the D_{p_s}.
+// original row S0_{p_a}, the counts mod 4; the block combines its waves'
+// shares in LDS and writes one. The last block to finish sums the blocks'
+// shares and forms lam(P_s) and the final signs of the D_{p_s}.
 constexpr u32 ROWS_T = 256;
 constexpr u32 ROWS_W = ROWS_T / 64;  // waves per block
 
@@ -325,7 +336,7 @@ __global__ __launch_bounds__(ROWS_T) void k_blk_rows(const u64 *__restrict__ X, 
                                                      u32 *__restrict__ patz, u32 *__restrict__ wpart,
                                                      MeasState *__restrict__ st) {
   __shared__ u64 s0x[ROWS_W][KB], s0z[ROWS_W][KB], sx[ROWS_W][KB], sz[ROWS_W][KB];
-  __shared__ u32 red[4][ROWS_W][KB];
+  __shared__ u32 red[4][ROWS_T / KB][KB];  // per-wave shares, then per-group sums
   __shared__ u32 s_last;
   const u32 k = bs->k;
   const u32 tid = threadIdx.x, lane = tid & 63u, wv = tid >> 6;
@@ -395,7 +406,7 @@ __global__ __launch_bounds__(ROWS_T) void k_blk_rows(const u64 *__restrict__ X, 
     }
   }
   __syncthreads();
-  if (lane < KB && cw < K) {
+  if (lane < KB) {
     const u32 a = lane;
     const u64 za = sz[wv][a];
     u32 qz = 0, r0 = 0;
@@ -412,11 +423,27 @@ __global__ __launch_bounds__(ROWS_T) void k_blk_rows(const u64 *__restrict__ X, 
       dx ^= sx[wv][b] & m;
       dz ^= sz[wv][b] & m;
     }
-    u32 *wp = wpart + (size_t)cw * 4u * KB;
-    wp[a] = qz;
-    wp[KB + a] = r0;
-    wp[2 * KB + a] = (u32)__popcll(dx & dz) & 3u;
-    wp[3 * KB + a] = (u32)__popcll(s0x[wv][a] & s0z[wv][a]) & 3u;
+    const bool live = cw < K;  // a wave past the last word adds nothing
+    red[0][wv][a] = live ? qz : 0u;
+    red[1][wv][a] = live ? r0 : 0u;
+    red[2][wv][a] = live ? (u32)__popcll(dx & dz) & 3u : 0u;
+    red[3][wv][a] = live ? (u32)__popcll(s0x[wv][a] & s0z[wv][a]) & 3u : 0u;
+  }
+  __syncthreads();
+  if (tid < KB) {  // the block's share, its waves combined
+    u32 q = 0, r = 0, d = 0, p0 = 0;
+#pragma unroll
+    for (u32 g = 0; g < ROWS_W; ++g) {
+      q ^= red[0][g][tid];
+      r ^= red[1][g][tid];
+      d += red[2][g][tid];
+      p0 += red[3][g][tid];
+    }
+    u32 *wp = wpart + (size_t)blockIdx.x * 4u * KB;
+    wp[tid] = q;
+    wp[KB + tid] = r;
+    wp[2 * KB + tid] = d;
+    wp[3 * KB + tid] = p0;
   }
   __threadfence();
   __syncthreads();
@@ -424,23 +451,24 @@ __global__ __launch_bounds__(ROWS_T) void k_blk_rows(const u64 *__restrict__ X, 
   __syncthreads();
   if (!s_last) return;
   __threadfence();
-  // sums over words: lane a of wave g takes the words g, g + ROWS_W, ...
+  // sums over the blocks' shares: thread t takes pivot t mod KB and the
+  // blocks g, g + G, ... with g = t / KB, G = ROWS_T / KB groups
   {
-    const u32 a = lane & (KB - 1u), g = wv;
+    constexpr u32 G = ROWS_T / KB;
+    const u32 a = tid & (KB - 1u), g = tid / KB;
     u32 q = 0, r = 0, d = 0, p0 = 0;
-    if (lane < KB) {
-      for (u32 w = g; w < K; w += ROWS_W) {
-        const u32 *wp = wpart + (size_t)w * 4u * KB;
-        q ^= wp[a];
-        r ^= wp[KB + a];
-        d += wp[2 * KB + a];
-        p0 += wp[3 * KB + a];
-      }
-      red[0][g][a] = q;
-      red[1][g][a] = r;
-      red[2][g][a] = d;
-      red[3][g][a] = p0;
+#pragma unroll 4
+    for (u32 bl = g; bl < gridDim.x; bl += G) {
+      const u32 *wp = wpart + (size_t)bl * 4u * KB;
+      q ^= wp[a];
+      r ^= wp[KB + a];
+      d += wp[2 * KB + a];
+      p0 += wp[3 * KB + a];
     }
+    red[0][g][a] = q;
+    red[1][g][a] = r;
+    red[2][g][a] = d;
+    red[3][g][a] = p0;
   }
   __syncthreads();
   if (wv != 0) return;
@@ -450,7 +478,7 @@ __global__ __launch_bounds__(ROWS_T) void k_blk_rows(const u64 *__restrict__ X, 
   if (on) {
     u32 p0 = 0;
 #pragma unroll
-    for (u32 g = 0; g < ROWS_W; ++g) {
+    for (u32 g = 0; g < ROWS_T / KB; ++g) {
       qs ^= red[0][g][s];
       rs ^= red[1][g][s];
       pd += red[2][g][s];
@@ -513,7 +541,8 @@ __global__ __launch_bounds__(256) void k_blk_pass(u64 *__restrict__ X, u64 *__re
   u64 any = 0;
 #pragma unroll
   for (u32 s = 0; s < KB; ++s) {
-    b[s] = (s < k) ? bm[(size_t)s * Ls + w] : 0ULL;
+    const u64 v = bm[(size_t)s * Ls + w];  // rows past k are allocated: load, then mask
+    b[s] = s < k ? v : 0ULL;
     any |= b[s];
   }
   if (any == 0) return;
@@ -735,7 +764,10 @@ __global__ __launch_bounds__(64) void k_blk_sv_update(u64 *__restrict__ sg, u32 
   if (k == 0 || w >= K) return;
   u64 b[KB];
 #pragma unroll
-  for (u32 s = 0; s < KB; ++s) b[s] = s < k ? bm[(size_t)s * Ls + K + w] : 0ULL;
+  for (u32 s = 0; s < KB; ++s) {  // rows past k are allocated: load, then mask
+    const u64 v = bm[(size_t)s * Ls + K + w];
+    b[s] = s < k ? v : 0ULL;
+  }
   u64 smask = 0;  // rows S_{p_s} in this word
   for (u32 s = 0; s < k; ++s)
     if ((bs->p[s] >> 6) == w) smask |= 1ULL << (bs->p[s] & 63u);

@@ -126,7 +126,7 @@ struct BlkState {
 };
 struct BlkBuffers {
   u64 *bm;                 // KB * Ls words: hit masks
-  u32 *wpart;              // K * 4 * KB: per 64-column word, its share of the pivot algebra
+  u32 *wpart;              // K * 4 * KB: per block of k_blk_rows, its share of the pivot algebra
   u32 *patx, *patz;        // n each: per column, bit s = pivot s has x (z) there
   u64 *part;               // chunks * BLK_PART * Ls partial counters and parities
   BlkState *bs;
