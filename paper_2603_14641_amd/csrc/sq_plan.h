@@ -62,8 +62,7 @@ class WideBuilder {
     n_ = n;
     L_ = L;
     window_ = std::max<u32>(window, 1);
-    front_.assign(n, -1);
-    grp_.assign(n, 0);
+    qs_.assign(n, QState{});
     lo_ = 0;
     open_.clear();
     words.clear();
@@ -89,13 +88,22 @@ class WideBuilder {
       return;
     }
     const bool two = is_two_qubit(type);
-    int64_t p = std::max<int64_t>(front_[a], lo_);
-    if (two) p = std::max<int64_t>(p, front_[b]);
+    QState &A = qs_[a];
+    QState &Bq = qs_[two ? b : a];
+    int64_t p = std::max<int64_t>(A.front, lo_);
+    if (two) p = std::max<int64_t>(p, Bq.front);
     for (;; ++p) {
-      while ((int64_t)(lo_ + open_.size()) <= p) open_.emplace_back();
+      while ((int64_t)(lo_ + open_.size()) <= p) {
+        if (!pool_.empty()) {
+          open_.push_back(std::move(pool_.back()));
+          pool_.pop_back();
+        } else {
+          open_.emplace_back();
+        }
+      }
       std::vector<WG> &pass = open_[p - lo_];
-      const int ga = front_[a] == p ? (int)grp_[a] : -1;
-      const int gb = two && front_[b] == p ? (int)grp_[b] : -1;
+      const int ga = A.front == p ? (int)A.grp : -1;
+      const int gb = two && Bq.front == p ? (int)Bq.grp : -1;
       u32 size, ops;
       if (!two) {
         size = ga >= 0 ? pass[ga].nq : 1;
@@ -138,15 +146,23 @@ class WideBuilder {
   u32 n_ = 0, L_ = 0, window_ = 8;
   int64_t lo_ = 0;                     // index of the oldest open pass
   std::deque<std::vector<WG>> open_;   // open_[i] holds pass lo_ + i
-  std::vector<int64_t> front_;         // per qubit: last pass holding it (-1 none)
-  std::vector<u32> grp_;               // per qubit: its group in that pass
+  std::vector<std::vector<WG>> pool_;  // emptied pass vectors, storage kept
+  // per qubit: the last pass holding it (-1 none), its group and slot there.
+  // A gate on q is placed at a pass p >= front, so q is in the chosen group
+  // exactly when front == p and grp is that group.
+  struct QState {
+    int64_t front = -1;
+    u32 grp = 0, slot = 0;
+  };
+  std::vector<QState> qs_;
 
   u32 slot_of(WG &G, u32 q, int g, int64_t p) {
-    for (u32 i = 0; i < G.nq; ++i)
-      if (G.q[i] == q) return i;
+    QState &Q = qs_[q];
+    if (Q.front == p && Q.grp == (u32)g) return Q.slot;
     G.q[G.nq] = q;
-    front_[q] = p;
-    grp_[q] = (u32)g;
+    Q.front = p;
+    Q.grp = (u32)g;
+    Q.slot = G.nq;
     return G.nq++;
   }
 
@@ -158,7 +174,11 @@ class WideBuilder {
     const u32 base = A.nq;
     for (u32 i = 0; i < B.nq; ++i) {
       A.q[base + i] = B.q[i];
-      if (front_[B.q[i]] == p) grp_[B.q[i]] = (u32)ga;
+      QState &Q = qs_[B.q[i]];
+      if (Q.front == p) {
+        Q.grp = (u32)ga;
+        Q.slot = base + i;
+      }
     }
     A.nq = (uint8_t)(base + B.nq);
     for (u32 k = 0; k < B.nops; ++k) {
@@ -203,6 +223,8 @@ class WideBuilder {
     }
     const u32 cnt = (u32)(offs.size() - first);
     if (cnt) passes.push_back(PassRange{first, cnt, bytes});
+    pass.clear();
+    pool_.push_back(std::move(pass));
     open_.pop_front();
     ++lo_;
   }
