@@ -548,11 +548,24 @@ __global__ __launch_bounds__(256) void k_blk_pass(u64 *__restrict__ X, u64 *__re
   if (any == 0) return;
   u64 yy = 0;          // z_{C_h} . x_h per row: XOR over columns of dz & x
   u64 d0 = 0, d1 = 0;  // |x & z| - |x' & z'| (mod 4), bit-sliced
+  // the row word of the next two columns is loaded ahead (the stores to
+  // column j cannot alias them, which the compiler cannot see by itself)
+  u64 xa = X[(size_t)j0 * Ls + w], za = Z[(size_t)j0 * Ls + w], xb = 0, zb = 0;
+  if (j0 + 1 < j1) {
+    xb = X[(size_t)(j0 + 1) * Ls + w];
+    zb = Z[(size_t)(j0 + 1) * Ls + w];
+  }
   for (u32 j = j0; j < j1; ++j) {
+    const size_t o = (size_t)j * Ls + w;
+    const u64 x = xa, z = za;
+    xa = xb;
+    za = zb;
+    if (j + 2 < j1) {
+      xb = X[o + 2 * (size_t)Ls];
+      zb = Z[o + 2 * (size_t)Ls];
+    }
     const u32 px = patx[j], pz = patz[j];
     if ((px | pz) == 0) continue;
-    const size_t o = (size_t)j * Ls + w;
-    const u64 x = X[o], z = Z[o];
     u64 dx = 0, dz = 0;
 #pragma unroll
     for (u32 s = 0; s < KB; ++s) {  // all-ones / zero masks from the uniform patterns

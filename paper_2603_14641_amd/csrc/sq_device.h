@@ -49,6 +49,31 @@ __device__ __forceinline__ void ldw(const u64 *p, u64 (&v)[WPT]) {
   }
 }
 
+// Streaming forms for tableau columns, which a pass reads and writes once
+// and which far exceed the caches: the accesses carry the non-temporal hint.
+template <int WPT>
+__device__ __forceinline__ void ldw_nt(const u64 *p, u64 (&v)[WPT]) {
+  if constexpr (WPT == 2) {
+    const u64x2 t = __builtin_nontemporal_load(reinterpret_cast<const u64x2 *>(p));
+    v[0] = t.x;
+    v[1] = t.y;
+  } else {
+    v[0] = __builtin_nontemporal_load(p);
+  }
+}
+
+template <int WPT>
+__device__ __forceinline__ void stw_nt(u64 *p, const u64 (&v)[WPT]) {
+  if constexpr (WPT == 2) {
+    u64x2 t;
+    t.x = v[0];
+    t.y = v[1];
+    __builtin_nontemporal_store(t, reinterpret_cast<u64x2 *>(p));
+  } else {
+    __builtin_nontemporal_store(v[0], p);
+  }
+}
+
 template <int WPT>
 __device__ __forceinline__ void stw(u64 *p, const u64 (&v)[WPT]) {
   if constexpr (WPT == 2) {

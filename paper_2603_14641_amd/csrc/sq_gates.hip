@@ -119,8 +119,8 @@ __device__ __forceinline__ void load_group(const u32 *rec, const u64 *__restrict
   for (u32 i = 0; i < WG_MAXQ; ++i) {
     if (i < nq) {
       const size_t o = (size_t)rec[1 + i] * Ls + w;
-      ldw<WPT>(X + o, c.x[i]);
-      ldw<WPT>(Z + o, c.z[i]);
+      ldw_nt<WPT>(X + o, c.x[i]);
+      ldw_nt<WPT>(Z + o, c.z[i]);
     }
   }
 }
@@ -145,8 +145,8 @@ __device__ __forceinline__ void finish_group(const u32 *rec, u64 *__restrict__ X
   for (u32 i = 0; i < WG_MAXQ; ++i) {
     if (i < nq) {
       const size_t o = (size_t)rec[1 + i] * Ls + w;
-      if ((hdr >> (WH_DX_SHIFT + i)) & 1u) stw<WPT>(X + o, c.x[i]);
-      if ((hdr >> (WH_DZ_SHIFT + i)) & 1u) stw<WPT>(Z + o, c.z[i]);
+      if ((hdr >> (WH_DX_SHIFT + i)) & 1u) stw_nt<WPT>(X + o, c.x[i]);
+      if ((hdr >> (WH_DZ_SHIFT + i)) & 1u) stw_nt<WPT>(Z + o, c.z[i]);
     }
   }
 }

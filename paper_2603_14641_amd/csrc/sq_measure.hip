@@ -200,8 +200,8 @@ __global__ __launch_bounds__(1024) void k_rowsum(u64 *__restrict__ X, u64 *__res
 #pragma unroll
     for (int b = 0; b < B; ++b) {
       const size_t o = (size_t)(e[b] & 0x3FFFFFFFu) * Ls + w;
-      ldw<WPT>(X + o, x[b]);
-      ldw<WPT>(Z + o, z[b]);
+      ldw_nt<WPT>(X + o, x[b]);
+      ldw_nt<WPT>(Z + o, z[b]);
     }
 #pragma unroll
     for (int b = 0; b < B; ++b) {
@@ -211,13 +211,13 @@ __global__ __launch_bounds__(1024) void k_rowsum(u64 *__restrict__ X, u64 *__res
         u64 v[WPT];
 #pragma unroll
         for (int k = 0; k < WPT; ++k) v[k] = x[b][k] ^ m[k];
-        stw<WPT>(X + o, v);
+        stw_nt<WPT>(X + o, v);
       }
       if ((e[b] >> 30) & 1u) {
         u64 v[WPT];
 #pragma unroll
         for (int k = 0; k < WPT; ++k) v[k] = z[b][k] ^ m[k];
-        stw<WPT>(Z + o, v);
+        stw_nt<WPT>(Z + o, v);
       }
     }
   }
