@@ -240,9 +240,24 @@ sq_status sq_plan_gates(uint32_t n, const sq_op *host_ops, uint64_t count, uint6
  * meas_base + i) is written to dev_out_bits[i] and, if not NULL,
  * dev_out_random[i]; both are device buffers of sq_program_num_measurements
  * bytes that must stay valid until the stream reaches that point.
- * Errors: SQ_EINVAL (NULL, n mismatch). */
+ * From the second run of a program on a tableau, each of its gate segments
+ * (the gate passes between two measurement runs) is launched as one HIP graph,
+ * captured on that run under the launch geometry then in force (see
+ * sq_set_graphs). Errors: SQ_EINVAL (NULL, n mismatch). */
 sq_status sq_run(sq_tableau *t, const sq_program *p, uint64_t seed, uint64_t shot, uint64_t meas_base,
                  uint8_t *dev_out_bits, uint8_t *dev_out_random);
+
+/* Graph replay of program gate segments (sq_run). A tableau keeps the
+ * instantiated graphs of the last 32 (program, segment, launch geometry)
+ * triples it ran, captured on a private stream and launched on its own; a
+ * segment run for the first time, or while kernel timing is on, is launched
+ * kernel by kernel. on = 0 launches every segment kernel by kernel and frees
+ * the graphs, on = 1 (the default) turns replay back on. Graphs of a destroyed
+ * program are never launched again (programs carry a unique id). */
+sq_status sq_set_graphs(sq_tableau *t, int on);
+/* Counts since the tableau was created: segments captured as graphs and graph
+ * launches. */
+sq_status sq_graph_stats(const sq_tableau *t, uint64_t *captures, uint64_t *replays);
 
 /* Copy rows out in canonical row-major form: for the k-th requested global
  * row g (0 <= g < 2n), host_x[k*W + j/64] bit j%64 = x_gj (W = ceil(n/64)),

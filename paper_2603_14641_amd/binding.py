@@ -32,7 +32,7 @@ EXPORTED = [
     "sq_plan_gates",
     "sq_run", "sq_export_rows", "sq_export", "sq_import", "sq_measure_stats", "sq_error_flags",
     "sq_get_tuning", "sq_set_tuning", "sq_profile_enable", "sq_profile_read", "sq_profile_reset",
-    "sq_qasm_parse", "sq_frame_sample",
+    "sq_qasm_parse", "sq_frame_sample", "sq_set_graphs", "sq_graph_stats",
 ]
 
 
@@ -118,6 +118,8 @@ def load(path: str = LIB_PATH):
         "sq_get_tuning": (i32, [vp, ctypes.POINTER(Tuning)]),
         "sq_set_tuning": (i32, [vp, ctypes.POINTER(Tuning)]),
         "sq_profile_enable": (i32, [vp, i32]),
+        "sq_set_graphs": (i32, [vp, i32]),
+        "sq_graph_stats": (i32, [vp, vp, vp]),
         "sq_profile_read": (i32, [vp, i32, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(u64)]),
         "sq_profile_reset": (i32, [vp]),
     }
@@ -327,6 +329,16 @@ class Tableau:
         for k, v in kw.items():
             setattr(t, k, int(v))
         _check(self.lib.sq_set_tuning(self.h, ctypes.byref(t)))
+
+    def set_graphs(self, on: bool = True):
+        """Replay program gate segments as HIP graphs from their second run (default on)."""
+        _check(self.lib.sq_set_graphs(self.h, 1 if on else 0))
+
+    def graph_stats(self) -> Tuple[int, int]:
+        """(segments captured as graphs, graph launches) since creation."""
+        c, r = ctypes.c_uint64(0), ctypes.c_uint64(0)
+        _check(self.lib.sq_graph_stats(self.h, ctypes.byref(c), ctypes.byref(r)))
+        return int(c.value), int(r.value)
 
     def profile(self, on: bool = True):
         _check(self.lib.sq_profile_enable(self.h, 1 if on else 0))

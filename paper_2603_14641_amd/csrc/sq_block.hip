@@ -521,12 +521,15 @@ __global__ __launch_bounds__(ROWS_T) void k_blk_rows(const u64 *__restrict__ X, 
   if (__ballot(on && (e & 1u)) && lane == 0) atomicOr(&st->flags, 1u);
 }
 
+constexpr u32 BLK_PASS_T = 512;
+
 // -------------------------------------------------------------- the pass
-// Grid (row tiles, column chunks). A thread owns one row word; per column
-// where some pivot is not the identity (patterns from k_blk_rows, uniform
-// over the wave): XOR in the masks of the pivots with x (z) on that column,
-// count |x & z| - |x' & z'| (mod 4) and the parities z_{P_s} . x_h.
-__global__ __launch_bounds__(256) void k_blk_pass(u64 *__restrict__ X, u64 *__restrict__ Z,
+// Grid (row tiles of BLK_PASS_T words, column chunks). A thread owns one row
+// word; per column where some pivot is not the identity (patterns from
+// k_blk_rows, uniform over the wave): XOR in the masks of the pivots with x
+// (z) on that column, count |x & z| - |x' & z'| (mod 4) and the parities
+// z_{P_s} . x_h. Columns are streamed with the non-temporal hint.
+__global__ __launch_bounds__(BLK_PASS_T) void k_blk_pass(u64 *__restrict__ X, u64 *__restrict__ Z,
                                                   const u64 *__restrict__ bm, const u32 *__restrict__ patx,
                                                   const u32 *__restrict__ patz, const BlkState *__restrict__ bs,
                                                   u64 *__restrict__ part, u32 Ls, u32 L, u32 n, u32 cpc) {
@@ -550,10 +553,11 @@ __global__ __launch_bounds__(256) void k_blk_pass(u64 *__restrict__ X, u64 *__re
   u64 d0 = 0, d1 = 0;  // |x & z| - |x' & z'| (mod 4), bit-sliced
   // the row word of the next two columns is loaded ahead (the stores to
   // column j cannot alias them, which the compiler cannot see by itself)
-  u64 xa = X[(size_t)j0 * Ls + w], za = Z[(size_t)j0 * Ls + w], xb = 0, zb = 0;
+  u64 xa = __builtin_nontemporal_load(X + (size_t)j0 * Ls + w);
+  u64 za = __builtin_nontemporal_load(Z + (size_t)j0 * Ls + w), xb = 0, zb = 0;
   if (j0 + 1 < j1) {
-    xb = X[(size_t)(j0 + 1) * Ls + w];
-    zb = Z[(size_t)(j0 + 1) * Ls + w];
+    xb = __builtin_nontemporal_load(X + (size_t)(j0 + 1) * Ls + w);
+    zb = __builtin_nontemporal_load(Z + (size_t)(j0 + 1) * Ls + w);
   }
   for (u32 j = j0; j < j1; ++j) {
     const size_t o = (size_t)j * Ls + w;
@@ -561,8 +565,8 @@ __global__ __launch_bounds__(256) void k_blk_pass(u64 *__restrict__ X, u64 *__re
     xa = xb;
     za = zb;
     if (j + 2 < j1) {
-      xb = X[o + 2 * (size_t)Ls];
-      zb = Z[o + 2 * (size_t)Ls];
+      xb = __builtin_nontemporal_load(X + o + 2 * (size_t)Ls);
+      zb = __builtin_nontemporal_load(Z + o + 2 * (size_t)Ls);
     }
     const u32 px = patx[j], pz = patz[j];
     if ((px | pz) == 0) continue;
@@ -580,8 +584,8 @@ __global__ __launch_bounds__(256) void k_blk_pass(u64 *__restrict__ X, u64 *__re
     d0 ^= plus;
     d0 ^= minus;
     d1 ^= d0 & minus;
-    if (px) X[o] = x2;
-    if (pz) Z[o] = z2;
+    if (px) __builtin_nontemporal_store(x2, X + o);
+    if (pz) __builtin_nontemporal_store(z2, Z + o);
   }
   const size_t cs = (size_t)blockIdx.y * BLK_PART * Ls;
   part[cs + w] = d0;
@@ -849,8 +853,8 @@ hipError_t launch_blk_prep(const TabDev &t, const BlkArgs &a, const BlkBuffers &
 // Stage 2: the streaming pass over the tableau.
 hipError_t launch_blk_pass(const TabDev &t, const BlkBuffers &b, u32 cpc, hipStream_t s) {
   const u32 nchunks = cdiv(t.n, cpc);
-  hipLaunchKernelGGL(k_blk_pass, dim3(cdiv(t.L, 256), nchunks), dim3(256), 0, s, t.X, t.Z, b.bm, b.patx, b.patz,
-                     b.bs, b.part, t.Ls, t.L, t.n, cpc);
+  hipLaunchKernelGGL(k_blk_pass, dim3(cdiv(t.L, BLK_PASS_T), nchunks), dim3(BLK_PASS_T), 0, s, t.X, t.Z, b.bm, b.patx,
+                     b.patz, b.bs, b.part, t.Ls, t.L, t.n, cpc);
   return hipGetLastError();
 }
 

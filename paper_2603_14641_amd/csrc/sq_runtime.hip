@@ -109,6 +109,16 @@ struct sq_tableau {
   size_t dev_offs_cap = 0;
   sq_tuning tun{};
   WideBuilder builder;
+  // program gate segments replayed as graphs, most recently used last
+  struct SegGraph {
+    u64 prog = 0, first = 0, count = 0;
+    u32 layer_block = 0, layer_wpt = 0, layer_groups = 0;
+    hipGraphExec_t exec = nullptr;  // null until the segment's second run
+  };
+  std::vector<SegGraph> graphs;
+  hipStream_t cap_stream = nullptr;
+  bool use_graphs = true;
+  uint64_t graph_captures = 0, graph_replays = 0;
   // profiling
   bool prof = false;
   std::vector<std::pair<hipEvent_t, hipEvent_t>> pending[SQ_K_COUNT];
@@ -118,6 +128,7 @@ struct sq_tableau {
 };
 
 struct sq_program {
+  u64 uid = 0;  // unique per program created in this process
   int device = 0;
   u32 n = 0;
   Dims d{};
@@ -270,8 +281,8 @@ sq_status collect_profile(sq_tableau *T) {
     if (s_ != SQ_OK) return s_;      \
   } while (0)
 
-sq_status run_passes(sq_tableau *T, const u32 *dev_words, const u32 *dev_offs, const std::vector<PassRange> &passes,
-                     size_t first, size_t count) {
+sq_status run_passes_on(sq_tableau *T, hipStream_t stream, const u32 *dev_words, const u32 *dev_offs,
+                        const std::vector<PassRange> &passes, size_t first, size_t count) {
   for (size_t i = first; i < first + count; ++i) {
     const PassRange &p = passes[i];
     const u32 gpc = layer_gpc(T, p.count);
@@ -279,10 +290,75 @@ sq_status run_passes(sq_tableau *T, const u32 *dev_words, const u32 *dev_offs, c
     const u32 *offs = dev_offs + p.offset;
     SQ_TRY(timed(T, SQ_K_LAYER, [&] {
       return launch_layer(T->t, dev_words, offs, p.count, T->tun.layer_block, T->tun.layer_wpt, gpc, T->sign_part,
-                          T->stream);
+                          stream);
     }));
-    SQ_TRY(timed(T, SQ_K_SIGNS, [&] { return launch_sign_reduce(T->t, T->sign_part, chunks, T->stream); }));
+    SQ_TRY(timed(T, SQ_K_SIGNS, [&] { return launch_sign_reduce(T->t, T->sign_part, chunks, stream); }));
   }
+  return SQ_OK;
+}
+
+sq_status run_passes(sq_tableau *T, const u32 *dev_words, const u32 *dev_offs, const std::vector<PassRange> &passes,
+                     size_t first, size_t count) {
+  return run_passes_on(T, T->stream, dev_words, dev_offs, passes, first, count);
+}
+
+constexpr size_t kMaxSegGraphs = 32;
+
+// A program's gate segment: kernel by kernel on its first run (or while
+// kernels are timed), captured as a graph on a private stream on its second
+// run (capturing runs nothing, so the order of T's stream is unaffected; the
+// null stream, which cannot be captured, is fine to launch on), then launched
+// as that graph. The graph holds T's buffers and the program's records, both
+// fixed for their lifetimes, and the launch geometry of the capture.
+sq_status run_gate_segment(sq_tableau *T, const sq_program *P, u64 first, u64 count) {
+  if (!T->use_graphs || T->prof || count == 0)
+    return run_passes(T, P->dev_words, P->dev_offs, P->passes, first, count);
+  const sq_tuning &tn = T->tun;
+  size_t i = 0;
+  for (; i < T->graphs.size(); ++i) {
+    const auto &g = T->graphs[i];
+    if (g.prog == P->uid && g.first == first && g.count == count && g.layer_block == tn.layer_block &&
+        g.layer_wpt == tn.layer_wpt && g.layer_groups == tn.layer_groups)
+      break;
+  }
+  if (i == T->graphs.size()) {  // first run: remember it, launch kernel by kernel
+    if (T->graphs.size() >= kMaxSegGraphs) {
+      if (T->graphs.front().exec) (void)hipGraphExecDestroy(T->graphs.front().exec);
+      T->graphs.erase(T->graphs.begin());
+    }
+    sq_tableau::SegGraph g;
+    g.prog = P->uid;
+    g.first = first;
+    g.count = count;
+    g.layer_block = tn.layer_block;
+    g.layer_wpt = tn.layer_wpt;
+    g.layer_groups = tn.layer_groups;
+    T->graphs.push_back(g);
+    return run_passes(T, P->dev_words, P->dev_offs, P->passes, first, count);
+  }
+  std::rotate(T->graphs.begin() + i, T->graphs.begin() + i + 1, T->graphs.end());  // most recently used last
+  sq_tableau::SegGraph &g = T->graphs.back();
+  if (!g.exec) {
+    if (!T->cap_stream) HIP_TRY(hipStreamCreateWithFlags(&T->cap_stream, hipStreamNonBlocking));
+    HIP_TRY(hipStreamBeginCapture(T->cap_stream, hipStreamCaptureModeThreadLocal));
+    const sq_status st = run_passes_on(T, T->cap_stream, P->dev_words, P->dev_offs, P->passes, first, count);
+    hipGraph_t graph = nullptr;
+    const hipError_t e = hipStreamEndCapture(T->cap_stream, &graph);
+    hipGraphExec_t ex = nullptr;
+    hipError_t ei = hipErrorUnknown;
+    if (st == SQ_OK && e == hipSuccess && graph) ei = hipGraphInstantiate(&ex, graph, nullptr, nullptr, 0);
+    if (graph) (void)hipGraphDestroy(graph);
+    if (st != SQ_OK) return st;
+    if (ei != hipSuccess || !ex) {  // no graph: this segment stays kernel by kernel
+      (void)hipGetLastError();
+      T->graphs.pop_back();
+      return run_passes(T, P->dev_words, P->dev_offs, P->passes, first, count);
+    }
+    g.exec = ex;
+    ++T->graph_captures;
+  }
+  HIP_TRY(hipGraphLaunch(g.exec, T->stream));
+  ++T->graph_replays;
   return SQ_OK;
 }
 
@@ -471,6 +547,9 @@ sq_status sq_destroy(sq_tableau *T) {
       (void)hipEventDestroy(pr.second);
     }
   for (hipEvent_t e : T->pool) (void)hipEventDestroy(e);
+  for (auto &g : T->graphs)
+    if (g.exec) (void)hipGraphExecDestroy(g.exec);
+  if (T->cap_stream) (void)hipStreamDestroy(T->cap_stream);
   if (T->dev_out) (void)hipFreeAsync(T->dev_out, T->stream);
   if (T->dev_words) (void)hipFreeAsync(T->dev_words, T->stream);
   if (T->dev_offs) (void)hipFreeAsync(T->dev_offs, T->stream);
@@ -893,6 +972,8 @@ sq_status sq_program_create(uint32_t n, const sq_op *ops, uint64_t count, sq_pro
   SQ_TRY(validate_ops(n, ops, count, true));
   sq_program *P = new (std::nothrow) sq_program();
   if (!P) return fail(SQ_ENOMEM, "host allocation failed");
+  static std::atomic<u64> next_uid{1};
+  P->uid = next_uid.fetch_add(1);
   (void)hipGetDevice(&P->device);
   P->n = n;
   P->d = dims_of(n);
@@ -999,7 +1080,7 @@ sq_status sq_run(sq_tableau *T, const sq_program *P, uint64_t seed, uint64_t sho
   }
   for (const sq_program::Seg &s : P->segs) {
     if (s.kind == 0) {
-      SQ_TRY(run_passes(T, P->dev_words, P->dev_offs, P->passes, s.first, s.count));
+      SQ_TRY(run_gate_segment(T, P, s.first, s.count));
     } else {
       SQ_TRY(measure_range(T, P->meas_qubits.data(), s.first, s.first + s.count, seed, shot, meas_base,
                            dev_out_bits, rand_base));
@@ -1185,6 +1266,25 @@ sq_status sq_set_tuning(sq_tableau *T, const sq_tuning *in) {
   if (in->pivot_waves) t.pivot_waves = in->pivot_waves;
   SQ_TRY(check_tuning(t));
   T->tun = t;
+  return SQ_OK;
+}
+
+sq_status sq_set_graphs(sq_tableau *T, int on) {
+  if (!T) return fail(SQ_EINVAL, "tableau is NULL");
+  T->use_graphs = on != 0;
+  if (!T->use_graphs) {
+    HIP_TRY(hipStreamSynchronize(T->stream));  // no launched graph may still be pending
+    for (auto &g : T->graphs)
+      if (g.exec) (void)hipGraphExecDestroy(g.exec);
+    T->graphs.clear();
+  }
+  return SQ_OK;
+}
+
+sq_status sq_graph_stats(const sq_tableau *T, uint64_t *captures, uint64_t *replays) {
+  if (!T || !captures || !replays) return fail(SQ_EINVAL, "NULL argument");
+  *captures = T->graph_captures;
+  *replays = T->graph_replays;
   return SQ_OK;
 }
 
