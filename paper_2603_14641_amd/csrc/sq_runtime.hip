@@ -206,9 +206,11 @@ u32 layer_gpc(const sq_tableau *T, u32 ngroups) {
   u32 gpc = T->tun.layer_groups;
   if (gpc == 0) {
     // about 6,000 workgroups: several rounds over the chip, so the last
-    // round's tail is short (measured on the MI355X at n = 180,000)
+    // round's tail is short (measured on the MI355X at n = 180,000). A
+    // workgroup applies its groups one after another, a memory round trip
+    // each, so small passes get one group per workgroup.
     const u32 want_chunks = std::max<u32>(1, 6144 / tiles);
-    gpc = std::max<u32>(16, cdiv(ngroups, want_chunks));
+    gpc = cdiv(ngroups, want_chunks);
   }
   gpc = std::max<u32>(gpc, cdiv(ngroups, kMaxChunks));
   return std::max<u32>(gpc, 1);
