@@ -175,6 +175,34 @@ def test_blocked_deep_pivots(n, hi0, pw):
     assert t.measure_stats().blocks > 0
 
 
+@pytest.mark.parametrize("n", [32768, 32769])
+def test_blocked_pivots_at_register_limit(n):
+    """The register pivot search at its largest size (8 tiles of 64
+    stabilizer words, 512 threads) and one qubit more (9 tiles: the tiled
+    search), with pivots in the last tiles: outcomes, flags and 1,024 rows
+    (the pivots' stabilizer and destabilizer rows among them) bit-exact with
+    one-at-a-time CHP."""
+    rng = np.random.default_rng(n)
+    ops = _deep_pivot_program(rng, n, 40, n - 3000, 96)
+    seed = 7
+    ref = orc.Tableau(n)
+    rb, rr, _ = ref.run(ops, seed=seed, shot=1)
+    assert ref.odd_count == 0 and ref.badscratch_count == 0
+    x, z, r = ref.rows_array()
+    t = _tab(n)
+    bits, rnd = gpu_run_calls(t, ops, seed, shot=1)
+    _assert_same(bits, rb, "outcomes")
+    _assert_same(rnd, rr, "random flags")
+    rows = np.concatenate([np.arange(n - 3000, n - 2700), np.arange(2 * n - 3000, 2 * n - 2700),
+                           np.arange(n, n + 40), np.arange(0, 40)])
+    rows = np.unique(np.concatenate([rows, rng.choice(2 * n, 1024 - rows.size, replace=False)]))
+    gx, gz, gr = t.export_rows(rows)
+    _assert_same(gx, x[rows], "sampled x rows")
+    _assert_same(gz, z[rows], "sampled z rows")
+    _assert_same(gr, r[rows], "sampled signs")
+    assert t.measure_stats().blocks > 0 and t.error_flags() == 0
+
+
 def test_blocked_pivots_share_words():
     """n = 40 (one word of rows per half): every pivot of a block sits in the
     same 64-row word, as do the D rows they overwrite."""
