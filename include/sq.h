@@ -105,8 +105,10 @@ sq_status sq_sync(sq_tableau *t);
 uint32_t sq_num_qubits(const sq_tableau *t);
 
 /* Apply gates (host array, program order) to every row. Qubits may repeat:
- * the library groups the sequence into passes of disjoint one- or two-qubit
- * groups and applies each pass in one fused launch. Asynchronous with
+ * the library groups the sequence into passes of disjoint groups of up to 8
+ * qubits and applies each pass in one fused launch. Lists of 2^20 gates or
+ * more are grouped in consecutive chunks of 2^19 gates on up to 8 host
+ * threads, the chunks' passes following each other. Asynchronous with
  * respect to the device (the host array may be reused on return).
  * Errors: SQ_EINVAL (NULL ops with count > 0, type not a gate, CX/CZ with
  * q0 == q1), SQ_ERANGE (qubit >= n). */
