@@ -341,8 +341,17 @@ sq_status run_gate_segment(sq_tableau *T, const sq_program *P, u64 first, u64 co
   std::rotate(T->graphs.begin() + i, T->graphs.begin() + i + 1, T->graphs.end());  // most recently used last
   sq_tableau::SegGraph &g = T->graphs.back();
   if (!g.exec) {
-    if (!T->cap_stream) HIP_TRY(hipStreamCreateWithFlags(&T->cap_stream, hipStreamNonBlocking));
-    HIP_TRY(hipStreamBeginCapture(T->cap_stream, hipStreamCaptureModeThreadLocal));
+    if (!T->cap_stream) {
+      hipStream_t cs = nullptr;
+      if (hipStreamCreateWithFlags(&cs, hipStreamNonBlocking) == hipSuccess) T->cap_stream = cs;
+    }
+    const bool ready =
+        T->cap_stream && hipStreamBeginCapture(T->cap_stream, hipStreamCaptureModeThreadLocal) == hipSuccess;
+    if (!ready) {  // no capture: this segment stays kernel by kernel
+      (void)hipGetLastError();
+      T->graphs.pop_back();
+      return run_passes(T, P->dev_words, P->dev_offs, P->passes, first, count);
+    }
     const sq_status st = run_passes_on(T, T->cap_stream, P->dev_words, P->dev_offs, P->passes, first, count);
     hipGraph_t graph = nullptr;
     const hipError_t e = hipStreamEndCapture(T->cap_stream, &graph);
