@@ -265,7 +265,13 @@ inline void plan_chunked(u32 n, u32 L, const sq_op *ops, u64 count, WideBuilder 
     if (g_plan_helpers.compare_exchange_weak(cur, cur + 1)) ++got;
   }
   std::vector<std::thread> helpers;
-  for (int i = 0; i < got; ++i) helpers.emplace_back(work);
+  for (int i = 0; i < got; ++i) {
+    try {
+      helpers.emplace_back(work);
+    } catch (...) {  // no thread to be had: the others (and this one) take its chunks
+      break;
+    }
+  }
   work();
   for (std::thread &t : helpers) t.join();
   g_plan_helpers -= got;

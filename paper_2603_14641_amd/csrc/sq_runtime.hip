@@ -325,7 +325,10 @@ sq_status run_gate_segment(sq_tableau *T, const sq_program *P, u64 first, u64 co
   }
   if (i == T->graphs.size()) {  // first run: remember it, launch kernel by kernel
     if (T->graphs.size() >= kMaxSegGraphs) {
-      if (T->graphs.front().exec) (void)hipGraphExecDestroy(T->graphs.front().exec);
+      if (T->graphs.front().exec) {
+        HIP_TRY(hipStreamSynchronize(T->stream));  // its last launch may still be queued
+        (void)hipGraphExecDestroy(T->graphs.front().exec);
+      }
       T->graphs.erase(T->graphs.begin());
     }
     sq_tableau::SegGraph g;

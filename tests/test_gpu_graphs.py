@@ -122,3 +122,31 @@ def test_destroyed_program_graph_is_not_reused():
         prog.close()
         _same(t.export(), ref.rows_array(), f"program {k}")
     assert t.graph_stats() == (4, 4)
+
+
+def test_cache_eviction_keeps_results():
+    """More distinct segments than the cache holds (32): the oldest graphs are
+    dropped (after the stream drains) and their programs, run again, start
+    over kernel by kernel; every tableau state matches the oracle."""
+    from paper_2603_14641_amd import Program, Tableau
+    n = 40
+    rng = np.random.default_rng(15)
+    t = Tableau(n)
+    ref = orc.Tableau(n)
+    progs = []
+    for k in range(36):
+        ops = mixed_program(rng, n, 2, p_meas=0.0)
+        progs.append((Program(n, ops), ops))
+        for _ in range(2):
+            t.run_to_host(progs[-1][0])
+            ref.run(ops)
+    _same(t.export(), ref.rows_array(), "after 36 programs")
+    assert t.graph_stats() == (36, 36)
+    for prog, ops in progs[:3]:  # evicted: first run again, then a new capture
+        for _ in range(2):
+            t.run_to_host(prog)
+            ref.run(ops)
+    _same(t.export(), ref.rows_array(), "after re-running evicted programs")
+    assert t.graph_stats() == (39, 39)
+    for prog, _ in progs:
+        prog.close()
