@@ -254,7 +254,9 @@ sq_status sq_run(sq_tableau *t, const sq_program *p, uint64_t seed, uint64_t sho
  * triples it ran, captured on a private stream and launched on its own; a
  * segment run for the first time, or while kernel timing is on, is launched
  * kernel by kernel. on = 0 launches every segment kernel by kernel and frees
- * the graphs, on = 1 (the default) turns replay back on. Graphs of a destroyed
+ * the graphs (after waiting for the handle's queued work), on = 1 (the
+ * default) turns replay back on. Dropping the oldest graph when a 33rd is
+ * captured also waits for the handle's queued work. Graphs of a destroyed
  * program are never launched again (programs carry a unique id). */
 sq_status sq_set_graphs(sq_tableau *t, int on);
 /* Counts since the tableau was created: segments captured as graphs and graph
