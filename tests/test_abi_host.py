@@ -56,6 +56,26 @@ def test_version_and_last_error():
     assert b"NULL" in lib.sq_last_error()
 
 
+def test_null_handles_are_rejected_without_a_device():
+    """Entry points given a NULL handle or output return SQ_EINVAL with a
+    message, before touching any device."""
+    import ctypes
+    lib = sqb.load()
+    c, r = ctypes.c_uint64(0), ctypes.c_uint64(0)
+    calls = [
+        lambda: lib.sq_set_graphs(None, 1),
+        lambda: lib.sq_graph_stats(None, ctypes.byref(c), ctypes.byref(r)),
+        lambda: lib.sq_apply_gates(None, None, 0),
+        lambda: lib.sq_reset(None),
+        lambda: lib.sq_run(None, None, 0, 0, 0, None, None),
+        lambda: lib.sq_set_tuning(None, None),
+        lambda: lib.sq_profile_enable(None, 1),
+    ]
+    for call in calls:
+        assert call() == sqb.SQ_EINVAL
+        assert lib.sq_last_error()
+
+
 # ---------------------------------------------------------------- pass compiler
 WOP_1Q = {1: orc.H, 2: orc.S, 3: orc.SDG, 4: orc.X, 5: orc.Y, 6: orc.Z}
 MAXQ, MAXOPS = 8, 32
