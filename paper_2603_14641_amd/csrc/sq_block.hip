@@ -288,13 +288,17 @@ __global__ __launch_bounds__(64 * PR_WAVES) void k_blk_pivots_reg(const u64 *__r
 // pass and are cleared.
 __global__ void k_blk_masks(const u64 *__restrict__ X, u64 *__restrict__ bm, const BlkState *__restrict__ bs,
                             BlkArgs a, u32 Ls, u32 L, u32 K) {
+  __shared__ u32 spv[KB];  // pivot rows
   const u32 k = bs->k;
+  if (k == 0) return;  // the same for every workgroup
+  if (threadIdx.x < KB) spv[threadIdx.x] = bs->p[threadIdx.x];  // entries past k are not read
+  __syncthreads();
   const u32 w = blockIdx.x * blockDim.x + threadIdx.x;
-  if (w >= L || k == 0) return;
+  if (w >= L) return;
   u64 special = 0;
   const u32 hw = w < K ? w : w - K;
   for (u32 t = 0; t < k; ++t)
-    if ((bs->p[t] >> 6) == hw) special |= 1ULL << (bs->p[t] & 63u);
+    if ((spv[t] >> 6) == hw) special |= 1ULL << (spv[t] & 63u);
   u64 b[KB];
 #pragma unroll
   for (u32 s = 0; s < KB; ++s) {  // all loads issued (past k: column q_0, masked)
@@ -648,8 +652,14 @@ __global__ __launch_bounds__(BLK_SIGN_T) void k_blk_signs(u64 *__restrict__ R, c
                                                            const BlkState *__restrict__ bs,
                                                            MeasState *__restrict__ st, MeasStats *__restrict__ stats,
                                                            u32 Ls, u32 L, u32 K) {
+  __shared__ u32 spv[KB], sfl[KB];  // per pivot: row, D-row sign (bit 0) and coin (bit 1)
   const u32 k = bs->k;
-  if (k == 0) return;
+  if (k == 0) return;  // the same for every workgroup
+  if (threadIdx.x < KB) {  // entries past k are not read
+    spv[threadIdx.x] = bs->p[threadIdx.x];
+    sfl[threadIdx.x] = (bs->dsign[threadIdx.x] ? 1u : 0u) | (bs->coin[threadIdx.x] ? 2u : 0u);
+  }
+  __syncthreads();
   const u32 w = blockIdx.x * blockDim.x + threadIdx.x;
   const bool in = w < L;
   u64 b[KB];
@@ -693,10 +703,10 @@ __global__ __launch_bounds__(BLK_SIGN_T) void k_blk_signs(u64 *__restrict__ R, c
     touched = true;
   }
   for (u32 s = 0; s < k; ++s) {
-    const u32 p = bs->p[s];
+    const u32 p = spv[s];
     const u64 bit = 1ULL << (p & 63u);
-    if (w == (p >> 6)) { r = (r & ~bit) | (bs->dsign[s] ? bit : 0ULL); touched = true; }
-    if (w == K + (p >> 6)) { r = (r & ~bit) | (bs->coin[s] ? bit : 0ULL); touched = true; }
+    if (w == (p >> 6)) { r = (r & ~bit) | ((sfl[s] & 1u) ? bit : 0ULL); touched = true; }
+    if (w == K + (p >> 6)) { r = (r & ~bit) | ((sfl[s] & 2u) ? bit : 0ULL); touched = true; }
   }
   if (touched) R[w] = r;
   if (w == 0) {
@@ -711,9 +721,20 @@ __global__ __launch_bounds__(BLK_SIGN_T) void k_blk_signs(u64 *__restrict__ R, c
 __global__ void k_blk_special(u64 *__restrict__ X, u64 *__restrict__ Z, const u32 *__restrict__ patx,
                               const u32 *__restrict__ patz, const BlkState *__restrict__ bs, BlkArgs a, u32 Ls, u32 K,
                               u32 n) {
+  __shared__ u32 spv[KB], sdh[KB], sqb[KB];  // per pivot: row, D-row factors, measured qubit
   const u32 k = bs->k;
-  const u32 j = blockIdx.x * blockDim.x + threadIdx.x;
-  if (k == 0 || j >= n) return;
+  if (k == 0) return;  // the same for every workgroup
+  const u32 tid = threadIdx.x;
+  if (tid < KB) {  // entries past k are not read
+    spv[tid] = bs->p[tid];
+    sdh[tid] = bs->dhits[tid] | (1u << tid);
+  }
+#pragma unroll
+  for (u32 s = 0; s < KB; ++s)
+    if (tid == s) sqb[s] = a.q[s];
+  __syncthreads();
+  const u32 j = blockIdx.x * blockDim.x + tid;
+  if (j >= n) return;
   const u32 px = patx[j], pz = patz[j];
   u64 *x = X + (size_t)j * Ls;
   u64 *z = Z + (size_t)j * Ls;
@@ -723,12 +744,12 @@ __global__ void k_blk_special(u64 *__restrict__ X, u64 *__restrict__ Z, const u3
     u64 mask = 0, xd = 0, zd = 0, zs = 0;
     for (u32 m = mem; m; m &= m - 1) {
       const u32 s = (u32)__builtin_ctz(m);
-      const u64 bit = 1ULL << (bs->p[s] & 63u);
-      const u32 dh = bs->dhits[s] | (1u << s);
+      const u64 bit = 1ULL << (spv[s] & 63u);
+      const u32 dh = sdh[s];
       mask |= bit;
       if (__popc(px & dh) & 1) xd |= bit;
       if (__popc(pz & dh) & 1) zd |= bit;
-      if (j == a.q[s]) zs |= bit;
+      if (j == sqb[s]) zs |= bit;
     }
     x[wd] = (x[wd] & ~mask) | xd;
     z[wd] = (z[wd] & ~mask) | zd;
