@@ -286,14 +286,15 @@ __global__ __launch_bounds__(64 * PR_WAVES) void k_blk_pivots_reg(const u64 *__r
 //   b_s = a_s ^ XOR_{s' < s} b_{s'} M[s'][s]
 // holds; the special rows (D_p and S_p of every pivot) take no part in the
 // pass and are cleared.
-__global__ void k_blk_masks(const u64 *__restrict__ X, u64 *__restrict__ bm, const BlkState *__restrict__ bs,
-                            BlkArgs a, u32 Ls, u32 L, u32 K) {
+__device__ __forceinline__ void blk_masks(const u64 *__restrict__ X, u64 *__restrict__ bm,
+                                          const BlkState *__restrict__ bs, const BlkArgs &a, u32 Ls, u32 L, u32 K,
+                                          u32 bid) {
   __shared__ u32 spv[KB];  // pivot rows
   const u32 k = bs->k;
   if (k == 0) return;  // the same for every workgroup
   if (threadIdx.x < KB) spv[threadIdx.x] = bs->p[threadIdx.x];  // entries past k are not read
   __syncthreads();
-  const u32 w = blockIdx.x * blockDim.x + threadIdx.x;
+  const u32 w = bid * blockDim.x + threadIdx.x;
   if (w >= L) return;
   u64 special = 0;
   const u32 hw = w < K ? w : w - K;
@@ -334,17 +335,16 @@ __global__ void k_blk_masks(const u64 *__restrict__ X, u64 *__restrict__ bm, con
 constexpr u32 ROWS_T = 256;
 constexpr u32 ROWS_W = ROWS_T / 64;  // waves per block
 
-__global__ __launch_bounds__(ROWS_T) void k_blk_rows(const u64 *__restrict__ X, const u64 *__restrict__ Z,
-                                                     const u64 *__restrict__ R, u32 Ls, u32 K, u32 n,
-                                                     BlkState *__restrict__ bs, u32 *__restrict__ patx,
-                                                     u32 *__restrict__ patz, u32 *__restrict__ wpart,
-                                                     MeasState *__restrict__ st) {
+__device__ __forceinline__ void blk_rows(const u64 *__restrict__ X, const u64 *__restrict__ Z,
+                                         const u64 *__restrict__ R, u32 Ls, u32 K, u32 n, BlkState *__restrict__ bs,
+                                         u32 *__restrict__ patx, u32 *__restrict__ patz, u32 *__restrict__ wpart,
+                                         MeasState *__restrict__ st, u32 bid, u32 nblocks) {
   __shared__ u64 s0x[ROWS_W][KB], s0z[ROWS_W][KB], sx[ROWS_W][KB], sz[ROWS_W][KB];
   __shared__ u32 red[4][ROWS_T / KB][KB];  // per-wave shares, then per-group sums
   __shared__ u32 s_last;
   const u32 k = bs->k;
   const u32 tid = threadIdx.x, lane = tid & 63u, wv = tid >> 6;
-  const u32 j = blockIdx.x * ROWS_T + tid;
+  const u32 j = bid * ROWS_T + tid;
   const u32 cw = j >> 6;  // uniform over the wave
   // (1) original rows, into LDS (rows past k stay zero)
   if (lane < KB) {
@@ -443,7 +443,7 @@ __global__ __launch_bounds__(ROWS_T) void k_blk_rows(const u64 *__restrict__ X, 
       d += red[2][g][tid];
       p0 += red[3][g][tid];
     }
-    u32 *wp = wpart + (size_t)blockIdx.x * 4u * KB;
+    u32 *wp = wpart + (size_t)bid * 4u * KB;
     wp[tid] = q;
     wp[KB + tid] = r;
     wp[2 * KB + tid] = d;
@@ -451,7 +451,7 @@ __global__ __launch_bounds__(ROWS_T) void k_blk_rows(const u64 *__restrict__ X, 
   }
   __threadfence();
   __syncthreads();
-  if (tid == 0) s_last = (atomicAdd(&bs->done, 1u) == gridDim.x - 1) ? 1u : 0u;
+  if (tid == 0) s_last = (atomicAdd(&bs->done, 1u) == nblocks - 1) ? 1u : 0u;
   __syncthreads();
   if (!s_last) return;
   __threadfence();
@@ -462,7 +462,7 @@ __global__ __launch_bounds__(ROWS_T) void k_blk_rows(const u64 *__restrict__ X, 
     const u32 a = tid & (KB - 1u), g = tid / KB;
     u32 q = 0, r = 0, d = 0, p0 = 0;
 #pragma unroll 4
-    for (u32 bl = g; bl < gridDim.x; bl += G) {
+    for (u32 bl = g; bl < nblocks; bl += G) {
       const u32 *wp = wpart + (size_t)bl * 4u * KB;
       q ^= wp[a];
       r ^= wp[KB + a];
@@ -525,12 +525,27 @@ __global__ __launch_bounds__(ROWS_T) void k_blk_rows(const u64 *__restrict__ X, 
   if (__ballot(on && (e & 1u)) && lane == 0) atomicOr(&st->flags, 1u);
 }
 
+
+// The hit masks and the pivot rows in one launch (they do not depend on each
+// other): workgroups [0, mblocks) compute the masks, the others the rows.
+__global__ __launch_bounds__(ROWS_T) void k_blk_masks_rows(const u64 *__restrict__ X, const u64 *__restrict__ Z,
+                                                           const u64 *__restrict__ R, u64 *__restrict__ bm,
+                                                           BlkState *__restrict__ bs, BlkArgs a,
+                                                           u32 *__restrict__ patx, u32 *__restrict__ patz,
+                                                           u32 *__restrict__ wpart, MeasState *__restrict__ st,
+                                                           u32 Ls, u32 L, u32 K, u32 n, u32 mblocks) {
+  if (blockIdx.x < mblocks)
+    blk_masks(X, bm, bs, a, Ls, L, K, blockIdx.x);
+  else
+    blk_rows(X, Z, R, Ls, K, n, bs, patx, patz, wpart, st, blockIdx.x - mblocks, gridDim.x - mblocks);
+}
+
 constexpr u32 BLK_PASS_T = 512;
 
 // -------------------------------------------------------------- the pass
 // Grid (row tiles of BLK_PASS_T words, column chunks). A thread owns one row
 // word; per column where some pivot is not the identity (patterns from
-// k_blk_rows, uniform over the wave): XOR in the masks of the pivots with x
+// k_blk_masks_rows, uniform over the wave): XOR in the masks of the pivots with x
 // (z) on that column, count |x & z| - |x' & z'| (mod 4) and the parities
 // z_{P_s} . x_h. Columns are streamed with the non-temporal hint.
 __global__ __launch_bounds__(BLK_PASS_T) void k_blk_pass(u64 *__restrict__ X, u64 *__restrict__ Z,
@@ -865,9 +880,9 @@ hipError_t launch_blk_pivots(const TabDev &t, const BlkArgs &a, const BlkBuffers
 // Stage 1: pivot rows, their algebra and the byte count.
 hipError_t launch_blk_prep(const TabDev &t, const BlkArgs &a, const BlkBuffers &b, MeasState *st, MeasStats *stats,
                            hipStream_t s) {
-  hipLaunchKernelGGL(k_blk_masks, dim3(cdiv(t.L, 256)), dim3(256), 0, s, t.X, b.bm, b.bs, a, t.Ls, t.L, t.K);
-  hipLaunchKernelGGL(k_blk_rows, dim3(cdiv(t.n, ROWS_T)), dim3(ROWS_T), 0, s, t.X, t.Z, t.R, t.Ls, t.K, t.n, b.bs,
-                     b.patx, b.patz, b.wpart, st);
+  const u32 mblocks = cdiv(t.L, ROWS_T), rblocks = cdiv(t.n, ROWS_T);
+  hipLaunchKernelGGL(k_blk_masks_rows, dim3(mblocks + rblocks), dim3(ROWS_T), 0, s, t.X, t.Z, t.R, b.bm, b.bs, a,
+                     b.patx, b.patz, b.wpart, st, t.Ls, t.L, t.K, t.n, mblocks);
   return hipGetLastError();
 }
 
