@@ -815,6 +815,15 @@ sq_status sq_batch_sample(const sq_batch_item *items, uint32_t nitems, const sq_
   std::vector<sq_status> wstatus(nworkers, SQ_OK);
   std::vector<std::string> werr(nworkers);
   std::vector<std::thread> workers;
+  // joins every worker on each way out of this function (a joinable thread
+  // destroyed unjoined would terminate the process)
+  struct JoinAll {
+    std::vector<std::thread> &v;
+    ~JoinAll() {
+      for (std::thread &th : v)
+        if (th.joinable()) th.join();
+    }
+  } join_all{workers};
   std::atomic<u32> next_large{0};
   int dev = 0;
   (void)hipGetDevice(&dev);
@@ -914,6 +923,8 @@ sq_status sq_batch_sample(const sq_batch_item *items, uint32_t nitems, const sq_
     uint8_t *ws = nullptr;
     if (hipMallocAsync((void **)&ws, ws_bytes, stream) != hipSuccess) {
       (void)hipGetLastError();
+      const sq_status ws_status = join_workers();  // the workers' own error, if any, comes first
+      if (ws_status != SQ_OK) return ws_status;
       return fail(SQ_ENOMEM, "device allocation of %zu bytes for the batch failed", ws_bytes);
     }
     for (size_t s = 0; s < small.size(); ++s) {

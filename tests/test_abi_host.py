@@ -246,3 +246,33 @@ def test_plan_rejects_bad_ops(bad, status):
     with pytest.raises(sqb.SqError) as e:
         sqb.plan_gates(5, np.array(bad, dtype=np.uint32))
     assert e.value.status == status
+
+
+def test_batch_sample_joins_workers_when_the_batch_allocation_fails():
+    """sq_batch_sample with one item for the persistent launch and one for the
+    worker threads, on a machine where every device call fails: the batch's
+    device allocation fails while a worker thread may still run, and the call
+    must return an error (joining its workers) rather than end the process.
+    Run in a child process so that a termination would fail the test instead
+    of the test session."""
+    import subprocess
+    import sys
+    code = r'''
+import sys
+sys.path.insert(0, sys.argv[1])
+import numpy as np
+from paper_2603_14641_amd import binding as sqb
+reqs = [dict(n=16, ops=np.zeros((0, 3), np.uint32), qubits=np.arange(16, dtype=np.uint32), shots=2),
+        dict(n=3000, ops=np.zeros((0, 3), np.uint32), qubits=np.arange(3000, dtype=np.uint32), shots=2)]
+try:
+    sqb.batch_sample(reqs, max_batch_n=1024, streams=1)
+except sqb.SqError as e:
+    print("status", e.status)
+    sys.exit(0)
+print("no error")
+sys.exit(3)
+'''
+    env = dict(os.environ, HIP_VISIBLE_DEVICES="-1")
+    res = subprocess.run([sys.executable, "-c", code, ROOT], capture_output=True, text=True, timeout=120, env=env)
+    assert res.returncode == 0, (res.returncode, res.stdout, res.stderr[-2000:])
+    assert "status" in res.stdout
