@@ -86,19 +86,56 @@ const char *sq_last_error(void);
 const char *sq_version(void);
 
 /* Device bytes a tableau of n qubits needs (tableau plus working buffers),
- * for admission control. 0 if n is 0 or above SQ_MAX_QUBITS. */
+ * for admission control and for sq_create_in. 0 if n is 0 or above
+ * SQ_MAX_QUBITS. Host only.
+ * Defined by: Algorithm alg:parallelSimulation, the allocation step (the
+ * extended tableau of 2n rows, X and Z bits plus a sign per row, packed into
+ * words of 64 bits), with the column-major layout of "Tableau Layout and
+ * Indexing"; plus this library's measurement working buffers. */
 #define SQ_MAX_QUBITS 1048576u
 size_t sq_bytes_required(uint32_t n);
 
+/* Where the tableau sits inside its device block (host only, no device work):
+ * X is n columns of Ls words starting x_offset bytes into the block
+ * (X[q * Ls + w], word w < K packs destabilizer rows 64w..64w+63, word K + w
+ * stabilizer rows; bit b = row 64w + b), Z likewise at z_offset, and the L
+ * sign words at r_offset. bytes = sq_bytes_required(n). Bits of rows >= n are
+ * always 0. Errors: SQ_EINVAL (out NULL), SQ_ERANGE (n is 0 or too large).
+ * Defined by: "Tableau Layout and Indexing" (column-major words over rows,
+ * destabilizer half then stabilizer half of each column). */
+typedef struct {
+  uint32_t n, K, L, Ls;   /* K = ceil(n/64) words per half column, L = 2K, Ls = column stride in words */
+  uint64_t x_offset, z_offset, r_offset, bytes;
+} sq_layout_info;
+sq_status sq_layout(uint32_t n, sq_layout_info *out);
+
 /* Create a tableau of n qubits (1 <= n <= SQ_MAX_QUBITS) in |0...0> on the
  * current HIP device. hip_stream is a hipStream_t (NULL = default stream);
- * the caller keeps the stream alive for the handle's lifetime.
+ * the caller keeps the stream alive for the handle's lifetime. The library
+ * allocates the device block (stream-ordered) and frees it in sq_destroy.
  * Errors: SQ_EINVAL (out == NULL, n == 0), SQ_ERANGE (n too large),
- * SQ_ENOMEM, SQ_EDEVICE. */
+ * SQ_ENOMEM, SQ_EDEVICE.
+ * Defined by: Algorithm alg:parallelSimulation (allocation and tableau
+ * initialisation); the initial extended tableau D_i = +X_i, S_i = +Z_i of
+ * equation tableauFormat2 for the all-zero basis state. */
 sq_status sq_create(uint32_t n, void *hip_stream, sq_tableau **out);
-/* Wait for the handle's work, then free it. NULL is accepted. */
+/* As sq_create, but the tableau lives in a device block the caller owns
+ * (for instance a torch tensor's storage): dev_buf, 256-byte aligned, of
+ * `bytes` >= sq_bytes_required(n) bytes on the current device. The block must
+ * stay allocated until sq_destroy returns; the library never frees it, and the
+ * caller must not write it while the handle lives (reading it, e.g. through
+ * the offsets of sq_layout, is fine between the handle's synchronizing
+ * calls). Calls that need per-call scratch (sq_measure's outcome buffer,
+ * sq_sample's workspace, sq_apply_gates' pass records) still allocate it
+ * stream-ordered. Errors: SQ_EINVAL (NULL, misaligned), SQ_ERANGE (n, or
+ * bytes too small), SQ_EDEVICE.
+ * Defined by: as sq_create. */
+sq_status sq_create_in(uint32_t n, void *dev_buf, size_t bytes, void *hip_stream, sq_tableau **out);
+/* Wait for the handle's work, then free it (and its device block unless it
+ * came from sq_create_in). NULL is accepted. */
 sq_status sq_destroy(sq_tableau *t);
-/* Reset to |0...0> and clear the error flags (asynchronous). */
+/* Reset to |0...0> and clear the error flags (asynchronous).
+ * Defined by: Algorithm alg:parallelSimulation, tableau initialisation. */
 sq_status sq_reset(sq_tableau *t);
 /* Block until all device work queued on the handle has finished. */
 sq_status sq_sync(sq_tableau *t);
@@ -113,19 +150,34 @@ uint32_t sq_num_qubits(const sq_tableau *t);
  * Errors: SQ_EINVAL (NULL ops with count > 0, type not a gate, CX/CZ with
  * q0 == q1), SQ_ERANGE (qubit >= n). */
 sq_status sq_apply_gates(sq_tableau *t, const sq_op *host_ops, uint64_t count);
+/*   Defined by: equation update_rules (H, S = P, CX applied column-wise to
+ *   every row, right-hand sides taken before the update), the other gates by
+ *   conjugation; fused application of disjoint gates from "Tableau Evolution
+ *   under Clifford Gates" (Algorithm alg:buildTableau) and the scheduling of
+ *   "Parallel Gate and Measurement Scheduling on CPU". */
 
 /* Measure Z on host_qubits[0..count) in that order (measurement index
  * meas_base + i for the i-th), updating the tableau after each. With
  * tuning.meas_block = k > 1, runs of consecutive random measurements are
- * applied k at a time in one pass over the tableau (bit-identical to one at a
- * time; the host reads each block's length, one small copy per block). Writes the
+ * applied up to k at a time in one pass over the tableau (bit-identical to
+ * one at a time). The list is copied to the device and swept by kernels that
+ * keep their position in device memory: the host queues one group of
+ * launches per k measurements and reads the position back once at the end
+ * (again only when deterministic measurements cut blocks short). Writes the
  * outcome bits (0/1) to host_out_bits[0..count) and, if host_out_random is
  * not NULL, 1/0 for random/deterministic outcomes. Blocks until written.
- * Errors: SQ_EINVAL, SQ_ERANGE (qubit >= n), SQ_ESTATE (a device check of
- * the phase arithmetic failed; the tableau is then unreliable). */
+ * Scratch: 6 bytes per measured qubit, allocated stream-ordered and kept by
+ * the handle for later calls.
+ * Errors: SQ_EINVAL, SQ_ERANGE (qubit >= n), SQ_ENOMEM, SQ_ESTATE (a device
+ * check failed, see sq_error_flags; the tableau is then unreliable). */
 sq_status sq_measure(sq_tableau *t, const uint32_t *host_qubits, uint32_t count,
                      uint64_t seed, uint64_t shot, uint64_t meas_base,
                      uint8_t *host_out_bits, uint8_t *host_out_random);
+/*   Defined by: "Measurements in the Stabilizer Formalism" (equation
+ *   eq:meastab: random iff some stabilizer anticommutes with Z_q) and "The CHP
+ *   algorithm" (probabilistic case: smallest pivot, every other anticommuting
+ *   row times the pivot, D_p <- S_p, S_p <- (-1)^coin Z_q; deterministic case:
+ *   the product of the stabilizers the destabilizers select). */
 
 /* Sample `shots` shots of measuring host_qubits[0..count) (in that order) on
  * the current state, without changing the tableau. Shot s (0 <= s < shots)
@@ -141,6 +193,8 @@ sq_status sq_measure(sq_tableau *t, const uint32_t *host_qubits, uint32_t count,
  * Errors: SQ_EINVAL, SQ_ERANGE (qubit >= n), SQ_ENOMEM, SQ_ESTATE. */
 sq_status sq_sample(sq_tableau *t, const uint32_t *host_qubits, uint32_t count, uint64_t seed, uint64_t shot_begin,
                     uint32_t shots, uint64_t meas_base, uint64_t *host_out);
+/*   Defined by: the many-shot workload of the "Sampling" section, each shot
+ *   with the per-shot semantics of "The CHP algorithm". */
 
 /* Batched sampling of many independent circuits (the batched/served
  * workload: circuits of uneven size, each with its own shot count).
@@ -176,11 +230,26 @@ typedef struct {
 } sq_batch_opts;
 
 sq_status sq_batch_sample(const sq_batch_item *items, uint32_t nitems, const sq_batch_opts *opts, void *hip_stream);
+/*   Defined by: as sq_sample, per item (the batching itself is this
+ *   library's; the paper runs one circuit at a time). */
+
+/* Device bytes sq_batch_sample holds for one item of n qubits, nops gates,
+ * count measured qubits and `shots` shots while it runs, routed as
+ * sq_batch_sample routes it under opts (NULL = automatic): the persistent
+ * launch's working set, or for larger items a tableau (sq_bytes_required),
+ * sq_sample's workspace and the compiled gate records (counted at their
+ * upper bound, 20 bytes per gate). 0 for an item with no measurement or no
+ * shot (it takes no device memory) and for n out of range. Host only. For
+ * admission control. */
+size_t sq_batch_item_bytes(uint32_t n, uint64_t nops, uint32_t count, uint32_t shots, const sq_batch_opts *opts);
 
 /* Compile a circuit of n qubits (gates and SQ_MEASURE records in program
  * order) into a device-resident program on the current device.
  * Errors as sq_apply_gates, plus SQ_ENOMEM. */
 sq_status sq_program_create(uint32_t n, const sq_op *host_ops, uint64_t count, sq_program **out);
+/*   Defined by: Algorithm alg:parallelSimulation (the circuit scheduled into
+ *   gate windows and measurements, copied to the device) and "Parallel Gate
+ *   and Measurement Scheduling on CPU". */
 sq_status sq_program_destroy(sq_program *p);
 uint64_t sq_program_num_measurements(const sq_program *p);
 uint64_t sq_program_num_gates(const sq_program *p);
@@ -204,6 +273,10 @@ uint64_t sq_program_num_passes(const sq_program *p);
  * another device), SQ_ENOMEM, SQ_EDEVICE. */
 sq_status sq_frame_sample(const sq_program *p, const uint8_t *host_ref, uint64_t seed, uint32_t shots,
                           uint64_t *host_out, void *hip_stream);
+/*   Defined by: the "Sampling" section, Algorithm alg:sampling (frames
+ *   initialised with random Z bits, conjugated by the gates, the x bit
+ *   recorded and z re-drawn at each measurement), read with the reference
+ *   sample XOR-ed in. */
 
 /* Read an OpenQASM 2.0 circuit (host only, no device work) into operation
  * records for sq_program_create / sq_apply_gates. Accepted: the version line,
@@ -220,6 +293,8 @@ sq_status sq_frame_sample(const sq_program *p, const uint8_t *host_ref, uint64_t
  * Errors: SQ_EINVAL for anything else (parameters, reset, if, opaque, U,
  * unknown names, bad indices, syntax), with the line in sq_last_error(). */
 sq_status sq_qasm_parse(const char *text, size_t len, sq_op *host_ops, uint64_t cap, uint64_t *count, uint32_t *n);
+/*   Defined by: the Experiments section (benchmarks given as OpenQASM files
+ *   over the gate set X, Y, Z, H, P, P^dagger, CX, CY, CZ, SWAP, iSWAP). */
 
 /* Host-only inspection of how a gate sequence is grouped into passes (no
  * device work; usable without a GPU). A pass holds groups on pairwise
@@ -236,18 +311,28 @@ sq_status sq_qasm_parse(const char *text, size_t len, sq_op *host_ops, uint64_t 
  * Errors as sq_apply_gates. */
 sq_status sq_plan_gates(uint32_t n, const sq_op *host_ops, uint64_t count, uint64_t *out, uint64_t cap,
                         uint64_t *out_len);
+/*   Defined by: "Parallel Gate and Measurement Scheduling on CPU" (gates on
+ *   disjoint qubits grouped so they can be applied together). */
 
-/* Run a program on a tableau of the same n. Asynchronous: all work is queued
- * on the handle's stream. Outcome i (i-th measurement of the program, index
- * meas_base + i) is written to dev_out_bits[i] and, if not NULL,
- * dev_out_random[i]; both are device buffers of sq_program_num_measurements
- * bytes that must stay valid until the stream reaches that point.
+/* Run a program on a tableau of the same n. All work is queued on the
+ * handle's stream; the call returns once the last measurement segment's
+ * sweep has been queued and its position read back (one 4-byte read per
+ * measurement segment, so the call waits for the work before it), with any
+ * gate segment after it queued asynchronously. Outcome i (i-th measurement
+ * of the program, index meas_base + i) is written to dev_out_bits[i] and, if
+ * not NULL, dev_out_random[i]; both are device buffers of
+ * sq_program_num_measurements bytes that must stay valid until the stream
+ * reaches that point.
  * From the second run of a program on a tableau, each of its gate segments
  * (the gate passes between two measurement runs) is launched as one HIP graph,
  * captured on that run under the launch geometry then in force (see
  * sq_set_graphs). Errors: SQ_EINVAL (NULL, n mismatch). */
 sq_status sq_run(sq_tableau *t, const sq_program *p, uint64_t seed, uint64_t shot, uint64_t meas_base,
                  uint8_t *dev_out_bits, uint8_t *dev_out_random);
+/*   Defined by: Algorithm alg:parallelSimulation (the simulation loop over
+ *   windows: gate windows applied on the device, measurement windows
+ *   dispatched to the measurement procedure), with "The CHP algorithm" for
+ *   the measurements. */
 
 /* Graph replay of program gate segments (sq_run). A tableau keeps the
  * instantiated graphs of the last 32 (program, segment, launch geometry)
@@ -268,7 +353,9 @@ sq_status sq_graph_stats(const sq_tableau *t, uint64_t *captures, uint64_t *repl
  * likewise host_z, and host_r[k] = r_g. Blocks. */
 sq_status sq_export_rows(sq_tableau *t, const uint32_t *host_rows, uint32_t nrows,
                          uint64_t *host_x, uint64_t *host_z, uint8_t *host_r);
-/* All 2n rows (host_x, host_z: 2n*W words; host_r: 2n bytes). Blocks. */
+/* All 2n rows (host_x, host_z: 2n*W words; host_r: 2n bytes). Blocks.
+ * Defined by (sq_export_rows, sq_export, sq_import): the row form of the
+ * extended tableau, equation tableauFormat2. */
 sq_status sq_export(sq_tableau *t, uint64_t *host_x, uint64_t *host_z, uint8_t *host_r);
 /* Replace the whole tableau from the canonical row-major form (bits at
  * positions >= n in the last word of a row must be 0). Blocks. */
@@ -289,6 +376,7 @@ typedef struct {
   uint64_t block_bytes;   /* algorithmic bytes of the blocked passes */
 } sq_meas_stats;
 sq_status sq_measure_stats(sq_tableau *t, sq_meas_stats *out);
+/*   (Accounting of this library; no passage of the paper.) */
 
 /* Algorithmic bytes of all gate passes of a program: per group, read x and z
  * of its one or two columns and write the columns its gates change (the
@@ -297,8 +385,12 @@ uint64_t sq_program_gate_bytes(const sq_program *p);
 
 /* Device-side consistency flags accumulated since creation or reset
  * (bit 0: a rowsum phase exponent was odd; bit 1: a deterministic product was
- * not +-Z_q). Blocks. */
+ * not +-Z_q; bit 2: the blocked pivot step judged a measurement deterministic
+ * that the single pivot search found random). Blocks. */
 sq_status sq_error_flags(sq_tableau *t, uint32_t *flags);
+/*   Defined by: the CHP invariants of "The CHP algorithm" (products of
+ *   commuting generators are Hermitian, so phase exponents are even; the
+ *   deterministic product equals +-Z_q). */
 
 /* Launch geometry. 0 in a field keeps the current value. Block sizes must be
  * multiples of 64 in [64, 1024]; words per thread 1 or 2. */
@@ -316,6 +408,8 @@ typedef struct {
                                   tiles, computed lazily, over that many waves */
 } sq_tuning;
 #define SQ_PIVOT_AUTO 255u
+/* (Launch control of this library; no passage of the paper. Shapes never
+ * change results.) */
 sq_status sq_get_tuning(const sq_tableau *t, sq_tuning *out);
 sq_status sq_set_tuning(sq_tableau *t, const sq_tuning *in);
 
@@ -334,6 +428,7 @@ enum {
   SQ_K_BFINAL = 9,  /* blocked measurements: signs and pivot rows */
   SQ_K_COUNT = 10
 };
+/* (Profiling of this library; no passage of the paper.) */
 sq_status sq_profile_enable(sq_tableau *t, int on);
 /* Sum of kernel durations (ms) and launch count for one kernel id since the
  * last sq_profile_reset. Blocks. */

@@ -33,6 +33,7 @@ EXPORTED = [
     "sq_run", "sq_export_rows", "sq_export", "sq_import", "sq_measure_stats", "sq_error_flags",
     "sq_get_tuning", "sq_set_tuning", "sq_profile_enable", "sq_profile_read", "sq_profile_reset",
     "sq_qasm_parse", "sq_frame_sample", "sq_set_graphs", "sq_graph_stats",
+    "sq_create_in", "sq_layout", "sq_batch_item_bytes",
 ]
 
 
@@ -58,6 +59,12 @@ class BatchItem(ctypes.Structure):
 class BatchOpts(ctypes.Structure):
     _fields_ = [("block", ctypes.c_uint32), ("grid", ctypes.c_uint32), ("max_batch_n", ctypes.c_uint32),
                 ("streams", ctypes.c_uint32)]
+
+
+class LayoutInfo(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_uint32), ("K", ctypes.c_uint32), ("L", ctypes.c_uint32), ("Ls", ctypes.c_uint32),
+                ("x_offset", ctypes.c_uint64), ("z_offset", ctypes.c_uint64), ("r_offset", ctypes.c_uint64),
+                ("bytes", ctypes.c_uint64)]
 
 
 class MeasStats(ctypes.Structure):
@@ -92,6 +99,9 @@ def load(path: str = LIB_PATH):
         "sq_version": (ctypes.c_char_p, []),
         "sq_bytes_required": (ctypes.c_size_t, [u32]),
         "sq_create": (i32, [u32, vp, pvp]),
+        "sq_create_in": (i32, [u32, vp, ctypes.c_size_t, vp, pvp]),
+        "sq_layout": (i32, [u32, ctypes.POINTER(LayoutInfo)]),
+        "sq_batch_item_bytes": (ctypes.c_size_t, [u32, u64, u32, u32, ctypes.POINTER(BatchOpts)]),
         "sq_destroy": (i32, [vp]),
         "sq_reset": (i32, [vp]),
         "sq_sync": (i32, [vp]),
@@ -201,12 +211,22 @@ class Program:
 
 
 class Tableau:
-    """A CHP tableau of n qubits resident on the current HIP device."""
+    """A CHP tableau of n qubits resident on the current HIP device.
 
-    def __init__(self, n: int, stream=None):
+    buffer: optional device tensor (e.g. ``torch.empty(bytes_required(n),
+    dtype=torch.uint8, device="cuda")``) whose storage holds the tableau
+    (sq_create_in); the tableau keeps a reference to it."""
+
+    def __init__(self, n: int, stream=None, buffer=None):
         self.lib = load()
         h = ctypes.c_void_p()
-        _check(self.lib.sq_create(int(n), _stream_ptr(stream), ctypes.byref(h)))
+        self.buffer = buffer
+        if buffer is None:
+            _check(self.lib.sq_create(int(n), _stream_ptr(stream), ctypes.byref(h)))
+        else:
+            nbytes = int(buffer.numel() * buffer.element_size())
+            _check(self.lib.sq_create_in(int(n), int(buffer.data_ptr()), nbytes, _stream_ptr(stream),
+                                         ctypes.byref(h)))
         self.h = h
         self.n = int(n)
         self.W = (self.n + 63) // 64
@@ -433,6 +453,19 @@ def parse_qasm(text) -> Tuple[int, np.ndarray]:
 
 def bytes_required(n: int) -> int:
     return int(load().sq_bytes_required(int(n)))
+
+
+def layout(n: int) -> dict:
+    """Where X, Z and the signs sit in a tableau's device block (sq_layout)."""
+    info = LayoutInfo()
+    _check(load().sq_layout(int(n), ctypes.byref(info)))
+    return {name: int(getattr(info, name)) for name, _ in LayoutInfo._fields_}
+
+
+def batch_item_bytes(n: int, nops: int, count: int, shots: int, block: int = 0, max_batch_n: int = 0) -> int:
+    """Device bytes sq_batch_sample holds for such an item (sq_batch_item_bytes)."""
+    opts = BatchOpts(block, 0, max_batch_n, 0)
+    return int(load().sq_batch_item_bytes(int(n), int(nops), int(count), int(shots), ctypes.byref(opts)))
 
 
 def version() -> str:

@@ -41,23 +41,42 @@ namespace sq {
 // costs two barriers; the per-pivot outputs are written once at the end.
 constexpr u32 PW_WAVES = 16;
 
+// The block's measurements: list[i0 .. i0 + want) from the cursor, want =
+// min(kb, end - i0), 0 once the list is done. Thread 0 reads the cursor and
+// the qubits into LDS; every thread returns with the values.
+__device__ __forceinline__ void block_take(const Cursor *__restrict__ cur, u32 *sq, u32 *s_hdr, u32 &i0, u32 &want) {
+  if (threadIdx.x == 0) {
+    const u32 i = cur->i, end = cur->end;
+    const u32 w = i < end ? min(cur->kb, end - i) : 0u;
+    s_hdr[0] = i;
+    s_hdr[1] = w;
+  }
+  __syncthreads();
+  i0 = s_hdr[0];
+  want = s_hdr[1];
+  if (threadIdx.x < KB) sq[threadIdx.x] = threadIdx.x < want ? cur->qubits[i0 + threadIdx.x] : 0u;
+  __syncthreads();
+}
+
 // The per-pivot outputs of a block, by wave 0 of the pivot kernels (lane s
-// for pivot s): positions, hit sets, M, the coins and outcome bytes, the
-// later pivots that hit each D_{p_s}, zeroed sums for the pivot algebra, and
-// the pivots grouped by row word.
-__device__ void pivots_finish(u32 lane, u32 k, const u32 *piv, const u32 *mrow, const u32 *mcol, const u32 *hits,
-                              const BlkArgs &a, BlkState *__restrict__ bs, uint8_t *__restrict__ out_bits,
-                              uint8_t *__restrict__ out_rand) {
+// for pivot s): positions, qubits, hit sets, M, the coins and outcome bytes,
+// the later pivots that hit each D_{p_s}, zeroed sums for the pivot algebra,
+// and the pivots grouped by row word. Lane 0 then advances the cursor past the
+// block and flags the deterministic measurement that ended it (if any) for the
+// slot's single kernels.
+__device__ void pivots_finish(u32 lane, u32 k, u32 want, u32 i0, const u32 *sq, const u32 *piv, const u32 *mrow,
+                              const u32 *mcol, const u32 *hits, Cursor *__restrict__ cur, BlkState *__restrict__ bs) {
   const u32 s = lane;
   const bool on = s < k;
+  if (s < KB) bs->q[s] = sq[s];
   if (on) {
-    const u32 c = coin_bit(a.seed, a.shot, a.m0 + s);
+    const u32 c = coin_bit(cur->seed, cur->shot, cur->meas_base + i0 + s);
     bs->p[s] = piv[s];
     bs->hitS[s] = hits[s];
     bs->M[s] = mrow[s];
     bs->coin[s] = c;
-    out_rand[s] = 1;
-    out_bits[s] = (uint8_t)c;
+    if (cur->out_rand) cur->out_rand[i0 + s] = 1;
+    if (cur->out_bits) cur->out_bits[i0 + s] = (uint8_t)c;
     // later pivots that hit D_{p_s} (which holds P_s from measurement s on)
     u32 h = 0;
     for (u32 s2 = s + 1; s2 < k; ++s2) h |= (((mrow[s] >> s2) ^ (u32)__popc(h & mcol[s2])) & 1u) << s2;
@@ -83,17 +102,19 @@ __device__ void pivots_finish(u32 lane, u32 k, const u32 *piv, const u32 *mrow, 
   }
   if (lane == 0) {
     bs->k = k;
+    bs->i0 = i0;
     bs->nwords = (u32)__popcll(fb);
     bs->ncols = 0;
     bs->done = 0;
+    cur->i = i0 + k;
+    cur->single = k < want ? 1u : 0u;
   }
 }
 
 
 __global__ __launch_bounds__(64 * PW_WAVES) void k_blk_pivots(const u64 *__restrict__ X, u64 *__restrict__ bm,
-                                                               u32 Ls, u32 K, BlkArgs a, BlkState *__restrict__ bs,
-                                                               uint8_t *__restrict__ out_bits,
-                                                               uint8_t *__restrict__ out_rand) {
+                                                               u32 Ls, u32 K, Cursor *__restrict__ cur,
+                                                               BlkState *__restrict__ bs) {
   __shared__ u32 s_wmin[2];  // double-buffered: step s uses s_wmin[s & 1]
   // per-step state in LDS (indexed by step, which is not a compile-time
   // constant); done[] is per wave and written by its lane 0
@@ -103,16 +124,15 @@ __global__ __launch_bounds__(64 * PW_WAVES) void k_blk_pivots(const u64 *__restr
   __shared__ u32 hits[KB];             // earlier pivots that hit S_{p_s}
   __shared__ u32 sdone[PW_WAVES][KB];  // tiles of each wave computed per step
   __shared__ u32 sq[KB];               // measured qubits (step s reads column q_s of X)
+  __shared__ u32 s_hdr[2];
   const u32 tid = threadIdx.x, lane = tid & 63u, wave = tid >> 6, nwv = blockDim.x >> 6;
   const u32 ntiles = (K + 63u) / 64u;
   u32 *done = sdone[wave];
   if (tid < KB) { piv[tid] = 0; mrow[tid] = 0; mcol[tid] = 0; hits[tid] = 0; }
   if (tid < 2) s_wmin[tid] = 0xFFFFFFFFu;
-#pragma unroll
-  for (u32 s = 0; s < KB; ++s)
-    if (tid == s) sq[s] = s < a.k ? a.q[s] : 0u;
   if (lane < KB) done[lane] = 0;
-  __syncthreads();
+  u32 i0, want;
+  block_take(cur, sq, s_hdr, i0, want);
   auto word_of = [&](u32 j) { return (j * nwv + wave) * 64u + lane; };  // local tile j
   auto tile_word = [&](u32 s, u32 w) -> u64 {
     if (w >= K) return 0ULL;
@@ -134,8 +154,8 @@ __global__ __launch_bounds__(64 * PW_WAVES) void k_blk_pivots(const u64 *__restr
     return v;
   };
   const u32 myt = ntiles > wave ? (ntiles - wave + nwv - 1) / nwv : 0;  // tiles of this wave
-  u32 k = a.k;
-  for (u32 s = 0; s < a.k; ++s) {
+  u32 k = want;
+  for (u32 s = 0; s < want; ++s) {
     u64 vlast = 0;  // this lane's word of step s in the last tile the wave computed
     for (u32 j = 0; j < myt; ++j) {
       // earlier steps first (their pivots are known, so their own bits are
@@ -180,11 +200,11 @@ __global__ __launch_bounds__(64 * PW_WAVES) void k_blk_pivots(const u64 *__restr
       // rows of earlier steps at word wmin (written before the barrier) and
       // every measured column of X there
       const u64 hv = lane < s ? bm[(size_t)lane * Ls + K + wmin] : 0ULL;
-      const u64 sv = lane < a.k ? X[(size_t)sq[lane] * Ls + K + wmin] : 0ULL;
+      const u64 sv = lane < want ? X[(size_t)sq[lane] * Ls + K + wmin] : 0ULL;
       const u32 hit = (u32)__ballot((hv & bit) != 0);  // earlier pivots that hit S_p
       // x bit of P_s at the later measured column q_lane: X's bit at p plus
       // the earlier pivots that hit S_p (M is known for those)
-      const bool later = lane > s && lane < a.k;
+      const bool later = lane > s && lane < want;
       const bool mine = later && ((((u32)(sv >> pb)) ^ (u32)__popc(hit & mcol[lane & (KB - 1u)])) & 1u);
       const u32 mb = (u32)__ballot(mine);
       if (lane == pl) bm[(size_t)s * Ls + K + wmin] = vmin & ~bit;  // S_p is not multiplied by P_s
@@ -197,7 +217,7 @@ __global__ __launch_bounds__(64 * PW_WAVES) void k_blk_pivots(const u64 *__restr
     }
     __syncthreads();
   }
-  if (wave == 0) pivots_finish(lane, k, piv, mrow, mcol, hits, a, bs, out_bits, out_rand);
+  if (wave == 0) pivots_finish(lane, k, want, i0, sq, piv, mrow, mcol, hits, cur, bs);
 }
 
 // Small tableaux (at most PR_WAVES tiles of 64 stabilizer words): lane l
@@ -209,29 +229,29 @@ __global__ __launch_bounds__(64 * PW_WAVES) void k_blk_pivots(const u64 *__restr
 constexpr u32 PR_WAVES = 8;
 
 __global__ __launch_bounds__(64 * PR_WAVES) void k_blk_pivots_reg(const u64 *__restrict__ X, u32 Ls, u32 K,
-                                                                  BlkArgs a, BlkState *__restrict__ bs,
-                                                                  uint8_t *__restrict__ out_bits,
-                                                                  uint8_t *__restrict__ out_rand) {
+                                                                  Cursor *__restrict__ cur,
+                                                                  BlkState *__restrict__ bs) {
   __shared__ u32 s_wmin[2];  // double-buffered: step s uses s_wmin[s & 1]
-  __shared__ u32 piv[KB], mrow[KB], mcol[KB], hits[KB];
+  __shared__ u32 piv[KB], mrow[KB], mcol[KB], hits[KB], sq[KB], s_hdr[2];
   const u32 tid = threadIdx.x, lane = tid & 63u, wave = tid >> 6;
   const u32 w = tid;  // this lane's stabilizer word
   const bool in = w < K;
   if (tid < KB) { piv[tid] = 0; mrow[tid] = 0; mcol[tid] = 0; hits[tid] = 0; }
   if (tid < 2) s_wmin[tid] = 0xFFFFFFFFu;
+  u32 i0, want;
+  block_take(cur, sq, s_hdr, i0, want);
   u64 sn[KB], rv[KB];
 #pragma unroll
-  for (u32 s = 0; s < KB; ++s) {  // steps past a.k are masked out below
-    // every load issued (steps past a.k read column q_0 and are masked), so
+  for (u32 s = 0; s < KB; ++s) {  // steps past want are masked out below
+    // every load issued (steps past want read column q_0 and are masked), so
     // that none waits behind a branch
-    const u64 v = in ? X[(size_t)(s < a.k ? a.q[s] : a.q[0]) * Ls + K + w] : 0ULL;
-    sn[s] = s < a.k ? v : 0ULL;
+    const u64 v = in ? X[(size_t)sq[s < want ? s : 0] * Ls + K + w] : 0ULL;
+    sn[s] = s < want ? v : 0ULL;
     rv[s] = 0;
   }
   u64 spec = 0;  // pivots found in this word so far (rows S_{p_s'}: Z now, no x)
-  const u32 kall = a.k >= KB ? 0xFFFFFFFFu : (1u << a.k) - 1u;
-  u32 k = a.k;
-  __syncthreads();
+  const u32 kall = want >= KB ? 0xFFFFFFFFu : (1u << want) - 1u;
+  u32 k = want;
 #pragma unroll
   for (u32 s = 0; s < KB; ++s) {
     if (s < k) {  // uniform
@@ -277,7 +297,7 @@ __global__ __launch_bounds__(64 * PR_WAVES) void k_blk_pivots_reg(const u64 *__r
       }
     }
   }
-  if (wave == 0) pivots_finish(lane, k, piv, mrow, mcol, hits, a, bs, out_bits, out_rand);
+  if (wave == 0) pivots_finish(lane, k, want, i0, sq, piv, mrow, mcol, hits, cur, bs);
 }
 
 // -------------------------------------------------------------- hit masks
@@ -287,12 +307,14 @@ __global__ __launch_bounds__(64 * PR_WAVES) void k_blk_pivots_reg(const u64 *__r
 // holds; the special rows (D_p and S_p of every pivot) take no part in the
 // pass and are cleared.
 __device__ __forceinline__ void blk_masks(const u64 *__restrict__ X, u64 *__restrict__ bm,
-                                          const BlkState *__restrict__ bs, const BlkArgs &a, u32 Ls, u32 L, u32 K,
-                                          u32 bid) {
-  __shared__ u32 spv[KB];  // pivot rows
+                                          const BlkState *__restrict__ bs, u32 Ls, u32 L, u32 K, u32 bid) {
+  __shared__ u32 spv[KB], sq[KB];  // pivot rows, measured qubits
   const u32 k = bs->k;
   if (k == 0) return;  // the same for every workgroup
-  if (threadIdx.x < KB) spv[threadIdx.x] = bs->p[threadIdx.x];  // entries past k are not read
+  if (threadIdx.x < KB) {  // entries past k are not read
+    spv[threadIdx.x] = bs->p[threadIdx.x];
+    sq[threadIdx.x] = bs->q[threadIdx.x];
+  }
   __syncthreads();
   const u32 w = bid * blockDim.x + threadIdx.x;
   if (w >= L) return;
@@ -303,7 +325,7 @@ __device__ __forceinline__ void blk_masks(const u64 *__restrict__ X, u64 *__rest
   u64 b[KB];
 #pragma unroll
   for (u32 s = 0; s < KB; ++s) {  // all loads issued (past k: column q_0, masked)
-    const u64 v = X[(size_t)(s < k ? a.q[s] : a.q[0]) * Ls + w];
+    const u64 v = X[(size_t)sq[s < k ? s : 0] * Ls + w];
     b[s] = s < k ? v : 0ULL;
   }
 #pragma unroll
@@ -343,6 +365,7 @@ __device__ __forceinline__ void blk_rows(const u64 *__restrict__ X, const u64 *_
   __shared__ u32 red[4][ROWS_T / KB][KB];  // per-wave shares, then per-group sums
   __shared__ u32 s_last;
   const u32 k = bs->k;
+  if (k == 0) return;  // the same for every workgroup
   const u32 tid = threadIdx.x, lane = tid & 63u, wv = tid >> 6;
   const u32 j = bid * ROWS_T + tid;
   const u32 cw = j >> 6;  // uniform over the wave
@@ -530,12 +553,12 @@ __device__ __forceinline__ void blk_rows(const u64 *__restrict__ X, const u64 *_
 // other): workgroups [0, mblocks) compute the masks, the others the rows.
 __global__ __launch_bounds__(ROWS_T) void k_blk_masks_rows(const u64 *__restrict__ X, const u64 *__restrict__ Z,
                                                            const u64 *__restrict__ R, u64 *__restrict__ bm,
-                                                           BlkState *__restrict__ bs, BlkArgs a,
+                                                           BlkState *__restrict__ bs,
                                                            u32 *__restrict__ patx, u32 *__restrict__ patz,
                                                            u32 *__restrict__ wpart, MeasState *__restrict__ st,
                                                            u32 Ls, u32 L, u32 K, u32 n, u32 mblocks) {
   if (blockIdx.x < mblocks)
-    blk_masks(X, bm, bs, a, Ls, L, K, blockIdx.x);
+    blk_masks(X, bm, bs, Ls, L, K, blockIdx.x);
   else
     blk_rows(X, Z, R, Ls, K, n, bs, patx, patz, wpart, st, blockIdx.x - mblocks, gridDim.x - mblocks);
 }
@@ -734,8 +757,7 @@ __global__ __launch_bounds__(BLK_SIGN_T) void k_blk_signs(u64 *__restrict__ R, c
 // read-modify-write per distinct row word holding pivots: D_{p_s} = P_s times
 // its later hits, S_{p_s} = Z_{q_s}.
 __global__ void k_blk_special(u64 *__restrict__ X, u64 *__restrict__ Z, const u32 *__restrict__ patx,
-                              const u32 *__restrict__ patz, const BlkState *__restrict__ bs, BlkArgs a, u32 Ls, u32 K,
-                              u32 n) {
+                              const u32 *__restrict__ patz, const BlkState *__restrict__ bs, u32 Ls, u32 K, u32 n) {
   __shared__ u32 spv[KB], sdh[KB], sqb[KB];  // per pivot: row, D-row factors, measured qubit
   const u32 k = bs->k;
   if (k == 0) return;  // the same for every workgroup
@@ -743,10 +765,8 @@ __global__ void k_blk_special(u64 *__restrict__ X, u64 *__restrict__ Z, const u3
   if (tid < KB) {  // entries past k are not read
     spv[tid] = bs->p[tid];
     sdh[tid] = bs->dhits[tid] | (1u << tid);
+    sqb[tid] = bs->q[tid];
   }
-#pragma unroll
-  for (u32 s = 0; s < KB; ++s)
-    if (tid == s) sqb[s] = a.q[s];
   __syncthreads();
   const u32 j = blockIdx.x * blockDim.x + tid;
   if (j >= n) return;
@@ -782,14 +802,16 @@ __global__ void k_blk_special(u64 *__restrict__ X, u64 *__restrict__ Z, const u3
 //   r'(h) = r(h) ^ XOR_s b_s(h) Lin(P_s),  Lin(P_s) = r(S0_{p_s}) ^ XOR_{s' hits s} Lin(P_{s'}),
 // and S_{p_s} becomes Z_{q_s} with its own coin (column m0 + s) as sign.
 
-// Thread t <= m0: sign column v = t (t < m0) or the constant (t = m0); bit s
-// of svt[t] = coefficient of column v in Lin(P_s).
-__global__ void k_blk_sv_prep(const u64 *__restrict__ sg, u32 Ks, u32 count, u32 m0,
-                              const BlkState *__restrict__ bs, u32 *__restrict__ svt) {
+// Thread t <= m0 (m0 = the block's list position): sign column v = t
+// (t < m0) or the constant (t = m0); bit s of svt[t] = coefficient of column
+// v in Lin(P_s).
+__global__ void k_blk_sv_prep(const u64 *__restrict__ sg, u32 Ks, u32 count, const BlkState *__restrict__ bs,
+                              u32 *__restrict__ svt) {
+  const u32 k = bs->k, m0 = bs->i0;
   const u32 t = blockIdx.x * blockDim.x + threadIdx.x;
-  if (t > m0) return;
+  if (k == 0 || t > m0) return;
   const u32 v = t < m0 ? t : count;
-  const u32 k = bs->k, nw = bs->nwords;
+  const u32 nw = bs->nwords;
   u32 s0 = 0;  // coefficients of the original pivot rows
   for (u32 i = 0; i < nw; ++i) {
     const u64 wv = sg[(size_t)v * Ks + bs->word[i]];
@@ -803,18 +825,19 @@ __global__ void k_blk_sv_prep(const u64 *__restrict__ sg, u32 Ks, u32 count, u32
   svt[t] = lin;
 }
 
-// Grid (stabilizer-word tiles, column chunks of SV_CHUNK): thread per
-// stabilizer word, looping over the chunk's columns t in [0, m0 + k]: t < m0
-// coin columns, m0 <= t < m0 + k this block's coins, t = m0 + k the constant.
-constexpr u32 SV_CHUNK = 16, SV_GROUP = 16;
+// Grid (stabilizer-word tiles, workgroups over column chunks of SV_CHUNK):
+// thread per stabilizer word; workgroup y takes the chunks y, y + gridDim.y,
+// ... of the columns t in [0, m0 + k]: t < m0 coin columns, m0 <= t < m0 + k
+// this block's coins, t = m0 + k the constant.
+constexpr u32 SV_CHUNK = 16, SV_GROUP = 16, SV_MAX_Y = 64;
 
-__global__ __launch_bounds__(64) void k_blk_sv_update(u64 *__restrict__ sg, u32 Ks, u32 count, u32 m0,
+__global__ __launch_bounds__(64) void k_blk_sv_update(u64 *__restrict__ sg, u32 Ks, u32 count,
                                                        const BlkState *__restrict__ bs, const u64 *__restrict__ bm,
                                                        const u32 *__restrict__ svt, const u64 *__restrict__ cvec,
                                                        u32 Ls, u32 K) {
-  const u32 k = bs->k;
+  const u32 k = bs->k, m0 = bs->i0;
   const u32 w = blockIdx.x * blockDim.x + threadIdx.x;  // stabilizer row word
-  if (k == 0 || w >= K) return;
+  if (k == 0 || w >= K || blockIdx.y * SV_CHUNK > m0 + k) return;
   u64 b[KB];
 #pragma unroll
   for (u32 s = 0; s < KB; ++s) {  // rows past k are allocated: load, then mask
@@ -824,64 +847,64 @@ __global__ __launch_bounds__(64) void k_blk_sv_update(u64 *__restrict__ sg, u32 
   u64 smask = 0;  // rows S_{p_s} in this word
   for (u32 s = 0; s < k; ++s)
     if ((bs->p[s] >> 6) == w) smask |= 1ULL << (bs->p[s] & 63u);
-  const u32 tlo = blockIdx.y * SV_CHUNK, thi = min(tlo + SV_CHUNK, m0 + k + 1);
-  // columns in groups of SV_GROUP: the group's loads are in flight together
-  for (u32 t0 = tlo; t0 < thi; t0 += SV_GROUP) {
-    u64 val[SV_GROUP];
+  for (u32 tlo = blockIdx.y * SV_CHUNK; tlo <= m0 + k; tlo += gridDim.y * SV_CHUNK) {
+    const u32 thi = min(tlo + SV_CHUNK, m0 + k + 1);
+    // columns in groups of SV_GROUP: the group's loads are in flight together
+    for (u32 t0 = tlo; t0 < thi; t0 += SV_GROUP) {
+      u64 val[SV_GROUP];
 #pragma unroll
-    for (u32 i = 0; i < SV_GROUP; ++i) {
-      const u32 t = t0 + i;
-      const u32 v = t < m0 + k ? t : count;
-      val[i] = t < thi ? sg[(size_t)v * Ks + w] : 0ULL;
-    }
-#pragma unroll
-    for (u32 i = 0; i < SV_GROUP; ++i) {
-      const u32 t = t0 + i;
-      if (t >= thi) continue;
-      const bool own = t >= m0 && t < m0 + k;  // a coin of this block
-      const u32 v = t < m0 + k ? t : count;
-      u64 x = val[i];
-      if (!own) {
-        const u32 lin = svt[t < m0 ? t : m0];
-        u64 acc = 0;
-#pragma unroll
-        for (u32 s = 0; s < KB; ++s) acc = xor_and(acc, b[s], 0u - ((lin >> s) & 1u));
-        x ^= acc;
-        if (v == count) x ^= cvec[K + w];
+      for (u32 i = 0; i < SV_GROUP; ++i) {
+        const u32 t = t0 + i;
+        const u32 v = t < m0 + k ? t : count;
+        val[i] = t < thi ? sg[(size_t)v * Ks + w] : 0ULL;
       }
-      if (smask) {
-        u64 set = 0;
-        if (own) {
-          const u32 p = bs->p[t - m0];
-          if ((p >> 6) == w) set = 1ULL << (p & 63u);
+#pragma unroll
+      for (u32 i = 0; i < SV_GROUP; ++i) {
+        const u32 t = t0 + i;
+        if (t >= thi) continue;
+        const bool own = t >= m0 && t < m0 + k;  // a coin of this block
+        const u32 v = t < m0 + k ? t : count;
+        u64 x = val[i];
+        if (!own) {
+          const u32 lin = svt[t < m0 ? t : m0];
+          u64 acc = 0;
+#pragma unroll
+          for (u32 s = 0; s < KB; ++s) acc = xor_and(acc, b[s], 0u - ((lin >> s) & 1u));
+          x ^= acc;
+          if (v == count) x ^= cvec[K + w];
         }
-        x = (x & ~smask) | set;
+        if (smask) {
+          u64 set = 0;
+          if (own) {
+            const u32 p = bs->p[t - m0];
+            if ((p >> 6) == w) set = 1ULL << (p & 63u);
+          }
+          x = (x & ~smask) | set;
+        }
+        sg[(size_t)v * Ks + w] = x;
       }
-      sg[(size_t)v * Ks + w] = x;
     }
   }
 }
 
 // -------------------------------------------------------------- launchers
-// Stage 0: the sequential pivot step (writes BlkState::k, which the host
-// reads before stage 1).
-hipError_t launch_blk_pivots(const TabDev &t, const BlkArgs &a, const BlkBuffers &b, uint8_t *out_bits,
-                             uint8_t *out_rand, u32 waves, hipStream_t s) {
+// Stage 0: the sequential pivot step on the cursor's next measurements (it
+// writes BlkState::k, which every later kernel of the block reads, and
+// advances the cursor).
+hipError_t launch_blk_pivots(const TabDev &t, Cursor *cur, const BlkBuffers &b, u32 waves, hipStream_t s) {
   const u32 tiles = std::max<u32>(1, cdiv(t.K, 64));
   if (waves == PIVOT_AUTO && tiles <= PR_WAVES)
-    hipLaunchKernelGGL(k_blk_pivots_reg, dim3(1), dim3(64 * tiles), 0, s, t.X, t.Ls, t.K, a, b.bs, out_bits,
-                       out_rand);
+    hipLaunchKernelGGL(k_blk_pivots_reg, dim3(1), dim3(64 * tiles), 0, s, t.X, t.Ls, t.K, cur, b.bs);
   else
     hipLaunchKernelGGL(k_blk_pivots, dim3(1), dim3(64 * std::min<u32>({PW_WAVES, tiles, waves})), 0, s, t.X,
-                       b.bm, t.Ls, t.K, a, b.bs, out_bits, out_rand);
+                       b.bm, t.Ls, t.K, cur, b.bs);
   return hipGetLastError();
 }
 
-// Stage 1: pivot rows, their algebra and the byte count.
-hipError_t launch_blk_prep(const TabDev &t, const BlkArgs &a, const BlkBuffers &b, MeasState *st, MeasStats *stats,
-                           hipStream_t s) {
+// Stage 1: hit masks, pivot rows and their algebra.
+hipError_t launch_blk_prep(const TabDev &t, const BlkBuffers &b, MeasState *st, hipStream_t s) {
   const u32 mblocks = cdiv(t.L, ROWS_T), rblocks = cdiv(t.n, ROWS_T);
-  hipLaunchKernelGGL(k_blk_masks_rows, dim3(mblocks + rblocks), dim3(ROWS_T), 0, s, t.X, t.Z, t.R, b.bm, b.bs, a,
+  hipLaunchKernelGGL(k_blk_masks_rows, dim3(mblocks + rblocks), dim3(ROWS_T), 0, s, t.X, t.Z, t.R, b.bm, b.bs,
                      b.patx, b.patz, b.wpart, st, t.Ls, t.L, t.K, t.n, mblocks);
   return hipGetLastError();
 }
@@ -895,24 +918,27 @@ hipError_t launch_blk_pass(const TabDev &t, const BlkBuffers &b, u32 cpc, hipStr
 }
 
 // Stage 3: chunk reduction, signs and the special rows.
-hipError_t launch_blk_final(const TabDev &t, const BlkArgs &a, const BlkBuffers &b, MeasState *st, MeasStats *stats,
-                            u32 cpc, hipStream_t s) {
+hipError_t launch_blk_final(const TabDev &t, const BlkBuffers &b, MeasState *st, MeasStats *stats, u32 cpc,
+                            hipStream_t s) {
   const u32 nchunks = cdiv(t.n, cpc);
   hipLaunchKernelGGL(k_blk_reduce, dim3(cdiv(t.L, 4), 2), dim3(256), 0, s, b.part, b.bm, b.bs, t.Ls, t.L, nchunks);
   hipLaunchKernelGGL(k_blk_signs, dim3(cdiv(t.L, BLK_SIGN_T)), dim3(BLK_SIGN_T), 0, s, t.R, b.bm, b.part, b.bs, st,
                      stats, t.Ls, t.L, t.K);
-  hipLaunchKernelGGL(k_blk_special, dim3(cdiv(t.n, 256)), dim3(256), 0, s, t.X, t.Z, b.patx, b.patz, b.bs, a, t.Ls,
-                     t.K, t.n);
+  hipLaunchKernelGGL(k_blk_special, dim3(cdiv(t.n, 256)), dim3(256), 0, s, t.X, t.Z, b.patx, b.patz, b.bs, t.Ls, t.K,
+                     t.n);
   return hipGetLastError();
 }
 
 // Symbolic signs after a block whose pass and special rows are done; cvec
 // holds the constants c(h) (the block ran with it as its zeroed sign array).
-hipError_t launch_blk_sv(u64 *sg, u32 Ks, u32 count, u32 m0, u32 kmax, const BlkBuffers &b, u32 *svt,
-                         const u64 *cvec, u32 Ls, u32 K, hipStream_t s) {
-  hipLaunchKernelGGL(k_blk_sv_prep, dim3(cdiv(m0 + 1, 256)), dim3(256), 0, s, sg, Ks, count, m0, b.bs, svt);
-  hipLaunchKernelGGL(k_blk_sv_update, dim3(cdiv(K, 64), cdiv(m0 + kmax + 1, SV_CHUNK)), dim3(64), 0, s, sg, Ks, count,
-                     m0, b.bs, b.bm, svt, cvec, Ls, K);
+// The block's list position is read on the device, so the grid covers every
+// position up to `count`.
+hipError_t launch_blk_sv(u64 *sg, u32 Ks, u32 count, const BlkBuffers &b, u32 *svt, const u64 *cvec, u32 Ls, u32 K,
+                         hipStream_t s) {
+  hipLaunchKernelGGL(k_blk_sv_prep, dim3(cdiv(count + 1, 256)), dim3(256), 0, s, sg, Ks, count, b.bs, svt);
+  const u32 ychunks = std::min<u32>(SV_MAX_Y, cdiv(count + 1, SV_CHUNK));
+  hipLaunchKernelGGL(k_blk_sv_update, dim3(cdiv(K, 64), ychunks), dim3(64), 0, s, sg, Ks, count, b.bs, b.bm, svt,
+                     cvec, Ls, K);
   return hipGetLastError();
 }
 

@@ -59,9 +59,33 @@ enum : u32 {
   WOP_H = 1, WOP_S = 2, WOP_SDG = 3, WOP_X = 4, WOP_Y = 5, WOP_Z = 6, WOP_CX = 7, WOP_CZ = 8, WOP_SWAP = 9
 };
 
+// Where the sweep over a measured list stands, in device memory. A sweep is
+// a fixed sequence of slots queued without host reads: each slot's kernels
+// read the list position here and advance it, so the host only reads `i`
+// back once after queuing enough slots for the whole list.
+//   kb == 1: a slot measures list[i] alone (pivot, gather, rowsum, post);
+//   kb >= 2: a slot offers list[i .. i + kb) to the blocked path, which takes
+//   its random prefix (k measurements), then measures list[i + k] alone when
+//   the block stopped at a deterministic one (`single`).
+struct Cursor {
+  u32 i;            // next position in the list
+  u32 end;          // list length
+  u32 kb;           // measurements offered per block (1: every measurement alone)
+  u32 single;       // set by the blocked pivot step: this slot's single kernels measure list[i]
+  u64 seed, shot;   // coin key
+  u64 meas_base;    // measurement index of list[0]
+  const u32 *qubits;  // the measured list (device)
+  uint8_t *out_bits;  // outcome of list[i] to out_bits[i] (NULL: not written)
+  uint8_t *out_rand;  // 1 random / 0 deterministic to out_rand[i] (NULL: not written)
+};
+
+constexpr int32_t P_NONE = -2;  // MeasState::p of a slot that measures nothing alone
+
 // Per-measurement device state (one per tableau, reused by every measurement).
 struct MeasState {
-  int32_t p;      // pivot stabilizer index, -1 if the outcome is deterministic
+  int32_t p;      // pivot stabilizer index, -1 if the outcome is deterministic, P_NONE if no measurement
+  u32 q;          // the qubit measured alone in this slot
+  u32 i;          // its position in the list
   u32 ncols;      // number of non-identity columns of S_p (compacted list length)
   u32 det_acc;    // deterministic case: sum of phase exponents (mod 2^32)
   u32 flags;      // sticky error flags: bit 0 odd rowsum phase, bit 1 bad det product
@@ -76,15 +100,16 @@ struct MeasState {
 
 // Symbolic-sign context of the sampler's sweep (sq_sample.hip); unused (zero)
 // on the plain path. Sign column v < count holds the coefficient of coin v,
-// column count the constant term, one bit per stabilizer row (K words, stride
-// Ks); i is the index of the current measurement in the list.
+// column `count` the constant term, one bit per stabilizer row (K words,
+// stride Ks). The position of the current measurement in the list comes from
+// MeasState::i (alone) or BlkState::i0 (blocks).
 struct SymCtx {
   u64 *sg;
   u32 *svlist;     // coin columns in which S_p has a 1
   uint8_t *kind;   // per measurement: 1 random, 0 deterministic
   u64 *fm;         // per deterministic measurement: coin coefficients (CW words)
   uint8_t *fc;     // ... and the constant term
-  u32 Ks, CW, count, i;
+  u32 Ks, CW, count, pad;
 };
 
 // Running totals over all measurements of a tableau, for byte accounting.
@@ -99,13 +124,10 @@ struct MeasStats {
 // Blocked random measurements (sq_block.hip): up to KB per pass.
 constexpr u32 KB = 32;
 constexpr u32 BLK_PART = 3;  // partial words per (chunk, row word): counter bits 0, 1 and the parity
-struct BlkArgs {
-  u32 k;          // measurements offered to the block
-  u32 q[KB];      // their qubits
-  u64 seed, shot, m0;  // coin key and the measurement index of the first
-};
 struct BlkState {
   u32 k;          // random prefix actually processed (the block ends before a deterministic one)
+  u32 i0;         // list position of the block's first measurement
+  u32 q[KB];      // the qubits of the block's measurements
   u32 p[KB];      // pivot stabilizer index of each
   u32 hitS[KB];   // bit s': pivot s' hit S_{p_s} before it became a pivot
   u32 M[KB];      // bit s2: x of P_s at q_{s2}
@@ -165,14 +187,15 @@ hipError_t launch_init_diag(const TabDev &t, hipStream_t s);
 hipError_t launch_layer(const TabDev &t, const u32 *words, const u32 *offs, u32 ngroups, u32 block, u32 wpt,
                         u32 gpc, u64 *sign_part, hipStream_t s);
 hipError_t launch_sign_reduce(const TabDev &t, const u64 *sign_part, u32 nchunks, hipStream_t s);
-hipError_t launch_pivot(const TabDev &t, u32 q, MeasState *st, u64 *mask, u64 seed, u64 shot, u64 m,
-                        uint8_t *out_bits, uint8_t *out_rand, hipStream_t s);
+hipError_t launch_cursor_init(Cursor *c, u32 end, u32 kb, u64 seed, u64 shot, u64 meas_base, const u32 *qubits,
+                              uint8_t *out_bits, uint8_t *out_rand, hipStream_t s);
+hipError_t launch_pivot(const TabDev &t, Cursor *cur, MeasState *st, u64 *mask, hipStream_t s);
 hipError_t launch_gather(const TabDev &t, MeasState *st, u64 *pivx, u64 *pivz, u32 *cols, const SymCtx *sym,
                          hipStream_t s);
 hipError_t launch_rowsum(const TabDev &t, const u64 *mask, const u32 *cols, const MeasState *st, u64 *cnt0,
                          u64 *cnt1, u32 block, u32 wpt, u32 cpc, u32 max_chunks, const SymCtx *sym, hipStream_t s);
-hipError_t launch_post(const TabDev &t, u32 q, const u64 *mask, const u64 *pivx, const u64 *pivz, const u64 *cnt0,
-                       const u64 *cnt1, MeasState *st, MeasStats *stats, uint8_t *out_bits, u32 cpc, u32 cpw,
+hipError_t launch_post(const TabDev &t, const Cursor *cur, const u64 *mask, const u64 *pivx, const u64 *pivz,
+                       const u64 *cnt0, const u64 *cnt1, MeasState *st, MeasStats *stats, u32 cpc, u32 cpw,
                        const SymCtx *sym, hipStream_t s);
 // Shot sampling (sq_sample.hip).
 hipError_t launch_sample_init(const TabDev &t, u64 *sg, u32 Ks, u32 count, hipStream_t s);
@@ -184,15 +207,13 @@ hipError_t launch_batch(const BatchItem *items, u32 nitems, u32 *next, u32 block
 // waves: PIVOT_AUTO (the C-ABI's SQ_PIVOT_AUTO), or 1..16 for the tiled search
 // with that many waves
 constexpr u32 PIVOT_AUTO = 255;
-hipError_t launch_blk_pivots(const TabDev &t, const BlkArgs &a, const BlkBuffers &b, uint8_t *out_bits,
-                             uint8_t *out_rand, u32 waves, hipStream_t s);
-hipError_t launch_blk_prep(const TabDev &t, const BlkArgs &a, const BlkBuffers &b, MeasState *st, MeasStats *stats,
-                           hipStream_t s);
+hipError_t launch_blk_pivots(const TabDev &t, Cursor *cur, const BlkBuffers &b, u32 waves, hipStream_t s);
+hipError_t launch_blk_prep(const TabDev &t, const BlkBuffers &b, MeasState *st, hipStream_t s);
 hipError_t launch_blk_pass(const TabDev &t, const BlkBuffers &b, u32 cpc, hipStream_t s);
-hipError_t launch_blk_final(const TabDev &t, const BlkArgs &a, const BlkBuffers &b, MeasState *st, MeasStats *stats,
-                            u32 cpc, hipStream_t s);
-hipError_t launch_blk_sv(u64 *sg, u32 Ks, u32 count, u32 m0, u32 kmax, const BlkBuffers &b, u32 *svt,
-                         const u64 *cvec, u32 Ls, u32 K, hipStream_t s);
+hipError_t launch_blk_final(const TabDev &t, const BlkBuffers &b, MeasState *st, MeasStats *stats, u32 cpc,
+                            hipStream_t s);
+hipError_t launch_blk_sv(u64 *sg, u32 Ks, u32 count, const BlkBuffers &b, u32 *svt, const u64 *cvec, u32 Ls, u32 K,
+                         hipStream_t s);
 hipError_t launch_frame_init(u64 *Fx, u64 *Fz, u32 n, u32 Lf, u32 Ls, u64 seed, hipStream_t s);
 hipError_t launch_frame_measure(const u64 *Fx, u64 *Fz, const u32 *qubits, u32 count, u64 m0, const uint8_t *ref,
                                 u64 *rec, u32 n, u32 Lf, u32 Ls, u64 seed, hipStream_t s);

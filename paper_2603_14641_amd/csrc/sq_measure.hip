@@ -14,19 +14,35 @@ namespace sq {
 constexpr u32 SIGN_COLS_PER_BLOCK = 32;  // coin columns per sign-XOR block of k_rowsum
 
 // ---------------------------------------------------------------------------
-// a3: pivot search for measuring qubit q. p = the smallest stabilizer index
-// with x(S_p)_q = 1 (first set bit of the stabilizer half of X column q), or
-// -1. Also snapshots column q into `mask` (the rows the rowsum pass must
-// touch), with the bits of D_p and S_p cleared, because the pass rewrites
-// column q in place. One workgroup; thread 0 also draws the coin.
-__global__ __launch_bounds__(1024) void k_pivot(const u64 *__restrict__ X, u32 Ls, u32 K, u32 L, u32 q,
-                                                MeasState *__restrict__ st, u64 *__restrict__ mask, u64 seed,
-                                                u64 shot, u64 m, uint8_t *__restrict__ out_bits,
-                                                uint8_t *__restrict__ out_rand) {
-  __shared__ u32 s_min;
+// a3: pivot search for measuring qubit q = list[i] alone, i the cursor's
+// position: with kb == 1 every slot measures its list entry this way; with
+// blocks only the deterministic measurement that ended the slot's block does
+// (the cursor's `single` flag), and any other slot measures nothing
+// (MeasState::p = P_NONE, which the slot's later kernels skip). p = the
+// smallest stabilizer index with x(S_p)_q = 1 (first set bit of the
+// stabilizer half of X column q), or -1. Also snapshots column q into `mask`
+// (the rows the rowsum pass must touch), with the bits of D_p and S_p
+// cleared, because the pass rewrites column q in place. One workgroup;
+// thread 0 also draws the coin and advances the cursor.
+__global__ __launch_bounds__(1024) void k_pivot(const u64 *__restrict__ X, u32 Ls, u32 K, u32 L,
+                                                Cursor *__restrict__ cur, MeasState *__restrict__ st,
+                                                u64 *__restrict__ mask) {
+  __shared__ u32 s_min, s_act, s_q, s_i;
   const u32 tid = threadIdx.x;
-  if (tid == 0) s_min = 0xFFFFFFFFu;
+  if (tid == 0) {
+    s_min = 0xFFFFFFFFu;
+    const u32 i = cur->i;
+    const u32 act = cur->kb <= 1u ? (i < cur->end ? 1u : 0u) : cur->single;
+    s_act = act;
+    s_i = i;
+    s_q = act ? cur->qubits[i] : 0u;
+  }
   __syncthreads();
+  if (!s_act) {
+    if (tid == 0) st->p = P_NONE;
+    return;
+  }
+  const u32 q = s_q, i = s_i;
   const u64 *col = X + (size_t)q * Ls;
   u32 first = 0xFFFFFFFFu;
   for (u32 w = tid; w < K; w += blockDim.x) {
@@ -39,6 +55,7 @@ __global__ __launch_bounds__(1024) void k_pivot(const u64 *__restrict__ X, u32 L
   const u32 wmin = s_min;
   int32_t p = -1;
   if (wmin != 0xFFFFFFFFu) p = (int32_t)(wmin * 64u + (u32)__builtin_ctzll(col[K + wmin]));
+  // (thread 0 may set p to P_NONE below; the snapshot uses the pivot found)
   const u32 wd = (p >= 0) ? ((u32)p >> 6) : 0xFFFFFFFFu;
   const u64 bit = (p >= 0) ? (1ULL << ((u32)p & 63u)) : 0ULL;
   __shared__ u32 s_mw, s_aw;
@@ -59,8 +76,17 @@ __global__ __launch_bounds__(1024) void k_pivot(const u64 *__restrict__ X, u32 L
   if ((tid & 63u) == 0) { atomicAdd(&s_mw, mw); atomicAdd(&s_aw, aw); }
   __syncthreads();
   if (tid == 0) {
-    const u32 c = coin_bit(seed, shot, m);
+    const u32 c = coin_bit(cur->seed, cur->shot, cur->meas_base + i);
+    const bool blocked = cur->kb > 1u;
+    if (blocked && p >= 0) {
+      // the blocked pivot step found no pivot for this measurement: the two
+      // searches disagree, which is a bug; flag it and measure nothing
+      atomicOr(&st->flags, 4u);
+      p = P_NONE;
+    }
     st->p = p;
+    st->q = q;
+    st->i = i;
     st->ncols = 0;
     st->nsv = 0;
     st->nx = 0;
@@ -70,8 +96,10 @@ __global__ __launch_bounds__(1024) void k_pivot(const u64 *__restrict__ X, u32 L
     st->det_acc = 0;
     st->det_done = 0;
     st->coin = c;
-    out_rand[0] = (uint8_t)(p >= 0);
-    if (p >= 0) out_bits[0] = (uint8_t)c;
+    if (p != P_NONE && cur->out_rand) cur->out_rand[i] = (uint8_t)(p >= 0);
+    if (p >= 0 && cur->out_bits) cur->out_bits[i] = (uint8_t)c;
+    cur->i = i + 1;
+    cur->single = 0;
   }
 }
 
@@ -93,7 +121,7 @@ __global__ void k_gather(const u64 *__restrict__ X, const u64 *__restrict__ Z, c
   const u32 colblocks = (n + blockDim.x - 1) / blockDim.x;
   if (SYM && blockIdx.x >= colblocks) {
     const u32 v = (blockIdx.x - colblocks) * blockDim.x + threadIdx.x;
-    const u32 b = (v < sym.i) ? (u32)(sym.sg[(size_t)v * sym.Ks + ((u32)p >> 6)] >> sh) & 1u : 0u;
+    const u32 b = (v < st->i) ? (u32)(sym.sg[(size_t)v * sym.Ks + ((u32)p >> 6)] >> sh) & 1u : 0u;
     const u64 bb = __ballot(b);
     u32 base = 0;
     if (lane == 0 && bb) base = atomicAdd(&st->nsv, (u32)__popcll(bb));
@@ -281,9 +309,11 @@ __global__ __launch_bounds__(256) void k_post(u64 *__restrict__ X, u64 *__restri
                                               const u64 *__restrict__ mask, const u64 *__restrict__ pivx,
                                               const u64 *__restrict__ pivz, const u64 *__restrict__ cnt0,
                                               const u64 *__restrict__ cnt1, MeasState *__restrict__ st,
-                                              MeasStats *__restrict__ stats, uint8_t *__restrict__ out_bits, u32 Ls,
-                                              u32 L, u32 K, u32 n, u32 q, u32 cpc, u32 cpw, SymCtx sym) {
+                                              MeasStats *__restrict__ stats, const Cursor *__restrict__ cur, u32 Ls,
+                                              u32 L, u32 K, u32 n, u32 cpc, u32 cpw, SymCtx sym) {
   const int32_t p = st->p;
+  if (p == P_NONE) return;  // the slot measures nothing alone
+  const u32 q = st->q, li = st->i;  // the qubit and its list position
   const u32 tid = threadIdx.x, lane = tid & 63u, wave = tid >> 6, nwaves = blockDim.x >> 6;
   const u32 t = blockIdx.x * blockDim.x + tid;
   if (p >= 0) {
@@ -352,8 +382,8 @@ __global__ __launch_bounds__(256) void k_post(u64 *__restrict__ X, u64 *__restri
     if (SYM) {
       if (t < st->nsv) sym.sg[(size_t)sym.svlist[t] * sym.Ks + wd] &= ~bit;
       if (t == 0) {
-        sym.sg[(size_t)sym.i * sym.Ks + wd] |= bit;
-        sym.kind[sym.i] = 1;
+        sym.sg[(size_t)li * sym.Ks + wd] |= bit;
+        sym.kind[li] = 1;
       }
     }
     return;
@@ -425,7 +455,7 @@ __global__ __launch_bounds__(256) void k_post(u64 *__restrict__ X, u64 *__restri
     __syncthreads();
     const u32 vbase = blockIdx.x * 64u;
     const u32 v0 = vbase + wave * PER;
-    if (v0 < sym.i) {
+    if (v0 < li) {
       u32 par[PER];
 #pragma unroll
       for (u32 k = 0; k < PER; ++k) par[k] = 0;
@@ -433,7 +463,7 @@ __global__ __launch_bounds__(256) void k_post(u64 *__restrict__ X, u64 *__restri
         const u64 m = mask[w];
         u64 c[PER];
 #pragma unroll
-        for (u32 k = 0; k < PER; ++k) c[k] = (v0 + k < sym.i) ? sym.sg[(size_t)(v0 + k) * sym.Ks + w] : 0ULL;
+        for (u32 k = 0; k < PER; ++k) c[k] = (v0 + k < li) ? sym.sg[(size_t)(v0 + k) * sym.Ks + w] : 0ULL;
 #pragma unroll
         for (u32 k = 0; k < PER; ++k) par[k] ^= (u32)__popcll(c[k] & m) & 1u;
       }
@@ -443,7 +473,7 @@ __global__ __launch_bounds__(256) void k_post(u64 *__restrict__ X, u64 *__restri
       if (lane == 0 && bits) atomicOr(&s_fw, bits << (v0 & 63u));
     }
     __syncthreads();
-    if (tid == 0 && vbase <= sym.i) sym.fm[(size_t)sym.i * sym.CW + blockIdx.x] = s_fw;
+    if (tid == 0 && vbase <= li) sym.fm[(size_t)li * sym.CW + blockIdx.x] = s_fw;
   }
   for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off);
   if (lane == 0) s_acc[wave] = acc;
@@ -473,10 +503,10 @@ __global__ __launch_bounds__(256) void k_post(u64 *__restrict__ X, u64 *__restri
     if (e & 1u) atomicOr(&st->flags, 1u);
     const uint8_t outcome = (uint8_t)(tot ^ (e >> 1));
     if (SYM) {
-      sym.fc[sym.i] = outcome;
-      sym.kind[sym.i] = 0;
+      sym.fc[li] = outcome;
+      sym.kind[li] = 0;
     } else {
-      out_bits[0] = outcome;
+      if (cur->out_bits) cur->out_bits[li] = outcome;
       // Algorithmic bytes: x and z of every column at each word holding a row of A.
       stats->n_det += 1;
       stats->det_bytes += (u64)st->awords * 8ULL * 2ULL * n;
@@ -485,10 +515,31 @@ __global__ __launch_bounds__(256) void k_post(u64 *__restrict__ X, u64 *__restri
 }
 
 // Launchers.
-hipError_t launch_pivot(const TabDev &t, u32 q, MeasState *st, u64 *mask, u64 seed, u64 shot, u64 m,
-                        uint8_t *out_bits, uint8_t *out_rand, hipStream_t s) {
-  hipLaunchKernelGGL(k_pivot, dim3(1), dim3(1024), 0, s, t.X, t.Ls, t.K, t.L, q, st, mask, seed, shot, m, out_bits,
+__global__ void k_cursor_init(Cursor *c, u32 end, u32 kb, u64 seed, u64 shot, u64 meas_base, const u32 *qubits,
+                              uint8_t *out_bits, uint8_t *out_rand) {
+  if (threadIdx.x == 0) {
+    c->i = 0;
+    c->end = end;
+    c->kb = kb;
+    c->single = 0;
+    c->seed = seed;
+    c->shot = shot;
+    c->meas_base = meas_base;
+    c->qubits = qubits;
+    c->out_bits = out_bits;
+    c->out_rand = out_rand;
+  }
+}
+
+hipError_t launch_cursor_init(Cursor *c, u32 end, u32 kb, u64 seed, u64 shot, u64 meas_base, const u32 *qubits,
+                              uint8_t *out_bits, uint8_t *out_rand, hipStream_t s) {
+  hipLaunchKernelGGL(k_cursor_init, dim3(1), dim3(64), 0, s, c, end, kb, seed, shot, meas_base, qubits, out_bits,
                      out_rand);
+  return hipGetLastError();
+}
+
+hipError_t launch_pivot(const TabDev &t, Cursor *cur, MeasState *st, u64 *mask, hipStream_t s) {
+  hipLaunchKernelGGL(k_pivot, dim3(1), dim3(1024), 0, s, t.X, t.Ls, t.K, t.L, cur, st, mask);
   return hipGetLastError();
 }
 
@@ -496,7 +547,7 @@ hipError_t launch_gather(const TabDev &t, MeasState *st, u64 *pivx, u64 *pivz, u
                          hipStream_t s) {
   const u32 colblocks = cdiv(t.n, 256);
   if (sym) {
-    const u32 vblocks = cdiv(sym->i, 256);
+    const u32 vblocks = cdiv(sym->count, 256);  // coin columns before the measurement's position
     hipLaunchKernelGGL(k_gather<true>, dim3(colblocks + vblocks), dim3(256), 0, s, t.X, t.Z, t.R, t.Ls, t.K, t.n, st,
                        pivx, pivz, cols, *sym);
   } else {
@@ -509,7 +560,7 @@ hipError_t launch_gather(const TabDev &t, MeasState *st, u64 *pivx, u64 *pivz, u
 hipError_t launch_rowsum(const TabDev &t, const u64 *mask, const u32 *cols, const MeasState *st, u64 *cnt0,
                          u64 *cnt1, u32 block, u32 wpt, u32 cpc, u32 max_chunks, const SymCtx *sym, hipStream_t s) {
   const u32 tiles = cdiv(t.L, (u64)block * wpt);
-  const u32 vchunks = sym ? cdiv(sym->i, SIGN_COLS_PER_BLOCK) : 0;
+  const u32 vchunks = sym ? cdiv(sym->count, SIGN_COLS_PER_BLOCK) : 0;
   dim3 grid(tiles, max_chunks + vchunks);
   const SymCtx sc = sym ? *sym : SymCtx{};
   if (sym) {
@@ -530,19 +581,20 @@ hipError_t launch_rowsum(const TabDev &t, const u64 *mask, const u32 *cols, cons
   return hipGetLastError();
 }
 
-hipError_t launch_post(const TabDev &t, u32 q, const u64 *mask, const u64 *pivx, const u64 *pivz, const u64 *cnt0,
-                       const u64 *cnt1, MeasState *st, MeasStats *stats, uint8_t *out_bits, u32 cpc, u32 cpw,
+hipError_t launch_post(const TabDev &t, const Cursor *cur, const u64 *mask, const u64 *pivx, const u64 *pivz,
+                       const u64 *cnt0, const u64 *cnt1, MeasState *st, MeasStats *stats, u32 cpc, u32 cpw,
                        const SymCtx *sym, hipStream_t s) {
   // roles: a wave per sign word (4 per block), a thread per column, a block per
-  // deterministic column range (and per affine-form word on the sampling path)
+  // deterministic column range (and per affine-form word on the sampling path,
+  // up to the last list position)
   u32 blocks = std::max(std::max(cdiv(t.L, 4), cdiv(t.n, 256)), cdiv(t.n, cpw));
-  if (sym) blocks = std::max(blocks, cdiv(sym->i + 1, 64));  // one affine-form word per block
+  if (sym) blocks = std::max(blocks, cdiv(sym->count + 1, 64));
   if (sym)
     hipLaunchKernelGGL(k_post<true>, dim3(blocks), dim3(256), 0, s, t.X, t.Z, t.R, mask, pivx, pivz, cnt0, cnt1, st,
-                       stats, out_bits, t.Ls, t.L, t.K, t.n, q, cpc, cpw, *sym);
+                       stats, cur, t.Ls, t.L, t.K, t.n, cpc, cpw, *sym);
   else
     hipLaunchKernelGGL(k_post<false>, dim3(blocks), dim3(256), 0, s, t.X, t.Z, t.R, mask, pivx, pivz, cnt0, cnt1, st,
-                       stats, out_bits, t.Ls, t.L, t.K, t.n, q, cpc, cpw, SymCtx{});
+                       stats, cur, t.Ls, t.L, t.K, t.n, cpc, cpw, SymCtx{});
   return hipGetLastError();
 }
 

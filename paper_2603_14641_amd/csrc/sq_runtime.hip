@@ -93,16 +93,20 @@ struct sq_tableau {
   hipStream_t stream = nullptr;
   Dims d{};
   TabDev t{};
-  u64 *base = nullptr;      // one allocation for every device buffer below
+  u64 *base = nullptr;      // one device block for every device buffer below
+  bool owns_base = true;    // false for sq_create_in: the caller's block
   u64 *mask = nullptr, *pivx = nullptr, *pivz = nullptr, *cnt0 = nullptr, *cnt1 = nullptr, *sign_part = nullptr;
   u32 *cols = nullptr;
   MeasState *st = nullptr;
   MeasStats *stats = nullptr;
   BlkBuffers blk{};
   u32 blk_cpc = 0;
-  u32 *blk_k_host = nullptr;  // pinned: random-prefix length of the last block
-  uint8_t *dev_out = nullptr;
+  Cursor *cur = nullptr;      // where the current measurement sweep stands (device)
+  u32 *cur_host = nullptr;    // pinned: the sweep's list position, read back once per round of slots
+  uint8_t *dev_out = nullptr;  // sq_measure: outcome and random-flag bytes
   size_t dev_out_cap = 0;
+  u32 *dev_q = nullptr;        // sq_measure: the measured list on the device
+  size_t dev_q_cap = 0;
   u32 *dev_words = nullptr;  // gate-pass records of the last sq_apply_gates call
   size_t dev_words_cap = 0;
   u32 *dev_offs = nullptr;
@@ -134,6 +138,7 @@ struct sq_program {
   Dims d{};
   u32 *dev_words = nullptr;  // gate-pass records and their offsets, device resident
   u32 *dev_offs = nullptr;
+  u32 *dev_meas = nullptr;   // the measured qubits in program order, device resident
   std::vector<PassRange> passes;
   struct Seg {
     int kind;  // 0 gate passes [first, first+count), 1 measurements [first, first+count)
@@ -157,11 +162,11 @@ u32 blk_cpc_of(const Dims &d) {
   return std::max<u32>(cpc, cdiv(d.n, kBlkMaxChunks));
 }
 
-constexpr int kLayoutSlots = 18;
+constexpr int kLayoutSlots = 19;
 
 size_t layout_words(const Dims &d, size_t *off) {
   // offsets (in words) of: X, Z, R, mask, pivx, pivz, cnt0, cnt1, sign_part, cols, st, stats,
-  // then the blocked-measurement buffers: bm, wpart, patx, patz, part, bs
+  // then the blocked-measurement buffers: bm, wpart, patx, patz, part, bs; then the sweep cursor
   size_t o = 0;
   auto take = [&](size_t words) {
     size_t r = o;
@@ -186,6 +191,7 @@ size_t layout_words(const Dims &d, size_t *off) {
   off[15] = take((d.n + 1) / 2);
   off[16] = take((size_t)cdiv(d.n, blk_cpc_of(d)) * BLK_PART * d.Ls);
   off[17] = take(sizeof(BlkState) / 8 + 1);
+  off[18] = take(sizeof(Cursor) / 8 + 1);
   return o;
 }
 
@@ -376,74 +382,119 @@ sq_status run_gate_segment(sq_tableau *T, const sq_program *P, u64 first, u64 co
   return SQ_OK;
 }
 
-sq_status measure_one(sq_tableau *T, u32 q, u64 seed, u64 shot, u64 m, uint8_t *dbits, uint8_t *drand) {
+// A measurement sweep over a device-resident list, driven by the cursor in
+// device memory (Cursor). Its kernels are queued in slots that read the list
+// position from the cursor and advance it, so nothing is read back per block:
+//   meas_block == 1: a slot is pivot, gather, rowsum, post for list[i];
+//   meas_block >= 2: a slot is the blocked path on list[i .. i + kb) (pivot
+//   step, masks and pivot rows, pass, signs and special rows), then pivot and
+//   post for the deterministic measurement that ended the block, if any
+//   (their kernels exit at once otherwise, as do the blocked ones once the
+//   list is done).
+// Every slot advances the cursor by at least one measurement until the list
+// is done. The host queues one slot per kb measurements, reads the position
+// back (one 4-byte copy), and only when deterministic measurements cut blocks
+// short queues more, sized from the measurements per slot seen so far.
+// Workspace of sq_sample (byte offsets, 256-byte aligned): X and Z copies,
+// sign columns, affine forms, coin and outcome words, the compacted coin
+// columns, per-measurement kind and constant, the blocked sweep's zeroed sign
+// words and pivot coefficients, a byte-count sink, and the measured list.
+struct SampleWs {
+  u32 Ks, CW;
+  size_t o_x, o_z, o_sg, o_fm, o_cw, o_out, o_sv, o_kind, o_fc, o_cvec, o_svt, o_stats, o_q;
+};
+
+size_t sample_ws(const Dims &d, u32 count, u32 shots, SampleWs *L) {
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    size_t r = off;
+    off += (bytes + 255) / 256 * 256;
+    return r;
+  };
+  L->Ks = round_up(d.K, 16);
+  L->CW = cdiv(count, 64);
+  L->o_x = take((size_t)d.n * d.Ls * 8);
+  L->o_z = take((size_t)d.n * d.Ls * 8);
+  L->o_sg = take((size_t)(count + 1) * L->Ks * 8);
+  L->o_fm = take((size_t)count * L->CW * 8);
+  L->o_cw = take((size_t)shots * L->CW * 8);
+  L->o_out = take((size_t)shots * L->CW * 8);
+  L->o_sv = take((size_t)(count + 1) * 4);
+  L->o_kind = take(count);
+  L->o_fc = take(count);
+  L->o_cvec = take((size_t)d.Ls * 8);
+  L->o_svt = take((size_t)(count + 1) * 4);
+  L->o_stats = take(sizeof(MeasStats));
+  L->o_q = take((size_t)count * 4);
+  return off;
+}
+
+struct SweepCtx {
+  TabDev tab;             // tableau the single path works on
+  TabDev tabb;            // tableau of the blocked path (the sampler's has zeroed signs, cvec)
+  const SymCtx *sym;      // sampler's symbolic signs, or NULL
+  MeasStats *bstats;      // byte counters of the blocked path
+  u64 *cvec;              // sampler: the blocked path's zeroed sign words, cleared per slot
+  u32 *svt;               // sampler: per sign column, its coefficients in the block's pivots
+};
+
+sq_status queue_slot(sq_tableau *T, const SweepCtx &c, u32 kb) {
+  if (kb <= 1) {
+    const u32 cpc = rowsum_cpc(T);
+    const u32 max_chunks = cdiv(T->d.n, cpc);
+    SQ_TRY(timed(T, SQ_K_PIVOT, [&] { return launch_pivot(c.tab, T->cur, T->st, T->mask, T->stream); }));
+    SQ_TRY(timed(T, SQ_K_GATHER, [&] {
+      return launch_gather(c.tab, T->st, T->pivx, T->pivz, T->cols, c.sym, T->stream);
+    }));
+    SQ_TRY(timed(T, SQ_K_ROWSUM, [&] {
+      return launch_rowsum(c.tab, T->mask, T->cols, T->st, T->cnt0, T->cnt1, T->tun.rowsum_block, T->tun.rowsum_wpt,
+                           cpc, max_chunks, c.sym, T->stream);
+    }));
+    SQ_TRY(timed(T, SQ_K_POST, [&] {
+      return launch_post(c.tab, T->cur, T->mask, T->pivx, T->pivz, T->cnt0, T->cnt1, T->st, T->stats, cpc, det_cpw(T),
+                         c.sym, T->stream);
+    }));
+    return SQ_OK;
+  }
+  if (c.cvec) HIP_TRY(launch_fill_zero(c.cvec, T->d.Ls, T->stream));
+  SQ_TRY(timed(T, SQ_K_BPIVOT, [&] { return launch_blk_pivots(c.tabb, T->cur, T->blk, T->tun.pivot_waves, T->stream); }));
+  SQ_TRY(timed(T, SQ_K_BPREP, [&] { return launch_blk_prep(c.tabb, T->blk, T->st, T->stream); }));
+  SQ_TRY(timed(T, SQ_K_BPASS, [&] { return launch_blk_pass(c.tabb, T->blk, T->blk_cpc, T->stream); }));
+  SQ_TRY(timed(T, SQ_K_BFINAL, [&] {
+    return launch_blk_final(c.tabb, T->blk, T->st, c.bstats, T->blk_cpc, T->stream);
+  }));
+  if (c.sym) HIP_TRY(launch_blk_sv(c.sym->sg, c.sym->Ks, c.sym->count, T->blk, c.svt, c.cvec, T->d.Ls, T->d.K,
+                                   T->stream));
+  // the deterministic measurement that ended the block: its product only
+  // (pivot search, mask snapshot, then the ordered product in k_post)
   const u32 cpc = rowsum_cpc(T);
-  const u32 max_chunks = cdiv(T->d.n, cpc);
-  SQ_TRY(timed(T, SQ_K_PIVOT, [&] {
-    return launch_pivot(T->t, q, T->st, T->mask, seed, shot, m, dbits, drand, T->stream);
-  }));
-  SQ_TRY(timed(T, SQ_K_GATHER, [&] {
-    return launch_gather(T->t, T->st, T->pivx, T->pivz, T->cols, nullptr, T->stream);
-  }));
-  SQ_TRY(timed(T, SQ_K_ROWSUM, [&] {
-    return launch_rowsum(T->t, T->mask, T->cols, T->st, T->cnt0, T->cnt1, T->tun.rowsum_block, T->tun.rowsum_wpt, cpc,
-                         max_chunks, nullptr, T->stream);
-  }));
+  SQ_TRY(timed(T, SQ_K_PIVOT, [&] { return launch_pivot(c.tab, T->cur, T->st, T->mask, T->stream); }));
   SQ_TRY(timed(T, SQ_K_POST, [&] {
-    return launch_post(T->t, q, T->mask, T->pivx, T->pivz, T->cnt0, T->cnt1, T->st, T->stats, dbits, cpc, det_cpw(T),
-                       nullptr, T->stream);
+    return launch_post(c.tab, T->cur, T->mask, T->pivx, T->pivz, T->cnt0, T->cnt1, T->st, T->stats, cpc, det_cpw(T),
+                       c.sym, T->stream);
   }));
   return SQ_OK;
 }
 
-// Measurements qubits[i0..i1) (indices meas_base + i), random runs KB at a
-// time through the blocked pass. Each block's length (the random prefix
-// before the first deterministic measurement) is read back before its pass;
-// the deterministic one then takes the single path. Blocks that end at once
-// (deterministic stretches) back off to the single path for 1, 2, 4, ... 64
-// measurements before the next try.
-sq_status measure_range(sq_tableau *T, const uint32_t *qubits, u64 i0, u64 i1, u64 seed, u64 shot, u64 meas_base,
-                        uint8_t *dbits, uint8_t *drand) {
+// Queue the sweep of a list of `count` measurements whose cursor has been
+// initialised on T's stream, and wait until it is done.
+sq_status run_sweep(sq_tableau *T, const SweepCtx &c, u32 count) {
+  if (count == 0) return SQ_OK;
   const u32 kb = std::min<u32>(T->tun.meas_block, KB);
-  u64 i = i0;
-  u32 single = 0, backoff = 1;
-  while (i < i1) {
-    const u32 want = (u32)std::min<u64>(kb, i1 - i);
-    if (want < 2 || single > 0) {
-      SQ_TRY(measure_one(T, qubits[i], seed, shot, meas_base + i, dbits + i, drand + i));
-      ++i;
-      if (single > 0) --single;
-      continue;
-    }
-    BlkArgs a{};
-    a.k = want;
-    for (u32 s = 0; s < want; ++s) a.q[s] = qubits[i + s];
-    a.seed = seed;
-    a.shot = shot;
-    a.m0 = meas_base + i;
-    SQ_TRY(timed(T, SQ_K_BPIVOT, [&] { return launch_blk_pivots(T->t, a, T->blk, dbits + i, drand + i, T->tun.pivot_waves, T->stream); }));
-    HIP_TRY(hipMemcpyAsync(T->blk_k_host, &T->blk.bs->k, sizeof(u32), hipMemcpyDeviceToHost, T->stream));
+  u64 queued = 0;
+  u64 slots = kb <= 1 ? count : cdiv(count, kb);
+  for (;;) {
+    for (u64 k = 0; k < slots; ++k) SQ_TRY(queue_slot(T, c, kb));
+    queued += slots;
+    HIP_TRY(hipMemcpyAsync(T->cur_host, &T->cur->i, sizeof(u32), hipMemcpyDeviceToHost, T->stream));
     HIP_TRY(hipStreamSynchronize(T->stream));
-    const u32 k = *T->blk_k_host;
-    if (k > want) return fail(SQ_ESTATE, "blocked measurement: bad block length %u", k);
-    if (k > 0) {
-      SQ_TRY(timed(T, SQ_K_BPREP, [&] { return launch_blk_prep(T->t, a, T->blk, T->st, T->stats, T->stream); }));
-      SQ_TRY(timed(T, SQ_K_BPASS, [&] { return launch_blk_pass(T->t, T->blk, T->blk_cpc, T->stream); }));
-      SQ_TRY(timed(T, SQ_K_BFINAL, [&] {
-        return launch_blk_final(T->t, a, T->blk, T->st, T->stats, T->blk_cpc, T->stream);
-      }));
-      i += k;
-      backoff = 1;
-    } else {
-      single = backoff - 1;
-      backoff = std::min<u32>(2 * backoff, 64);
-    }
-    if (k < want) {  // measurement i is deterministic
-      SQ_TRY(measure_one(T, qubits[i], seed, shot, meas_base + i, dbits + i, drand + i));
-      ++i;
-    }
+    const u32 pos = *T->cur_host;
+    if (pos == count) return SQ_OK;
+    if (pos > count || pos < queued) return fail(SQ_ESTATE, "measurement sweep: cursor at %u of %u after %llu slots",
+                                                 pos, count, (unsigned long long)queued);
+    const double per = std::max(1.0, (double)pos / (double)queued);  // measurements per slot so far
+    slots = std::max<u64>(1, (u64)((double)(count - pos) / per));
   }
-  return SQ_OK;
 }
 
 // Grow a stream-ordered u32 device buffer of the handle to hold `need` words.
@@ -495,11 +546,27 @@ size_t sq_bytes_required(uint32_t n) {
   return layout_words(dims_of(n), off) * 8;
 }
 
-sq_status sq_create(uint32_t n, void *hip_stream, sq_tableau **out) {
+}  // extern "C"
+
+namespace {
+
+// sq_create / sq_create_in: dev_buf NULL allocates the device block
+// (stream-ordered), else the caller's block of `bytes` bytes is used and never
+// freed by the library.
+sq_status create_tableau(uint32_t n, void *hip_stream, void *dev_buf, size_t bytes, sq_tableau **out) {
   if (!out) return fail(SQ_EINVAL, "out is NULL");
   *out = nullptr;
   if (n == 0) return fail(SQ_EINVAL, "n must be >= 1");
   if (n > SQ_MAX_QUBITS) return fail(SQ_ERANGE, "n=%u above the limit %u", n, SQ_MAX_QUBITS);
+  const Dims d = dims_of(n);
+  size_t off[kLayoutSlots];
+  const size_t words = layout_words(d, off);
+  if (dev_buf) {
+    if (bytes < words * 8)
+      return fail(SQ_ERANGE, "device buffer of %zu bytes, n=%u needs %zu (sq_bytes_required)", bytes, n, words * 8);
+    if ((uintptr_t)dev_buf % 256)
+      return fail(SQ_EINVAL, "device buffer must be 256-byte aligned");
+  }
   sq_tableau *T = new (std::nothrow) sq_tableau();
   if (!T) return fail(SQ_ENOMEM, "host allocation failed");
   if (hipGetDevice(&T->device) != hipSuccess) {
@@ -507,19 +574,20 @@ sq_status sq_create(uint32_t n, void *hip_stream, sq_tableau **out) {
     return fail(SQ_EDEVICE, "no HIP device");
   }
   T->stream = (hipStream_t)hip_stream;
-  T->d = dims_of(n);
-  size_t off[kLayoutSlots];
-  const size_t words = layout_words(T->d, off);
-  if (hipHostMalloc((void **)&T->blk_k_host, sizeof(u32), hipHostMallocDefault) != hipSuccess) {
+  T->d = d;
+  if (hipHostMalloc((void **)&T->cur_host, sizeof(u32), hipHostMallocDefault) != hipSuccess) {
     (void)hipGetLastError();
     delete T;
     return fail(SQ_ENOMEM, "pinned host allocation failed");
   }
-  // stream-ordered allocation: no device-wide synchronization, so handles can
-  // be created and destroyed while other streams keep working
-  if (hipMallocAsync((void **)&T->base, words * 8, T->stream) != hipSuccess) {
+  if (dev_buf) {
+    T->base = (u64 *)dev_buf;
+    T->owns_base = false;
+  } else if (hipMallocAsync((void **)&T->base, words * 8, T->stream) != hipSuccess) {
+    // stream-ordered allocation: no device-wide synchronization, so handles can
+    // be created and destroyed while other streams keep working
     (void)hipGetLastError();
-    (void)hipHostFree(T->blk_k_host);
+    (void)hipHostFree(T->cur_host);
     delete T;
     return fail(SQ_ENOMEM, "device allocation of %zu bytes failed", words * 8);
   }
@@ -536,19 +604,50 @@ sq_status sq_create(uint32_t n, void *hip_stream, sq_tableau **out) {
   T->stats = reinterpret_cast<MeasStats *>(b + off[11]);
   T->blk = BlkBuffers{b + off[12], reinterpret_cast<u32 *>(b + off[13]), reinterpret_cast<u32 *>(b + off[14]),
                       reinterpret_cast<u32 *>(b + off[15]), b + off[16], reinterpret_cast<BlkState *>(b + off[17])};
+  T->cur = reinterpret_cast<Cursor *>(b + off[18]);
   T->blk_cpc = blk_cpc_of(T->d);
   default_tuning(T->d, &T->tun);
   T->builder.init(n, T->d.L);
   sq_status s = reset_device(T);
   if (s == SQ_OK && hipStreamSynchronize(T->stream) != hipSuccess) s = fail(SQ_EDEVICE, "initialisation failed");
   if (s != SQ_OK) {
-    (void)hipFreeAsync(T->base, T->stream);
+    if (T->owns_base) (void)hipFreeAsync(T->base, T->stream);
     (void)hipStreamSynchronize(T->stream);
-    (void)hipHostFree(T->blk_k_host);
+    (void)hipHostFree(T->cur_host);
     delete T;
     return s;
   }
   *out = T;
+  return SQ_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+sq_status sq_create(uint32_t n, void *hip_stream, sq_tableau **out) {
+  return create_tableau(n, hip_stream, nullptr, 0, out);
+}
+
+sq_status sq_create_in(uint32_t n, void *dev_buf, size_t bytes, void *hip_stream, sq_tableau **out) {
+  if (!dev_buf) return fail(SQ_EINVAL, "dev_buf is NULL");
+  return create_tableau(n, hip_stream, dev_buf, bytes, out);
+}
+
+sq_status sq_layout(uint32_t n, sq_layout_info *out) {
+  if (!out) return fail(SQ_EINVAL, "out is NULL");
+  if (n == 0 || n > SQ_MAX_QUBITS) return fail(SQ_ERANGE, "bad n=%u", n);
+  const Dims d = dims_of(n);
+  size_t off[kLayoutSlots];
+  const size_t words = layout_words(d, off);
+  out->n = n;
+  out->K = d.K;
+  out->L = d.L;
+  out->Ls = d.Ls;
+  out->x_offset = off[0] * 8;
+  out->z_offset = off[1] * 8;
+  out->r_offset = off[2] * 8;
+  out->bytes = words * 8;
   return SQ_OK;
 }
 
@@ -565,11 +664,12 @@ sq_status sq_destroy(sq_tableau *T) {
     if (g.exec) (void)hipGraphExecDestroy(g.exec);
   if (T->cap_stream) (void)hipStreamDestroy(T->cap_stream);
   if (T->dev_out) (void)hipFreeAsync(T->dev_out, T->stream);
+  if (T->dev_q) (void)hipFreeAsync(T->dev_q, T->stream);
   if (T->dev_words) (void)hipFreeAsync(T->dev_words, T->stream);
   if (T->dev_offs) (void)hipFreeAsync(T->dev_offs, T->stream);
-  (void)hipFreeAsync(T->base, T->stream);
+  if (T->owns_base) (void)hipFreeAsync(T->base, T->stream);
   (void)hipStreamSynchronize(T->stream);
-  (void)hipHostFree(T->blk_k_host);
+  (void)hipHostFree(T->cur_host);
   delete T;
   return SQ_OK;
 }
@@ -619,9 +719,13 @@ sq_status sq_measure(sq_tableau *T, const uint32_t *qubits, uint32_t count, uint
     }
     T->dev_out_cap = need;
   }
+  SQ_TRY(ensure_capacity(T, &T->dev_q, &T->dev_q_cap, count));
   MeasState before{}, after{};
   HIP_TRY(hipMemcpyAsync(&before, T->st, sizeof(MeasState), hipMemcpyDeviceToHost, T->stream));
-  SQ_TRY(measure_range(T, qubits, 0, count, seed, shot, meas_base, T->dev_out, T->dev_out + count));
+  HIP_TRY(hipMemcpyAsync(T->dev_q, qubits, (size_t)count * 4, hipMemcpyHostToDevice, T->stream));
+  HIP_TRY(launch_cursor_init(T->cur, count, std::min<u32>(T->tun.meas_block, KB), seed, shot, meas_base, T->dev_q,
+                             T->dev_out, T->dev_out + count, T->stream));
+  SQ_TRY(run_sweep(T, SweepCtx{T->t, T->t, nullptr, T->stats, nullptr, nullptr}, count));
   HIP_TRY(hipMemcpyAsync(out_bits, T->dev_out, count, hipMemcpyDeviceToHost, T->stream));
   if (out_random)
     HIP_TRY(hipMemcpyAsync(out_random, T->dev_out + count, count, hipMemcpyDeviceToHost, T->stream));
@@ -640,108 +744,38 @@ sq_status sq_sample(sq_tableau *T, const uint32_t *qubits, uint32_t count, uint6
   for (u32 i = 0; i < count; ++i)
     if (qubits[i] >= T->d.n) return fail(SQ_ERANGE, "qubit %u >= n=%u", qubits[i], T->d.n);
   const Dims &d = T->d;
-  const u32 Ks = round_up(d.K, 16);
-  const u32 CW = cdiv(count, 64);
-  // workspace: X, Z copies | sign columns | Fm | cw | out | svlist | kind | fc | dummy |
-  // blocked sweep: constants c(h) | pivot coefficients per column | outcome and stats sinks
-  size_t off = 0;
-  auto take = [&](size_t bytes) {
-    size_t r = off;
-    off += (bytes + 255) / 256 * 256;
-    return r;
-  };
-  const size_t o_x = take((size_t)d.n * d.Ls * 8), o_z = take((size_t)d.n * d.Ls * 8);
-  const size_t o_sg = take((size_t)(count + 1) * Ks * 8), o_fm = take((size_t)count * CW * 8);
-  const size_t o_cw = take((size_t)shots * CW * 8), o_out = take((size_t)shots * CW * 8);
-  const size_t o_sv = take((size_t)(count + 1) * 4), o_kind = take(count), o_fc = take(count), o_dummy = take(2);
-  const size_t o_cvec = take((size_t)d.Ls * 8), o_svt = take((size_t)(count + 1) * 4), o_bits = take(KB);
-  const size_t o_stats = take(sizeof(MeasStats));
+  SampleWs L;
+  const size_t ws_bytes = sample_ws(d, count, shots, &L);
   uint8_t *ws = nullptr;
-  if (hipMallocAsync((void **)&ws, off, T->stream) != hipSuccess) {
+  if (hipMallocAsync((void **)&ws, ws_bytes, T->stream) != hipSuccess) {
     (void)hipGetLastError();
-    return fail(SQ_ENOMEM, "device allocation of %zu bytes for sampling failed", off);
+    return fail(SQ_ENOMEM, "device allocation of %zu bytes for sampling failed", ws_bytes);
   }
-  u64 *sg = (u64 *)(ws + o_sg), *fm = (u64 *)(ws + o_fm), *cw = (u64 *)(ws + o_cw), *dout = (u64 *)(ws + o_out);
-  u32 *svlist = (u32 *)(ws + o_sv);
-  uint8_t *kind = ws + o_kind, *fc = ws + o_fc, *dummy = ws + o_dummy;
-  TabDev ts{(u64 *)(ws + o_x), (u64 *)(ws + o_z), T->t.R, d.n, d.K, d.L, d.Ls};
+  const u32 Ks = L.Ks, CW = L.CW;
+  u64 *sg = (u64 *)(ws + L.o_sg), *fm = (u64 *)(ws + L.o_fm), *cw = (u64 *)(ws + L.o_cw), *dout = (u64 *)(ws + L.o_out);
+  u32 *svlist = (u32 *)(ws + L.o_sv), *dq = (u32 *)(ws + L.o_q);
+  uint8_t *kind = ws + L.o_kind, *fc = ws + L.o_fc;
+  TabDev ts{(u64 *)(ws + L.o_x), (u64 *)(ws + L.o_z), T->t.R, d.n, d.K, d.L, d.Ls};
   // the blocked kernels run with a zeroed sign array (they then produce the
   // constants c(h)); the real signs live in the sign columns
-  u64 *cvec = (u64 *)(ws + o_cvec);
-  u32 *svt = (u32 *)(ws + o_svt);
-  MeasStats *sstats = (MeasStats *)(ws + o_stats);
+  u64 *cvec = (u64 *)(ws + L.o_cvec);
+  u32 *svt = (u32 *)(ws + L.o_svt);
+  MeasStats *sstats = (MeasStats *)(ws + L.o_stats);
   TabDev tb{ts.X, ts.Z, cvec, d.n, d.K, d.L, d.Ls};
-  const u32 cpc = rowsum_cpc(T);
-  const u32 max_chunks = cdiv(d.n, cpc);
+  const SymCtx sym{sg, svlist, kind, fm, fc, Ks, CW, count, 0};
   MeasState before{}, after{};
   sq_status s = SQ_OK;
   auto run = [&]() -> sq_status {
     HIP_TRY(hipMemcpyAsync(&before, T->st, sizeof(MeasState), hipMemcpyDeviceToHost, T->stream));
     HIP_TRY(hipMemcpyAsync(ts.X, T->t.X, (size_t)d.n * d.Ls * 8, hipMemcpyDeviceToDevice, T->stream));
     HIP_TRY(hipMemcpyAsync(ts.Z, T->t.Z, (size_t)d.n * d.Ls * 8, hipMemcpyDeviceToDevice, T->stream));
+    HIP_TRY(hipMemcpyAsync(dq, qubits, (size_t)count * 4, hipMemcpyHostToDevice, T->stream));
     HIP_TRY(launch_sample_init(T->t, sg, Ks, count, T->stream));
-    auto single = [&](u32 i) -> sq_status {
-      const u32 q = qubits[i];
-      SymCtx sym{sg, svlist, kind, fm, fc, Ks, CW, count, i};
-      SQ_TRY(timed(T, SQ_K_PIVOT, [&] {
-        return launch_pivot(ts, q, T->st, T->mask, seed, 0, 0, dummy, dummy + 1, T->stream);
-      }));
-      SQ_TRY(timed(T, SQ_K_GATHER, [&] {
-        return launch_gather(ts, T->st, T->pivx, T->pivz, T->cols, &sym, T->stream);
-      }));
-      SQ_TRY(timed(T, SQ_K_ROWSUM, [&] {
-        return launch_rowsum(ts, T->mask, T->cols, T->st, T->cnt0, T->cnt1, T->tun.rowsum_block, T->tun.rowsum_wpt,
-                             cpc, max_chunks, &sym, T->stream);
-      }));
-      SQ_TRY(timed(T, SQ_K_POST, [&] {
-        return launch_post(ts, q, T->mask, T->pivx, T->pivz, T->cnt0, T->cnt1, T->st, T->stats, dummy, cpc,
-                           det_cpw(T), &sym, T->stream);
-      }));
-      return SQ_OK;
-    };
-    // runs of random measurements up to meas_block at a time (as in
-    // measure_range), the deterministic ones one by one
-    const u32 kb = std::min<u32>(T->tun.meas_block, KB);
-    u32 i = 0, single_left = 0, backoff = 1;
-    while (i < count) {
-      const u32 want = std::min<u32>(kb, count - i);
-      if (want < 2 || single_left > 0) {
-        SQ_TRY(single(i));
-        ++i;
-        if (single_left > 0) --single_left;
-        continue;
-      }
-      BlkArgs a{};
-      a.k = want;
-      for (u32 s2 = 0; s2 < want; ++s2) a.q[s2] = qubits[i + s2];
-      a.seed = seed;
-      a.m0 = i;
-      HIP_TRY(launch_fill_zero(cvec, d.Ls, T->stream));
-      SQ_TRY(timed(T, SQ_K_BPIVOT, [&] {
-        return launch_blk_pivots(tb, a, T->blk, ws + o_bits, kind + i, T->tun.pivot_waves, T->stream);
-      }));
-      HIP_TRY(hipMemcpyAsync(T->blk_k_host, &T->blk.bs->k, sizeof(u32), hipMemcpyDeviceToHost, T->stream));
-      HIP_TRY(hipStreamSynchronize(T->stream));
-      const u32 k = *T->blk_k_host;
-      if (k > want) return fail(SQ_ESTATE, "blocked sampling sweep: bad block length %u", k);
-      if (k > 0) {
-        SQ_TRY(timed(T, SQ_K_BPREP, [&] { return launch_blk_prep(tb, a, T->blk, T->st, sstats, T->stream); }));
-        SQ_TRY(timed(T, SQ_K_BPASS, [&] { return launch_blk_pass(tb, T->blk, T->blk_cpc, T->stream); }));
-        SQ_TRY(timed(T, SQ_K_BFINAL, [&] {
-          return launch_blk_final(tb, a, T->blk, T->st, sstats, T->blk_cpc, T->stream);
-        }));
-        HIP_TRY(launch_blk_sv(sg, Ks, count, i, want, T->blk, svt, cvec, d.Ls, d.K, T->stream));
-        i += k;
-        backoff = 1;
-      } else {
-        single_left = backoff - 1;
-        backoff = std::min<u32>(2 * backoff, 64);
-      }
-      if (k < want) {  // measurement i is deterministic
-        SQ_TRY(single(i));
-        ++i;
-      }
-    }
+    // the sweep: outcomes are not written (a random measurement's outcome is
+    // its coin, a deterministic one an affine form), kind[] takes the flags
+    HIP_TRY(launch_cursor_init(T->cur, count, std::min<u32>(T->tun.meas_block, KB), seed, 0, 0, dq, nullptr, kind,
+                               T->stream));
+    SQ_TRY(run_sweep(T, SweepCtx{ts, tb, &sym, sstats, cvec, svt}, count));
     HIP_TRY(launch_coins(cw, seed, shot_begin, meas_base, shots, count, CW, T->stream));
     HIP_TRY(launch_eval(cw, kind, fm, fc, dout, shots, count, CW, T->stream));
     HIP_TRY(hipMemcpyAsync(host_out, dout, (size_t)shots * CW * 8, hipMemcpyDeviceToHost, T->stream));
@@ -760,6 +794,17 @@ sq_status sq_sample(sq_tableau *T, const uint32_t *qubits, uint32_t count, uint6
 namespace {
 constexpr u32 kBatchMaxN = 16384;
 constexpr u32 kBatchMaxCount = 32767;
+// Automatic: one workgroup per circuit pays off up to about a thousand
+// qubits; larger circuits finish sooner on the whole GPU (measured on the
+// MI355X on the batched/served mix: 1024 qubits and 8 streams 2.2 s, 4096
+// qubits 6.9 s).
+constexpr u32 kBatchAutoMaxN = 1024;
+
+// Whether sq_batch_sample runs an item in the persistent launch.
+bool batched_item(u32 n, u32 count, u32 block, u32 max_n) {
+  const u32 L = 2 * cdiv(n, 64);
+  return n <= max_n && count <= kBatchMaxCount && L <= 2 * block;
+}
 
 // One item through the single-tableau path: create, gates, sample, destroy.
 sq_status batch_item_plain(const sq_batch_item &it, hipStream_t stream) {
@@ -772,16 +817,27 @@ sq_status batch_item_plain(const sq_batch_item &it, hipStream_t stream) {
 }
 }  // namespace
 
+size_t sq_batch_item_bytes(uint32_t n, uint64_t nops, uint32_t count, uint32_t shots, const sq_batch_opts *opts) {
+  if (n == 0 || n > SQ_MAX_QUBITS || count == 0 || shots == 0) return 0;
+  const u32 block = opts && opts->block ? opts->block : 256;
+  const u32 max_n = std::min(opts && opts->max_batch_n ? opts->max_batch_n : kBatchAutoMaxN, kBatchMaxN);
+  const Dims d = dims_of(n);
+  auto r256 = [](size_t b) { return (b + 255) / 256 * 256; };
+  if (batched_item(n, count, block, max_n)) {
+    const size_t Ks = round_up(d.K, 16), CW = cdiv(count, 64);
+    return 2 * r256((size_t)n * d.Ls * 8) + r256((count + 1) * Ks * 8) + r256(count * CW * 8) +
+           2 * r256((size_t)shots * CW * 8) + 2 * r256(count) + 16 * nops + 4 * (size_t)count + sizeof(BatchItem) + 8;
+  }
+  SampleWs L;
+  return sq_bytes_required(n) + sample_ws(d, count, shots, &L) + 20 * nops + 32768;
+}
+
 sq_status sq_batch_sample(const sq_batch_item *items, uint32_t nitems, const sq_batch_opts *opts, void *hip_stream) {
   if (nitems == 0) return SQ_OK;
   if (!items) return fail(SQ_EINVAL, "items is NULL");
   hipStream_t stream = (hipStream_t)hip_stream;
   u32 block = opts && opts->block ? opts->block : 256;
-  // Automatic: one workgroup per circuit pays off up to about a thousand
-  // qubits; larger circuits finish sooner on the whole GPU (measured on the
-  // MI355X on the batched/served mix: 1024 qubits and 8 streams 2.2 s, 4096
-  // qubits 6.9 s).
-  u32 max_n = opts && opts->max_batch_n ? opts->max_batch_n : 1024;
+  u32 max_n = opts && opts->max_batch_n ? opts->max_batch_n : kBatchAutoMaxN;
   if (block % 64 || block < 64 || block > 512) return fail(SQ_EINVAL, "batch block must be a multiple of 64 in [64, 512]");
   max_n = std::min(max_n, kBatchMaxN);
   for (u32 k = 0; k < nitems; ++k) {
@@ -797,8 +853,7 @@ sq_status sq_batch_sample(const sq_batch_item *items, uint32_t nitems, const sq_
   for (u32 k = 0; k < nitems; ++k) {
     const sq_batch_item &it = items[k];
     if (it.count == 0 || it.shots == 0) continue;
-    const u32 L = 2 * cdiv(it.n, 64);
-    if (it.n <= max_n && it.count <= kBatchMaxCount && L <= 2 * block) small.push_back(k);
+    if (batched_item(it.n, it.count, block, max_n)) small.push_back(k);
     else large.push_back(k);
   }
   // largest first: cost ~ n^2 * count (rowsum sweep) + gates
@@ -1024,11 +1079,29 @@ sq_status sq_program_create(uint32_t n, const sq_op *ops, uint64_t count, sq_pro
   }
   P->passes = pb.passes;
   for (const PassRange &r : P->passes) P->gate_bytes += r.bytes;
+  if (!P->meas_qubits.empty()) {
+    if (P->meas_qubits.size() >= 0xFFFFFFFFull) {
+      delete P;
+      return fail(SQ_ERANGE, "a program holds at most 2^32 - 2 measurements");
+    }
+    if (hipMalloc((void **)&P->dev_meas, P->meas_qubits.size() * 4) != hipSuccess) {
+      (void)hipGetLastError();
+      delete P;
+      return fail(SQ_ENOMEM, "device allocation of %zu measured qubits failed", P->meas_qubits.size());
+    }
+    if (hipMemcpy(P->dev_meas, P->meas_qubits.data(), P->meas_qubits.size() * 4, hipMemcpyHostToDevice) !=
+        hipSuccess) {
+      (void)hipFree(P->dev_meas);
+      delete P;
+      return fail(SQ_EDEVICE, "upload of the measured qubits failed");
+    }
+  }
   if (!pb.offs.empty()) {
     if (hipMalloc((void **)&P->dev_words, pb.words.size() * 4) != hipSuccess ||
         hipMalloc((void **)&P->dev_offs, pb.offs.size() * 4) != hipSuccess) {
       (void)hipGetLastError();
       (void)hipFree(P->dev_words);
+      (void)hipFree(P->dev_meas);
       delete P;
       return fail(SQ_ENOMEM, "device allocation of %zu gate-pass words failed", pb.words.size() + pb.offs.size());
     }
@@ -1036,6 +1109,7 @@ sq_status sq_program_create(uint32_t n, const sq_op *ops, uint64_t count, sq_pro
         hipMemcpy(P->dev_offs, pb.offs.data(), pb.offs.size() * 4, hipMemcpyHostToDevice) != hipSuccess) {
       (void)hipFree(P->dev_words);
       (void)hipFree(P->dev_offs);
+      (void)hipFree(P->dev_meas);
       delete P;
       return fail(SQ_EDEVICE, "upload of gate passes failed");
     }
@@ -1074,6 +1148,7 @@ sq_status sq_program_destroy(sq_program *P) {
   if (!P) return SQ_OK;
   (void)hipFree(P->dev_words);
   (void)hipFree(P->dev_offs);
+  (void)hipFree(P->dev_meas);
   delete P;
   return SQ_OK;
 }
@@ -1087,28 +1162,15 @@ sq_status sq_run(sq_tableau *T, const sq_program *P, uint64_t seed, uint64_t sho
   if (!T || !P) return fail(SQ_EINVAL, "tableau or program is NULL");
   if (P->n != T->d.n) return fail(SQ_EINVAL, "program has n=%u, tableau n=%u", P->n, T->d.n);
   if (!P->meas_qubits.empty() && !dev_out_bits) return fail(SQ_EINVAL, "dev_out_bits is NULL");
-  // The random flags need a place to go; without a caller buffer they land in the handle's scratch.
-  uint8_t *rand_base = dev_out_random;
-  if (!rand_base && !P->meas_qubits.empty()) {
-    const size_t need = P->meas_qubits.size();
-    if (need > T->dev_out_cap) {
-      if (T->dev_out) (void)hipFreeAsync(T->dev_out, T->stream);
-      T->dev_out = nullptr;
-      T->dev_out_cap = 0;
-      if (hipMallocAsync((void **)&T->dev_out, need, T->stream) != hipSuccess) {
-        (void)hipGetLastError();
-        return fail(SQ_ENOMEM, "device allocation of %zu bytes failed", need);
-      }
-      T->dev_out_cap = need;
-    }
-    rand_base = T->dev_out;
-  }
+  const u32 kb = std::min<u32>(T->tun.meas_block, KB);
   for (const sq_program::Seg &s : P->segs) {
     if (s.kind == 0) {
       SQ_TRY(run_gate_segment(T, P, s.first, s.count));
     } else {
-      SQ_TRY(measure_range(T, P->meas_qubits.data(), s.first, s.first + s.count, seed, shot, meas_base,
-                           dev_out_bits, rand_base));
+      HIP_TRY(launch_cursor_init(T->cur, (u32)s.count, kb, seed, shot, meas_base + s.first, P->dev_meas + s.first,
+                                 dev_out_bits + s.first, dev_out_random ? dev_out_random + s.first : nullptr,
+                                 T->stream));
+      SQ_TRY(run_sweep(T, SweepCtx{T->t, T->t, nullptr, T->stats, nullptr, nullptr}, (u32)s.count));
     }
   }
   return SQ_OK;
