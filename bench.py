@@ -1,17 +1,37 @@
 #!/usr/bin/env python3
 """Throughput of the stabilizer-tableau hot path on one MI355X.
 
-Workload (the 180,000-qubit, depth-1000 generator circuit): each step resets
-the tableau to |0...0>, applies all 1000 random layers (about 198 million
-non-identity gates, fused into passes) and then performs the first M Z
-measurements (qubits 0..M-1 in order) of the circuit's final all-qubit
-measurement. Inputs (the compiled gate passes) are resident in HBM before
-timing starts; outcomes stay on the device.
+Timed step (the 180,000-qubit, depth-1000 generator circuit): reset to
+|0...0>, apply all 1000 random layers (about 198 million non-identity gates,
+fused into passes), then the first M Z measurements (qubits 0..M-1 in order)
+of the circuit's final all-qubit measurement. Inputs (the compiled gate
+passes and the measured list) are resident in HBM before timing starts;
+outcomes stay on the device.
 
-Prints one JSON line: gates/s of the gate phase as `value`, measurements/s of
-the measurement phase, the roofline of the dominant kernel (algorithmic bytes
-per launch / average launch duration, both measured here with HIP events on
-the library's stream) and the CPU oracle timed on a bounded sample.
+After the timed steps (not part of `value`):
+  * full_sweep: the same circuit once more with all 180,000 final
+    measurements (measurements/s over the whole sweep);
+  * deterministic: the first 1000 qubits measured again on the swept
+    tableau, every outcome deterministic;
+  * batched_served: the 512-request batched/served mix, all of it, on the
+    plain per-circuit path, the batched path, the serving loop (Poisson
+    arrivals) and the Pauli-frame path, plus sampling requests against
+    resident tableaux (sessions);
+  * cpu_baseline: the CPU oracle on a bounded sample of the timed workload.
+
+Every roofline entry gives the kernel's bandwidth two ways: `achieved` =
+the per-unit bytes of the method's cost model (a gate layer reads and writes
+the X and Z columns of every qubit it touches, plus the sign column; a
+random measurement reads and writes X and Z of every row word; a
+deterministic one reads n columns of the stabilizer half twice) times the
+units one launch processes, over the launch's average duration (HIP events
+on the library's stream); and `achieved_moved` = the bytes the launch
+actually streams (counted by the library) over the same duration. The two
+differ because a pass fuses about 2.4 generator layers and a blocked pass
+applies up to 32 measurements, so `frac` (cost-model bytes) can exceed 1;
+`frac_moved` is the physical fraction of HBM peak.
+
+Prints one JSON line.
 """
 from __future__ import annotations
 
@@ -28,14 +48,15 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, AMD public specification
 HBM_SUMMARY = "hbm_counters_n180000_bench.md"  # profiles/ summary of FETCH_SIZE / WRITE_SIZE on this workload
+METRIC = "gates/s & measurements/s at n=180k (HBM % of peak); batched vs plain shots/s"
 
 
 def log(msg: str):
     print(f"[bench {time.strftime('%H:%M:%S')}] {msg}", file=sys.stderr, flush=True)
 
 
-def build_ops(cfg, layers: int, nmeas: int):
-    from workload import OP_DTYPE, OP_MEASURE, iter_circuit
+def build_ops(cfg, layers: int):
+    from workload import OP_DTYPE, iter_circuit
     parts = []
     t0 = time.time()
     for k, (kind, arr) in enumerate(iter_circuit(cfg, depth=layers, final_measure=False)):
@@ -43,11 +64,43 @@ def build_ops(cfg, layers: int, nmeas: int):
         if (k + 1) % 200 == 0:
             log(f"generated {k + 1}/{layers} layers ({time.time() - t0:.1f} s)")
     gates = np.concatenate(parts) if parts else np.empty(0, dtype=OP_DTYPE)
-    meas = np.empty(nmeas, dtype=OP_DTYPE)
-    meas["type"] = OP_MEASURE
-    meas["q0"] = np.arange(nmeas, dtype=np.uint32)
-    meas["q1"] = 0
-    return gates, meas, parts
+    return gates, parts
+
+
+def meas_ops(qubits):
+    q = np.asarray(qubits, dtype=np.uint32)
+    return np.stack([np.full(q.size, 15, np.uint32), q, np.zeros(q.size, np.uint32)], 1)
+
+
+def layer_model_bytes(parts, n: int, L: int) -> int:
+    """Cost-model bytes of the gate layers: per layer, 4 column reads and
+    writes (X and Z) of every distinct qubit it touches plus the sign column
+    read and written, a column being L words of 8 bytes."""
+    C = 8 * L
+    total = 0
+    for arr in parts:
+        two = arr["type"] >= 7
+        touched = np.unique(np.concatenate([arr["q0"], arr["q1"][two]]))
+        total += touched.size * 4 * C + 2 * C
+    return total
+
+
+def roof(name, ms, launches, model_bytes, moved_bytes, unit_desc, traffic=None):
+    """A roofline entry from the total kernel time and launches (all timed
+    steps) and the bytes of those launches."""
+    launches = max(launches, 1)
+    avg_s = ms / launches * 1e-3
+    per_model = model_bytes / launches
+    per_moved = moved_bytes / launches
+    ach = per_model / avg_s / 1e9 if avg_s > 0 else 0.0
+    mov = per_moved / avg_s / 1e9 if avg_s > 0 else 0.0
+    return {"kernel": name, "bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": traffic,
+            "traffic_unit": "bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
+            "achieved_moved": round(mov, 1), "frac_moved": round(mov / HBM_PEAK_GBS, 4),
+            "bytes_per_launch": int(per_model), "moved_bytes_per_launch": int(per_moved),
+            "traffic_over_moved": round(traffic / per_moved, 3) if traffic and per_moved else None,
+            "model_unit": unit_desc, "avg_launch_ms": round(ms / launches, 4), "launches": int(launches)}
 
 
 def cpu_baseline(cfg, layer_parts, seconds: float, nrows: int = 64):
@@ -79,27 +132,172 @@ def cpu_baseline(cfg, layer_parts, seconds: float, nrows: int = 64):
     }
 
 
-def served_mix(nreq: int, budget_bytes: int):
-    """The batched/served workload on its first `nreq` requests: the plain
-    per-circuit path (one tableau at a time: create, gates, sq_sample), one
-    batched call over all of them, and the serving loop with Poisson arrivals
-    at 0.8 x the plain path's request rate. Returns shots/s of each and the
-    served p50/p99 latency."""
+# ---------------------------------------------------------------- the 180,000-qubit circuit
+def main_steps(args, sq, sqb, profsum, cfg, pg, pm, parts, L):
+    import torch
+    n = cfg.n
+    stream = torch.cuda.current_stream()
+    t = sq.Tableau(n, stream=stream)
+    out_bits = torch.zeros(max(args.meas, 1), dtype=torch.uint8, device="cuda")
+    out_rand = torch.zeros(max(args.meas, 1), dtype=torch.uint8, device="cuda")
+
+    def step(record=None):
+        t.reset()
+        if record:
+            record[0].record(stream)
+        t.run(pg, cfg.seed, 0, 0, out_bits.data_ptr(), out_rand.data_ptr())
+        if record:
+            record[1].record(stream)
+        if pm is not None:
+            t.run(pm, cfg.seed, 0, 0, out_bits.data_ptr(), out_rand.data_ptr())
+        if record:
+            record[2].record(stream)
+
+    for w in range(args.warmup):
+        step()
+        torch.cuda.synchronize()
+        log(f"warmup step {w + 1}/{args.warmup} done")
+    t.profile_reset()
+    t.profile(True)
+    events = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(args.steps)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        step(events[k])
+        if k + 1 < args.steps:
+            torch.cuda.synchronize()
+            log(f"step {k + 1}/{args.steps} done")
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    t.profile(False)
+    log(f"timed {args.steps} steps in {wall:.2f} s")
+    st1 = t.measure_stats()  # each step starts from reset, which clears the counters: one step
+    gate_ms = sum(e[0].elapsed_time(e[1]) for e in events)
+    meas_ms = sum(e[1].elapsed_time(e[2]) for e in events)
+    assert t.error_flags() == 0
+    kern = {name: t.profile_read(i) for i, name in enumerate(sqb.KERNEL_NAMES)}
+    layer_ms, layer_n = kern["layer"]
+    assert layer_n > 0
+    C = 8 * L
+    model_gate = layer_model_bytes(parts, n, L)
+    traffic = profsum.traffic_per_dispatch("k_layer", HBM_SUMMARY)
+    roofs = [roof("k_layer", layer_ms, layer_n, model_gate * args.steps, pg.gate_bytes * args.steps,
+                  f"gate layer: 4 C per distinct qubit touched + 2 C (C = {C} B); "
+                  f"{len(parts) / max(pg.num_passes, 1):.2f} layers per launch", traffic)]
+    if kern["block_pass"][1]:
+        nb = max(st1.blocks, 1)
+        roofs.append(roof("k_blk_pass", *kern["block_pass"], st1.n_random * 4 * n * C * args.steps,
+                          st1.block_bytes * args.steps,
+                          f"random measurement: 4 n C = {4 * n * C / 1e9:.1f} GB (every row word read and "
+                          f"written in X and Z); {st1.n_random / nb:.1f} measurements per launch",
+                          profsum.traffic_per_dispatch("k_blk_pass", HBM_SUMMARY)))
+    roofs.sort(key=lambda r: -r["avg_launch_ms"] * r["launches"])
+    res = {
+        "value": pg.num_gates * args.steps / (gate_ms * 1e-3),
+        "ms_per_step": wall * 1e3 / args.steps,
+        "measurements_per_s": args.meas * args.steps / (meas_ms * 1e-3) if args.meas else None,
+        "gate_phase_ms_per_step": gate_ms / args.steps,
+        "meas_phase_ms_per_step": meas_ms / args.steps,
+        "random_measurements_per_step": int(st1.n_random),
+        "measurement_blocks_per_step": int(st1.blocks),
+        "gate_model_bytes_per_step": int(model_gate),
+        "gate_moved_bytes_per_step": int(pg.gate_bytes),
+        "roofline": roofs[0],
+        "roofline_other": roofs[1:],
+        "kernel_ms": {k: round(v[0], 3) for k, v in kern.items()},
+        "kernel_launches": {k: v[1] for k, v in kern.items()},
+    }
+    return t, res
+
+
+def full_sweep(t, cfg, pg, sqb, L):
+    """All n final measurements once (after the gates), then the first 1000
+    again (deterministic)."""
+    import torch
+    n = cfg.n
+    C = 8 * L
+    stream = torch.cuda.current_stream()
+    out = torch.zeros(n, dtype=torch.uint8, device="cuda")
+    rnd = torch.zeros(n, dtype=torch.uint8, device="cuda")
+    sweep = sqb.Program(n, meas_ops(np.arange(n)))
+    t.reset()
+    t.run(pg, cfg.seed, 0, 0, out.data_ptr(), rnd.data_ptr())
+    torch.cuda.synchronize()
+    log("full sweep: gates done; measuring all qubits")
+    t.profile_reset()
+    t.profile(True)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    t.run(sweep, cfg.seed, 0, 0, out.data_ptr(), rnd.data_ptr())
+    e1.record(stream)
+    torch.cuda.synchronize()
+    t.profile(False)
+    ms = e0.elapsed_time(e1)
+    st = t.measure_stats()
+    kern = {name: t.profile_read(i) for i, name in enumerate(sqb.KERNEL_NAMES)}
+    assert t.error_flags() == 0
+    sweep.close()
+    log(f"full sweep: {n} measurements in {ms / 1e3:.2f} s")
+    res = {
+        "workload": f"all {n} final Z measurements of the n={n} depth-1000 circuit after its gates",
+        "measurements": n, "seconds": ms / 1e3, "measurements_per_s": n / (ms * 1e-3),
+        "random": int(st.n_random), "deterministic": int(st.n_det), "blocks": int(st.blocks),
+        "roofline": roof("k_blk_pass", *kern["block_pass"], st.n_random * 4 * n * C, st.block_bytes,
+                         f"random measurement: 4 n C = {4 * n * C / 1e9:.1f} GB; "
+                         f"{st.n_random / max(st.blocks, 1):.1f} measurements per launch"),
+        "kernel_ms": {k: round(v[0], 1) for k, v in kern.items()},
+    }
+    # deterministic: the first 1000 qubits again
+    k = min(1000, n)
+    again = sqb.Program(n, meas_ops(np.arange(k)))
+    out2 = torch.zeros(k, dtype=torch.uint8, device="cuda")
+    rnd2 = torch.zeros(k, dtype=torch.uint8, device="cuda")
+    st0 = t.measure_stats()
+    t.profile_reset()
+    t.profile(True)
+    e0.record(stream)
+    t.run(again, cfg.seed, 0, n, out2.data_ptr(), rnd2.data_ptr())
+    e1.record(stream)
+    torch.cuda.synchronize()
+    t.profile(False)
+    dms = e0.elapsed_time(e1)
+    st1 = t.measure_stats()
+    kern2 = {name: t.profile_read(i) for i, name in enumerate(sqb.KERNEL_NAMES)}
+    same = bool(torch.equal(out2, out[:k])) and not bool(rnd2.any())
+    assert same and t.error_flags() == 0, "re-measured outcomes differ or were random"
+    again.close()
+    ndet = st1.n_det - st0.n_det
+    det_moved = st1.det_bytes - st0.det_bytes
+    log(f"deterministic: {k} measurements in {dms / 1e3:.2f} s")
+    det = {
+        "workload": f"qubits 0..{k - 1} measured again after the full sweep (all deterministic)",
+        "measurements": k, "seconds": dms / 1e3, "measurements_per_s": k / (dms * 1e-3),
+        "deterministic": int(ndet), "outcomes_repeat": same,
+        "roofline": roof("k_post (deterministic)", *kern2["post"], ndet * n * C, det_moved,
+                         f"deterministic measurement: n C = {n * C / 1e9:.1f} GB (x and z of the stabilizer "
+                         f"half of every column read once)"),
+        "kernel_ms": {kk: round(v[0], 1) for kk, v in kern2.items()},
+    }
+    return res, det
+
+
+# ---------------------------------------------------------------- the batched/served mix
+def served_mix(nreq: int, budget_bytes: int, session_requests: int):
     import torch
     import paper_2603_14641_amd as sq
     from paper_2603_14641_amd import autotune, serving
     from workload import circuit_ops, served_requests
 
+    log(f"served mix: drawing {nreq} circuits")
     base = served_requests()[:nreq]
     reqs = []
     for r in base:
-        cfg = r.config()
-        ops = circuit_ops(cfg, final_measure=False)
+        ops = circuit_ops(r.config(), final_measure=False)
         ops = np.stack([ops["type"], ops["q0"], ops["q1"]], 1).astype(np.uint32)
-        reqs.append(dict(n=cfg.n, ops=ops, qubits=np.arange(cfg.n, dtype=np.uint32), shots=r.shots,
-                         seed=r.coin_seed))
+        reqs.append(dict(n=r.n, ops=ops, qubits=np.arange(r.n, dtype=np.uint32), shots=r.shots, seed=r.coin_seed))
     shots = sum(r["shots"] for r in reqs)
     log(f"served mix: {nreq} requests, {shots} shots; plain path")
+    torch.cuda.synchronize()
     t0 = time.perf_counter()
     plain_out = []
     for r in reqs:
@@ -108,14 +306,8 @@ def served_mix(nreq: int, budget_bytes: int):
         plain_out.append(t.sample(r["qubits"], r["shots"], seed=r["seed"]))
         t.close()
     plain_s = time.perf_counter() - t0
-    # Pauli-frame path (the paper's sampling mode): per request, one CHP run
-    # of the circuit with its final measurement for the reference sample, then
-    # the frames; same distribution as the per-shot CHP outcomes, other bits
     log(f"plain {plain_s:.2f} s; Pauli frames")
-    progs = []
-    for r in reqs:
-        meas = np.stack([np.full(r["n"], sq.MEASURE, np.uint32), r["qubits"], np.zeros(r["n"], np.uint32)], 1)
-        progs.append(sq.Program(r["n"], np.concatenate([r["ops"], meas])))
+    progs = [sq.Program(r["n"], np.concatenate([r["ops"], meas_ops(r["qubits"])])) for r in reqs]
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for r, pg in zip(reqs, progs):
@@ -134,34 +326,102 @@ def served_mix(nreq: int, budget_bytes: int):
     batch_out = sq.batch_sample(reqs, **kw)
     batch_s = time.perf_counter() - t0
     same = all(np.array_equal(a, b) for a, b in zip(plain_out, batch_out))
-    rate = 0.8 * nreq / plain_s
-    rng = np.random.Generator(np.random.PCG64(4))
-    arrivals = np.cumsum(rng.exponential(1.0 / rate, nreq))
-    sreqs = [serving.Request(rid=k, n=r["n"], ops=r["ops"], qubits=r["qubits"], shots=r["shots"], seed=r["seed"],
-                             arrival=float(a)) for k, (r, a) in enumerate(zip(reqs, arrivals))]
-    log(f"batched {batch_s:.2f} s; serving at {rate:.2f} requests/s")
-    st = serving.Server(budget_bytes=budget_bytes, workers=2, batch_kwargs=kw).run(sreqs)
-    same = same and all(np.array_equal(r.result, b) for r, b in zip(sreqs, batch_out))
-    log(f"served makespan {st.makespan_s:.2f} s, p50 {st.latency_p50_s:.3f} s, p99 {st.latency_p99_s:.3f} s")
-    return {
-        "workload": f"first {nreq} of the 512 batched/served requests (n log-uniform 16..16384, depth 10..500, "
-                    f"1..4096 shots, final all-qubit Z measurement)",
+    res = {
+        "workload": f"all {nreq} batched/served requests (n log-uniform 16..16384, depth 10..500, 1..4096 shots, "
+                    f"final all-qubit Z measurement)",
         "requests": nreq, "shots": shots,
-        "plain_shots_per_s": shots / plain_s,
-        "batched_shots_per_s": shots / batch_s,
-        "served_shots_per_s": st.shots_per_s,
+        "plain_s": plain_s, "plain_shots_per_s": shots / plain_s,
+        "batched_s": batch_s, "batched_shots_per_s": shots / batch_s,
         "batched_vs_plain": plain_s / batch_s,
-        "frame_shots_per_s": shots / frame_s,
+        "frame_s": frame_s, "frame_shots_per_s": shots / frame_s,
         "frame_note": "Pauli frames: reference CHP run plus frames per request, same distribution, other bits",
-        "served_arrival_rate_per_s": rate,
-        "served_latency_p50_s": st.latency_p50_s,
-        "served_latency_p99_s": st.latency_p99_s,
-        "served_batches": st.batches,
-        "served_mean_batch": st.mean_batch,
-        "served_budget_bytes": budget_bytes,
         "batch_schedule": dict(kw, tuned_on_requests=int(tuned["sample"])),
-        "outputs_identical_across_paths": bool(same),
+        "served": [],
     }
+    # the serving loop with Poisson arrivals: at 0.8 x the plain path's request
+    # rate (latency), and at 4 x (arrivals outpace service, so batches form)
+    for mult in (0.8, 4.0):
+        rate = mult * nreq / plain_s
+        rng = np.random.Generator(np.random.PCG64(4))
+        arrivals = np.cumsum(rng.exponential(1.0 / rate, nreq))
+        sreqs = [serving.CircuitRequest(n=r["n"], ops=r["ops"], qubits=r["qubits"], shots=r["shots"], seed=r["seed"],
+                                        arrival=float(a)) for r, a in zip(reqs, arrivals)]
+        log(f"serving at {rate:.2f} requests/s")
+        st = serving.Server(budget_bytes=budget_bytes, workers=2, batch_kwargs=kw).run(sreqs)
+        ok = all(r.ok for r in sreqs) and all(np.array_equal(r.result, b) for r, b in zip(sreqs, batch_out))
+        same = same and ok
+        log(f"served makespan {st.makespan_s:.2f} s, p50 {st.latency_p50_s:.3f} s, p99 {st.latency_p99_s:.3f} s, "
+            f"mean batch {st.mean_batch:.2f}")
+        res["served"].append({"arrival_rate_per_s": rate, "rate_over_plain": mult, "shots_per_s": st.shots_per_s,
+                              "makespan_s": st.makespan_s, "latency_p50_s": st.latency_p50_s,
+                              "latency_p99_s": st.latency_p99_s, "batches": st.batches,
+                              "mean_batch": st.mean_batch, "max_in_flight_bytes": st.max_in_flight_bytes,
+                              "budget_bytes": budget_bytes, "completed": st.completed})
+    if session_requests > 0:
+        res["sessions"] = sessions_run(reqs, session_requests, budget_bytes)
+        same = same and res["sessions"]["served_equals_alone"]
+    res["outputs_identical_across_paths"] = bool(same)
+    return res
+
+
+def sessions_run(reqs, nsample: int, budget_bytes: int):
+    """Resident tableaux: 16 of the mix's circuits opened as sessions, then
+    `nsample` sampling requests (Poisson, each on a random session, shots
+    log-uniform 1..4096) served with per-session batching (queued requests
+    on one session share one measurement sweep), against the same requests
+    run one by one on the same resident tableaux."""
+    import torch
+    import paper_2603_14641_amd as sq
+    from paper_2603_14641_amd import serving
+
+    pick = [r for r in reqs if 1024 <= r["n"] <= 8192][:16]
+    rng = np.random.Generator(np.random.PCG64(44))
+    draws = [(int(rng.integers(len(pick))), int(round(np.exp(rng.uniform(0, np.log(4096))))), int(rng.integers(1 << 30)))
+             for _ in range(nsample)]
+    # alone: every request by itself on the resident tableau
+    tabs = []
+    for r in pick:
+        t = sq.Tableau(r["n"])
+        t.apply_gates(r["ops"])
+        tabs.append(t)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    alone = [tabs[k].sample(pick[k]["qubits"], s, seed=seed) for k, s, seed in draws]
+    alone_s = time.perf_counter() - t0
+    for t in tabs:
+        t.close()
+    shots = sum(s for _, s, _ in draws)
+    log(f"sessions: {nsample} sampling requests alone in {alone_s:.2f} s; serving")
+    # served: open the sessions, then the requests at 2 x the alone rate
+    rate = 2.0 * nsample / alone_s
+    arr = np.cumsum(rng.exponential(1.0 / rate, nsample))
+    srv = serving.Server(budget_bytes=budget_bytes, workers=2)
+    srv.start()
+    opens = [srv.submit(serving.OpenSession(session=f"s{k}", n=r["n"], ops=r["ops"])) for k, r in enumerate(pick)]
+    while any(o.state not in ("done", "failed") for o in opens):
+        time.sleep(0.01)
+    base = srv._now()
+    sreqs = [serving.SampleRequest(session=f"s{k}", qubits=pick[k]["qubits"], shots=s, seed=seed, arrival=base + a)
+             for (k, s, seed), a in zip(draws, arr)]
+    for r in sreqs:
+        delay = r.arrival - srv._now()
+        if delay > 0:
+            time.sleep(delay)
+        srv.submit(r)
+    for k in range(len(pick)):
+        srv.submit(serving.CloseSession(session=f"s{k}"))
+    srv.stop()
+    st = srv.stats(sreqs)
+    equal = all(r.ok for r in sreqs) and all(np.array_equal(r.result, a) for r, a in zip(sreqs, alone))
+    sweeps = srv.batch_sizes("sample")
+    log(f"sessions served: {st.shots_per_s:.3g} shots/s vs alone {shots / alone_s:.3g}, "
+        f"{len(sweeps)} sweeps for {nsample} requests")
+    return {"sessions": len(pick), "session_n": [r["n"] for r in pick], "sampling_requests": nsample, "shots": shots,
+            "alone_s": alone_s, "alone_shots_per_s": shots / alone_s, "arrival_rate_per_s": rate,
+            "served_shots_per_s": st.shots_per_s, "served_makespan_s": st.makespan_s,
+            "latency_p50_s": st.latency_p50_s, "latency_p99_s": st.latency_p99_s,
+            "requests_per_sweep_mean": float(np.mean(sweeps)) if sweeps else 0.0, "sweeps": len(sweeps),
+            "served_equals_alone": bool(equal)}
 
 
 def stream_ceiling():
@@ -200,8 +460,11 @@ def main():
     ap.add_argument("--meas", type=int, default=1000)
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--served-requests", type=int, default=48,
-                    help="requests of the batched/served mix to time (0 skips that part)")
+    ap.add_argument("--no-full-sweep", action="store_true", help="skip the full 180,000-measurement sweep")
+    ap.add_argument("--served-requests", type=int, default=512,
+                    help="requests of the batched/served mix to run (0 skips that part)")
+    ap.add_argument("--session-requests", type=int, default=96,
+                    help="sampling requests against resident tableaux (0 skips)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="first run a plain 1 GiB device copy (scale reference for HBM byte counters)")
     args = ap.parse_args()
@@ -229,93 +492,22 @@ def main():
         log("copy calibration: 3 copies of 1 GiB done")
     cfg = CONFIGS[4]
     n = cfg.n
+    L = sqb.layout(n)["L"]
     log(f"generating {args.layers} layers of n={n}")
-    gates, meas, layer_parts = build_ops(cfg, args.layers, args.meas)
+    gates, parts = build_ops(cfg, args.layers)
     log(f"{gates.size} gates; compiling")
     pg = sq.Program(n, gates)
-    pm = sq.Program(n, meas)
-    log(f"{pg.num_passes} gate passes, {pg.gate_bytes / 1e9:.1f} GB algorithmic per step")
-    stream = torch.cuda.current_stream()
-    t = sq.Tableau(n, stream=stream)
-    out_bits = torch.zeros(max(args.meas, 1), dtype=torch.uint8, device="cuda")
-    out_rand = torch.zeros(max(args.meas, 1), dtype=torch.uint8, device="cuda")
-
-    def step(record=None):
-        t.reset()
-        if record:
-            record[0].record(stream)
-        t.run(pg, cfg.seed, 0, 0, out_bits.data_ptr(), out_rand.data_ptr())
-        if record:
-            record[1].record(stream)
-        t.run(pm, cfg.seed, 0, 0, out_bits.data_ptr(), out_rand.data_ptr())
-        if record:
-            record[2].record(stream)
-
-    for w in range(args.warmup):
-        step()
-        torch.cuda.synchronize()
-        log(f"warmup step {w + 1}/{args.warmup} done")
-
-    t.profile_reset()
-    t.profile(True)
-    events = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(args.steps)]
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for k in range(args.steps):
-        step(events[k])
-        if k + 1 < args.steps:
-            torch.cuda.synchronize()
-            log(f"step {k + 1}/{args.steps} done")
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    t.profile(False)
-    log(f"timed {args.steps} steps in {wall:.2f} s")
-    # Each step starts from reset (which also clears the byte accounting) and
-    # does identical work, so the counters now hold exactly one step.
-    st1 = t.measure_stats()
-    gate_ms = sum(e[0].elapsed_time(e[1]) for e in events)
-    meas_ms = sum(e[1].elapsed_time(e[2]) for e in events)
-    assert t.error_flags() == 0
-
-    kern = {name: t.profile_read(i) for i, name in enumerate(sqb.KERNEL_NAMES)}
-    assert kern["layer"][1] > 0
-    layer_ms, layer_n = kern["layer"]
-    n_random = st1.n_random
-
-    def roof(name, ms, launches, total_bytes):
-        per = total_bytes / max(launches, 1)
-        gbs = per / (ms / launches * 1e-3) / 1e9 if launches else 0.0
-        # HBM bytes per launch from the committed rocprofv3 counter summary of
-        # this workload (its first layers and measurements), or None if that
-        # kernel's source changed since or the run measures far beyond the
-        # start of the sweep, where a block's bytes differ
-        traffic = profsum.traffic_per_dispatch(name, HBM_SUMMARY) if args.meas <= 1000 else None
-        return {"kernel": name, "bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(gbs / HBM_PEAK_GBS, 4), "traffic": traffic, "traffic_unit": "bytes per launch",
-                "traffic_over_algorithmic": round(traffic / per, 3) if traffic and per else None,
-                "bytes_per_launch": int(per),
-                "avg_launch_ms": round(ms / max(launches, 1), 4), "launches_per_step": launches // args.steps,
-                "ms_per_step": round(ms / args.steps, 3)}
-
-    # The library's byte counters hold one step (each step starts from reset);
-    # the profile holds all timed steps.
-    roofs = [roof("k_layer", layer_ms, layer_n, pg.gate_bytes * args.steps)]
-    if kern["block_pass"][1]:
-        roofs.append(roof("k_blk_pass", *kern["block_pass"], st1.block_bytes * args.steps))
-    if kern["rowsum"][1]:
-        roofs.append(roof("k_rowsum", *kern["rowsum"], st1.rowsum_bytes * args.steps))
-    roofs.sort(key=lambda r: -r["ms_per_step"])
-    dominant, others = roofs[0], roofs[1:]
-
-    gates_per_step = int(pg.num_gates)
+    pm = sq.Program(n, meas_ops(np.arange(args.meas))) if args.meas else None
+    log(f"{pg.num_passes} gate passes, {pg.gate_bytes / 1e9:.1f} GB moved per step")
+    t, res = main_steps(args, sq, sqb, profsum, cfg, pg, pm, parts, L)
     result = {
-        "metric": "gates/s & measurements/s at n=180k (HBM % of peak); batched vs plain shots/s",
-        "value": gates_per_step * args.steps / (gate_ms * 1e-3),
+        "metric": METRIC,
+        "value": res.pop("value"),
         "unit": "gates/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": wall * 1e3 / args.steps,
+        "ms_per_step": res.pop("ms_per_step"),
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
@@ -324,26 +516,25 @@ def main():
         "config": {
             "workload": f"n=180000 generator circuit (seed {cfg.seed}): {args.layers} layers + first "
                         f"{args.meas} of the final 180000 Z-measurements per step",
-            "n": n, "layers": args.layers, "gates_per_step": gates_per_step, "passes_per_step": pg.num_passes,
+            "n": n, "layers": args.layers, "gates_per_step": int(pg.num_gates), "passes_per_step": pg.num_passes,
             "measurements_per_step": args.meas,
         },
-        "measurements_per_s": args.meas * args.steps / (meas_ms * 1e-3),
-        "gate_phase_ms_per_step": gate_ms / args.steps,
-        "meas_phase_ms_per_step": meas_ms / args.steps,
-        "random_measurements_per_step": int(n_random),
-        "measurement_blocks_per_step": int(st1.blocks),
-        "roofline": dominant,
-        "roofline_other": others,
-        "kernel_ms": {k: round(v[0], 3) for k, v in kern.items()},
-        "kernel_launches": {k: v[1] for k, v in kern.items()},
     }
+    result.update(res)
+    if not args.no_full_sweep and args.layers == 1000:
+        result["full_sweep"], result["deterministic"] = full_sweep(t, cfg, pg, sqb, L)
     t.close()
+    pg.close()
+    if pm is not None:
+        pm.close()
+    torch.cuda.synchronize()
+    torch.cuda.empty_cache()
     result["hbm_stream_ceiling_gbs"] = stream_ceiling()
     if args.served_requests > 0:
-        result["batched_served"] = served_mix(args.served_requests, budget_bytes=8 << 30)
+        result["batched_served"] = served_mix(args.served_requests, 8 << 30, args.session_requests)
     if not args.no_cpu_baseline:
         log(f"CPU oracle baseline (~{args.cpu_seconds:.0f} s)")
-        result["cpu_baseline"] = cpu_baseline(cfg, layer_parts, args.cpu_seconds)
+        result["cpu_baseline"] = cpu_baseline(cfg, parts, args.cpu_seconds)
     else:
         result["cpu_baseline"] = None
     print(json.dumps(result), flush=True)

@@ -196,6 +196,25 @@ sq_status sq_sample(sq_tableau *t, const uint32_t *host_qubits, uint32_t count, 
 /*   Defined by: the many-shot workload of the "Sampling" section, each shot
  *   with the per-shot semantics of "The CHP algorithm". */
 
+/* Several shot sets of the same measured list on the current state, sharing
+ * one measurement sweep (which depends on the list, not on the coins): set k
+ * gives exactly what sq_sample(t, host_qubits, count, sets[k].seed,
+ * sets[k].shot_begin, sets[k].shots, sets[k].meas_base, sets[k].out) gives.
+ * The tableau is unchanged. Scratch as sq_sample with the largest set's shot
+ * count (sq_sample_bytes). Blocks. Errors as sq_sample.
+ * Defined by: as sq_sample. */
+typedef struct {
+  uint64_t seed, shot_begin, meas_base;
+  uint32_t shots, pad;
+  uint64_t *out;   /* host, shots * ceil(count/64) words */
+} sq_shot_set;
+sq_status sq_sample_many(sq_tableau *t, const uint32_t *host_qubits, uint32_t count, const sq_shot_set *sets,
+                         uint32_t nsets);
+/* Device scratch bytes sq_sample (and sq_sample_many) allocate for a tableau
+ * of n qubits, count measured qubits and `shots` shots. Host only; 0 for n
+ * out of range. */
+size_t sq_sample_bytes(uint32_t n, uint32_t count, uint32_t shots);
+
 /* Batched sampling of many independent circuits (the batched/served
  * workload: circuits of uneven size, each with its own shot count).
  * Item k is, bit for bit, the result of sq_create(n), sq_apply_gates(ops),

@@ -33,7 +33,7 @@ EXPORTED = [
     "sq_run", "sq_export_rows", "sq_export", "sq_import", "sq_measure_stats", "sq_error_flags",
     "sq_get_tuning", "sq_set_tuning", "sq_profile_enable", "sq_profile_read", "sq_profile_reset",
     "sq_qasm_parse", "sq_frame_sample", "sq_set_graphs", "sq_graph_stats",
-    "sq_create_in", "sq_layout", "sq_batch_item_bytes",
+    "sq_create_in", "sq_layout", "sq_batch_item_bytes", "sq_sample_many", "sq_sample_bytes",
 ]
 
 
@@ -65,6 +65,11 @@ class LayoutInfo(ctypes.Structure):
     _fields_ = [("n", ctypes.c_uint32), ("K", ctypes.c_uint32), ("L", ctypes.c_uint32), ("Ls", ctypes.c_uint32),
                 ("x_offset", ctypes.c_uint64), ("z_offset", ctypes.c_uint64), ("r_offset", ctypes.c_uint64),
                 ("bytes", ctypes.c_uint64)]
+
+
+class ShotSet(ctypes.Structure):
+    _fields_ = [("seed", ctypes.c_uint64), ("shot_begin", ctypes.c_uint64), ("meas_base", ctypes.c_uint64),
+                ("shots", ctypes.c_uint32), ("pad", ctypes.c_uint32), ("out", ctypes.c_void_p)]
 
 
 class MeasStats(ctypes.Structure):
@@ -102,6 +107,8 @@ def load(path: str = LIB_PATH):
         "sq_create_in": (i32, [u32, vp, ctypes.c_size_t, vp, pvp]),
         "sq_layout": (i32, [u32, ctypes.POINTER(LayoutInfo)]),
         "sq_batch_item_bytes": (ctypes.c_size_t, [u32, u64, u32, u32, ctypes.POINTER(BatchOpts)]),
+        "sq_sample_many": (i32, [vp, vp, u32, ctypes.POINTER(ShotSet), u32]),
+        "sq_sample_bytes": (ctypes.c_size_t, [u32, u32, u32]),
         "sq_destroy": (i32, [vp]),
         "sq_reset": (i32, [vp]),
         "sq_sync": (i32, [vp]),
@@ -277,6 +284,26 @@ class Tableau:
         _check(self.lib.sq_sample(self.h, q.ctypes.data, q.size, seed, shot_begin, int(shots), meas_base,
                                   out.ctypes.data))
         return out[:int(shots), :W]
+
+    def sample_many(self, qubits: Sequence[int], sets) -> list:
+        """Several shot sets (dicts with shots and optional seed, shot_begin,
+        meas_base) of one measured list, sharing one sweep (sq_sample_many).
+        Returns one (shots, ceil(count/64)) uint64 array per set."""
+        q = np.ascontiguousarray(np.asarray(qubits, dtype=np.uint32).reshape(-1))
+        W = (q.size + 63) // 64
+        arr = (ShotSet * max(len(sets), 1))()
+        outs = []
+        for k, e in enumerate(sets):
+            shots = int(e["shots"])
+            out = np.zeros((max(shots, 1), max(W, 1)), dtype=np.uint64)
+            outs.append(out)
+            arr[k].seed = int(e.get("seed", 0))
+            arr[k].shot_begin = int(e.get("shot_begin", 0))
+            arr[k].meas_base = int(e.get("meas_base", 0))
+            arr[k].shots = shots
+            arr[k].out = out.ctypes.data
+        _check(self.lib.sq_sample_many(self.h, q.ctypes.data, q.size, arr, len(sets)))
+        return [o[:int(e["shots"]), :W] for o, e in zip(outs, sets)]
 
     def sample_bits(self, qubits: Sequence[int], shots: int, seed: int = 0, shot_begin: int = 0,
                     meas_base: int = 0) -> np.ndarray:
@@ -460,6 +487,11 @@ def layout(n: int) -> dict:
     info = LayoutInfo()
     _check(load().sq_layout(int(n), ctypes.byref(info)))
     return {name: int(getattr(info, name)) for name, _ in LayoutInfo._fields_}
+
+
+def sample_bytes(n: int, count: int, shots: int) -> int:
+    """Device scratch bytes of sq_sample / sq_sample_many (sq_sample_bytes)."""
+    return int(load().sq_sample_bytes(int(n), int(count), int(shots)))
 
 
 def batch_item_bytes(n: int, nops: int, count: int, shots: int, block: int = 0, max_batch_n: int = 0) -> int:

@@ -594,10 +594,15 @@ __global__ __launch_bounds__(BLK_PASS_T) void k_blk_pass(u64 *__restrict__ X, u6
   u64 yy = 0;          // z_{C_h} . x_h per row: XOR over columns of dz & x
   u64 d0 = 0, d1 = 0;  // |x & z| - |x' & z'| (mod 4), bit-sliced
   // the row word of the next two columns is loaded ahead (the stores to
-  // column j cannot alias them, which the compiler cannot see by itself)
-  u64 xa = __builtin_nontemporal_load(X + (size_t)j0 * Ls + w);
-  u64 za = __builtin_nontemporal_load(Z + (size_t)j0 * Ls + w), xb = 0, zb = 0;
-  if (j0 + 1 < j1) {
+  // column j cannot alias them, which the compiler cannot see by itself);
+  // columns where every pivot is the identity are neither loaded nor stored
+  auto supported = [&](u32 j) { return (patx[j] | patz[j]) != 0u; };  // uniform over the wave
+  u64 xa = 0, za = 0, xb = 0, zb = 0;
+  if (supported(j0)) {
+    xa = __builtin_nontemporal_load(X + (size_t)j0 * Ls + w);
+    za = __builtin_nontemporal_load(Z + (size_t)j0 * Ls + w);
+  }
+  if (j0 + 1 < j1 && supported(j0 + 1)) {
     xb = __builtin_nontemporal_load(X + (size_t)(j0 + 1) * Ls + w);
     zb = __builtin_nontemporal_load(Z + (size_t)(j0 + 1) * Ls + w);
   }
@@ -606,7 +611,7 @@ __global__ __launch_bounds__(BLK_PASS_T) void k_blk_pass(u64 *__restrict__ X, u6
     const u64 x = xa, z = za;
     xa = xb;
     za = zb;
-    if (j + 2 < j1) {
+    if (j + 2 < j1 && supported(j + 2)) {
       xb = __builtin_nontemporal_load(X + o + 2 * (size_t)Ls);
       zb = __builtin_nontemporal_load(Z + o + 2 * (size_t)Ls);
     }

@@ -701,13 +701,48 @@ sq_status sq_apply_gates(sq_tableau *T, const sq_op *ops, uint64_t count) {
   return run_passes(T, T->dev_words, T->dev_offs, pb.passes, 0, pb.passes.size());
 }
 
-sq_status sq_measure(sq_tableau *T, const uint32_t *qubits, uint32_t count, uint64_t seed, uint64_t shot,
-                     uint64_t meas_base, uint8_t *out_bits, uint8_t *out_random) {
+}  // extern "C"
+
+namespace {
+
+// The measurement of a host list through device buffers the caller provides:
+// dq (count words) for the list, dout (2 * count bytes) for outcomes and
+// random flags. Copies the list in, sweeps, copies the results out, checks
+// the device flags.
+sq_status measure_list(sq_tableau *T, const uint32_t *qubits, uint32_t count, uint64_t seed, uint64_t shot,
+                       uint64_t meas_base, uint8_t *out_bits, uint8_t *out_random, u32 *dq, uint8_t *dout) {
+  MeasState before{}, after{};
+  HIP_TRY(hipMemcpyAsync(&before, T->st, sizeof(MeasState), hipMemcpyDeviceToHost, T->stream));
+  HIP_TRY(hipMemcpyAsync(dq, qubits, (size_t)count * 4, hipMemcpyHostToDevice, T->stream));
+  HIP_TRY(launch_cursor_init(T->cur, count, std::min<u32>(T->tun.meas_block, KB), seed, shot, meas_base, dq, dout,
+                             dout + count, T->stream));
+  SQ_TRY(run_sweep(T, SweepCtx{T->t, T->t, nullptr, T->stats, nullptr, nullptr}, count));
+  HIP_TRY(hipMemcpyAsync(out_bits, dout, count, hipMemcpyDeviceToHost, T->stream));
+  if (out_random) HIP_TRY(hipMemcpyAsync(out_random, dout + count, count, hipMemcpyDeviceToHost, T->stream));
+  HIP_TRY(hipMemcpyAsync(&after, T->st, sizeof(MeasState), hipMemcpyDeviceToHost, T->stream));
+  HIP_TRY(hipStreamSynchronize(T->stream));
+  if (after.flags != before.flags)
+    return fail(SQ_ESTATE, "device consistency check failed (flags 0x%x)", after.flags);
+  return SQ_OK;
+}
+
+sq_status check_measure_args(sq_tableau *T, const uint32_t *qubits, uint32_t count, uint8_t *out_bits) {
   if (!T) return fail(SQ_EINVAL, "tableau is NULL");
   if (count == 0) return SQ_OK;
   if (!qubits || !out_bits) return fail(SQ_EINVAL, "qubits/out_bits is NULL");
   for (u32 i = 0; i < count; ++i)
     if (qubits[i] >= T->d.n) return fail(SQ_ERANGE, "qubit %u >= n=%u", qubits[i], T->d.n);
+  return SQ_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+sq_status sq_measure(sq_tableau *T, const uint32_t *qubits, uint32_t count, uint64_t seed, uint64_t shot,
+                     uint64_t meas_base, uint8_t *out_bits, uint8_t *out_random) {
+  SQ_TRY(check_measure_args(T, qubits, count, out_bits));
+  if (count == 0) return SQ_OK;
   const size_t need = 2 * (size_t)count;
   if (need > T->dev_out_cap) {
     if (T->dev_out) (void)hipFreeAsync(T->dev_out, T->stream);
@@ -720,27 +755,32 @@ sq_status sq_measure(sq_tableau *T, const uint32_t *qubits, uint32_t count, uint
     T->dev_out_cap = need;
   }
   SQ_TRY(ensure_capacity(T, &T->dev_q, &T->dev_q_cap, count));
-  MeasState before{}, after{};
-  HIP_TRY(hipMemcpyAsync(&before, T->st, sizeof(MeasState), hipMemcpyDeviceToHost, T->stream));
-  HIP_TRY(hipMemcpyAsync(T->dev_q, qubits, (size_t)count * 4, hipMemcpyHostToDevice, T->stream));
-  HIP_TRY(launch_cursor_init(T->cur, count, std::min<u32>(T->tun.meas_block, KB), seed, shot, meas_base, T->dev_q,
-                             T->dev_out, T->dev_out + count, T->stream));
-  SQ_TRY(run_sweep(T, SweepCtx{T->t, T->t, nullptr, T->stats, nullptr, nullptr}, count));
-  HIP_TRY(hipMemcpyAsync(out_bits, T->dev_out, count, hipMemcpyDeviceToHost, T->stream));
-  if (out_random)
-    HIP_TRY(hipMemcpyAsync(out_random, T->dev_out + count, count, hipMemcpyDeviceToHost, T->stream));
-  HIP_TRY(hipMemcpyAsync(&after, T->st, sizeof(MeasState), hipMemcpyDeviceToHost, T->stream));
-  HIP_TRY(hipStreamSynchronize(T->stream));
-  if (after.flags != before.flags)
-    return fail(SQ_ESTATE, "device consistency check failed (flags 0x%x)", after.flags);
-  return SQ_OK;
+  return measure_list(T, qubits, count, seed, shot, meas_base, out_bits, out_random, T->dev_q, T->dev_out);
 }
 
 sq_status sq_sample(sq_tableau *T, const uint32_t *qubits, uint32_t count, uint64_t seed, uint64_t shot_begin,
                     uint32_t shots, uint64_t meas_base, uint64_t *host_out) {
+  const sq_shot_set one{seed, shot_begin, meas_base, shots, 0, host_out};
+  return sq_sample_many(T, qubits, count, &one, 1);
+}
+
+size_t sq_sample_bytes(uint32_t n, uint32_t count, uint32_t shots) {
+  if (n == 0 || n > SQ_MAX_QUBITS) return 0;
+  SampleWs L;
+  return sample_ws(dims_of(n), count, shots, &L);
+}
+
+sq_status sq_sample_many(sq_tableau *T, const uint32_t *qubits, uint32_t count, const sq_shot_set *sets,
+                         uint32_t nsets) {
   if (!T) return fail(SQ_EINVAL, "tableau is NULL");
+  if (nsets && !sets) return fail(SQ_EINVAL, "sets is NULL");
+  u32 shots = 0;  // the largest set sizes the coin and outcome buffers
+  for (u32 k = 0; k < nsets; ++k) {
+    if (sets[k].shots && !sets[k].out) return fail(SQ_EINVAL, "set %u: out is NULL", k);
+    shots = std::max(shots, sets[k].shots);
+  }
   if (count == 0 || shots == 0) return SQ_OK;
-  if (!qubits || !host_out) return fail(SQ_EINVAL, "qubits/host_out is NULL");
+  if (!qubits) return fail(SQ_EINVAL, "qubits is NULL");
   for (u32 i = 0; i < count; ++i)
     if (qubits[i] >= T->d.n) return fail(SQ_ERANGE, "qubit %u >= n=%u", qubits[i], T->d.n);
   const Dims &d = T->d;
@@ -773,12 +813,17 @@ sq_status sq_sample(sq_tableau *T, const uint32_t *qubits, uint32_t count, uint6
     HIP_TRY(launch_sample_init(T->t, sg, Ks, count, T->stream));
     // the sweep: outcomes are not written (a random measurement's outcome is
     // its coin, a deterministic one an affine form), kind[] takes the flags
-    HIP_TRY(launch_cursor_init(T->cur, count, std::min<u32>(T->tun.meas_block, KB), seed, 0, 0, dq, nullptr, kind,
+    HIP_TRY(launch_cursor_init(T->cur, count, std::min<u32>(T->tun.meas_block, KB), 0, 0, 0, dq, nullptr, kind,
                                T->stream));
     SQ_TRY(run_sweep(T, SweepCtx{ts, tb, &sym, sstats, cvec, svt}, count));
-    HIP_TRY(launch_coins(cw, seed, shot_begin, meas_base, shots, count, CW, T->stream));
-    HIP_TRY(launch_eval(cw, kind, fm, fc, dout, shots, count, CW, T->stream));
-    HIP_TRY(hipMemcpyAsync(host_out, dout, (size_t)shots * CW * 8, hipMemcpyDeviceToHost, T->stream));
+    // per shot set: its coins, its outcomes, its copy out (the sweep is shared)
+    for (u32 k = 0; k < nsets; ++k) {
+      const sq_shot_set &e = sets[k];
+      if (e.shots == 0) continue;
+      HIP_TRY(launch_coins(cw, e.seed, e.shot_begin, e.meas_base, e.shots, count, CW, T->stream));
+      HIP_TRY(launch_eval(cw, kind, fm, fc, dout, e.shots, count, CW, T->stream));
+      HIP_TRY(hipMemcpyAsync(e.out, dout, (size_t)e.shots * CW * 8, hipMemcpyDeviceToHost, T->stream));
+    }
     HIP_TRY(hipMemcpyAsync(&after, T->st, sizeof(MeasState), hipMemcpyDeviceToHost, T->stream));
     HIP_TRY(hipStreamSynchronize(T->stream));
     return SQ_OK;
