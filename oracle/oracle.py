@@ -16,6 +16,7 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "chp_oracle.c")
+_STIM_SRC = os.path.join(_HERE, "stim_oracle.c")
 _LIB = os.path.join(_HERE, "libsq_oracle.so")
 
 # Operation type codes (records of three uint32: type, q0, q1).
@@ -23,10 +24,10 @@ I, H, S, SDG, X, Y, Z, CX, CZ, CY, SWAP, ISWAP, MEASURE = 0, 1, 2, 3, 4, 5, 6, 7
 TWO_QUBIT = (CX, CZ, CY, SWAP, ISWAP)
 
 
-def build_oracle(src: str = _SRC, out: str = _LIB, extra_flags: Sequence[str] = ()) -> str:
-    """Compile the oracle with gcc (always recompiles)."""
+def build_oracle(src: str = _SRC, out: str = _LIB, extra_flags: Sequence[str] = (), stim_src: str = _STIM_SRC) -> str:
+    """Compile the oracle (the CHP tableau and the operator-tableau collapse) with gcc (always recompiles)."""
     tmp = out + ".tmp"
-    cmd = ["gcc", "-O2", "-std=c11", "-fopenmp", "-fPIC", "-shared", *extra_flags, src, "-o", tmp]
+    cmd = ["gcc", "-O2", "-std=c11", "-fopenmp", "-fPIC", "-shared", *extra_flags, src, stim_src, "-o", tmp]
     subprocess.run(cmd, check=True)
     os.replace(tmp, out)
     return out
@@ -74,6 +75,20 @@ def _bind(lib):
     lib.sqo_gsum_word.argtypes = [u64, u64, u64, u64]
     lib.sqo_num_threads.restype = ctypes.c_int
     lib.sqo_num_threads.argtypes = []
+    lib.sqo_otab_create.restype = vp
+    lib.sqo_otab_create.argtypes = [u32]
+    lib.sqo_otab_destroy.restype = None
+    lib.sqo_otab_destroy.argtypes = [vp]
+    lib.sqo_otab_odd_count.restype = u64
+    lib.sqo_otab_odd_count.argtypes = [vp]
+    lib.sqo_otab_run.restype = i64
+    lib.sqo_otab_run.argtypes = [vp, vp, u64, u64, u64, u64, vp, vp]
+    lib.sqo_otab_get.restype = None
+    lib.sqo_otab_get.argtypes = [vp] * 7
+    lib.sqo_otab_set.restype = None
+    lib.sqo_otab_set.argtypes = [vp] * 7
+    lib.sqo_otab_image.restype = ctypes.c_int
+    lib.sqo_otab_image.argtypes = [vp, vp, vp, ctypes.c_int, vp, vp, vp]
     del i32
     return lib
 
@@ -171,6 +186,72 @@ class Tableau:
     @property
     def badscratch_count(self) -> int:
         return int(self.lib.sqo_badscratch_count(self.h))
+
+
+class OTableau:
+    """The operator tableau T = C^dagger of the paper's CX-injection collapse
+    (Algorithm alg:stim), held by the oracle: matrices XS, XD, ZS, ZD
+    [generator k, qubit q] and sign vectors SignsS, SignsD over qubits."""
+
+    def __init__(self, n: int, lib=None):
+        self.lib = lib if lib is not None else load()
+        self.n = int(n)
+        h = self.lib.sqo_otab_create(self.n)
+        if not h:
+            raise ValueError("oracle: bad operator tableau size")
+        self.h = ctypes.c_void_p(h)
+        self.W = (self.n + 63) // 64
+
+    def close(self):
+        if self.h:
+            self.lib.sqo_otab_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def run(self, ops, seed: int = 0, shot: int = 0, meas_base: int = 0) -> Tuple[np.ndarray, np.ndarray]:
+        """Run operations in order; returns (outcomes, was_random)."""
+        a = _ops_array(ops)
+        nmeas = int(np.count_nonzero(a[:, 0] == MEASURE))
+        bits = np.zeros(max(nmeas, 1), dtype=np.uint8)
+        rnd = np.zeros(max(nmeas, 1), dtype=np.uint8)
+        m = self.lib.sqo_otab_run(self.h, a.ctypes.data, a.shape[0], seed, shot, meas_base,
+                                  bits.ctypes.data, rnd.ctypes.data)
+        return bits[:m].copy(), rnd[:m].copy()
+
+    def arrays(self):
+        """(xs, xd, zs, zd, ss, sd): four (n, W) uint64 matrices and two (W,) sign vectors."""
+        mats = [np.zeros((self.n, self.W), dtype=np.uint64) for _ in range(4)]
+        sv = [np.zeros(self.W, dtype=np.uint64) for _ in range(2)]
+        self.lib.sqo_otab_get(self.h, *[m.ctypes.data for m in mats], *[v.ctypes.data for v in sv])
+        return (*mats, *sv)
+
+    def set_arrays(self, xs, xd, zs, zd, ss, sd):
+        arrs = [np.ascontiguousarray(a, dtype=np.uint64) for a in (xs, xd, zs, zd, ss, sd)]
+        for a in arrs[:4]:
+            assert a.shape == (self.n, self.W)
+        for a in arrs[4:]:
+            assert a.shape == (self.W,)
+        self.lib.sqo_otab_set(self.h, *[a.ctypes.data for a in arrs])
+
+    def image(self, x, z, r: int):
+        """T(P) of the Pauli (x, z, r) in the CHP encoding: (ox, oz, sign, phase_not_real)."""
+        x = np.ascontiguousarray(x, dtype=np.uint64)
+        z = np.ascontiguousarray(z, dtype=np.uint64)
+        ox = np.zeros(self.W, dtype=np.uint64)
+        oz = np.zeros(self.W, dtype=np.uint64)
+        sg = np.zeros(1, dtype=np.uint8)
+        bad = self.lib.sqo_otab_image(self.h, x.ctypes.data, z.ctypes.data, int(r), ox.ctypes.data,
+                                      oz.ctypes.data, sg.ctypes.data)
+        return ox, oz, int(sg[0]), bool(bad)
+
+    @property
+    def odd_count(self) -> int:
+        return int(self.lib.sqo_otab_odd_count(self.h))
 
 
 def philox4x64_10(ctr: Sequence[int], key: Sequence[int]) -> np.ndarray:

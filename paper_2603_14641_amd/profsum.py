@@ -32,7 +32,7 @@ COPY_KIB = 1 << 20   # the calibration copy moves 1 GiB each way
 KERNEL_SOURCES = {
     "k_layer": "sq_gates.hip", "k_sign_reduce": "sq_gates.hip",
     "k_pivot": "sq_measure.hip", "k_gather": "sq_measure.hip", "k_rowsum": "sq_measure.hip",
-    "k_post": "sq_measure.hip",
+    "k_post": "sq_measure.hip", "k_cursor_init": "sq_measure.hip",
     "k_blk_": "sq_block.hip",
     "k_sample_init": "sq_sample.hip", "k_coins": "sq_sample.hip", "k_eval": "sq_sample.hip",
     "k_batch": "sq_batch.hip",
