@@ -207,6 +207,7 @@ def main_steps(args, sq, sqb, profsum, cfg, pg, pm, parts, L):
         "kernel_ms": {k: round(v[0], 3) for k, v in kern.items()},
         "kernel_launches": {k: v[1] for k, v in kern.items()},
     }
+    t.last_bits = out_bits
     return t, res
 
 
@@ -279,6 +280,69 @@ def full_sweep(t, cfg, pg, sqb, L):
         "kernel_ms": {kk: round(v[0], 1) for kk, v in kern2.items()},
     }
     return res, det
+
+
+def inject_collapse(sq, sqb, cfg, pg, L, ref_bits, meas: int):
+    """The paper's own collapse (CX injection on the operator tableau) on the
+    same circuit: the gate passes in that mode (image signs), then the first
+    `meas` final measurements, then the same qubits again (deterministic).
+    Outcomes must equal the rowsum collapse's (`ref_bits`, same coins)."""
+    import torch
+    n = cfg.n
+    C = 8 * L
+    stream = torch.cuda.current_stream()
+    t = sq.Tableau(n, stream=stream, collapse=sqb.COLLAPSE_INJECT)
+    out = torch.zeros(meas, dtype=torch.uint8, device="cuda")
+    rnd = torch.zeros(meas, dtype=torch.uint8, device="cuda")
+    pm = sqb.Program(n, meas_ops(np.arange(meas)))
+    e = [torch.cuda.Event(enable_timing=True) for _ in range(5)]
+    t.run(pg, cfg.seed, 0, 0, out.data_ptr(), rnd.data_ptr())  # first run: kernel by kernel, graphs captured next
+    torch.cuda.synchronize()
+    t.reset()
+    t.profile_reset()
+    t.profile(True)
+    e[0].record(stream)
+    t.run(pg, cfg.seed, 0, 0, out.data_ptr(), rnd.data_ptr())
+    e[1].record(stream)
+    t.run(pm, cfg.seed, 0, 0, out.data_ptr(), rnd.data_ptr())
+    e[2].record(stream)
+    torch.cuda.synchronize()
+    st = t.measure_stats()
+    out2 = torch.zeros(meas, dtype=torch.uint8, device="cuda")
+    rnd2 = torch.zeros(meas, dtype=torch.uint8, device="cuda")
+    e[3].record(stream)
+    t.run(pm, cfg.seed + 1, 1, meas, out2.data_ptr(), rnd2.data_ptr())
+    e[4].record(stream)
+    torch.cuda.synchronize()
+    t.profile(False)
+    kern = {name: t.profile_read(i) for i, name in enumerate(sqb.KERNEL_NAMES)}
+    assert t.error_flags() == 0
+    same = bool(torch.equal(out, ref_bits[:meas].to(out.device)))
+    repeat = bool(torch.equal(out2, out)) and not bool(rnd2.any())
+    assert same and repeat, "CX-injection outcomes differ from the rowsum collapse's, or did not repeat"
+    gms, mms, dms = e[0].elapsed_time(e[1]), e[1].elapsed_time(e[2]), e[3].elapsed_time(e[4])
+    ia_ms, ia_n = kern["inject_apply"]
+    nr = int(st.n_random)
+    res = {
+        "workload": f"n={n} depth-1000 circuit on the operator tableau: gate passes with image signs, then the "
+                    f"first {meas} final Z measurements (CX-injection collapse), then the same {meas} again",
+        "gates_per_s": pg.num_gates / (gms * 1e-3), "gate_phase_ms": gms,
+        "measurements_per_s": meas / (mms * 1e-3), "random": nr,
+        "deterministic_measurements_per_s": meas / (dms * 1e-3),
+        "outcomes_equal_rowsum_collapse": same, "remeasured_deterministic": repeat,
+        "roofline_gates": roof("k_layer_op", *kern["layer"], pg.gate_bytes, pg.gate_bytes,
+                               "bytes the pass moves (column reads + changed-column writes), same plans as k_layer"),
+        "roofline": roof("k_inj_apply", ia_ms, ia_n, st.inject_bytes, st.inject_bytes,
+                         f"per column: read x, z of the destabilizer word of every target word and read+write "
+                         f"the stabilizer word where the pivot has x (z); random measurement with B_word = "
+                         f"{4 * n * C / 1e9:.1f} GB for comparison"),
+        "kernel_ms": {k: round(v[0], 2) for k, v in kern.items() if v[1]},
+        "kernel_launches": {k: v[1] for k, v in kern.items() if v[1]},
+    }
+    log(f"inject collapse: gates {res['gates_per_s']:.3g}/s, {meas} measurements {res['measurements_per_s']:.3g}/s")
+    pm.close()
+    t.close()
+    return res
 
 
 # ---------------------------------------------------------------- the batched/served mix
@@ -465,6 +529,8 @@ def main():
                     help="requests of the batched/served mix to run (0 skips that part)")
     ap.add_argument("--session-requests", type=int, default=96,
                     help="sampling requests against resident tableaux (0 skips)")
+    ap.add_argument("--inject-meas", type=int, default=256,
+                    help="final measurements run with the CX-injection collapse (0 skips that part)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="first run a plain 1 GiB device copy (scale reference for HBM byte counters)")
     args = ap.parse_args()
@@ -521,9 +587,15 @@ def main():
         },
     }
     result.update(res)
+    res_bits = None
+    if args.inject_meas and args.meas >= args.inject_meas:
+        res_bits = t.last_bits.clone()
     if not args.no_full_sweep and args.layers == 1000:
         result["full_sweep"], result["deterministic"] = full_sweep(t, cfg, pg, sqb, L)
     t.close()
+    torch.cuda.empty_cache()
+    if res_bits is not None:
+        result["inject_collapse"] = inject_collapse(sq, sqb, cfg, pg, L, res_bits, args.inject_meas)
     pg.close()
     if pm is not None:
         pm.close()

@@ -139,6 +139,44 @@ sq_status sq_destroy(sq_tableau *t);
 sq_status sq_reset(sq_tableau *t);
 /* Block until all device work queued on the handle has finished. */
 sq_status sq_sync(sq_tableau *t);
+
+/* How measurements collapse the state, and with it what the sign bits mean.
+ *
+ * SQ_COLLAPSE_ROWSUM (default): the state tableau above, one sign per
+ *   generator row; a random measurement multiplies every other row that
+ *   anticommutes with Z_q by the pivot stabilizer (CHP rowsum), a
+ *   deterministic one forms the destabilizer-selected product.
+ *   Defined by: "The CHP algorithm" (probabilistic and deterministic cases).
+ *
+ * SQ_COLLAPSE_INJECT: the operator tableau of Algorithm alg:stim. For the
+ *   circuit C applied so far, T = C^dagger maps X_q to A_q and Z_q to B_q,
+ *   Pauli strings over generator positions k = 0..n-1 with one sign each.
+ *   The bit matrices are exactly the state tableau's (row k of the
+ *   stabilizer half holds the x part of every B_q and the x part of every
+ *   A_q in X and Z, row k of the destabilizer half their z parts: the
+ *   paper's XS, ZS, XD, ZD), so gates move the same bits; a gate changes
+ *   the images' signs by the phases of image products. Measuring Z_q: the
+ *   pivot p is the smallest position with x_q(S_p) = 1; if there is one,
+ *   CX gates are injected from p into every later position t with
+ *   x_q(S_t) = 1, position p is rotated (H, or the inverse phase gate when
+ *   x_q(D_p) = 1 by then) and an X is injected at p when B_q's sign differs
+ *   from the coin; the outcome is B_q's sign (the coin when random).
+ *   Deterministic outcomes cost a pivot search only. Sign bytes of
+ *   sq_export/sq_export_rows/sq_import mean: entry i < n the sign of A_i,
+ *   entry n + i the sign of B_i. Outcomes, and the stabilizer group, equal
+ *   the rowsum collapse's under the same coins; tableau bits differ.
+ *   Defined by: Algorithm alg:stim (ProbabilisticMeasurement, GE,
+ *   SwapAntiComm, InjectCX, InjectInvP, InjectHad, InjectX), with the
+ *   prefix-XOR unfolding of the injection loop (equations CXSign, zc) and
+ *   the target compaction of Algorithm alg:compactPivots.
+ *   Not available in this mode: sq_sample, sq_sample_many (SQ_EINVAL).
+ *
+ * sq_set_collapse resets the tableau to |0...0> (where both readings agree)
+ * in the chosen mode; sq_reset keeps the mode. Blocks until the reset is
+ * queued; SQ_EINVAL for an unknown mode. */
+typedef enum { SQ_COLLAPSE_ROWSUM = 0, SQ_COLLAPSE_INJECT = 1 } sq_collapse;
+sq_status sq_set_collapse(sq_tableau *t, uint32_t mode);
+uint32_t sq_get_collapse(const sq_tableau *t);  /* 0 for a NULL handle */
 uint32_t sq_num_qubits(const sq_tableau *t);
 
 /* Apply gates (host array, program order) to every row. Qubits may repeat:
@@ -393,6 +431,9 @@ typedef struct {
   uint64_t det_bytes;
   uint64_t blocks;        /* blocked passes (each applying several random measurements) */
   uint64_t block_bytes;   /* algorithmic bytes of the blocked passes */
+  uint64_t inject_bytes;  /* CX-injection collapse: per column, read the destabilizer words of x and z at each
+                             word holding a target, and read and write the stabilizer word of x (z) there
+                             where the pivot has x (z) */
 } sq_meas_stats;
 sq_status sq_measure_stats(sq_tableau *t, sq_meas_stats *out);
 /*   (Accounting of this library; no passage of the paper.) */
@@ -445,7 +486,9 @@ enum {
   SQ_K_BPREP = 7,   /* blocked measurements: pivot rows and their algebra */
   SQ_K_BPASS = 8,   /* blocked measurements: the streaming pass */
   SQ_K_BFINAL = 9,  /* blocked measurements: signs and pivot rows */
-  SQ_K_COUNT = 10
+  SQ_K_IPIVOT = 10, /* CX-injection collapse: pivot, target compaction, column q's decisions */
+  SQ_K_IAPPLY = 11, /* CX-injection collapse: injections, rotation and X injection on every column */
+  SQ_K_COUNT = 12
 };
 /* (Profiling of this library; no passage of the paper.) */
 sq_status sq_profile_enable(sq_tableau *t, int on);

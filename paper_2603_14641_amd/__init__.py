@@ -7,5 +7,5 @@ package is the Python binding (``binding``) and the build step (``build``).
 from .binding import (  # noqa: F401
     Program, SqError, Tableau, Tuning, batch_sample, bytes_required, load, ops_array, parse_qasm, version,
     words_to_bits,
-    I, H, S, SDG, X, Y, Z, CX, CZ, CY, SWAP, ISWAP, MEASURE,
+    I, H, S, SDG, X, Y, Z, CX, CZ, CY, SWAP, ISWAP, MEASURE, COLLAPSE_ROWSUM, COLLAPSE_INJECT,
 )

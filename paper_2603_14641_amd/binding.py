@@ -18,9 +18,11 @@ LIB_PATH = os.path.join(_PKG, "libsq.so")
 # status codes and op types (include/sq.h)
 SQ_OK, SQ_EINVAL, SQ_ENOMEM, SQ_EDEVICE, SQ_ERANGE, SQ_ESTATE = 0, -1, -2, -3, -5, -6
 I, H, S, SDG, X, Y, Z, CX, CZ, CY, SWAP, ISWAP, MEASURE = 0, 1, 2, 3, 4, 5, 6, 7, 8, 9, 10, 11, 15
-K_LAYER, K_SIGNS, K_PIVOT, K_GATHER, K_ROWSUM, K_POST, K_BPIVOT, K_BPREP, K_BPASS, K_BFINAL = range(10)
+(K_LAYER, K_SIGNS, K_PIVOT, K_GATHER, K_ROWSUM, K_POST, K_BPIVOT, K_BPREP, K_BPASS, K_BFINAL,
+ K_IPIVOT, K_IAPPLY) = range(12)
 KERNEL_NAMES = ["layer", "signs", "pivot", "gather", "rowsum", "post",
-                "block_pivot", "block_prep", "block_pass", "block_final"]
+                "block_pivot", "block_prep", "block_pass", "block_final", "inject_pivot", "inject_apply"]
+COLLAPSE_ROWSUM, COLLAPSE_INJECT = 0, 1  # sq_set_collapse modes
 MAX_MEAS_BLOCK = 32
 PIVOT_AUTO = 255         # sq_tuning.pivot_waves: choose the pivot search automatically
 
@@ -34,6 +36,7 @@ EXPORTED = [
     "sq_get_tuning", "sq_set_tuning", "sq_profile_enable", "sq_profile_read", "sq_profile_reset",
     "sq_qasm_parse", "sq_frame_sample", "sq_set_graphs", "sq_graph_stats",
     "sq_create_in", "sq_layout", "sq_batch_item_bytes", "sq_sample_many", "sq_sample_bytes",
+    "sq_set_collapse", "sq_get_collapse",
 ]
 
 
@@ -75,7 +78,8 @@ class ShotSet(ctypes.Structure):
 class MeasStats(ctypes.Structure):
     _fields_ = [("n_random", ctypes.c_uint64), ("n_det", ctypes.c_uint64),
                 ("rowsum_bytes", ctypes.c_uint64), ("det_bytes", ctypes.c_uint64),
-                ("blocks", ctypes.c_uint64), ("block_bytes", ctypes.c_uint64)]
+                ("blocks", ctypes.c_uint64), ("block_bytes", ctypes.c_uint64),
+                ("inject_bytes", ctypes.c_uint64)]
 
 
 _lib = None
@@ -112,6 +116,8 @@ def load(path: str = LIB_PATH):
         "sq_destroy": (i32, [vp]),
         "sq_reset": (i32, [vp]),
         "sq_sync": (i32, [vp]),
+        "sq_set_collapse": (i32, [vp, u32]),
+        "sq_get_collapse": (u32, [vp]),
         "sq_num_qubits": (u32, [vp]),
         "sq_apply_gates": (i32, [vp, vp, u64]),
         "sq_measure": (i32, [vp, vp, u32, u64, u64, u64, vp, vp]),
@@ -224,7 +230,7 @@ class Tableau:
     dtype=torch.uint8, device="cuda")``) whose storage holds the tableau
     (sq_create_in); the tableau keeps a reference to it."""
 
-    def __init__(self, n: int, stream=None, buffer=None):
+    def __init__(self, n: int, stream=None, buffer=None, collapse: int = COLLAPSE_ROWSUM):
         self.lib = load()
         h = ctypes.c_void_p()
         self.buffer = buffer
@@ -237,6 +243,8 @@ class Tableau:
         self.h = h
         self.n = int(n)
         self.W = (self.n + 63) // 64
+        if collapse != COLLAPSE_ROWSUM:
+            self.set_collapse(collapse)
 
     def close(self):
         if getattr(self, "h", None):
@@ -261,6 +269,15 @@ class Tableau:
 
     def sync(self):
         _check(self.lib.sq_sync(self.h))
+
+    def set_collapse(self, mode: int):
+        """COLLAPSE_ROWSUM (generator signs, CHP rowsum) or COLLAPSE_INJECT
+        (image signs, CX-injection collapse); resets to |0...0>."""
+        _check(self.lib.sq_set_collapse(self.h, int(mode)))
+
+    @property
+    def collapse(self) -> int:
+        return int(self.lib.sq_get_collapse(self.h))
 
     def apply_gates(self, ops):
         a = ops_array(ops)

@@ -213,4 +213,234 @@ hipError_t launch_sign_reduce(const TabDev &t, const u64 *sign_part, u32 nchunks
   return hipGetLastError();
 }
 
+// ---------------------------------------------------------------------------
+// Operator-tableau gate pass (the tableau of Algorithm alg:stim: for each
+// qubit q the images A_q of X_q and B_q of Z_q over generator positions k,
+// a sign per image). Its bits are those of the state tableau, position k
+// being row pair (D_k, S_k): B_q has x part x_q(S_k) and z part x_q(D_k),
+// A_q has x part z_q(S_k) and z part z_q(D_k). Appending a gate therefore
+// moves bits exactly like the column rules above; what differs is the signs,
+// one per image, which change by the phase of products of whole images:
+//   H: swap A_q, B_q             S: A_q <- -i A_q B_q    S^dagger: A_q <- i A_q B_q
+//   X: -B_q   Z: -A_q   Y: both  CX(c,t): A_c <- A_c A_t, B_t <- B_t B_c
+//   CZ(a,b): A_a <- A_a B_b, A_b <- A_b B_a     SWAP: swap the images
+// The phase of P Q over 64 positions, with Y = iXZ, is (mod 4)
+//   |P.x & P.z| + |Q.x & Q.z| + 2 |P.z & Q.x| - |(P.x ^ Q.x) & (P.z ^ Q.z)|,
+// the sum of Aaronson and Gottesman's g function over the positions.
+// A workgroup takes one group at a time and walks every position word of its
+// columns (thread = position word: the D word w and the S word K + w of each
+// column), so each product's phase is a reduction within the workgroup; a
+// micro-op's two products are bit-sliced 2-bit counters 2i and 2i + 1 of a
+// 64-bit pair. Thread 0 then replays the group's micro-ops on the 2 sign
+// bits per qubit (held in R: word q/64 the A signs, word K + q/64 the B
+// signs) and XORs the changes in; the groups of a pass touch disjoint qubits.
+__device__ __forceinline__ u32 prod_phase(u64 px, u64 pz, u64 qx, u64 qz) {
+  return ((u32)__popcll(px & pz) + (u32)__popcll(qx & qz) + 2u * (u32)__popcll(pz & qx) -
+          (u32)__popcll((px ^ qx) & (pz ^ qz))) & 3u;
+}
+
+// the phases a micro-op's products pick up, c1 | c2 << 2, from pre-op values
+template <int A>
+__device__ __forceinline__ u32 ph1(const Cols<2> &c) {
+  return prod_phase(c.z[A][1], c.z[A][0], c.x[A][1], c.x[A][0]);  // A_a B_a
+}
+
+template <int A, int B>
+__device__ __forceinline__ u32 ph2(u32 t, const Cols<2> &c) {
+  if constexpr (A == B) {
+    return 0u;
+  } else {
+    if (t == WOP_CX)  // A_a A_b, B_b B_a
+      return prod_phase(c.z[A][1], c.z[A][0], c.z[B][1], c.z[B][0]) |
+             (prod_phase(c.x[B][1], c.x[B][0], c.x[A][1], c.x[A][0]) << 2);
+    if (t == WOP_CZ)  // A_a B_b, A_b B_a
+      return prod_phase(c.z[A][1], c.z[A][0], c.x[B][1], c.x[B][0]) |
+             (prod_phase(c.z[B][1], c.z[B][0], c.x[A][1], c.x[A][0]) << 2);
+    return 0u;  // SWAP
+  }
+}
+
+template <int A>
+__device__ __forceinline__ u32 ph2_row(u32 t, u32 b, const Cols<2> &c) {
+  switch (b) {
+    case 0: return ph2<A, 0>(t, c);
+    case 1: return ph2<A, 1>(t, c);
+    case 2: return ph2<A, 2>(t, c);
+    case 3: return ph2<A, 3>(t, c);
+    case 4: return ph2<A, 4>(t, c);
+    case 5: return ph2<A, 5>(t, c);
+    case 6: return ph2<A, 6>(t, c);
+    default: return ph2<A, 7>(t, c);
+  }
+}
+
+__device__ __forceinline__ u32 op_phase(u32 op, const Cols<2> &c) {
+  const u32 t = op & 15u, a = (op >> 4) & 15u, b = (op >> 8) & 15u;
+  if (t == WOP_S || t == WOP_SDG) {
+    switch (a) {
+      case 0: return ph1<0>(c);
+      case 1: return ph1<1>(c);
+      case 2: return ph1<2>(c);
+      case 3: return ph1<3>(c);
+      case 4: return ph1<4>(c);
+      case 5: return ph1<5>(c);
+      case 6: return ph1<6>(c);
+      default: return ph1<7>(c);
+    }
+  }
+  if (t < WOP_CX) return 0u;
+  switch (a) {
+    case 0: return ph2_row<0>(t, b, c);
+    case 1: return ph2_row<1>(t, b, c);
+    case 2: return ph2_row<2>(t, b, c);
+    case 3: return ph2_row<3>(t, b, c);
+    case 4: return ph2_row<4>(t, b, c);
+    case 5: return ph2_row<5>(t, b, c);
+    case 6: return ph2_row<6>(t, b, c);
+    default: return ph2_row<7>(t, b, c);
+  }
+}
+
+// (lo, hi) += (nlo, nhi): 64 independent 2-bit counters, bit-sliced
+__device__ __forceinline__ void add2(u64 &lo, u64 &hi, u64 nlo, u64 nhi) {
+  hi ^= nhi ^ (lo & nlo);
+  lo ^= nlo;
+}
+
+// Replay a group's micro-ops on its qubits' image signs (thread 0). The
+// phase exponent of every product must be even; an odd one sets flag bit 0.
+__device__ void replay_signs(const u32 *rec, u64 lo, u64 hi, u64 *__restrict__ R, u32 K, u32 *__restrict__ flags) {
+  const u32 hdr = rec[0];
+  const u32 nq = hdr & 15u, nops = (hdr >> WH_NOPS_SHIFT) & 63u;
+  const u32 *ops = rec + 1 + nq;
+  u32 sa[WG_MAXQ], sb[WG_MAXQ], sa0[WG_MAXQ], sb0[WG_MAXQ];  // signs of A_q and B_q per slot
+  for (u32 i = 0; i < nq; ++i) {
+    const u32 q = rec[1 + i];
+    sa[i] = sa0[i] = (u32)(R[q >> 6] >> (q & 63u)) & 1u;
+    sb[i] = sb0[i] = (u32)(R[K + (q >> 6)] >> (q & 63u)) & 1u;
+  }
+  u32 odd = 0;
+  for (u32 k = 0; k < nops; ++k) {
+    const u32 op = (ops[k >> 1] >> ((k & 1u) * 16u)) & 0xFFFFu;
+    const u32 t = op & 15u, a = (op >> 4) & 15u, b = (op >> 8) & 15u;
+    const u32 c1 = (u32)((lo >> (2 * k)) & 1u) | ((u32)((hi >> (2 * k)) & 1u) << 1);
+    const u32 c2 = (u32)((lo >> (2 * k + 1)) & 1u) | ((u32)((hi >> (2 * k + 1)) & 1u) << 1);
+    u32 e1, e2;
+    switch (t) {
+      case WOP_H: { const u32 v = sa[a]; sa[a] = sb[a]; sb[a] = v; } break;
+      case WOP_S: e1 = (2 * sa[a] + 2 * sb[a] + 3 + c1) & 3u; odd |= e1; sa[a] = e1 >> 1; break;
+      case WOP_SDG: e1 = (2 * sa[a] + 2 * sb[a] + 1 + c1) & 3u; odd |= e1; sa[a] = e1 >> 1; break;
+      case WOP_X: sb[a] ^= 1u; break;
+      case WOP_Y: sa[a] ^= 1u; sb[a] ^= 1u; break;
+      case WOP_Z: sa[a] ^= 1u; break;
+      case WOP_CX:
+        e1 = (2 * sa[a] + 2 * sa[b] + c1) & 3u;
+        e2 = (2 * sb[b] + 2 * sb[a] + c2) & 3u;
+        odd |= e1 | e2;
+        sa[a] = e1 >> 1;
+        sb[b] = e2 >> 1;
+        break;
+      case WOP_CZ:
+        e1 = (2 * sa[a] + 2 * sb[b] + c1) & 3u;
+        e2 = (2 * sa[b] + 2 * sb[a] + c2) & 3u;
+        odd |= e1 | e2;
+        sa[a] = e1 >> 1;
+        sa[b] = e2 >> 1;
+        break;
+      default: {  // SWAP
+        u32 v = sa[a]; sa[a] = sa[b]; sa[b] = v;
+        v = sb[a]; sb[a] = sb[b]; sb[b] = v;
+      } break;
+    }
+  }
+  if (odd & 1u) atomicOr(flags, 1u);
+  for (u32 i = 0; i < nq; ++i) {
+    const u32 q = rec[1 + i];
+    if (sa0[i] != sa[i]) atomicXor(&R[q >> 6], 1ULL << (q & 63u));
+    if (sb0[i] != sb[i]) atomicXor(&R[K + (q >> 6)], 1ULL << (q & 63u));
+  }
+}
+
+__global__ __launch_bounds__(256) void k_layer_op(u64 *__restrict__ X, u64 *__restrict__ Z, u64 *__restrict__ R,
+                                                  const u32 *__restrict__ words, const u32 *__restrict__ offs,
+                                                  u32 ngroups, u32 gpc, u32 Ls, u32 K, u32 *__restrict__ flags) {
+  __shared__ u64 s_lo[4], s_hi[4];
+  const u32 tid = threadIdx.x, lane = tid & 63u, wave = tid >> 6, nwaves = blockDim.x >> 6;
+  const u32 g0 = blockIdx.x * gpc;
+  const u32 g1 = min(g0 + gpc, ngroups);
+  u64 sdummy[2];
+  for (u32 g = g0; g < g1; ++g) {
+    const u32 *rec = words + offs[g];
+    const u32 hdr = rec[0];
+    const u32 nq = hdr & 15u, nops = (hdr >> WH_NOPS_SHIFT) & 63u;
+    const u32 *ops = rec + 1 + nq;
+    const u32 nw = (nops + 1u) >> 1;
+    u64 lo = 0, hi = 0;
+    for (u32 w = tid; w < K; w += blockDim.x) {
+      Cols<2> c;
+#pragma unroll
+      for (u32 i = 0; i < WG_MAXQ; ++i) {
+        c.x[i][0] = c.x[i][1] = c.z[i][0] = c.z[i][1] = 0;
+        if (i < nq) {
+          const size_t o = (size_t)rec[1 + i] * Ls + w;
+          c.x[i][0] = __builtin_nontemporal_load(X + o);
+          c.x[i][1] = __builtin_nontemporal_load(X + o + K);
+          c.z[i][0] = __builtin_nontemporal_load(Z + o);
+          c.z[i][1] = __builtin_nontemporal_load(Z + o + K);
+        }
+      }
+      u64 nlo = 0, nhi = 0;
+      for (u32 j = 0; j < nw; ++j) {
+        const u32 cur = ops[j];
+#pragma unroll
+        for (u32 h = 0; h < 2; ++h) {
+          const u32 k = 2 * j + h;
+          if (k < nops) {
+            const u32 op = (cur >> (16u * h)) & 0xFFFFu;
+            const u32 ph = op_phase(op, c);
+            nlo |= ((u64)(ph & 1u) << (2 * k)) | ((u64)((ph >> 2) & 1u) << (2 * k + 1));
+            nhi |= ((u64)((ph >> 1) & 1u) << (2 * k)) | ((u64)((ph >> 3) & 1u) << (2 * k + 1));
+            run_op<2>(op, c, sdummy);
+          }
+        }
+      }
+      add2(lo, hi, nlo, nhi);
+#pragma unroll
+      for (u32 i = 0; i < WG_MAXQ; ++i) {
+        if (i < nq) {
+          const size_t o = (size_t)rec[1 + i] * Ls + w;
+          if ((hdr >> (WH_DX_SHIFT + i)) & 1u) {
+            __builtin_nontemporal_store(c.x[i][0], X + o);
+            __builtin_nontemporal_store(c.x[i][1], X + o + K);
+          }
+          if ((hdr >> (WH_DZ_SHIFT + i)) & 1u) {
+            __builtin_nontemporal_store(c.z[i][0], Z + o);
+            __builtin_nontemporal_store(c.z[i][1], Z + o + K);
+          }
+        }
+      }
+    }
+    // wave, then workgroup, sum of the counters
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) add2(lo, hi, shfl_xor_u64(lo, off), shfl_xor_u64(hi, off));
+    if (nwaves > 1) {
+      if (lane == 0) { s_lo[wave] = lo; s_hi[wave] = hi; }
+      __syncthreads();
+      if (tid == 0)
+        for (u32 v = 1; v < nwaves; ++v) add2(lo, hi, s_lo[v], s_hi[v]);
+    }
+    if (tid == 0) replay_signs(rec, lo, hi, R, K, flags);
+    if (nwaves > 1) __syncthreads();
+  }
+}
+
+// One workgroup per chunk of gpc groups; block is 64 (K <= 64) or 256.
+hipError_t launch_layer_op(const TabDev &t, const u32 *words, const u32 *offs, u32 ngroups, u32 gpc, u32 *flags,
+                           hipStream_t s) {
+  const u32 block = t.K <= 64 ? 64 : 256;
+  hipLaunchKernelGGL(k_layer_op, dim3(cdiv(ngroups, gpc)), dim3(block), 0, s, t.X, t.Z, t.R, words, offs, ngroups,
+                     gpc, t.Ls, t.K, flags);
+  return hipGetLastError();
+}
+
 }  // namespace sq

@@ -96,6 +96,7 @@ struct MeasState {
   u32 nx, nz;     // pivot-row columns with x_pj = 1, with z_pj = 1
   u32 nsv;        // sampling: coin columns in which S_p has a 1 (compacted list length)
   u32 det_done;   // deterministic case: blocks of k_post that have added their phase sums
+  u32 inj;        // CX-injection collapse: bit 0 inverse-phase rotation (else H), bit 1 X injection
 };
 
 // Symbolic-sign context of the sampler's sweep (sq_sample.hip); unused (zero)
@@ -119,6 +120,7 @@ struct MeasStats {
   u64 det_bytes;      // algorithmic bytes of the deterministic-phase passes
   u64 blocks;         // blocked passes (several random measurements each)
   u64 block_bytes;    // algorithmic bytes of the blocked passes
+  u64 inject_bytes;   // algorithmic bytes of the CX-injection passes
 };
 
 // Blocked random measurements (sq_block.hip): up to KB per pass.
@@ -187,6 +189,14 @@ hipError_t launch_init_diag(const TabDev &t, hipStream_t s);
 hipError_t launch_layer(const TabDev &t, const u32 *words, const u32 *offs, u32 ngroups, u32 block, u32 wpt,
                         u32 gpc, u64 *sign_part, hipStream_t s);
 hipError_t launch_sign_reduce(const TabDev &t, const u64 *sign_part, u32 nchunks, hipStream_t s);
+// Operator-tableau mode (sq_gates.hip, sq_inject.hip): R holds the image
+// signs, word w < K the signs of A_q = image of X_q, word K + w those of B_q.
+hipError_t launch_layer_op(const TabDev &t, const u32 *words, const u32 *offs, u32 ngroups, u32 gpc, u32 *flags,
+                           hipStream_t s);
+hipError_t launch_inj_pivot(const TabDev &t, Cursor *cur, MeasState *st, u64 *mask, u32 *tw, MeasStats *stats,
+                            hipStream_t s);
+hipError_t launch_inj_apply(const TabDev &t, const MeasState *st, const u64 *mask, const u32 *tw, MeasStats *stats,
+                            hipStream_t s);
 hipError_t launch_cursor_init(Cursor *c, u32 end, u32 kb, u64 seed, u64 shot, u64 meas_base, const u32 *qubits,
                               uint8_t *out_bits, uint8_t *out_rand, hipStream_t s);
 hipError_t launch_pivot(const TabDev &t, Cursor *cur, MeasState *st, u64 *mask, hipStream_t s);

@@ -112,11 +112,12 @@ struct sq_tableau {
   u32 *dev_offs = nullptr;
   size_t dev_offs_cap = 0;
   sq_tuning tun{};
+  u32 collapse = SQ_COLLAPSE_ROWSUM;  // what the sign bits mean and how measurements collapse
   WideBuilder builder;
   // program gate segments replayed as graphs, most recently used last
   struct SegGraph {
     u64 prog = 0, first = 0, count = 0;
-    u32 layer_block = 0, layer_wpt = 0, layer_groups = 0;
+    u32 layer_block = 0, layer_wpt = 0, layer_groups = 0, collapse = 0;
     hipGraphExec_t exec = nullptr;  // null until the segment's second run
   };
   std::vector<SegGraph> graphs;
@@ -289,8 +290,25 @@ sq_status collect_profile(sq_tableau *T) {
     if (s_ != SQ_OK) return s_;      \
   } while (0)
 
+// Groups per workgroup of the operator-tableau gate pass: a workgroup walks
+// whole columns, so a pass wants about 4,096 workgroups.
+u32 layer_op_gpc(const sq_tableau *T, u32 ngroups) {
+  u32 gpc = T->tun.layer_groups ? T->tun.layer_groups : cdiv(ngroups, 4096);
+  return std::max<u32>(gpc, 1);
+}
+
 sq_status run_passes_on(sq_tableau *T, hipStream_t stream, const u32 *dev_words, const u32 *dev_offs,
                         const std::vector<PassRange> &passes, size_t first, size_t count) {
+  if (T->collapse == SQ_COLLAPSE_INJECT) {
+    for (size_t i = first; i < first + count; ++i) {
+      const PassRange &p = passes[i];
+      const u32 *offs = dev_offs + p.offset;
+      SQ_TRY(timed(T, SQ_K_LAYER, [&] {
+        return launch_layer_op(T->t, dev_words, offs, p.count, layer_op_gpc(T, p.count), &T->st->flags, stream);
+      }));
+    }
+    return SQ_OK;
+  }
   for (size_t i = first; i < first + count; ++i) {
     const PassRange &p = passes[i];
     const u32 gpc = layer_gpc(T, p.count);
@@ -326,7 +344,7 @@ sq_status run_gate_segment(sq_tableau *T, const sq_program *P, u64 first, u64 co
   for (; i < T->graphs.size(); ++i) {
     const auto &g = T->graphs[i];
     if (g.prog == P->uid && g.first == first && g.count == count && g.layer_block == tn.layer_block &&
-        g.layer_wpt == tn.layer_wpt && g.layer_groups == tn.layer_groups)
+        g.layer_wpt == tn.layer_wpt && g.layer_groups == tn.layer_groups && g.collapse == T->collapse)
       break;
   }
   if (i == T->graphs.size()) {  // first run: remember it, launch kernel by kernel
@@ -344,6 +362,7 @@ sq_status run_gate_segment(sq_tableau *T, const sq_program *P, u64 first, u64 co
     g.layer_block = tn.layer_block;
     g.layer_wpt = tn.layer_wpt;
     g.layer_groups = tn.layer_groups;
+    g.collapse = T->collapse;
     T->graphs.push_back(g);
     return run_passes(T, P->dev_words, P->dev_offs, P->passes, first, count);
   }
@@ -439,6 +458,13 @@ struct SweepCtx {
 };
 
 sq_status queue_slot(sq_tableau *T, const SweepCtx &c, u32 kb) {
+  if (T->collapse == SQ_COLLAPSE_INJECT) {
+    SQ_TRY(timed(T, SQ_K_IPIVOT, [&] {
+      return launch_inj_pivot(c.tab, T->cur, T->st, T->mask, T->cols, T->stats, T->stream);
+    }));
+    SQ_TRY(timed(T, SQ_K_IAPPLY, [&] { return launch_inj_apply(c.tab, T->st, T->mask, T->cols, T->stats, T->stream); }));
+    return SQ_OK;
+  }
   if (kb <= 1) {
     const u32 cpc = rowsum_cpc(T);
     const u32 max_chunks = cdiv(T->d.n, cpc);
@@ -476,11 +502,16 @@ sq_status queue_slot(sq_tableau *T, const SweepCtx &c, u32 kb) {
   return SQ_OK;
 }
 
+// Measurements offered per slot: the CX-injection collapse takes one at a time.
+u32 sweep_kb(const sq_tableau *T) {
+  return T->collapse == SQ_COLLAPSE_INJECT ? 1u : std::min<u32>(T->tun.meas_block, KB);
+}
+
 // Queue the sweep of a list of `count` measurements whose cursor has been
 // initialised on T's stream, and wait until it is done.
 sq_status run_sweep(sq_tableau *T, const SweepCtx &c, u32 count) {
   if (count == 0) return SQ_OK;
-  const u32 kb = std::min<u32>(T->tun.meas_block, KB);
+  const u32 kb = sweep_kb(T);
   u64 queued = 0;
   u64 slots = kb <= 1 ? count : cdiv(count, kb);
   for (;;) {
@@ -679,6 +710,15 @@ sq_status sq_reset(sq_tableau *T) {
   return reset_device(T);
 }
 
+sq_status sq_set_collapse(sq_tableau *T, uint32_t mode) {
+  if (!T) return fail(SQ_EINVAL, "tableau is NULL");
+  if (mode != SQ_COLLAPSE_ROWSUM && mode != SQ_COLLAPSE_INJECT) return fail(SQ_EINVAL, "unknown collapse mode %u", mode);
+  T->collapse = mode;
+  return reset_device(T);
+}
+
+uint32_t sq_get_collapse(const sq_tableau *T) { return T ? T->collapse : 0u; }
+
 sq_status sq_sync(sq_tableau *T) {
   if (!T) return fail(SQ_EINVAL, "tableau is NULL");
   HIP_TRY(hipStreamSynchronize(T->stream));
@@ -714,8 +754,7 @@ sq_status measure_list(sq_tableau *T, const uint32_t *qubits, uint32_t count, ui
   MeasState before{}, after{};
   HIP_TRY(hipMemcpyAsync(&before, T->st, sizeof(MeasState), hipMemcpyDeviceToHost, T->stream));
   HIP_TRY(hipMemcpyAsync(dq, qubits, (size_t)count * 4, hipMemcpyHostToDevice, T->stream));
-  HIP_TRY(launch_cursor_init(T->cur, count, std::min<u32>(T->tun.meas_block, KB), seed, shot, meas_base, dq, dout,
-                             dout + count, T->stream));
+  HIP_TRY(launch_cursor_init(T->cur, count, sweep_kb(T), seed, shot, meas_base, dq, dout, dout + count, T->stream));
   SQ_TRY(run_sweep(T, SweepCtx{T->t, T->t, nullptr, T->stats, nullptr, nullptr}, count));
   HIP_TRY(hipMemcpyAsync(out_bits, dout, count, hipMemcpyDeviceToHost, T->stream));
   if (out_random) HIP_TRY(hipMemcpyAsync(out_random, dout + count, count, hipMemcpyDeviceToHost, T->stream));
@@ -773,6 +812,8 @@ size_t sq_sample_bytes(uint32_t n, uint32_t count, uint32_t shots) {
 sq_status sq_sample_many(sq_tableau *T, const uint32_t *qubits, uint32_t count, const sq_shot_set *sets,
                          uint32_t nsets) {
   if (!T) return fail(SQ_EINVAL, "tableau is NULL");
+  if (T->collapse != SQ_COLLAPSE_ROWSUM)
+    return fail(SQ_EINVAL, "shot sampling needs the rowsum collapse (generator signs); see sq_set_collapse");
   if (nsets && !sets) return fail(SQ_EINVAL, "sets is NULL");
   u32 shots = 0;  // the largest set sizes the coin and outcome buffers
   for (u32 k = 0; k < nsets; ++k) {
@@ -1207,7 +1248,7 @@ sq_status sq_run(sq_tableau *T, const sq_program *P, uint64_t seed, uint64_t sho
   if (!T || !P) return fail(SQ_EINVAL, "tableau or program is NULL");
   if (P->n != T->d.n) return fail(SQ_EINVAL, "program has n=%u, tableau n=%u", P->n, T->d.n);
   if (!P->meas_qubits.empty() && !dev_out_bits) return fail(SQ_EINVAL, "dev_out_bits is NULL");
-  const u32 kb = std::min<u32>(T->tun.meas_block, KB);
+  const u32 kb = sweep_kb(T);
   for (const sq_program::Seg &s : P->segs) {
     if (s.kind == 0) {
       SQ_TRY(run_gate_segment(T, P, s.first, s.count));
@@ -1364,6 +1405,7 @@ sq_status sq_measure_stats(sq_tableau *T, sq_meas_stats *out) {
   out->det_bytes = s.det_bytes;
   out->blocks = s.blocks;
   out->block_bytes = s.block_bytes;
+  out->inject_bytes = s.inject_bytes;
   return SQ_OK;
 }
 
