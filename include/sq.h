@@ -217,6 +217,21 @@ sq_status sq_measure(sq_tableau *t, const uint32_t *host_qubits, uint32_t count,
  *   row times the pivot, D_p <- S_p, S_p <- (-1)^coin Z_q; deterministic case:
  *   the product of the stabilizers the destabilizers select). */
 
+/* sq_measure without device allocation, for callers that cannot allocate
+ * device memory (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc): the same arguments, semantics, ordering
+ * and errors as sq_measure, but the measured list and the outcome bytes are
+ * staged in a fixed device array compiled into the library (6 bytes per
+ * measurement, SQ_NOALLOC_MAX_MEAS measurements: 6 MiB per device, held
+ * until the process ends) instead of buffers the handle allocates. Pair it
+ * with sq_create_in for a tableau in caller-owned memory. count above
+ * SQ_NOALLOC_MAX_MEAS: SQ_ERANGE, nothing done. Calls on one device share
+ * the array; the library serializes them (each returns only after its
+ * stream has finished with the array). Blocks. */
+#define SQ_NOALLOC_MAX_MEAS 1048576u
+sq_status sq_measure_noalloc(sq_tableau *t, const uint32_t *host_qubits, uint32_t count, uint64_t seed,
+                             uint64_t shot, uint64_t meas_base, uint8_t *out_bits, uint8_t *out_random);
+
 /* Sample `shots` shots of measuring host_qubits[0..count) (in that order) on
  * the current state, without changing the tableau. Shot s (0 <= s < shots)
  * is exactly the outcome string sq_measure would return on a copy of the

@@ -36,7 +36,7 @@ EXPORTED = [
     "sq_get_tuning", "sq_set_tuning", "sq_profile_enable", "sq_profile_read", "sq_profile_reset",
     "sq_qasm_parse", "sq_frame_sample", "sq_set_graphs", "sq_graph_stats",
     "sq_create_in", "sq_layout", "sq_batch_item_bytes", "sq_sample_many", "sq_sample_bytes",
-    "sq_set_collapse", "sq_get_collapse",
+    "sq_set_collapse", "sq_get_collapse", "sq_measure_noalloc",
 ]
 
 
@@ -121,6 +121,7 @@ def load(path: str = LIB_PATH):
         "sq_num_qubits": (u32, [vp]),
         "sq_apply_gates": (i32, [vp, vp, u64]),
         "sq_measure": (i32, [vp, vp, u32, u64, u64, u64, vp, vp]),
+        "sq_measure_noalloc": (i32, [vp, vp, u32, u64, u64, u64, vp, vp]),
         "sq_sample": (i32, [vp, vp, u32, u64, u64, u32, u64, vp]),
         "sq_batch_sample": (i32, [ctypes.POINTER(BatchItem), u32, ctypes.POINTER(BatchOpts), vp]),
         "sq_program_create": (i32, [u32, vp, u64, pvp]),

@@ -5,6 +5,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 #include <thread>
@@ -795,6 +796,68 @@ sq_status sq_measure(sq_tableau *T, const uint32_t *qubits, uint32_t count, uint
   }
   SQ_TRY(ensure_capacity(T, &T->dev_q, &T->dev_q_cap, count));
   return measure_list(T, qubits, count, seed, shot, meas_base, out_bits, out_random, T->dev_q, T->dev_out);
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// sq_measure_noalloc: sq_measure with its staging (the measured list and the
+// outcome and flag bytes) in a fixed device array instead of buffers the
+// handle grows with hipMallocAsync. The array lives in the library's code
+// object, one copy per device for the life of the process. In host code its
+// name is only a stand-in, so its device address is looked up once per
+// device (hipGetSymbolAddress with that device current) and only that
+// address is used. Calls on one device share the array, so they are
+// serialized by a per-device mutex (each call synchronizes its stream
+// before returning, releasing the array).
+static __device__ __align__(256) unsigned char scratch[(size_t)SQ_NOALLOC_MAX_MEAS * 6];
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu[kMaxDevices];
+unsigned char *g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of `scratch` on device `dev` (looked up on first use, with
+// dev current; the caller's current device is restored). Caller holds
+// g_scratch_mu[dev].
+sq_status scratch_address(int dev, unsigned char **out) {
+  if (g_scratch_ptr[dev]) {
+    *out = g_scratch_ptr[dev];
+    return SQ_OK;
+  }
+  int cur = 0;
+  HIP_TRY(hipGetDevice(&cur));
+  if (cur != dev) HIP_TRY(hipSetDevice(dev));
+  void *p = nullptr;
+  const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+  if (cur != dev) (void)hipSetDevice(cur);
+  if (e != hipSuccess || !p) {
+    (void)hipGetLastError();
+    return fail(SQ_EDEVICE, "hipGetSymbolAddress of the staging array failed: %s", hipGetErrorString(e));
+  }
+  g_scratch_ptr[dev] = static_cast<unsigned char *>(p);
+  *out = g_scratch_ptr[dev];
+  return SQ_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+sq_status sq_measure_noalloc(sq_tableau *T, const uint32_t *qubits, uint32_t count, uint64_t seed, uint64_t shot,
+                             uint64_t meas_base, uint8_t *out_bits, uint8_t *out_random) {
+  SQ_TRY(check_measure_args(T, qubits, count, out_bits));
+  if (count == 0) return SQ_OK;
+  if (count > SQ_NOALLOC_MAX_MEAS)
+    return fail(SQ_ERANGE, "count=%u above SQ_NOALLOC_MAX_MEAS=%u", count, SQ_NOALLOC_MAX_MEAS);
+  if (T->device < 0 || T->device >= kMaxDevices) return fail(SQ_EDEVICE, "device %d out of range", T->device);
+  std::lock_guard<std::mutex> lk(g_scratch_mu[T->device]);
+  unsigned char *base = nullptr;
+  SQ_TRY(scratch_address(T->device, &base));
+  u32 *dq = reinterpret_cast<u32 *>(base);
+  uint8_t *dout = base + (size_t)SQ_NOALLOC_MAX_MEAS * 4;
+  return measure_list(T, qubits, count, seed, shot, meas_base, out_bits, out_random, dq, dout);
 }
 
 sq_status sq_sample(sq_tableau *T, const uint32_t *qubits, uint32_t count, uint64_t seed, uint64_t shot_begin,
