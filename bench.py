@@ -345,6 +345,113 @@ def inject_collapse(sq, sqb, cfg, pg, L, ref_bits, meas: int):
     return res
 
 
+def row_layout(sq, sqb, cfg, pg, L, ref_bits, meas: int):
+    """The dual layout: after the gates, transpose to rows, the first `meas`
+    final measurements one at a time on whole rows, the same qubits again
+    (deterministic), transpose back, the same qubits again in columns
+    (deterministic, column kernels); then, from the same post-gate state,
+    the first `meas` measurements one at a time in columns (no blocks): the
+    row-granular and word-granular costs of the same measurements."""
+    import torch
+    n = cfg.n
+    C = 8 * L
+    stream = torch.cuda.current_stream()
+    t = sq.Tableau(n, stream=stream)
+    out = torch.zeros(meas, dtype=torch.uint8, device="cuda")
+    rnd = torch.zeros(meas, dtype=torch.uint8, device="cuda")
+    out2, rnd2 = torch.zeros_like(out), torch.zeros_like(rnd)
+    out3, rnd3 = torch.zeros_like(out), torch.zeros_like(rnd)
+    pm = sqb.Program(n, meas_ops(np.arange(meas)))
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(8)]
+    t.run(pg, cfg.seed, 0, 0, out.data_ptr(), rnd.data_ptr())
+    torch.cuda.synchronize()
+    t.profile_reset()
+    t.profile(True)
+    ev[0].record(stream)
+    t.set_layout(sqb.LAYOUT_ROWS)
+    ev[1].record(stream)
+    t.run(pm, cfg.seed, 0, 0, out.data_ptr(), rnd.data_ptr())
+    ev[2].record(stream)
+    torch.cuda.synchronize()
+    st_r = t.measure_stats()
+    ev[3].record(stream)
+    t.run(pm, cfg.seed + 1, 1, meas, out2.data_ptr(), rnd2.data_ptr())
+    ev[4].record(stream)
+    torch.cuda.synchronize()
+    st_d = t.measure_stats()
+    ev[5].record(stream)
+    t.set_layout(sqb.LAYOUT_COLUMNS)
+    ev[6].record(stream)
+    t.run(pm, cfg.seed + 2, 2, 2 * meas, out3.data_ptr(), rnd3.data_ptr())
+    ev[7].record(stream)
+    torch.cuda.synchronize()
+    t.profile(False)
+    st_c = t.measure_stats()
+    kern = {name: t.profile_read(i) for i, name in enumerate(sqb.KERNEL_NAMES)}
+    assert t.error_flags() == 0
+    same = bool(torch.equal(out, ref_bits[:meas].to(out.device)))
+    repeat = bool(torch.equal(out2, out)) and bool(torch.equal(out3, out)) and not bool(rnd2.any() or rnd3.any())
+    assert same and repeat, "row-layout outcomes differ from the column layout's, or did not repeat"
+    # the same measurements one at a time in columns, from the same state
+    t.reset()
+    t.run(pg, cfg.seed, 0, 0, out2.data_ptr(), rnd2.data_ptr())
+    t.set_tuning(meas_block=1)
+    torch.cuda.synchronize()
+    st0 = t.measure_stats()
+    t.profile_reset()
+    t.profile(True)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    t.run(pm, cfg.seed, 0, 0, out3.data_ptr(), rnd3.data_ptr())
+    e1.record(stream)
+    torch.cuda.synchronize()
+    t.profile(False)
+    st1 = t.measure_stats()
+    kc = {name: t.profile_read(i) for i, name in enumerate(sqb.KERNEL_NAMES)}
+    assert bool(torch.equal(out3, out)) and t.error_flags() == 0
+    ms = [ev[k].elapsed_time(ev[k + 1]) for k in range(7)]
+    det_rows_moved = st_d.det_bytes - st_r.det_bytes
+    det_cols_moved = st_c.det_bytes - st_d.det_bytes
+    nr = int(st_r.n_random)
+    tr_bytes = 2 * 2 * 64 * sqb.layout(n)["K"] * 2 * sqb.layout(n)["K"] * 8  # X and Z, read and written
+    res = {
+        "workload": f"n={n} depth-1000 circuit: transpose to rows, the first {meas} final measurements one at a "
+                    f"time on rows, the same qubits again (deterministic) on rows, transpose back, again on "
+                    f"columns; then from the same post-gate state the {meas} measurements one at a time on columns",
+        "transpose_ms": [round(ms[0], 3), round(ms[5], 3)],
+        "measurements_per_s_rows": meas / (ms[1] * 1e-3), "random": nr,
+        "measurements_per_s_columns_single": meas / (e0.elapsed_time(e1) * 1e-3),
+        "deterministic_per_s_rows": meas / (ms[3] * 1e-3),
+        "deterministic_per_s_columns": meas / (ms[6] * 1e-3),
+        "rowsum_bytes_per_measurement_rows": int(st_r.rowsum_bytes / max(nr, 1)),
+        "rowsum_bytes_per_measurement_columns": int((st1.rowsum_bytes - st0.rowsum_bytes) / max(nr, 1)),
+        "det_bytes_per_measurement_rows": int(det_rows_moved / meas),
+        "det_bytes_per_measurement_columns": int(det_cols_moved / meas),
+        "outcomes_equal_blocked_columns": same,
+        "roofline_transpose": roof("k_transpose", *kern["transpose"], tr_bytes * kern["transpose"][1],
+                                   tr_bytes * kern["transpose"][1],
+                                   "X and Z, both halves, every word read and written once"),
+        "roofline": roof("k_row_rowsum", *kern["row_rowsum"], nr * n * 4 * (L // 2) * 8, st_r.rowsum_bytes,
+                         f"random measurement, row granular: the rows with x_q = 1 (about n of 2n) read and "
+                         f"written in x and z; cost model n rows x 4 x {L // 2} words; B_word = "
+                         f"{4 * n * C / 1e9:.1f} GB for comparison"),
+        "roofline_det": roof("k_row_det", *kern["row_det"], det_rows_moved, det_rows_moved,
+                             "deterministic: x and z of every stabilizer row in the product, read once"),
+        "roofline_columns_single": roof("k_rowsum", *kc["rowsum"], nr * 4 * n * C,
+                                        st1.rowsum_bytes - st0.rowsum_bytes,
+                                        f"random measurement, word granular: B_word = {4 * n * C / 1e9:.1f} GB"),
+        "kernel_ms": {k: round(v[0], 2) for k, v in kern.items() if v[1]},
+        "kernel_ms_columns_single": {k: round(v[0], 2) for k, v in kc.items() if v[1]},
+    }
+    log(f"row layout: transposes {ms[0]:.1f} / {ms[5]:.1f} ms, {meas} measurements "
+        f"{res['measurements_per_s_rows']:.3g}/s on rows vs {res['measurements_per_s_columns_single']:.3g}/s "
+        f"single on columns; deterministic {res['deterministic_per_s_rows']:.3g}/s rows vs "
+        f"{res['deterministic_per_s_columns']:.3g}/s columns")
+    pm.close()
+    t.close()
+    return res
+
+
 # ---------------------------------------------------------------- the batched/served mix
 def served_mix(nreq: int, budget_bytes: int, session_requests: int):
     import torch
@@ -426,6 +533,45 @@ def served_mix(nreq: int, budget_bytes: int, session_requests: int):
         same = same and res["sessions"]["served_equals_alone"]
     res["outputs_identical_across_paths"] = bool(same)
     return res
+
+
+def served_kernels_single_thread(nreq: int):
+    """The kernels of the batched/served paths driven from one host thread
+    (for a kernel trace): the plain per-circuit sampling of every request
+    (gates, symbolic sweep, per-shot evaluation), the Pauli-frame path, and
+    the persistent batched launch on the requests it takes (n <= 1024, so no
+    worker threads start)."""
+    import torch
+    import paper_2603_14641_amd as sq
+    from workload import circuit_ops, served_requests
+
+    reqs = []
+    for r in served_requests()[:nreq]:
+        ops = circuit_ops(r.config(), final_measure=False)
+        ops = np.stack([ops["type"], ops["q0"], ops["q1"]], 1).astype(np.uint32)
+        reqs.append(dict(n=r.n, ops=ops, qubits=np.arange(r.n, dtype=np.uint32), shots=r.shots, seed=r.coin_seed))
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for r in reqs:
+        t = sq.Tableau(r["n"])
+        t.apply_gates(r["ops"])
+        t.sample(r["qubits"], r["shots"], seed=r["seed"])
+        t.close()
+    plain_s = time.perf_counter() - t0
+    small = [r for r in reqs if r["n"] <= 1024]
+    t0 = time.perf_counter()
+    sq.batch_sample(small, block=256, max_batch_n=1024, streams=1)
+    batch_s = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    for r in reqs[:64]:
+        pg = sq.Program(r["n"], np.concatenate([r["ops"], meas_ops(r["qubits"])]))
+        pg.frame_sample(r["shots"], seed=r["seed"])
+        pg.close()
+    frame_s = time.perf_counter() - t0
+    log(f"single-thread served kernels: plain {plain_s:.2f} s, batched ({len(small)} small) {batch_s:.2f} s, "
+        f"frames (64) {frame_s:.2f} s")
+    return {"requests": nreq, "plain_s": plain_s, "batched_small_requests": len(small), "batched_s": batch_s,
+            "frame_requests": 64, "frame_s": frame_s}
 
 
 def sessions_run(reqs, nsample: int, budget_bytes: int):
@@ -531,6 +677,10 @@ def main():
                     help="sampling requests against resident tableaux (0 skips)")
     ap.add_argument("--inject-meas", type=int, default=256,
                     help="final measurements run with the CX-injection collapse (0 skips that part)")
+    ap.add_argument("--row-meas", type=int, default=256,
+                    help="final measurements run one at a time in the row layout (0 skips that part)")
+    ap.add_argument("--served-single-thread", action="store_true",
+                    help="run only the batched/served paths' kernels from one host thread (for kernel traces)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="first run a plain 1 GiB device copy (scale reference for HBM byte counters)")
     args = ap.parse_args()
@@ -588,21 +738,26 @@ def main():
     }
     result.update(res)
     res_bits = None
-    if args.inject_meas and args.meas >= args.inject_meas:
+    if max(args.inject_meas, args.row_meas) and args.meas >= max(args.inject_meas, args.row_meas):
         res_bits = t.last_bits.clone()
     if not args.no_full_sweep and args.layers == 1000:
         result["full_sweep"], result["deterministic"] = full_sweep(t, cfg, pg, sqb, L)
     t.close()
     torch.cuda.empty_cache()
-    if res_bits is not None:
+    if res_bits is not None and args.inject_meas:
         result["inject_collapse"] = inject_collapse(sq, sqb, cfg, pg, L, res_bits, args.inject_meas)
+        torch.cuda.empty_cache()
+    if res_bits is not None and args.row_meas:
+        result["row_layout"] = row_layout(sq, sqb, cfg, pg, L, res_bits, args.row_meas)
     pg.close()
     if pm is not None:
         pm.close()
     torch.cuda.synchronize()
     torch.cuda.empty_cache()
     result["hbm_stream_ceiling_gbs"] = stream_ceiling()
-    if args.served_requests > 0:
+    if args.served_requests > 0 and args.served_single_thread:
+        result["served_single_thread"] = served_kernels_single_thread(args.served_requests)
+    elif args.served_requests > 0:
         result["batched_served"] = served_mix(args.served_requests, 8 << 30, args.session_requests)
     if not args.no_cpu_baseline:
         log(f"CPU oracle baseline (~{args.cpu_seconds:.0f} s)")

@@ -177,6 +177,31 @@ sq_status sq_sync(sq_tableau *t);
 typedef enum { SQ_COLLAPSE_ROWSUM = 0, SQ_COLLAPSE_INJECT = 1 } sq_collapse;
 sq_status sq_set_collapse(sq_tableau *t, uint32_t mode);
 uint32_t sq_get_collapse(const sq_tableau *t);  /* 0 for a NULL handle */
+
+/* Memory layout of the tableau's bits (the dual layout of "Tableau Layout
+ * and Indexing"; the switch is the tile-wise in-place transpose of
+ * Algorithm alg:transpose, each 64 x 64 bit tile transposed in registers
+ * and exchanged with its mirror, the same operation both ways).
+ *
+ * SQ_LAYOUT_COLUMNS (default): column-major, as described at sq_layout
+ *   (X[q * Ls + w] packs 64 generator rows of qubit q).
+ * SQ_LAYOUT_ROWS: row-contiguous: slot r (the same Ls-word stride) holds
+ *   the generator pair r, words w < K the bits of D_r at qubits
+ *   64w .. 64w+63, words K + w those of S_r; slots r >= n are zero (X and Z
+ *   hold 64K slots in both layouts). Sign words are the same. Measurements
+ *   (sq_measure, sq_run measurement segments) then touch whole rows: a
+ *   random measurement reads and writes only the rows that anticommute with
+ *   Z_q, a deterministic one reads only the stabilizer rows it multiplies
+ *   (row-granular bytes), one measurement at a time.
+ * Gate application (sq_apply_gates, program gate segments), sampling,
+ * export and import switch back to columns first. Only with the rowsum
+ * collapse (SQ_EINVAL otherwise). Results are identical in both layouts.
+ * Queues the transpose (if the layout changes) on the handle's stream.
+ * Defined by: "Tableau Layout and Indexing" (row-major layout for
+ * measurement), Algorithm alg:transpose. */
+typedef enum { SQ_LAYOUT_COLUMNS = 0, SQ_LAYOUT_ROWS = 1 } sq_layout_kind;
+sq_status sq_set_layout(sq_tableau *t, uint32_t layout);
+uint32_t sq_get_layout(const sq_tableau *t);  /* 0 for a NULL handle */
 uint32_t sq_num_qubits(const sq_tableau *t);
 
 /* Apply gates (host array, program order) to every row. Qubits may repeat:
@@ -503,7 +528,12 @@ enum {
   SQ_K_BFINAL = 9,  /* blocked measurements: signs and pivot rows */
   SQ_K_IPIVOT = 10, /* CX-injection collapse: pivot, target compaction, column q's decisions */
   SQ_K_IAPPLY = 11, /* CX-injection collapse: injections, rotation and X injection on every column */
-  SQ_K_COUNT = 12
+  SQ_K_TRANSPOSE = 12, /* layout switch: tile transpose of X and Z */
+  SQ_K_RPREP = 13,  /* row layout: pivot search and pivot-row copy */
+  SQ_K_RROWSUM = 14, /* row layout: rows times the pivot */
+  SQ_K_RDET = 15,   /* row layout: deterministic product (block partials and their cross terms) */
+  SQ_K_RFINISH = 16, /* row layout: pivot rows, outcome */
+  SQ_K_COUNT = 17
 };
 /* (Profiling of this library; no passage of the paper.) */
 sq_status sq_profile_enable(sq_tableau *t, int on);

@@ -410,8 +410,8 @@ int sqo_num_threads(void) {
  * is not used). The frame starts with x = 0 and z drawn at random; measuring
  * qubit q records x_q and draws z_q afresh. The outcome of measurement i in
  * shot s is the reference sample's outcome i XOR the recorded x_q (the
- * paper records the frame bit alone; the reference XOR is this build's
- * reading, which makes the outcome a sample of the circuit).
+ * paper records the frame bit alone; the reference XOR is the reading
+ * taken here, which makes the outcome a sample of the circuit).
  *
  * Random bit of shot s for event e: bit (s mod 64) of output word 0 of
  * Philox4x64-10 with key (seed, 2^63 + floor(s / 64)) and counter

@@ -8,4 +8,5 @@ from .binding import (  # noqa: F401
     Program, SqError, Tableau, Tuning, batch_sample, bytes_required, load, ops_array, parse_qasm, version,
     words_to_bits,
     I, H, S, SDG, X, Y, Z, CX, CZ, CY, SWAP, ISWAP, MEASURE, COLLAPSE_ROWSUM, COLLAPSE_INJECT,
+    LAYOUT_COLUMNS, LAYOUT_ROWS,
 )

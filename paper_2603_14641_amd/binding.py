@@ -19,9 +19,11 @@ LIB_PATH = os.path.join(_PKG, "libsq.so")
 SQ_OK, SQ_EINVAL, SQ_ENOMEM, SQ_EDEVICE, SQ_ERANGE, SQ_ESTATE = 0, -1, -2, -3, -5, -6
 I, H, S, SDG, X, Y, Z, CX, CZ, CY, SWAP, ISWAP, MEASURE = 0, 1, 2, 3, 4, 5, 6, 7, 8, 9, 10, 11, 15
 (K_LAYER, K_SIGNS, K_PIVOT, K_GATHER, K_ROWSUM, K_POST, K_BPIVOT, K_BPREP, K_BPASS, K_BFINAL,
- K_IPIVOT, K_IAPPLY) = range(12)
+ K_IPIVOT, K_IAPPLY, K_TRANSPOSE, K_RPREP, K_RROWSUM, K_RDET, K_RFINISH) = range(17)
 KERNEL_NAMES = ["layer", "signs", "pivot", "gather", "rowsum", "post",
-                "block_pivot", "block_prep", "block_pass", "block_final", "inject_pivot", "inject_apply"]
+                "block_pivot", "block_prep", "block_pass", "block_final", "inject_pivot", "inject_apply",
+                "transpose", "row_prep", "row_rowsum", "row_det", "row_finish"]
+LAYOUT_COLUMNS, LAYOUT_ROWS = 0, 1  # sq_set_layout
 COLLAPSE_ROWSUM, COLLAPSE_INJECT = 0, 1  # sq_set_collapse modes
 MAX_MEAS_BLOCK = 32
 PIVOT_AUTO = 255         # sq_tuning.pivot_waves: choose the pivot search automatically
@@ -36,7 +38,7 @@ EXPORTED = [
     "sq_get_tuning", "sq_set_tuning", "sq_profile_enable", "sq_profile_read", "sq_profile_reset",
     "sq_qasm_parse", "sq_frame_sample", "sq_set_graphs", "sq_graph_stats",
     "sq_create_in", "sq_layout", "sq_batch_item_bytes", "sq_sample_many", "sq_sample_bytes",
-    "sq_set_collapse", "sq_get_collapse", "sq_measure_noalloc",
+    "sq_set_collapse", "sq_get_collapse", "sq_measure_noalloc", "sq_set_layout", "sq_get_layout",
 ]
 
 
@@ -118,6 +120,8 @@ def load(path: str = LIB_PATH):
         "sq_sync": (i32, [vp]),
         "sq_set_collapse": (i32, [vp, u32]),
         "sq_get_collapse": (u32, [vp]),
+        "sq_set_layout": (i32, [vp, u32]),
+        "sq_get_layout": (u32, [vp]),
         "sq_num_qubits": (u32, [vp]),
         "sq_apply_gates": (i32, [vp, vp, u64]),
         "sq_measure": (i32, [vp, vp, u32, u64, u64, u64, vp, vp]),
@@ -279,6 +283,14 @@ class Tableau:
     @property
     def collapse(self) -> int:
         return int(self.lib.sq_get_collapse(self.h))
+
+    def set_layout(self, layout: int):
+        """LAYOUT_COLUMNS or LAYOUT_ROWS (queues the in-place transpose)."""
+        _check(self.lib.sq_set_layout(self.h, int(layout)))
+
+    @property
+    def layout(self) -> int:
+        return int(self.lib.sq_get_layout(self.h))
 
     def apply_gates(self, ops):
         a = ops_array(ops)

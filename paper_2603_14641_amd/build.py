@@ -8,7 +8,7 @@ PKG = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 LIB = os.path.join(PKG, "libsq.so")
-SOURCES = ["sq_gates.hip", "sq_measure.hip", "sq_block.hip", "sq_inject.hip", "sq_sample.hip", "sq_batch.hip", "sq_io.hip",
+SOURCES = ["sq_gates.hip", "sq_measure.hip", "sq_block.hip", "sq_inject.hip", "sq_rows.hip", "sq_sample.hip", "sq_batch.hip", "sq_io.hip",
            "sq_runtime.hip", "sq_qasm.hip", "sq_frames.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

@@ -104,6 +104,30 @@ __device__ __forceinline__ u64 xor_and(u64 a, u64 b, u32 m) {
   return ((u64)hi << 32) | lo;
 }
 
+// Transpose of a 64 x 64 bit tile held one word per lane: on return lane l
+// holds the word whose bit b is bit l of lane b's input word. Six butterfly
+// steps exchange blocks of 32, 16, ... 1 bits between lanes l and l ^ j
+// (the bit-group shuffle with masks 0x00000000FFFFFFFF ... 0x5555...).
+// Every lane of the wave must take part.
+__device__ __forceinline__ u64 transpose64(u64 v) {
+  const u32 lane = threadIdx.x & 63u;
+  const u64 masks[6] = {0x00000000FFFFFFFFULL, 0x0000FFFF0000FFFFULL, 0x00FF00FF00FF00FFULL,
+                        0x0F0F0F0F0F0F0F0FULL, 0x3333333333333333ULL, 0x5555555555555555ULL};
+#pragma unroll
+  for (int k = 0; k < 6; ++k) {
+    const u32 j = 32u >> k;
+    const u64 other = shfl_xor_u64(v, (int)j);
+    if ((lane & j) == 0) {
+      const u64 t = ((v >> j) ^ other) & masks[k];
+      v ^= t << j;
+    } else {
+      const u64 t = ((other >> j) ^ v) & masks[k];
+      v ^= t;
+    }
+  }
+  return v;
+}
+
 // 64-bit broadcast of lane src's value, as two 32-bit shuffles.
 __device__ __forceinline__ u64 shfl_u64(u64 v, int src) {
   const u32 lo = (u32)__shfl((int)(u32)v, src), hi = (u32)__shfl((int)(u32)(v >> 32), src);

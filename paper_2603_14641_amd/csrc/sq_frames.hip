@@ -51,21 +51,7 @@ __global__ __launch_bounds__(256) void k_frame_transpose(const u64 *__restrict__
   const u32 iw = (u32)(tile % W), w = (u32)(tile / W);
   if (w >= Lf) return;  // uniform over the wave
   const u64 m = (u64)iw * 64u + lane;
-  u64 v = m < M ? rec[m * Lf + w] : 0ULL;
-  const u64 masks[6] = {0x00000000FFFFFFFFULL, 0x0000FFFF0000FFFFULL, 0x00FF00FF00FF00FFULL,
-                        0x0F0F0F0F0F0F0F0FULL, 0x3333333333333333ULL, 0x5555555555555555ULL};
-#pragma unroll
-  for (int k = 0; k < 6; ++k) {
-    const u32 j = 32u >> k;
-    const u64 other = shfl_xor_u64(v, (int)j);
-    if ((lane & j) == 0) {
-      const u64 t = ((v >> j) ^ other) & masks[k];
-      v ^= t << j;
-    } else {
-      const u64 t = ((other >> j) ^ v) & masks[k];
-      v ^= t;
-    }
-  }
+  const u64 v = transpose64(m < M ? rec[m * Lf + w] : 0ULL);
   const u64 s = (u64)w * 64u + lane;
   if (s < shots) out[s * W + iw] = v;
 }

@@ -307,8 +307,9 @@ __device__ __forceinline__ void add2(u64 &lo, u64 &hi, u64 nlo, u64 nhi) {
   lo ^= nlo;
 }
 
-// Replay a group's micro-ops on its qubits' image signs (thread 0). The
-// phase exponent of every product must be even; an odd one sets flag bit 0.
+// Replay a group's micro-ops on its qubits' image signs, given the total
+// phase counters (lo, hi) of its products. The phase exponent of every
+// product must be even; an odd one sets flag bit 0.
 __device__ void replay_signs(const u32 *rec, u64 lo, u64 hi, u64 *__restrict__ R, u32 K, u32 *__restrict__ flags) {
   const u32 hdr = rec[0];
   const u32 nq = hdr & 15u, nops = (hdr >> WH_NOPS_SHIFT) & 63u;
@@ -361,50 +362,62 @@ __device__ void replay_signs(const u32 *rec, u64 lo, u64 hi, u64 *__restrict__ R
   }
 }
 
-__global__ __launch_bounds__(256) void k_layer_op(u64 *__restrict__ X, u64 *__restrict__ Z, u64 *__restrict__ R,
+// Grid (position tiles, group chunks), as k_layer: a thread owns position
+// word w (destabilizer word w and stabilizer word K + w of each column of
+// the group) and walks its chunk's groups, applying the micro-ops and adding
+// each product's phase over its 64 positions into bit-sliced counters. Per
+// group a wave sums its counters (butterfly) and lane 0 writes them to
+// part[(g - g_base) * nw + wave], nw being the waves along the position
+// dimension; k_layer_op_signs then adds a group's nw partials and replays
+// its micro-ops on the signs. No barriers: every lane takes part in the
+// butterflies (lanes past the last position word hold zero counters).
+__global__ __launch_bounds__(256) void k_layer_op(u64 *__restrict__ X, u64 *__restrict__ Z,
                                                   const u32 *__restrict__ words, const u32 *__restrict__ offs,
-                                                  u32 ngroups, u32 gpc, u32 Ls, u32 K, u32 *__restrict__ flags) {
-  __shared__ u64 s_lo[4], s_hi[4];
-  const u32 tid = threadIdx.x, lane = tid & 63u, wave = tid >> 6, nwaves = blockDim.x >> 6;
-  const u32 g0 = blockIdx.x * gpc;
-  const u32 g1 = min(g0 + gpc, ngroups);
+                                                  u32 g_base, u32 g_end, u32 gpc, u32 Ls, u32 K,
+                                                  u64x2 *__restrict__ part) {
+  const u32 tid = threadIdx.x, lane = tid & 63u;
+  const u32 w = blockIdx.x * blockDim.x + tid;
+  const bool act = w < K;
+  const u32 nw = gridDim.x * (blockDim.x >> 6), wv = blockIdx.x * (blockDim.x >> 6) + (tid >> 6);
+  const u32 g0 = g_base + blockIdx.y * gpc;
+  const u32 g1 = min(g0 + gpc, g_end);
   u64 sdummy[2];
   for (u32 g = g0; g < g1; ++g) {
     const u32 *rec = words + offs[g];
     const u32 hdr = rec[0];
     const u32 nq = hdr & 15u, nops = (hdr >> WH_NOPS_SHIFT) & 63u;
     const u32 *ops = rec + 1 + nq;
-    const u32 nw = (nops + 1u) >> 1;
+    Cols<2> c;
+#pragma unroll
+    for (u32 i = 0; i < WG_MAXQ; ++i) {
+      c.x[i][0] = c.x[i][1] = c.z[i][0] = c.z[i][1] = 0;
+      if (i < nq && act) {
+        const size_t o = (size_t)rec[1 + i] * Ls + w;
+        c.x[i][0] = __builtin_nontemporal_load(X + o);
+        c.x[i][1] = __builtin_nontemporal_load(X + o + K);
+        c.z[i][0] = __builtin_nontemporal_load(Z + o);
+        c.z[i][1] = __builtin_nontemporal_load(Z + o + K);
+      }
+    }
     u64 lo = 0, hi = 0;
-    for (u32 w = tid; w < K; w += blockDim.x) {
-      Cols<2> c;
+    const u32 nwd = (nops + 1u) >> 1;
+    u32 cur = ops[0];
+    for (u32 j = 0; j < nwd; ++j) {
+      const u32 nxt = (j + 1 < nwd) ? ops[j + 1] : 0u;
 #pragma unroll
-      for (u32 i = 0; i < WG_MAXQ; ++i) {
-        c.x[i][0] = c.x[i][1] = c.z[i][0] = c.z[i][1] = 0;
-        if (i < nq) {
-          const size_t o = (size_t)rec[1 + i] * Ls + w;
-          c.x[i][0] = __builtin_nontemporal_load(X + o);
-          c.x[i][1] = __builtin_nontemporal_load(X + o + K);
-          c.z[i][0] = __builtin_nontemporal_load(Z + o);
-          c.z[i][1] = __builtin_nontemporal_load(Z + o + K);
+      for (u32 h = 0; h < 2; ++h) {
+        const u32 k = 2 * j + h;
+        if (k < nops) {
+          const u32 op = (cur >> (16u * h)) & 0xFFFFu;
+          const u32 ph = op_phase(op, c);
+          lo |= ((u64)(ph & 1u) << (2 * k)) | ((u64)((ph >> 2) & 1u) << (2 * k + 1));
+          hi |= ((u64)((ph >> 1) & 1u) << (2 * k)) | ((u64)((ph >> 3) & 1u) << (2 * k + 1));
+          run_op<2>(op, c, sdummy);
         }
       }
-      u64 nlo = 0, nhi = 0;
-      for (u32 j = 0; j < nw; ++j) {
-        const u32 cur = ops[j];
-#pragma unroll
-        for (u32 h = 0; h < 2; ++h) {
-          const u32 k = 2 * j + h;
-          if (k < nops) {
-            const u32 op = (cur >> (16u * h)) & 0xFFFFu;
-            const u32 ph = op_phase(op, c);
-            nlo |= ((u64)(ph & 1u) << (2 * k)) | ((u64)((ph >> 2) & 1u) << (2 * k + 1));
-            nhi |= ((u64)((ph >> 1) & 1u) << (2 * k)) | ((u64)((ph >> 3) & 1u) << (2 * k + 1));
-            run_op<2>(op, c, sdummy);
-          }
-        }
-      }
-      add2(lo, hi, nlo, nhi);
+      cur = nxt;
+    }
+    if (act) {
 #pragma unroll
       for (u32 i = 0; i < WG_MAXQ; ++i) {
         if (i < nq) {
@@ -420,26 +433,46 @@ __global__ __launch_bounds__(256) void k_layer_op(u64 *__restrict__ X, u64 *__re
         }
       }
     }
-    // wave, then workgroup, sum of the counters
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) add2(lo, hi, shfl_xor_u64(lo, off), shfl_xor_u64(hi, off));
-    if (nwaves > 1) {
-      if (lane == 0) { s_lo[wave] = lo; s_hi[wave] = hi; }
-      __syncthreads();
-      if (tid == 0)
-        for (u32 v = 1; v < nwaves; ++v) add2(lo, hi, s_lo[v], s_hi[v]);
+    if (lane == 0) {
+      u64x2 v;
+      v.x = lo;
+      v.y = hi;
+      part[(size_t)(g - g_base) * nw + wv] = v;
     }
-    if (tid == 0) replay_signs(rec, lo, hi, R, K, flags);
-    if (nwaves > 1) __syncthreads();
   }
 }
 
-// One workgroup per chunk of gpc groups; block is 64 (K <= 64) or 256.
-hipError_t launch_layer_op(const TabDev &t, const u32 *words, const u32 *offs, u32 ngroups, u32 gpc, u32 *flags,
-                           hipStream_t s) {
-  const u32 block = t.K <= 64 ? 64 : 256;
-  hipLaunchKernelGGL(k_layer_op, dim3(cdiv(ngroups, gpc)), dim3(block), 0, s, t.X, t.Z, t.R, words, offs, ngroups,
-                     gpc, t.Ls, t.K, flags);
+// A thread per group of [g_base, g_end): the sum of its nw partial counters,
+// then the sign replay.
+__global__ void k_layer_op_signs(u64 *__restrict__ R, const u32 *__restrict__ words, const u32 *__restrict__ offs,
+                                 u32 g_base, u32 g_end, u32 nw, u32 K, const u64x2 *__restrict__ part,
+                                 u32 *__restrict__ flags) {
+  const u32 g = g_base + blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= g_end) return;
+  u64 lo = 0, hi = 0;
+  const u64x2 *pp = part + (size_t)(g - g_base) * nw;
+  for (u32 v = 0; v < nw; ++v) {
+    const u64x2 t = pp[v];
+    add2(lo, hi, t.x, t.y);
+  }
+  replay_signs(words + offs[g], lo, hi, R, K, flags);
+}
+
+// A pass in ranges of at most max_groups groups (the partial counters of
+// one range fill `part`): per range the gate kernel, then the sign replay.
+hipError_t launch_layer_op(const TabDev &t, const u32 *words, const u32 *offs, u32 ngroups, u32 block, u32 gpc,
+                           u32 max_groups, u64 *part, u32 *flags, hipStream_t s) {
+  const u32 tiles = cdiv(t.K, block);
+  const u32 nw = tiles * (block / 64);
+  for (u32 g0 = 0; g0 < ngroups; g0 += max_groups) {
+    const u32 g1 = std::min(ngroups, g0 + max_groups);
+    hipLaunchKernelGGL(k_layer_op, dim3(tiles, cdiv(g1 - g0, gpc)), dim3(block), 0, s, t.X, t.Z, words, offs, g0, g1,
+                       gpc, t.Ls, t.K, reinterpret_cast<u64x2 *>(part));
+    hipLaunchKernelGGL(k_layer_op_signs, dim3(cdiv(g1 - g0, 256)), dim3(256), 0, s, t.R, words, offs, g0, g1, nw,
+                       t.K, reinterpret_cast<const u64x2 *>(part), flags);
+  }
   return hipGetLastError();
 }
 

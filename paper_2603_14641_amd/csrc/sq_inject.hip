@@ -181,11 +181,15 @@ __global__ __launch_bounds__(256) void k_inj_apply(u64 *__restrict__ X, u64 *__r
     const u32 cx = (u32)(xc[K + wp] >> sh) & 1u, cz = (u32)(zc[K + wp] >> sh) & 1u;
     const u32 d0x = (u32)(xc[wp] >> sh) & 1u, d0z = (u32)(zc[wp] >> sh) & 1u;
     u32 carx = d0x, carz = d0z, gx = 0, gz = 0;
+    // dense target list (every word from wp on holds a target, the usual
+    // case): the word index is the list index, so no list load
+    const bool dense = nT == K - wp;
+#pragma unroll 2
     for (u32 b = 0; b < nT; b += 64) {
       const u32 e = b + lane;
       u64 xd = 0, zd = 0, xs = 0, zs = 0;
       if (e < nT) {
-        const u32 w = tw[e];
+        const u32 w = dense ? wp + e : tw[e];
         const u64 m = mask[w];
         xd = __builtin_nontemporal_load(xc + w) & m;
         zd = __builtin_nontemporal_load(zc + w) & m;

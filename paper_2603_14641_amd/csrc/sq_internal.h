@@ -97,6 +97,8 @@ struct MeasState {
   u32 nsv;        // sampling: coin columns in which S_p has a 1 (compacted list length)
   u32 det_done;   // deterministic case: blocks of k_post that have added their phase sums
   u32 inj;        // CX-injection collapse: bit 0 inverse-phase rotation (else H), bit 1 X injection
+  u32 pc;         // row layout: pivot candidate (grid-wide minimum; 0xFFFFFFFF none)
+  u32 naff;       // row layout: rows multiplied by the pivot in this measurement
 };
 
 // Symbolic-sign context of the sampler's sweep (sq_sample.hip); unused (zero)
@@ -154,6 +156,7 @@ struct BlkBuffers {
   u32 *patx, *patz;        // n each: per column, bit s = pivot s has x (z) there
   u64 *part;               // chunks * BLK_PART * Ls partial counters and parities
   BlkState *bs;
+  u32 *clist;              // n: the block's supported columns (some pivot not the identity), any order
 };
 
 // One circuit of a batched launch (sq_batch.hip): |0...0>, gate passes
@@ -191,10 +194,18 @@ hipError_t launch_layer(const TabDev &t, const u32 *words, const u32 *offs, u32 
 hipError_t launch_sign_reduce(const TabDev &t, const u64 *sign_part, u32 nchunks, hipStream_t s);
 // Operator-tableau mode (sq_gates.hip, sq_inject.hip): R holds the image
 // signs, word w < K the signs of A_q = image of X_q, word K + w those of B_q.
-hipError_t launch_layer_op(const TabDev &t, const u32 *words, const u32 *offs, u32 ngroups, u32 gpc, u32 *flags,
-                           hipStream_t s);
+hipError_t launch_layer_op(const TabDev &t, const u32 *words, const u32 *offs, u32 ngroups, u32 block, u32 gpc,
+                           u32 max_groups, u64 *part, u32 *flags, hipStream_t s);
 hipError_t launch_inj_pivot(const TabDev &t, Cursor *cur, MeasState *st, u64 *mask, u32 *tw, MeasStats *stats,
                             hipStream_t s);
+// Row-contiguous layout (sq_rows.hip).
+hipError_t launch_transpose(const TabDev &t, hipStream_t s);
+hipError_t launch_row_begin(MeasState *st, hipStream_t s);
+hipError_t launch_row_prep(const TabDev &t, Cursor *cur, MeasState *st, u64 *pivx, u64 *pivz, hipStream_t s);
+hipError_t launch_row_rowsum(const TabDev &t, MeasState *st, const u64 *pivx, const u64 *pivz, hipStream_t s);
+hipError_t launch_row_det(const TabDev &t, MeasState *st, u64 *xsum, u64 *zsum, u32 det_blocks, hipStream_t s);
+hipError_t launch_row_finish(const TabDev &t, Cursor *cur, MeasState *st, const u64 *pivx, const u64 *pivz,
+                             MeasStats *stats, hipStream_t s);
 hipError_t launch_inj_apply(const TabDev &t, const MeasState *st, const u64 *mask, const u32 *tw, MeasStats *stats,
                             hipStream_t s);
 hipError_t launch_cursor_init(Cursor *c, u32 end, u32 kb, u64 seed, u64 shot, u64 meas_base, const u32 *qubits,

@@ -114,6 +114,7 @@ struct sq_tableau {
   size_t dev_offs_cap = 0;
   sq_tuning tun{};
   u32 collapse = SQ_COLLAPSE_ROWSUM;  // what the sign bits mean and how measurements collapse
+  bool rows = false;                  // row-contiguous layout (sq_set_layout)
   WideBuilder builder;
   // program gate segments replayed as graphs, most recently used last
   struct SegGraph {
@@ -164,7 +165,7 @@ u32 blk_cpc_of(const Dims &d) {
   return std::max<u32>(cpc, cdiv(d.n, kBlkMaxChunks));
 }
 
-constexpr int kLayoutSlots = 19;
+constexpr int kLayoutSlots = 20;
 
 size_t layout_words(const Dims &d, size_t *off) {
   // offsets (in words) of: X, Z, R, mask, pivx, pivz, cnt0, cnt1, sign_part, cols, st, stats,
@@ -175,8 +176,10 @@ size_t layout_words(const Dims &d, size_t *off) {
     o += (words + 31) / 32 * 32;  // 256-byte alignment
     return r;
   };
-  off[0] = take((size_t)d.n * d.Ls);
-  off[1] = take((size_t)d.n * d.Ls);
+  // X and Z hold 64K column slots (K = ceil(n/64)): the row layout needs a
+  // square 64K x 64K bit matrix per half; slots n .. 64K-1 stay zero
+  off[0] = take((size_t)64 * d.K * d.Ls);
+  off[1] = take((size_t)64 * d.K * d.Ls);
   off[2] = take(d.Ls);
   off[3] = take(d.Ls);
   off[4] = take(d.K);
@@ -194,6 +197,7 @@ size_t layout_words(const Dims &d, size_t *off) {
   off[16] = take((size_t)cdiv(d.n, blk_cpc_of(d)) * BLK_PART * d.Ls);
   off[17] = take(sizeof(BlkState) / 8 + 1);
   off[18] = take(sizeof(Cursor) / 8 + 1);
+  off[19] = take((d.n + 1) / 2);  // supported-column list of a measurement block (n u32)
   return o;
 }
 
@@ -291,11 +295,22 @@ sq_status collect_profile(sq_tableau *T) {
     if (s_ != SQ_OK) return s_;      \
   } while (0)
 
-// Groups per workgroup of the operator-tableau gate pass: a workgroup walks
-// whole columns, so a pass wants about 4,096 workgroups.
-u32 layer_op_gpc(const sq_tableau *T, u32 ngroups) {
-  u32 gpc = T->tun.layer_groups ? T->tun.layer_groups : cdiv(ngroups, 4096);
-  return std::max<u32>(gpc, 1);
+// Operator-tableau gate pass (k_layer_op): a thread per position word, the
+// workgroup size 64 for K <= 64 words, else 256; about 6,000 workgroups per
+// pass as for k_layer; its per-wave phase counters (16 bytes per group and
+// wave) live in the sign_part buffer, which bounds the groups per launch.
+struct OpGeom {
+  u32 block, gpc, max_groups;
+};
+OpGeom layer_op_geom(const sq_tableau *T, u32 ngroups) {
+  OpGeom g;
+  g.block = T->d.K <= 64 ? 64 : 256;
+  const u32 tiles = cdiv(T->d.K, g.block);
+  const u32 nw = tiles * (g.block / 64);
+  g.gpc = T->tun.layer_groups ? T->tun.layer_groups : cdiv(ngroups, std::max<u32>(1, 6144 / tiles));
+  g.gpc = std::max<u32>(g.gpc, 1);
+  g.max_groups = (u32)std::min<size_t>((size_t)kMaxChunks * T->d.Ls / 2 / nw, 1u << 30);
+  return g;
 }
 
 sq_status run_passes_on(sq_tableau *T, hipStream_t stream, const u32 *dev_words, const u32 *dev_offs,
@@ -305,7 +320,9 @@ sq_status run_passes_on(sq_tableau *T, hipStream_t stream, const u32 *dev_words,
       const PassRange &p = passes[i];
       const u32 *offs = dev_offs + p.offset;
       SQ_TRY(timed(T, SQ_K_LAYER, [&] {
-        return launch_layer_op(T->t, dev_words, offs, p.count, layer_op_gpc(T, p.count), &T->st->flags, stream);
+        const OpGeom g = layer_op_geom(T, p.count);
+        return launch_layer_op(T->t, dev_words, offs, p.count, g.block, g.gpc, g.max_groups, T->sign_part,
+                               &T->st->flags, stream);
       }));
     }
     return SQ_OK;
@@ -329,6 +346,20 @@ sq_status run_passes(sq_tableau *T, const u32 *dev_words, const u32 *dev_offs, c
   return run_passes_on(T, T->stream, dev_words, dev_offs, passes, first, count);
 }
 
+// Row blocks of the row layout's deterministic product (partial XORs in cnt0
+// and cnt1, which hold kMaxChunks rows of Ls words).
+constexpr u32 kRowDetBlocks = 64;
+static_assert(kRowDetBlocks <= kMaxChunks, "row-layout block sums must fit the chunk buffers");
+
+// Switch the layout (the transpose is its own inverse).
+sq_status set_rows(sq_tableau *T, bool rows) {
+  if (T->rows == rows) return SQ_OK;
+  SQ_TRY(timed(T, SQ_K_TRANSPOSE, [&] { return launch_transpose(T->t, T->stream); }));
+  if (rows) HIP_TRY(launch_row_begin(T->st, T->stream));
+  T->rows = rows;
+  return SQ_OK;
+}
+
 constexpr size_t kMaxSegGraphs = 32;
 
 // A program's gate segment: kernel by kernel on its first run (or while
@@ -338,6 +369,7 @@ constexpr size_t kMaxSegGraphs = 32;
 // as that graph. The graph holds T's buffers and the program's records, both
 // fixed for their lifetimes, and the launch geometry of the capture.
 sq_status run_gate_segment(sq_tableau *T, const sq_program *P, u64 first, u64 count) {
+  if (count) SQ_TRY(set_rows(T, false));  // gate passes work on columns
   if (!T->use_graphs || T->prof || count == 0)
     return run_passes(T, P->dev_words, P->dev_offs, P->passes, first, count);
   const sq_tuning &tn = T->tun;
@@ -459,6 +491,17 @@ struct SweepCtx {
 };
 
 sq_status queue_slot(sq_tableau *T, const SweepCtx &c, u32 kb) {
+  if (T->rows) {
+    SQ_TRY(timed(T, SQ_K_RPREP, [&] { return launch_row_prep(c.tab, T->cur, T->st, T->pivx, T->pivz, T->stream); }));
+    SQ_TRY(timed(T, SQ_K_RROWSUM, [&] { return launch_row_rowsum(c.tab, T->st, T->pivx, T->pivz, T->stream); }));
+    SQ_TRY(timed(T, SQ_K_RDET, [&] {
+      return launch_row_det(c.tab, T->st, T->cnt0, T->cnt1, kRowDetBlocks, T->stream);
+    }));
+    SQ_TRY(timed(T, SQ_K_RFINISH, [&] {
+      return launch_row_finish(c.tab, T->cur, T->st, T->pivx, T->pivz, T->stats, T->stream);
+    }));
+    return SQ_OK;
+  }
   if (T->collapse == SQ_COLLAPSE_INJECT) {
     SQ_TRY(timed(T, SQ_K_IPIVOT, [&] {
       return launch_inj_pivot(c.tab, T->cur, T->st, T->mask, T->cols, T->stats, T->stream);
@@ -505,7 +548,7 @@ sq_status queue_slot(sq_tableau *T, const SweepCtx &c, u32 kb) {
 
 // Measurements offered per slot: the CX-injection collapse takes one at a time.
 u32 sweep_kb(const sq_tableau *T) {
-  return T->collapse == SQ_COLLAPSE_INJECT ? 1u : std::min<u32>(T->tun.meas_block, KB);
+  return (T->collapse == SQ_COLLAPSE_INJECT || T->rows) ? 1u : std::min<u32>(T->tun.meas_block, KB);
 }
 
 // Queue the sweep of a list of `count` measurements whose cursor has been
@@ -545,6 +588,7 @@ sq_status ensure_capacity(sq_tableau *T, u32 **buf, size_t *cap, size_t need) {
 }
 
 sq_status reset_device(sq_tableau *T) {
+  T->rows = false;
   size_t off[kLayoutSlots];
   const size_t words = layout_words(T->d, off);
   HIP_TRY(launch_fill_zero(T->base, words, T->stream));
@@ -635,7 +679,7 @@ sq_status create_tableau(uint32_t n, void *hip_stream, void *dev_buf, size_t byt
   T->st = reinterpret_cast<MeasState *>(b + off[10]);
   T->stats = reinterpret_cast<MeasStats *>(b + off[11]);
   T->blk = BlkBuffers{b + off[12], reinterpret_cast<u32 *>(b + off[13]), reinterpret_cast<u32 *>(b + off[14]),
-                      reinterpret_cast<u32 *>(b + off[15]), b + off[16], reinterpret_cast<BlkState *>(b + off[17])};
+                      reinterpret_cast<u32 *>(b + off[15]), b + off[16], reinterpret_cast<BlkState *>(b + off[17]), reinterpret_cast<u32 *>(b + off[19])};
   T->cur = reinterpret_cast<Cursor *>(b + off[18]);
   T->blk_cpc = blk_cpc_of(T->d);
   default_tuning(T->d, &T->tun);
@@ -720,6 +764,16 @@ sq_status sq_set_collapse(sq_tableau *T, uint32_t mode) {
 
 uint32_t sq_get_collapse(const sq_tableau *T) { return T ? T->collapse : 0u; }
 
+sq_status sq_set_layout(sq_tableau *T, uint32_t layout) {
+  if (!T) return fail(SQ_EINVAL, "tableau is NULL");
+  if (layout != SQ_LAYOUT_COLUMNS && layout != SQ_LAYOUT_ROWS) return fail(SQ_EINVAL, "unknown layout %u", layout);
+  if (layout == SQ_LAYOUT_ROWS && T->collapse != SQ_COLLAPSE_ROWSUM)
+    return fail(SQ_EINVAL, "the row layout serves the rowsum collapse only");
+  return set_rows(T, layout == SQ_LAYOUT_ROWS);
+}
+
+uint32_t sq_get_layout(const sq_tableau *T) { return T && T->rows ? (uint32_t)SQ_LAYOUT_ROWS : 0u; }
+
 sq_status sq_sync(sq_tableau *T) {
   if (!T) return fail(SQ_EINVAL, "tableau is NULL");
   HIP_TRY(hipStreamSynchronize(T->stream));
@@ -732,6 +786,7 @@ sq_status sq_apply_gates(sq_tableau *T, const sq_op *ops, uint64_t count) {
   if (!T) return fail(SQ_EINVAL, "tableau is NULL");
   SQ_TRY(validate_ops(T->d.n, ops, count, false));
   if (count == 0) return SQ_OK;
+  SQ_TRY(set_rows(T, false));  // gate passes work on columns
   WideBuilder &pb = T->builder;
   plan_gate_list(T->d.n, T->d.L, ops, count, pb);
   if (pb.offs.empty()) return SQ_OK;
@@ -884,6 +939,7 @@ sq_status sq_sample_many(sq_tableau *T, const uint32_t *qubits, uint32_t count, 
     shots = std::max(shots, sets[k].shots);
   }
   if (count == 0 || shots == 0) return SQ_OK;
+  SQ_TRY(set_rows(T, false));  // the sampling sweep works on a column-layout copy
   if (!qubits) return fail(SQ_EINVAL, "qubits is NULL");
   for (u32 i = 0; i < count; ++i)
     if (qubits[i] >= T->d.n) return fail(SQ_ERANGE, "qubit %u >= n=%u", qubits[i], T->d.n);
@@ -1394,6 +1450,7 @@ sq_status sq_export_rows(sq_tableau *T, const uint32_t *rows, uint32_t nrows, ui
   if (!rows || !hx || !hz || !hr) return fail(SQ_EINVAL, "NULL buffer");
   for (u32 k = 0; k < nrows; ++k)
     if (rows[k] >= 2 * T->d.n) return fail(SQ_ERANGE, "row %u >= 2n=%u", rows[k], 2 * T->d.n);
+  SQ_TRY(set_rows(T, false));
   const u32 W = T->d.K;
   const size_t xwords = (size_t)nrows * W;
   void *buf = nullptr;
@@ -1437,6 +1494,7 @@ sq_status sq_import(sq_tableau *T, const uint64_t *hx, const uint64_t *hz, const
       if ((hx[g * W + W - 1] & bad) || (hz[g * W + W - 1] & bad))
         return fail(SQ_EINVAL, "row %zu has bits at qubit positions >= n", g);
   }
+  SQ_TRY(set_rows(T, false));
   void *buf = nullptr;
   const size_t bytes = 2 * xwords * 8 + rows + 256;
   if (hipMallocAsync(&buf, bytes, T->stream) != hipSuccess) {

@@ -33,7 +33,7 @@ KERNEL_SOURCES = {
     "k_layer": "sq_gates.hip", "k_sign_reduce": "sq_gates.hip",
     "k_pivot": "sq_measure.hip", "k_gather": "sq_measure.hip", "k_rowsum": "sq_measure.hip",
     "k_post": "sq_measure.hip", "k_cursor_init": "sq_measure.hip",
-    "k_blk_": "sq_block.hip",
+    "k_blk_": "sq_block.hip", "k_inj_": "sq_inject.hip", "k_transpose": "sq_rows.hip", "k_row_": "sq_rows.hip",
     "k_sample_init": "sq_sample.hip", "k_coins": "sq_sample.hip", "k_eval": "sq_sample.hip",
     "k_batch": "sq_batch.hip",
     "k_frame_": "sq_frames.hip",

@@ -4,7 +4,7 @@ batched path (sq_batch_sample, default schedule) against the single-tableau
 path on every shot of every request, and against the oracle's per-shot CHP
 outcomes stored in tests/golden/served_mix_oracle.json (every shot where
 n <= 256; shots {0, 1, S-1} and 5 seeded others where n <= 2048; shots
-{0, S-1} of 12 seeded requests above that), compared through the SHA-256
+{0, S-1} of 8 seeded requests with 2048 < n <= 8192), compared through the SHA-256
 of the checked shots' outcome words. Needs an MI355X."""
 import hashlib
 import json
@@ -49,7 +49,9 @@ def _digest(words, shots):
 @pytest.mark.timeout(1200)
 def test_served_mix_all_requests_batched_plain_and_oracle():
     from paper_2603_14641_amd import Tableau, batch_sample
-    golden = json.load(open(GOLDEN))["requests"]
+    doc = json.load(open(GOLDEN))
+    assert doc.get("complete", False), "the oracle fixture is incomplete: rerun its script"
+    golden = doc["requests"]
     t0 = time.time()
     reqs = _requests()
     print(f"512 requests drawn in {time.time() - t0:.1f} s", flush=True)
