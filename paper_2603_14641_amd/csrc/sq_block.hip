@@ -360,7 +360,8 @@ constexpr u32 ROWS_W = ROWS_T / 64;  // waves per block
 __device__ __forceinline__ void blk_rows(const u64 *__restrict__ X, const u64 *__restrict__ Z,
                                          const u64 *__restrict__ R, u32 Ls, u32 K, u32 n, BlkState *__restrict__ bs,
                                          u32 *__restrict__ patx, u32 *__restrict__ patz, u32 *__restrict__ wpart,
-                                         MeasState *__restrict__ st, u32 bid, u32 nblocks) {
+                                         u32 *__restrict__ clist, MeasState *__restrict__ st, u32 bid,
+                                         u32 nblocks) {
   __shared__ u64 s0x[ROWS_W][KB], s0z[ROWS_W][KB], sx[ROWS_W][KB], sz[ROWS_W][KB];
   __shared__ u32 red[4][ROWS_T / KB][KB];  // per-wave shares, then per-group sums
   __shared__ u32 s_last;
@@ -422,8 +423,14 @@ __device__ __forceinline__ void blk_rows(const u64 *__restrict__ X, const u64 *_
     patx[j] = px;
     patz[j] = pz;
   }
-  const u32 c = (u32)__popcll(__ballot(j < n && (px | pz) != 0));
-  if (lane == 0 && c) atomicAdd(&bs->ncols, c);
+  // the supported columns, compacted into clist (any order: the pass sums
+  // over columns)
+  const bool sup = j < n && (px | pz) != 0;
+  const u64 sb = __ballot(sup);
+  u32 cbase = 0;
+  if (lane == 0 && sb) cbase = atomicAdd(&bs->ncols, (u32)__popcll(sb));
+  cbase = (u32)__shfl((int)cbase, 0);
+  if (sup) clist[cbase + (u32)__popcll(sb & lanemask_lt())] = j;
   // (4) pair shares, lane a for pivot a
   if (lane == 0) {
 #pragma unroll
@@ -555,85 +562,101 @@ __global__ __launch_bounds__(ROWS_T) void k_blk_masks_rows(const u64 *__restrict
                                                            const u64 *__restrict__ R, u64 *__restrict__ bm,
                                                            BlkState *__restrict__ bs,
                                                            u32 *__restrict__ patx, u32 *__restrict__ patz,
-                                                           u32 *__restrict__ wpart, MeasState *__restrict__ st,
-                                                           u32 Ls, u32 L, u32 K, u32 n, u32 mblocks) {
+                                                           u32 *__restrict__ wpart, u32 *__restrict__ clist,
+                                                           MeasState *__restrict__ st, u32 Ls, u32 L, u32 K, u32 n,
+                                                           u32 mblocks) {
   if (blockIdx.x < mblocks)
     blk_masks(X, bm, bs, Ls, L, K, blockIdx.x);
   else
-    blk_rows(X, Z, R, Ls, K, n, bs, patx, patz, wpart, st, blockIdx.x - mblocks, gridDim.x - mblocks);
+    blk_rows(X, Z, R, Ls, K, n, bs, patx, patz, wpart, clist, st, blockIdx.x - mblocks, gridDim.x - mblocks);
 }
 
 constexpr u32 BLK_PASS_T = 512;
 
 // -------------------------------------------------------------- the pass
 // Grid (row tiles of BLK_PASS_T words, column chunks). A thread owns one row
-// word; per column where some pivot is not the identity (patterns from
-// k_blk_masks_rows, uniform over the wave): XOR in the masks of the pivots with x
-// (z) on that column, count |x & z| - |x' & z'| (mod 4) and the parities
-// z_{P_s} . x_h. Columns are streamed with the non-temporal hint.
+// word. The chunks split the block's list of supported columns (those where
+// some pivot is not the identity, compacted by k_blk_masks_rows) evenly; a
+// workgroup stages its share of the list in LDS (BLK_LIST entries at a
+// time) and walks it with the row words of the next two columns loaded
+// ahead. Per column (patterns uniform over the wave): XOR in the masks of
+// the pivots with x (z) there, count |x & z| - |x' & z'| (mod 4) and the
+// parities z_{P_s} . x_h. Columns are streamed with the non-temporal hint;
+// unsupported columns are never touched.
+constexpr u32 BLK_LIST = 2048;
+
 __global__ __launch_bounds__(BLK_PASS_T) void k_blk_pass(u64 *__restrict__ X, u64 *__restrict__ Z,
                                                   const u64 *__restrict__ bm, const u32 *__restrict__ patx,
                                                   const u32 *__restrict__ patz, const BlkState *__restrict__ bs,
-                                                  u64 *__restrict__ part, u32 Ls, u32 L, u32 n, u32 cpc) {
+                                                  const u32 *__restrict__ clist, u64 *__restrict__ part, u32 Ls,
+                                                  u32 L) {
+  __shared__ u32 s_cols[BLK_LIST];
   const u32 k = bs->k;
-  if (k == 0) return;
+  if (k == 0) return;  // the same for every workgroup
   const u32 w = blockIdx.x * blockDim.x + threadIdx.x;
-  if (w >= L) return;
-  const u32 j0 = blockIdx.y * cpc;
-  if (j0 >= n) return;
-  const u32 j1 = min(j0 + cpc, n);
+  const u32 nc = bs->ncols;
+  const u32 e0 = (u32)(((u64)blockIdx.y * nc) / gridDim.y), e1 = (u32)(((u64)(blockIdx.y + 1) * nc) / gridDim.y);
   u64 b[KB];
   u64 any = 0;
 #pragma unroll
   for (u32 s = 0; s < KB; ++s) {
-    const u64 v = bm[(size_t)s * Ls + w];  // rows past k are allocated: load, then mask
+    const u64 v = w < L ? bm[(size_t)s * Ls + w] : 0ULL;  // rows past k are allocated: load, then mask
     b[s] = s < k ? v : 0ULL;
     any |= b[s];
   }
-  if (any == 0) return;
+  const bool act = any != 0;  // row words holding no hit row are left alone (and so are their partials)
   u64 yy = 0;          // z_{C_h} . x_h per row: XOR over columns of dz & x
   u64 d0 = 0, d1 = 0;  // |x & z| - |x' & z'| (mod 4), bit-sliced
-  // the row word of the next two columns is loaded ahead (the stores to
-  // column j cannot alias them, which the compiler cannot see by itself);
-  // columns where every pivot is the identity are neither loaded nor stored
-  auto supported = [&](u32 j) { return (patx[j] | patz[j]) != 0u; };  // uniform over the wave
-  u64 xa = 0, za = 0, xb = 0, zb = 0;
-  if (supported(j0)) {
-    xa = __builtin_nontemporal_load(X + (size_t)j0 * Ls + w);
-    za = __builtin_nontemporal_load(Z + (size_t)j0 * Ls + w);
-  }
-  if (j0 + 1 < j1 && supported(j0 + 1)) {
-    xb = __builtin_nontemporal_load(X + (size_t)(j0 + 1) * Ls + w);
-    zb = __builtin_nontemporal_load(Z + (size_t)(j0 + 1) * Ls + w);
-  }
-  for (u32 j = j0; j < j1; ++j) {
-    const size_t o = (size_t)j * Ls + w;
-    const u64 x = xa, z = za;
-    xa = xb;
-    za = zb;
-    if (j + 2 < j1 && supported(j + 2)) {
-      xb = __builtin_nontemporal_load(X + o + 2 * (size_t)Ls);
-      zb = __builtin_nontemporal_load(Z + o + 2 * (size_t)Ls);
+  for (u32 c0 = e0; c0 < e1; c0 += BLK_LIST) {
+    const u32 cn = min(e1 - c0, BLK_LIST);
+    __syncthreads();  // the previous share of the list is consumed
+    for (u32 i = threadIdx.x; i < cn; i += blockDim.x) s_cols[i] = clist[c0 + i];
+    __syncthreads();
+    if (!act) continue;
+    // the row word of the next two columns is loaded ahead (the stores to
+    // column j cannot alias them, which the compiler cannot see by itself)
+    u64 xa = 0, za = 0, xb = 0, zb = 0;
+    {
+      const size_t oa = (size_t)s_cols[0] * Ls + w;
+      xa = __builtin_nontemporal_load(X + oa);
+      za = __builtin_nontemporal_load(Z + oa);
     }
-    const u32 px = patx[j], pz = patz[j];
-    if ((px | pz) == 0) continue;
-    u64 dx = 0, dz = 0;
+    if (cn > 1) {
+      const size_t ob = (size_t)s_cols[1] * Ls + w;
+      xb = __builtin_nontemporal_load(X + ob);
+      zb = __builtin_nontemporal_load(Z + ob);
+    }
+    for (u32 i = 0; i < cn; ++i) {
+      const u32 j = s_cols[i];
+      const size_t o = (size_t)j * Ls + w;
+      const u64 x = xa, z = za;
+      xa = xb;
+      za = zb;
+      if (i + 2 < cn) {
+        const size_t o2 = (size_t)s_cols[i + 2] * Ls + w;
+        xb = __builtin_nontemporal_load(X + o2);
+        zb = __builtin_nontemporal_load(Z + o2);
+      }
+      const u32 px = patx[j], pz = patz[j];
+      u64 dx = 0, dz = 0;
 #pragma unroll
-    for (u32 s = 0; s < KB; ++s) {  // all-ones / zero masks from the uniform patterns
-      dx = xor_and(dx, b[s], 0u - ((px >> s) & 1u));
-      dz = xor_and(dz, b[s], 0u - ((pz >> s) & 1u));
+      for (u32 s = 0; s < KB; ++s) {  // all-ones / zero masks from the uniform patterns
+        dx = xor_and(dx, b[s], 0u - ((px >> s) & 1u));
+        dz = xor_and(dz, b[s], 0u - ((pz >> s) & 1u));
+      }
+      yy ^= dz & x;
+      const u64 x2 = x ^ dx, z2 = z ^ dz;
+      const u64 o1 = x & z, n1 = x2 & z2;
+      const u64 plus = o1 & ~n1, minus = n1 & ~o1;
+      d1 ^= d0 & plus;
+      d0 ^= plus;
+      d0 ^= minus;
+      d1 ^= d0 & minus;
+      if (px) __builtin_nontemporal_store(x2, X + o);
+      if (pz) __builtin_nontemporal_store(z2, Z + o);
     }
-    yy ^= dz & x;
-    const u64 x2 = x ^ dx, z2 = z ^ dz;
-    const u64 o1 = x & z, n1 = x2 & z2;
-    const u64 plus = o1 & ~n1, minus = n1 & ~o1;
-    d1 ^= d0 & plus;
-    d0 ^= plus;
-    d0 ^= minus;
-    d1 ^= d0 & minus;
-    if (px) __builtin_nontemporal_store(x2, X + o);
-    if (pz) __builtin_nontemporal_store(z2, Z + o);
   }
+  if (!act) return;
   const size_t cs = (size_t)blockIdx.y * BLK_PART * Ls;
   part[cs + w] = d0;
   part[cs + Ls + w] = d1;
@@ -910,7 +933,7 @@ hipError_t launch_blk_pivots(const TabDev &t, Cursor *cur, const BlkBuffers &b, 
 hipError_t launch_blk_prep(const TabDev &t, const BlkBuffers &b, MeasState *st, hipStream_t s) {
   const u32 mblocks = cdiv(t.L, ROWS_T), rblocks = cdiv(t.n, ROWS_T);
   hipLaunchKernelGGL(k_blk_masks_rows, dim3(mblocks + rblocks), dim3(ROWS_T), 0, s, t.X, t.Z, t.R, b.bm, b.bs,
-                     b.patx, b.patz, b.wpart, st, t.Ls, t.L, t.K, t.n, mblocks);
+                     b.patx, b.patz, b.wpart, b.clist, st, t.Ls, t.L, t.K, t.n, mblocks);
   return hipGetLastError();
 }
 
@@ -918,7 +941,7 @@ hipError_t launch_blk_prep(const TabDev &t, const BlkBuffers &b, MeasState *st, 
 hipError_t launch_blk_pass(const TabDev &t, const BlkBuffers &b, u32 cpc, hipStream_t s) {
   const u32 nchunks = cdiv(t.n, cpc);
   hipLaunchKernelGGL(k_blk_pass, dim3(cdiv(t.L, BLK_PASS_T), nchunks), dim3(BLK_PASS_T), 0, s, t.X, t.Z, b.bm, b.patx,
-                     b.patz, b.bs, b.part, t.Ls, t.L, t.n, cpc);
+                     b.patz, b.bs, b.clist, b.part, t.Ls, t.L);
   return hipGetLastError();
 }
 

@@ -157,15 +157,16 @@ __global__ __launch_bounds__(1024) void k_inj_pivot(const u64 *__restrict__ X, c
 // l + 64, ...), flips the stabilizer words where S_p has a 1 and scans the
 // destabilizer bits, then applies the rotation and the X injection to the
 // pivot pair and the column's two signs. The pair's words may have been
-// rewritten by the scan, so those last bit changes are atomic XORs issued
-// after a fence; signs of 64 columns share a word (atomic XORs as well).
+// rewritten by the scan, so the pair's bit changes go to pair[j] (bit 0:
+// x of S_p, 1: x of D_p, 2: z of S_p, 3: z of D_p) and k_inj_pair applies
+// them after this kernel; signs of 64 columns share a word (atomic XORs).
 // Byte accounting: per column, read the two destabilizer words of each
 // target word, and read and write the stabilizer word of X (Z) where the
 // pivot has x (z).
 __global__ __launch_bounds__(256) void k_inj_apply(u64 *__restrict__ X, u64 *__restrict__ Z, u64 *__restrict__ R,
                                                    u32 Ls, u32 K, u32 n, const MeasState *__restrict__ st,
                                                    const u64 *__restrict__ mask, const u32 *__restrict__ tw,
-                                                   MeasStats *__restrict__ stats) {
+                                                   uint8_t *__restrict__ pair, MeasStats *__restrict__ stats) {
   const int32_t ps = st->p;
   if (ps < 0) return;
   __shared__ u32 s_cnt;
@@ -234,13 +235,8 @@ __global__ __launch_bounds__(256) void k_inj_apply(u64 *__restrict__ X, u64 *__r
       sb ^= dx;
       sa ^= dz;
     }
-    __threadfence();
     if (lane == 0) {
-      const u64 bit = 1ULL << sh;
-      if (sx != cx) atomicXor(xc + K + wp, bit);
-      if (dx != d0x) atomicXor(xc + wp, bit);
-      if (sz != cz) atomicXor(zc + K + wp, bit);
-      if (dz != d0z) atomicXor(zc + wp, bit);
+      pair[j] = (uint8_t)((sx ^ cx) | ((dx ^ d0x) << 1) | ((sz ^ cz) << 2) | ((dz ^ d0z) << 3));
       if (sb) atomicXor(R + K + (j >> 6), 1ULL << (j & 63u));
       if (sa) atomicXor(R + (j >> 6), 1ULL << (j & 63u));
       atomicAdd(&s_cnt, cx + cz);
@@ -254,16 +250,35 @@ __global__ __launch_bounds__(256) void k_inj_apply(u64 *__restrict__ X, u64 *__r
   }
 }
 
+// Thread per column: the pivot pair's bit changes recorded by k_inj_apply.
+__global__ void k_inj_pair(u64 *__restrict__ X, u64 *__restrict__ Z, u32 Ls, u32 K, u32 n,
+                           const MeasState *__restrict__ st, const uint8_t *__restrict__ pair) {
+  const int32_t ps = st->p;
+  if (ps < 0) return;
+  const u32 j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= n) return;
+  const u32 c = pair[j];
+  if (!c) return;
+  const u32 wp = (u32)ps >> 6;
+  const u64 bit = 1ULL << ((u32)ps & 63u);
+  u64 *xc = X + (size_t)j * Ls, *zc = Z + (size_t)j * Ls;
+  if (c & 1u) xc[K + wp] ^= bit;
+  if (c & 2u) xc[wp] ^= bit;
+  if (c & 4u) zc[K + wp] ^= bit;
+  if (c & 8u) zc[wp] ^= bit;
+}
+
 hipError_t launch_inj_pivot(const TabDev &t, Cursor *cur, MeasState *st, u64 *mask, u32 *tw, MeasStats *stats,
                             hipStream_t s) {
   hipLaunchKernelGGL(k_inj_pivot, dim3(1), dim3(1024), 0, s, t.X, t.R, t.Ls, t.K, cur, st, mask, tw, stats);
   return hipGetLastError();
 }
 
-hipError_t launch_inj_apply(const TabDev &t, const MeasState *st, const u64 *mask, const u32 *tw, MeasStats *stats,
-                            hipStream_t s) {
+hipError_t launch_inj_apply(const TabDev &t, const MeasState *st, const u64 *mask, const u32 *tw, uint8_t *pair,
+                            MeasStats *stats, hipStream_t s) {
   hipLaunchKernelGGL(k_inj_apply, dim3(cdiv(t.n, 4)), dim3(256), 0, s, t.X, t.Z, t.R, t.Ls, t.K, t.n, st, mask, tw,
-                     stats);
+                     pair, stats);
+  hipLaunchKernelGGL(k_inj_pair, dim3(cdiv(t.n, 256)), dim3(256), 0, s, t.X, t.Z, t.Ls, t.K, t.n, st, pair);
   return hipGetLastError();
 }
 

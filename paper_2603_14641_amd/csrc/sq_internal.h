@@ -206,8 +206,8 @@ hipError_t launch_row_rowsum(const TabDev &t, MeasState *st, const u64 *pivx, co
 hipError_t launch_row_det(const TabDev &t, MeasState *st, u64 *xsum, u64 *zsum, u32 det_blocks, hipStream_t s);
 hipError_t launch_row_finish(const TabDev &t, Cursor *cur, MeasState *st, const u64 *pivx, const u64 *pivz,
                              MeasStats *stats, hipStream_t s);
-hipError_t launch_inj_apply(const TabDev &t, const MeasState *st, const u64 *mask, const u32 *tw, MeasStats *stats,
-                            hipStream_t s);
+hipError_t launch_inj_apply(const TabDev &t, const MeasState *st, const u64 *mask, const u32 *tw, uint8_t *pair,
+                            MeasStats *stats, hipStream_t s);
 hipError_t launch_cursor_init(Cursor *c, u32 end, u32 kb, u64 seed, u64 shot, u64 meas_base, const u32 *qubits,
                               uint8_t *out_bits, uint8_t *out_rand, hipStream_t s);
 hipError_t launch_pivot(const TabDev &t, Cursor *cur, MeasState *st, u64 *mask, hipStream_t s);

@@ -33,57 +33,81 @@
 
 namespace sq {
 
-constexpr u32 TB = 16;  // tiles per side of a transposed block of tiles
+constexpr u32 TB = 16;         // tiles per side of a transposed block of tiles
+constexpr u32 TLINE = TB + 1;  // LDS words per staged slot line (padded against bank conflicts)
 
-// Grid (nb * nb, 4): block (bi, bj) of 16 x 16 tiles of one half of X or Z,
-// processed with its mirror (bj, bi); blocks below the diagonal exit. Wave v
-// holds slots 64 (16 bi + v) .. + 63 of side A (lane = slot), words
-// 16 bj .. 16 bj + 15 of each (one 128-byte line per lane), and the mirror
-// side likewise; every load precedes every store (barrier), so a diagonal
-// block can be done in place by its own workgroup.
+// Grid (nb * nb, 4): block (bi, bj) of 16 x 16 tiles of one half of X or Z
+// (y: matrix and half), processed with its mirror block (bj, bi); blocks
+// below the diagonal exit. A side is 1024 slots (64 per tile column) times
+// 16 words: one 128-byte line per slot. Lines move between HBM and LDS
+// coalesced (8 lanes per line, 16 bytes each); wave v then holds slots
+// 64 v .. 64 v + 63 of a side (a lane per slot, its 16 words in registers),
+// transposes each tile in registers and writes it to its mirror position in
+// LDS, from where the mirror side's lines are stored, again coalesced. Both
+// sides are in registers before anything is stored, so a diagonal block is
+// done in place by its own workgroup.
+__device__ __forceinline__ void stage_in(const u64 *__restrict__ M, u64 *buf, u32 Ls, u32 K, u32 off, u32 slot0,
+                                         u32 word0) {
+  const u32 tid = threadIdx.x;
+#pragma unroll
+  for (u32 pass = 0; pass < 8; ++pass) {
+    const u32 line = pass * 128u + (tid >> 3), c = (tid & 7u) * 2u;
+    const u32 slot = slot0 + line, w = word0 + c;
+    const bool ok = (slot >> 6) < K;
+    const u64 *src = M + (size_t)slot * Ls + off + w;
+    buf[line * TLINE + c] = (ok && w < K) ? __builtin_nontemporal_load(src) : 0ULL;
+    buf[line * TLINE + c + 1] = (ok && w + 1 < K) ? __builtin_nontemporal_load(src + 1) : 0ULL;
+  }
+}
+
+__device__ __forceinline__ void stage_out(u64 *__restrict__ M, const u64 *buf, u32 Ls, u32 K, u32 off, u32 slot0,
+                                          u32 word0) {
+  const u32 tid = threadIdx.x;
+#pragma unroll
+  for (u32 pass = 0; pass < 8; ++pass) {
+    const u32 line = pass * 128u + (tid >> 3), c = (tid & 7u) * 2u;
+    const u32 slot = slot0 + line, w = word0 + c;
+    if ((slot >> 6) >= K) continue;
+    u64 *dst = M + (size_t)slot * Ls + off + w;
+    if (w < K) __builtin_nontemporal_store(buf[line * TLINE + c], dst);
+    if (w + 1 < K) __builtin_nontemporal_store(buf[line * TLINE + c + 1], dst + 1);
+  }
+}
+
 __global__ __launch_bounds__(1024) void k_transpose(u64 *__restrict__ X, u64 *__restrict__ Z, u32 Ls, u32 K, u32 nb) {
+  __shared__ u64 buf[64 * TB * TLINE];
   const u32 bi = blockIdx.x / nb, bj = blockIdx.x - bi * nb;
-  if (bi > bj) return;
+  if (bi > bj) return;  // uniform over the workgroup
   u64 *M = (blockIdx.y >> 1) ? Z : X;
   const u32 off = (blockIdx.y & 1u) ? K : 0u;
   const u32 v = threadIdx.x >> 6, lane = threadIdx.x & 63u;
   const bool diag = bi == bj;
-  const u32 a = TB * bi + v, b = TB * bj + v;
+  const u32 slotA = 64u * TB * bi, wordA = TB * bj;  // side A: its slots hold words wordA ..
+  const u32 slotB = 64u * TB * bj, wordB = TB * bi;  // the mirror side
   u64 A[TB], B[TB];
-#pragma unroll
-  for (u32 d = 0; d < TB; ++d) A[d] = B[d] = 0;
-  if (a < K) {
-    const u64 *src = M + (size_t)(64u * a + lane) * Ls + off + TB * bj;
-#pragma unroll
-    for (u32 d = 0; d < TB; ++d)
-      if (TB * bj + d < K) A[d] = __builtin_nontemporal_load(src + d);
-  }
-  if (!diag && b < K) {
-    const u64 *src = M + (size_t)(64u * b + lane) * Ls + off + TB * bi;
-#pragma unroll
-    for (u32 d = 0; d < TB; ++d)
-      if (TB * bi + d < K) B[d] = __builtin_nontemporal_load(src + d);
-  }
+  stage_in(M, buf, Ls, K, off, slotA, wordA);
   __syncthreads();
-  if (a < K) {
 #pragma unroll
-    for (u32 d = 0; d < TB; ++d) {
-      const u32 w = TB * bj + d;
-      if (w < K) {
-        const u64 t = transpose64(A[d]);
-        __builtin_nontemporal_store(t, M + (size_t)(64u * w + lane) * Ls + off + a);
-      }
-    }
+  for (u32 d = 0; d < TB; ++d) A[d] = buf[(v * 64u + lane) * TLINE + d];
+  __syncthreads();
+  if (!diag) {
+    stage_in(M, buf, Ls, K, off, slotB, wordB);
+    __syncthreads();
+#pragma unroll
+    for (u32 d = 0; d < TB; ++d) B[d] = buf[(v * 64u + lane) * TLINE + d];
+    __syncthreads();
   }
-  if (!diag && b < K) {
+  // tile (16 bi + v, 16 bj + d) of side A becomes, lane j, slot 64 (16 bj + d) + j of side B at word 16 bi + v
 #pragma unroll
-    for (u32 d = 0; d < TB; ++d) {
-      const u32 w = TB * bi + d;
-      if (w < K) {
-        const u64 t = transpose64(B[d]);
-        __builtin_nontemporal_store(t, M + (size_t)(64u * w + lane) * Ls + off + b);
-      }
-    }
+  for (u32 d = 0; d < TB; ++d) buf[(d * 64u + lane) * TLINE + v] = transpose64(A[d]);
+  __syncthreads();
+  stage_out(M, buf, Ls, K, off, slotB, wordB);
+  if (!diag) {
+    __syncthreads();
+#pragma unroll
+    for (u32 d = 0; d < TB; ++d) buf[(d * 64u + lane) * TLINE + v] = transpose64(B[d]);
+    __syncthreads();
+    stage_out(M, buf, Ls, K, off, slotA, wordA);
   }
 }
 
@@ -195,6 +219,7 @@ __global__ __launch_bounds__(256) void k_row_rowsum(u64 *__restrict__ X, u64 *__
     if (((X[base + wq] >> sh) & 1ULL) == 0) continue;
     ++aff;
     u32 ph = 0;
+#pragma unroll 2
     for (u32 c = lane; c < K; c += 64) {
       const u64 px = pivx[c], pz = pivz[c];
       const u64 x = __builtin_nontemporal_load(X + base + c), z = __builtin_nontemporal_load(Z + base + c);

@@ -506,7 +506,11 @@ sq_status queue_slot(sq_tableau *T, const SweepCtx &c, u32 kb) {
     SQ_TRY(timed(T, SQ_K_IPIVOT, [&] {
       return launch_inj_pivot(c.tab, T->cur, T->st, T->mask, T->cols, T->stats, T->stream);
     }));
-    SQ_TRY(timed(T, SQ_K_IAPPLY, [&] { return launch_inj_apply(c.tab, T->st, T->mask, T->cols, T->stats, T->stream); }));
+    // the pair's bit changes are staged one byte per column in cnt0 (unused in this mode)
+    SQ_TRY(timed(T, SQ_K_IAPPLY, [&] {
+      return launch_inj_apply(c.tab, T->st, T->mask, T->cols, reinterpret_cast<uint8_t *>(T->cnt0), T->stats,
+                              T->stream);
+    }));
     return SQ_OK;
   }
   if (kb <= 1) {
