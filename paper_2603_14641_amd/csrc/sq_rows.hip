@@ -35,80 +35,97 @@ namespace sq {
 
 constexpr u32 TB = 16;         // tiles per side of a transposed block of tiles
 constexpr u32 TLINE = TB + 1;  // LDS words per staged slot line (padded against bank conflicts)
+constexpr u32 TLINES = 512;    // slot lines staged in LDS at a time (half a side)
 
-// Grid (nb * nb, 4): block (bi, bj) of 16 x 16 tiles of one half of X or Z
-// (y: matrix and half), processed with its mirror block (bj, bi); blocks
-// below the diagonal exit. A side is 1024 slots (64 per tile column) times
-// 16 words: one 128-byte line per slot. Lines move between HBM and LDS
-// coalesced (8 lanes per line, 16 bytes each); wave v then holds slots
+// Grid (nb (nb + 1) / 2, 4): block (bi, bj), bi <= bj, of 16 x 16 tiles of
+// one half of X or Z (y: matrix and half), processed with its mirror block
+// (bj, bi); x enumerates the upper triangle row by row. A side is 1024 slots
+// (64 per tile column) times 16 words: one 128-byte line per slot. Lines
+// move between HBM and LDS coalesced, 512 at a time (70 KB of LDS, so two
+// workgroups share a CU and overlap their phases); wave v holds slots
 // 64 v .. 64 v + 63 of a side (a lane per slot, its 16 words in registers),
 // transposes each tile in registers and writes it to its mirror position in
-// LDS, from where the mirror side's lines are stored, again coalesced. Both
-// sides are in registers before anything is stored, so a diagonal block is
-// done in place by its own workgroup.
+// LDS, from where the mirror side's lines are stored. Both sides are in
+// registers before anything is stored, so a diagonal block is done in place
+// by its own workgroup.
+//
+// Lines move 16 lanes per line, a word per lane: each wave instruction
+// covers four whole 128-byte lines.
 __device__ __forceinline__ void stage_in(const u64 *__restrict__ M, u64 *buf, u32 Ls, u32 K, u32 off, u32 slot0,
-                                         u32 word0) {
+                                         u32 word0, u32 line0) {
   const u32 tid = threadIdx.x;
 #pragma unroll
-  for (u32 pass = 0; pass < 8; ++pass) {
-    const u32 line = pass * 128u + (tid >> 3), c = (tid & 7u) * 2u;
-    const u32 slot = slot0 + line, w = word0 + c;
-    const bool ok = (slot >> 6) < K;
-    const u64 *src = M + (size_t)slot * Ls + off + w;
-    buf[line * TLINE + c] = (ok && w < K) ? __builtin_nontemporal_load(src) : 0ULL;
-    buf[line * TLINE + c + 1] = (ok && w + 1 < K) ? __builtin_nontemporal_load(src + 1) : 0ULL;
+  for (u32 pass = 0; pass < TLINES / 64; ++pass) {
+    const u32 line = pass * 64u + (tid >> 4), c = tid & 15u;
+    const u32 slot = slot0 + line0 + line, w = word0 + c;
+    const bool ok = (slot >> 6) < K && w < K;
+    buf[line * TLINE + c] = ok ? __builtin_nontemporal_load(M + (size_t)slot * Ls + off + w) : 0ULL;
   }
 }
 
 __device__ __forceinline__ void stage_out(u64 *__restrict__ M, const u64 *buf, u32 Ls, u32 K, u32 off, u32 slot0,
-                                          u32 word0) {
+                                          u32 word0, u32 line0) {
   const u32 tid = threadIdx.x;
 #pragma unroll
-  for (u32 pass = 0; pass < 8; ++pass) {
-    const u32 line = pass * 128u + (tid >> 3), c = (tid & 7u) * 2u;
-    const u32 slot = slot0 + line, w = word0 + c;
-    if ((slot >> 6) >= K) continue;
-    u64 *dst = M + (size_t)slot * Ls + off + w;
-    if (w < K) __builtin_nontemporal_store(buf[line * TLINE + c], dst);
-    if (w + 1 < K) __builtin_nontemporal_store(buf[line * TLINE + c + 1], dst + 1);
+  for (u32 pass = 0; pass < TLINES / 64; ++pass) {
+    const u32 line = pass * 64u + (tid >> 4), c = tid & 15u;
+    const u32 slot = slot0 + line0 + line, w = word0 + c;
+    if ((slot >> 6) < K && w < K)
+      __builtin_nontemporal_store(buf[line * TLINE + c], M + (size_t)slot * Ls + off + w);
+  }
+}
+
+// One side into registers: lines [0, 512) then [512, 1024) through LDS.
+__device__ __forceinline__ void side_in(const u64 *__restrict__ M, u64 *buf, u32 Ls, u32 K, u32 off, u32 slot0,
+                                        u32 word0, u64 (&R)[TB]) {
+  const u32 v = threadIdx.x >> 6, lane = threadIdx.x & 63u;
+#pragma unroll
+  for (u32 h = 0; h < 2; ++h) {
+    stage_in(M, buf, Ls, K, off, slot0, word0, h * TLINES);
+    __syncthreads();
+    if ((v >> 3) == h) {
+#pragma unroll
+      for (u32 d = 0; d < TB; ++d) R[d] = buf[((v & 7u) * 64u + lane) * TLINE + d];
+    }
+    __syncthreads();
+  }
+}
+
+// One side's transposed tiles out to the mirror side: tiles d < 8 fill the
+// mirror's lines [0, 512), tiles d >= 8 its lines [512, 1024).
+__device__ __forceinline__ void side_out(u64 *__restrict__ M, u64 *buf, u32 Ls, u32 K, u32 off, u32 slot0,
+                                         u32 word0, const u64 (&R)[TB]) {
+  const u32 v = threadIdx.x >> 6, lane = threadIdx.x & 63u;
+#pragma unroll
+  for (u32 h = 0; h < 2; ++h) {
+#pragma unroll
+    for (u32 d = 0; d < TB / 2; ++d) buf[(d * 64u + lane) * TLINE + v] = transpose64(R[h * (TB / 2) + d]);
+    __syncthreads();
+    stage_out(M, buf, Ls, K, off, slot0, word0, h * TLINES);
+    __syncthreads();
   }
 }
 
 __global__ __launch_bounds__(1024) void k_transpose(u64 *__restrict__ X, u64 *__restrict__ Z, u32 Ls, u32 K, u32 nb) {
-  __shared__ u64 buf[64 * TB * TLINE];
-  const u32 bi = blockIdx.x / nb, bj = blockIdx.x - bi * nb;
-  if (bi > bj) return;  // uniform over the workgroup
+  __shared__ u64 buf[TLINES * TLINE];
+  // row bi of the triangle starts at bi nb - bi (bi - 1) / 2
+  const u32 t = blockIdx.x;
+  u32 bi = (u32)(((double)(2 * nb + 1) - sqrt((double)(2 * nb + 1) * (2 * nb + 1) - 8.0 * t)) * 0.5);
+  auto row0 = [&](u32 r) { return r * nb - r * (r - 1) / 2; };
+  while (bi > 0 && row0(bi) > t) --bi;
+  while (row0(bi + 1) <= t) ++bi;
+  const u32 bj = bi + (t - row0(bi));
   u64 *M = (blockIdx.y >> 1) ? Z : X;
   const u32 off = (blockIdx.y & 1u) ? K : 0u;
-  const u32 v = threadIdx.x >> 6, lane = threadIdx.x & 63u;
   const bool diag = bi == bj;
   const u32 slotA = 64u * TB * bi, wordA = TB * bj;  // side A: its slots hold words wordA ..
   const u32 slotB = 64u * TB * bj, wordB = TB * bi;  // the mirror side
   u64 A[TB], B[TB];
-  stage_in(M, buf, Ls, K, off, slotA, wordA);
-  __syncthreads();
-#pragma unroll
-  for (u32 d = 0; d < TB; ++d) A[d] = buf[(v * 64u + lane) * TLINE + d];
-  __syncthreads();
-  if (!diag) {
-    stage_in(M, buf, Ls, K, off, slotB, wordB);
-    __syncthreads();
-#pragma unroll
-    for (u32 d = 0; d < TB; ++d) B[d] = buf[(v * 64u + lane) * TLINE + d];
-    __syncthreads();
-  }
+  side_in(M, buf, Ls, K, off, slotA, wordA, A);
+  if (!diag) side_in(M, buf, Ls, K, off, slotB, wordB, B);
   // tile (16 bi + v, 16 bj + d) of side A becomes, lane j, slot 64 (16 bj + d) + j of side B at word 16 bi + v
-#pragma unroll
-  for (u32 d = 0; d < TB; ++d) buf[(d * 64u + lane) * TLINE + v] = transpose64(A[d]);
-  __syncthreads();
-  stage_out(M, buf, Ls, K, off, slotB, wordB);
-  if (!diag) {
-    __syncthreads();
-#pragma unroll
-    for (u32 d = 0; d < TB; ++d) buf[(d * 64u + lane) * TLINE + v] = transpose64(B[d]);
-    __syncthreads();
-    stage_out(M, buf, Ls, K, off, slotA, wordA);
-  }
+  side_out(M, buf, Ls, K, off, slotB, wordB, A);
+  if (!diag) side_out(M, buf, Ls, K, off, slotA, wordA, B);
 }
 
 // The pivot candidate starts at "none" (k_row_gather resets it after use).
@@ -202,41 +219,91 @@ __device__ __forceinline__ u32 word_phase(u64 px, u64 pz, u64 qx, u64 qz) {
 // S_p, becomes S_p times itself: x ^= x_p, z ^= z_p (stored only where the
 // pivot word is nonzero) and r <- (2 r + 2 r_p + phase) / 2, the phase of
 // S_p * row summed over the row's words (must be even, else flag bit 0).
-__global__ __launch_bounds__(256) void k_row_rowsum(u64 *__restrict__ X, u64 *__restrict__ Z, u64 *__restrict__ R,
-                                                    u32 Ls, u32 K, u32 n, MeasState *__restrict__ st,
-                                                    const u64 *__restrict__ pivx, const u64 *__restrict__ pivz) {
+// The affected halves are walked as one run of words (both halves of a
+// slot are contiguous), four rounds of loads in flight per lane; with
+// LDS = true the workgroup first stages the pivot row (2K words) in LDS.
+constexpr u32 ROWSUM_T = 1024;
+constexpr u32 ROWSUM_LDS_MAX_K = 4096;  // 64 KB of pivot row
+
+template <bool LDS>
+__global__ __launch_bounds__(ROWSUM_T) void k_row_rowsum(u64 *__restrict__ X, u64 *__restrict__ Z,
+                                                         u64 *__restrict__ R, u32 Ls, u32 K, u32 n,
+                                                         MeasState *__restrict__ st, const u64 *__restrict__ pivx,
+                                                         const u64 *__restrict__ pivz) {
+  extern __shared__ u64 spiv[];
   const int32_t p = st->p;
-  if (p < 0) return;
+  if (p < 0) return;  // the same for every workgroup
+  if constexpr (LDS) {
+    for (u32 c = threadIdx.x; c < K; c += blockDim.x) {
+      spiv[c] = pivx[c];
+      spiv[K + c] = pivz[c];
+    }
+    __syncthreads();
+  }
   const u32 lane = threadIdx.x & 63u;
   const u32 r = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
-  if (r >= n) return;  // uniform over the wave; no barriers below
+  if (r >= n || r == (u32)p) return;  // uniform over the wave; no barriers below (D_p, S_p skipped)
   const u32 q = st->q, wq = q >> 6, sh = q & 63u, rp = st->rp;
-  u32 aff = 0;
-#pragma unroll
-  for (u32 h = 0; h < 2; ++h) {
-    if (r == (u32)p) continue;  // D_p is overwritten, S_p is the pivot
-    const size_t base = (size_t)r * Ls + h * K;
-    if (((X[base + wq] >> sh) & 1ULL) == 0) continue;
-    ++aff;
-    u32 ph = 0;
+  const size_t base = (size_t)r * Ls;
+  const bool aD = (X[base + wq] >> sh) & 1ULL, aS = (X[base + K + wq] >> sh) & 1ULL;
+  if (!aD && !aS) return;
+  // words [c0, c1) of the slot change; the walk goes in 16-byte pairs from
+  // the even word below c0 (a word outside [c0, c1) is stored back as read:
+  // the wave owns the slot)
+  const u32 c0 = aD ? 0u : K, c1 = aS ? 2u * K : K;
+  u32 phD = 0, phS = 0;
 #pragma unroll 2
-    for (u32 c = lane; c < K; c += 64) {
-      const u64 px = pivx[c], pz = pivz[c];
-      const u64 x = __builtin_nontemporal_load(X + base + c), z = __builtin_nontemporal_load(Z + base + c);
-      ph += word_phase(px, pz, x, z);
-      if (px) __builtin_nontemporal_store(x ^ px, X + base + c);
-      if (pz) __builtin_nontemporal_store(z ^ pz, Z + base + c);
+  for (u32 c = (c0 & ~1u) + 2u * lane; c < c1; c += 128u) {
+    const u64x2 xv = __builtin_nontemporal_load(reinterpret_cast<const u64x2 *>(X + base + c));
+    const u64x2 zv = __builtin_nontemporal_load(reinterpret_cast<const u64x2 *>(Z + base + c));
+    u64 xo[2] = {xv.x, xv.y}, zo[2] = {zv.x, zv.y};
+    bool any = false;
+#pragma unroll
+    for (u32 h = 0; h < 2; ++h) {
+      const u32 cc = c + h;
+      if (cc < c0 || cc >= c1) continue;
+      const u32 cw = cc < K ? cc : cc - K;
+      u64 px, pz;
+      if constexpr (LDS) {
+        px = spiv[cw];
+        pz = spiv[K + cw];
+      } else {
+        px = pivx[cw];
+        pz = pivz[cw];
+      }
+      const u32 ph = word_phase(px, pz, xo[h], zo[h]);
+      if (cc < K) phD += ph;
+      else phS += ph;
+      xo[h] ^= px;
+      zo[h] ^= pz;
+      any |= (px | pz) != 0;
     }
-    for (int off = 32; off > 0; off >>= 1) ph += (u32)__shfl_xor((int)ph, off);
-    if (lane == 0) {
+    if (any) {
+      u64x2 xw, zw;
+      xw.x = xo[0];
+      xw.y = xo[1];
+      zw.x = zo[0];
+      zw.y = zo[1];
+      __builtin_nontemporal_store(xw, reinterpret_cast<u64x2 *>(X + base + c));
+      __builtin_nontemporal_store(zw, reinterpret_cast<u64x2 *>(Z + base + c));
+    }
+  }
+  for (int off = 32; off > 0; off >>= 1) {
+    phD += (u32)__shfl_xor((int)phD, off);
+    phS += (u32)__shfl_xor((int)phS, off);
+  }
+  if (lane == 0) {
+#pragma unroll
+    for (u32 h = 0; h < 2; ++h) {
+      if (!(h ? aS : aD)) continue;
       u64 *rw = R + h * K + (r >> 6);
       const u32 rh = (u32)(*rw >> (r & 63u)) & 1u;
-      const u32 e = (2u * rh + 2u * rp + ph) & 3u;
+      const u32 e = (2u * rh + 2u * rp + (h ? phS : phD)) & 3u;
       if (e & 1u) atomicOr(&st->flags, 1u);
       if ((e >> 1) != rh) atomicXor(rw, 1ULL << (r & 63u));
     }
+    atomicAdd(&st->naff, (u32)aD + (u32)aS);
   }
-  if (lane == 0 && aff) atomicAdd(&st->naff, aff);
 }
 
 // Deterministic case, grid (row blocks, word ranges of 64): a wave walks the
@@ -349,7 +416,7 @@ __global__ __launch_bounds__(1024) void k_row_finish(u64 *__restrict__ X, u64 *_
 // Launchers.
 hipError_t launch_transpose(const TabDev &t, hipStream_t s) {
   const u32 nb = cdiv(t.K, TB);
-  hipLaunchKernelGGL(k_transpose, dim3(nb * nb, 4), dim3(1024), 0, s, t.X, t.Z, t.Ls, t.K, nb);
+  hipLaunchKernelGGL(k_transpose, dim3(nb * (nb + 1) / 2, 4), dim3(1024), 0, s, t.X, t.Z, t.Ls, t.K, nb);
   return hipGetLastError();
 }
 
@@ -366,8 +433,12 @@ hipError_t launch_row_prep(const TabDev &t, Cursor *cur, MeasState *st, u64 *piv
 }
 
 hipError_t launch_row_rowsum(const TabDev &t, MeasState *st, const u64 *pivx, const u64 *pivz, hipStream_t s) {
-  hipLaunchKernelGGL(k_row_rowsum, dim3(cdiv(t.n, 4)), dim3(256), 0, s, t.X, t.Z, t.R, t.Ls, t.K, t.n, st, pivx,
-                     pivz);
+  const dim3 grid(cdiv(t.n, ROWSUM_T / 64)), block(ROWSUM_T);
+  if (t.K <= ROWSUM_LDS_MAX_K)
+    hipLaunchKernelGGL(k_row_rowsum<true>, grid, block, (size_t)2 * t.K * 8, s, t.X, t.Z, t.R, t.Ls, t.K, t.n, st,
+                       pivx, pivz);
+  else
+    hipLaunchKernelGGL(k_row_rowsum<false>, grid, block, 0, s, t.X, t.Z, t.R, t.Ls, t.K, t.n, st, pivx, pivz);
   return hipGetLastError();
 }
 

@@ -155,12 +155,16 @@ struct sq_program {
 
 namespace {
 
-// Columns per chunk of the blocked pass: about 2048 workgroups in all.
+// Columns per chunk of the blocked pass: 8192 / (L / 256) chunks, so that
+// late in a measurement sweep, when the stabilizer half's row words stop
+// being hit and their tiles exit at once, the remaining tiles still have
+// enough workgroups (at n = 180,000: 11 tiles of 512 row words x 372
+// chunks).
 static_assert(SQ_PIVOT_AUTO == PIVOT_AUTO, "pivot_waves sentinel");
 
 u32 blk_cpc_of(const Dims &d) {
   const u32 tiles = cdiv(d.L, 256);
-  const u32 want = std::max<u32>(1, 2048 / tiles);
+  const u32 want = std::max<u32>(1, 8192 / tiles);
   u32 cpc = std::max<u32>(16, cdiv(d.n, want));
   return std::max<u32>(cpc, cdiv(d.n, kBlkMaxChunks));
 }

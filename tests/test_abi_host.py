@@ -70,10 +70,28 @@ def test_null_handles_are_rejected_without_a_device():
         lambda: lib.sq_run(None, None, 0, 0, 0, None, None),
         lambda: lib.sq_set_tuning(None, None),
         lambda: lib.sq_profile_enable(None, 1),
+        lambda: lib.sq_set_collapse(None, sqb.COLLAPSE_INJECT),
+        lambda: lib.sq_set_layout(None, sqb.LAYOUT_ROWS),
+        lambda: lib.sq_measure_noalloc(None, None, 1, 0, 0, 0, None, None),
     ]
     for call in calls:
         assert call() == sqb.SQ_EINVAL
         assert lib.sq_last_error()
+    assert lib.sq_get_collapse(None) == sqb.COLLAPSE_ROWSUM
+    assert lib.sq_get_layout(None) == sqb.LAYOUT_COLUMNS
+
+
+def test_layout_holds_64k_slots():
+    """X and Z are allocated with 64 * ceil(n / 64) column slots (the row
+    layout needs each half to be a square bit matrix), at the reported
+    offsets, and the block is large enough for both."""
+    for n in (1, 63, 64, 65, 180000):
+        info = sqb.layout(n)
+        K, Ls = info["K"], info["Ls"]
+        assert info["L"] == 2 * K and Ls % 16 == 0 and Ls >= 2 * K
+        assert info["z_offset"] - info["x_offset"] >= 64 * K * Ls * 8
+        assert info["r_offset"] - info["z_offset"] >= 64 * K * Ls * 8
+        assert info["bytes"] == sqb.bytes_required(n)
 
 
 # ---------------------------------------------------------------- pass compiler
