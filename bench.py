@@ -48,6 +48,7 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, AMD public specification
 HBM_SUMMARY = "hbm_counters_n180000_bench.md"  # profiles/ summary of FETCH_SIZE / WRITE_SIZE on this workload
+HBM_SUMMARY_IR = "hbm_counters_n180000_inject_rows.md"  # the same for the CX-injection and row-layout sections
 METRIC = "gates/s & measurements/s at n=180k (HBM % of peak); batched vs plain shots/s"
 
 
@@ -288,6 +289,7 @@ def inject_collapse(sq, sqb, cfg, pg, L, ref_bits, meas: int):
     `meas` final measurements, then the same qubits again (deterministic).
     Outcomes must equal the rowsum collapse's (`ref_bits`, same coins)."""
     import torch
+    from paper_2603_14641_amd import profsum
     n = cfg.n
     C = 8 * L
     stream = torch.cuda.current_stream()
@@ -330,12 +332,15 @@ def inject_collapse(sq, sqb, cfg, pg, L, ref_bits, meas: int):
         "measurements_per_s": meas / (mms * 1e-3), "random": nr,
         "deterministic_measurements_per_s": meas / (dms * 1e-3),
         "outcomes_equal_rowsum_collapse": same, "remeasured_deterministic": repeat,
-        "roofline_gates": roof("k_layer_op", *kern["layer"], pg.gate_bytes, pg.gate_bytes,
-                               "bytes the pass moves (column reads + changed-column writes), same plans as k_layer"),
+        "roofline_gates": roof("k_layer_op", *kern["layer"], pg.gate_bytes * kern["layer"][1] // max(pg.num_passes, 1),
+                               pg.gate_bytes * kern["layer"][1] // max(pg.num_passes, 1),
+                               "bytes the pass moves (column reads + changed-column writes), same plans as k_layer",
+                               profsum.traffic_per_dispatch("k_layer_op", HBM_SUMMARY_IR)),
         "roofline": roof("k_inj_apply", ia_ms, ia_n, st.inject_bytes, st.inject_bytes,
                          f"per column: read x, z of the destabilizer word of every target word and read+write "
                          f"the stabilizer word where the pivot has x (z); random measurement with B_word = "
-                         f"{4 * n * C / 1e9:.1f} GB for comparison"),
+                         f"{4 * n * C / 1e9:.1f} GB for comparison",
+                         profsum.traffic_per_dispatch("k_inj_apply", HBM_SUMMARY_IR)),
         "kernel_ms": {k: round(v[0], 2) for k, v in kern.items() if v[1]},
         "kernel_launches": {k: v[1] for k, v in kern.items() if v[1]},
     }
@@ -353,6 +358,7 @@ def row_layout(sq, sqb, cfg, pg, L, ref_bits, meas: int):
     the first `meas` measurements one at a time in columns (no blocks): the
     row-granular and word-granular costs of the same measurements."""
     import torch
+    from paper_2603_14641_amd import profsum
     n = cfg.n
     C = 8 * L
     stream = torch.cuda.current_stream()
@@ -430,11 +436,13 @@ def row_layout(sq, sqb, cfg, pg, L, ref_bits, meas: int):
         "outcomes_equal_blocked_columns": same,
         "roofline_transpose": roof("k_transpose", *kern["transpose"], tr_bytes * kern["transpose"][1],
                                    tr_bytes * kern["transpose"][1],
-                                   "X and Z, both halves, every word read and written once"),
+                                   "X and Z, both halves, every word read and written once",
+                                   profsum.traffic_per_dispatch("k_transpose", HBM_SUMMARY_IR)),
         "roofline": roof("k_row_rowsum", *kern["row_rowsum"], nr * n * 4 * (L // 2) * 8, st_r.rowsum_bytes,
                          f"random measurement, row granular: the rows with x_q = 1 (about n of 2n) read and "
                          f"written in x and z; cost model n rows x 4 x {L // 2} words; B_word = "
-                         f"{4 * n * C / 1e9:.1f} GB for comparison"),
+                         f"{4 * n * C / 1e9:.1f} GB for comparison",
+                         profsum.traffic_per_dispatch("k_row_rowsum<true>", HBM_SUMMARY_IR)),
         "roofline_det": roof("k_row_det", *kern["row_det"], det_rows_moved, det_rows_moved,
                              "deterministic: x and z of every stabilizer row in the product, read once"),
         "roofline_columns_single": roof("k_rowsum", *kc["rowsum"], nr * 4 * n * C,
