@@ -13,6 +13,9 @@ After the timed steps (not part of `value`):
     measurements (measurements/s over the whole sweep);
   * deterministic: the first 1000 qubits measured again on the swept
     tableau, every outcome deterministic;
+  * dense_deterministic: deterministic measurements whose product spans
+    about n/2 stabilizers (a basis-state-preserving circuit with planted
+    outcomes), in columns and on rows;
   * batched_served: the 512-request batched/served mix, all of it, on the
     plain per-circuit path, the batched path, the serving loop (Poisson
     arrivals) and the Pauli-frame path, plus sampling requests against
@@ -461,6 +464,73 @@ def row_layout(sq, sqb, cfg, pg, L, ref_bits, meas: int):
 
 
 # ---------------------------------------------------------------- the batched/served mix
+def dense_deterministic(sq, sqb, meas: int, layers: int = 64):
+    """Deterministic measurements whose product spans about n/2 stabilizers:
+    n = 180,000 after `layers` layers of basis-state-preserving gates
+    (workload.basis_circuit: CX, CZ, SWAP, S, SDG, X, Y, Z), then qubits
+    0..meas-1, every one deterministic with the circuit's planted outcome.
+    Here the set A of the CHP deterministic case is dense, so each
+    measurement reads x and z of nearly every stabilizer word of every
+    column, the n C bytes of the cost model. Timed in columns (k_pivot +
+    k_post), then the same qubits again on rows (k_row_det)."""
+    import torch
+    from workload import basis_circuit
+    n = 180000
+    L = sqb.layout(n)["L"]
+    C = 8 * L
+    log(f"dense deterministic: generating {layers} basis-preserving layers")
+    ops, planted = basis_circuit(n, layers, seed=21)
+    gates = np.stack([ops["type"], ops["q0"], ops["q1"]], 1).astype(np.uint32)
+    pg = sq.Program(n, gates)
+    pm = sq.Program(n, meas_ops(np.arange(meas)))
+    t = sq.Tableau(n)
+    stream = torch.cuda.current_stream()
+    out = torch.zeros(meas, dtype=torch.uint8, device="cuda")
+    rnd = torch.zeros(meas, dtype=torch.uint8, device="cuda")
+    t.run(pg, 1, 0, 0, 0, 0)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+
+    def timed(tag):
+        st0 = t.measure_stats()
+        t.profile_reset()
+        t.profile(True)
+        e0.record(stream)
+        t.run(pm, 1, 0, 0, out.data_ptr(), rnd.data_ptr())
+        e1.record(stream)
+        torch.cuda.synchronize()
+        t.profile(False)
+        st1 = t.measure_stats()
+        ok = bool(np.array_equal(out.cpu().numpy(), planted[:meas])) and not bool(rnd.any())
+        assert ok and t.error_flags() == 0, f"dense deterministic ({tag}): outcomes differ from the planted bits"
+        kern = {name: t.profile_read(i) for i, name in enumerate(sqb.KERNEL_NAMES)}
+        return e0.elapsed_time(e1), st1.n_det - st0.n_det, st1.det_bytes - st0.det_bytes, kern
+
+    ms_c, nd_c, moved_c, kc = timed("columns")
+    t.set_layout(sqb.LAYOUT_ROWS)
+    torch.cuda.synchronize()
+    ms_r, nd_r, moved_r, kr = timed("rows")
+    t.close()
+    pg.close()
+    pm.close()
+    log(f"dense deterministic: {meas / (ms_c * 1e-3):.3g}/s columns, {meas / (ms_r * 1e-3):.3g}/s rows")
+    return {
+        "workload": f"n={n}: {layers} layers of CX/CZ/SWAP/S/SDG/X/Y/Z from |0...0> ({gates.shape[0]} gates), "
+                    f"then qubits 0..{meas - 1} (all deterministic, dense products, planted outcomes)",
+        "measurements": meas, "outcomes_equal_planted": True,
+        "measurements_per_s_columns": meas / (ms_c * 1e-3),
+        "measurements_per_s_rows": meas / (ms_r * 1e-3),
+        "avg_rows_in_product": round(moved_r / max(nd_r, 1) / (16 * (L // 2)), 1),
+        "roofline": roof("k_post (deterministic, dense A)", *kc["post"], nd_c * n * C, moved_c,
+                         f"deterministic measurement: n C = {n * C / 1e9:.1f} GB (x and z of the stabilizer half "
+                         f"of every column read once); moved = the nonzero words of A in every column"),
+        "roofline_rows": roof("k_row_det", *kr["row_det"], moved_r, moved_r,
+                              "x and z of every stabilizer row in the product, read once"),
+        "kernel_ms_columns": {k: round(v[0], 2) for k, v in kc.items() if v[1]},
+        "kernel_ms_rows": {k: round(v[0], 2) for k, v in kr.items() if v[1]},
+    }
+
+
 def served_mix(nreq: int, budget_bytes: int, session_requests: int):
     import torch
     import paper_2603_14641_amd as sq
@@ -687,6 +757,8 @@ def main():
                     help="final measurements run with the CX-injection collapse (0 skips that part)")
     ap.add_argument("--row-meas", type=int, default=256,
                     help="final measurements run one at a time in the row layout (0 skips that part)")
+    ap.add_argument("--det-meas", type=int, default=256,
+                    help="deterministic measurements with dense products (0 skips that part)")
     ap.add_argument("--served-single-thread", action="store_true",
                     help="run only the batched/served paths' kernels from one host thread (for kernel traces)")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -762,6 +834,9 @@ def main():
         pm.close()
     torch.cuda.synchronize()
     torch.cuda.empty_cache()
+    if args.det_meas:
+        result["dense_deterministic"] = dense_deterministic(sq, sqb, args.det_meas)
+        torch.cuda.empty_cache()
     result["hbm_stream_ceiling_gbs"] = stream_ceiling()
     if args.served_requests > 0 and args.served_single_thread:
         result["served_single_thread"] = served_kernels_single_thread(args.served_requests)

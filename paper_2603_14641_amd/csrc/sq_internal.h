@@ -210,14 +210,15 @@ hipError_t launch_inj_apply(const TabDev &t, const MeasState *st, const u64 *mas
                             MeasStats *stats, hipStream_t s);
 hipError_t launch_cursor_init(Cursor *c, u32 end, u32 kb, u64 seed, u64 shot, u64 meas_base, const u32 *qubits,
                               uint8_t *out_bits, uint8_t *out_rand, hipStream_t s);
-hipError_t launch_pivot(const TabDev &t, Cursor *cur, MeasState *st, u64 *mask, hipStream_t s);
+hipError_t launch_pivot(const TabDev &t, Cursor *cur, MeasState *st, u64 *mask, u32 *alist, u64 *amask,
+                        hipStream_t s);
 hipError_t launch_gather(const TabDev &t, MeasState *st, u64 *pivx, u64 *pivz, u32 *cols, const SymCtx *sym,
                          hipStream_t s);
 hipError_t launch_rowsum(const TabDev &t, const u64 *mask, const u32 *cols, const MeasState *st, u64 *cnt0,
                          u64 *cnt1, u32 block, u32 wpt, u32 cpc, u32 max_chunks, const SymCtx *sym, hipStream_t s);
 hipError_t launch_post(const TabDev &t, const Cursor *cur, const u64 *mask, const u64 *pivx, const u64 *pivz,
-                       const u64 *cnt0, const u64 *cnt1, MeasState *st, MeasStats *stats, u32 cpc, u32 cpw,
-                       const SymCtx *sym, hipStream_t s);
+                       const u64 *cnt0, const u64 *cnt1, const u32 *alist, MeasState *st, MeasStats *stats, u32 cpc,
+                       u32 cpw, const SymCtx *sym, hipStream_t s);
 // Shot sampling (sq_sample.hip).
 hipError_t launch_sample_init(const TabDev &t, u64 *sg, u32 Ks, u32 count, hipStream_t s);
 hipError_t launch_coins(u64 *cw, u64 seed, u64 shot_begin, u64 meas_base, u32 shots, u32 count, u32 CW,

@@ -22,11 +22,15 @@ constexpr u32 SIGN_COLS_PER_BLOCK = 32;  // coin columns per sign-XOR block of k
 // smallest stabilizer index with x(S_p)_q = 1 (first set bit of the
 // stabilizer half of X column q), or -1. Also snapshots column q into `mask`
 // (the rows the rowsum pass must touch), with the bits of D_p and S_p
-// cleared, because the pass rewrites column q in place. One workgroup;
-// thread 0 also draws the coin and advances the cursor.
+// cleared, because the pass rewrites column q in place. With no pivot (the
+// deterministic case) it also lists the nonzero destabilizer-half words of
+// column q in ascending order: alist[e] = word index, amask[e] = its bits
+// (the rows of A), e < awords. One workgroup; thread 0 also draws the coin
+// and advances the cursor.
 __global__ __launch_bounds__(1024) void k_pivot(const u64 *__restrict__ X, u32 Ls, u32 K, u32 L,
                                                 Cursor *__restrict__ cur, MeasState *__restrict__ st,
-                                                u64 *__restrict__ mask) {
+                                                u64 *__restrict__ mask, u32 *__restrict__ alist,
+                                                u64 *__restrict__ amask) {
   __shared__ u32 s_min, s_act, s_q, s_i;
   const u32 tid = threadIdx.x;
   if (tid == 0) {
@@ -75,6 +79,31 @@ __global__ __launch_bounds__(1024) void k_pivot(const u64 *__restrict__ X, u32 L
   }
   if ((tid & 63u) == 0) { atomicAdd(&s_mw, mw); atomicAdd(&s_aw, aw); }
   __syncthreads();
+  if (p < 0) {  // uniform: p comes from s_min
+    // ordered compaction, one round of blockDim words at a time: wave ballot
+    // rank plus the counts of the lower waves and of earlier rounds
+    __shared__ u32 s_wc[16];
+    const u32 wave = tid >> 6, nwaves = blockDim.x >> 6;
+    u32 base = 0;
+    for (u32 r0 = 0; r0 < K; r0 += blockDim.x) {
+      const u32 w = r0 + tid;
+      const u64 v = (w < K) ? col[w] : 0ULL;
+      const u64 b = __ballot(v != 0);
+      if ((tid & 63u) == 0) s_wc[wave] = (u32)__popcll(b);
+      __syncthreads();
+      u32 e = base + (u32)__popcll(b & lanemask_lt()), tot = 0;
+      for (u32 u = 0; u < nwaves; ++u) {
+        if (u < wave) e += s_wc[u];
+        tot += s_wc[u];
+      }
+      if (v != 0) {
+        alist[e] = w;
+        amask[e] = v;
+      }
+      base += tot;
+      __syncthreads();  // s_wc is rewritten in the next round
+    }
+  }
   if (tid == 0) {
     const u32 c = coin_bit(cur->seed, cur->shot, cur->meas_base + i);
     const bool blocked = cur->kb > 1u;
@@ -284,6 +313,30 @@ __device__ __forceinline__ u64 prefix_xor_incl(u64 v) {
   return v;
 }
 
+// One word of a deterministic product in a column: x1/z1 are the column's
+// stabilizer bits at 64 rows of A (zero outside A), one word per lane in
+// ascending row order across the wave; cx/cz the XOR of the column's bits over
+// the rows of A before this wave-wide word group. The running product before
+// row i has x/z equal to that carry plus the exclusive prefix XOR inside the
+// word group, and S_i's phase contribution against it is +1, -1 or 0 (the
+// g function of the rowsum). Call with the whole wave.
+constexpr u32 DET_U = 4;   // list entries per lane per round (A beyond one round)
+constexpr u32 DET_CB = 4;  // columns per batch of loads (A within one round)
+
+__device__ __forceinline__ void det_word(u64 x1, u64 z1, u32 &cx, u32 &cz, int &acc) {
+  const u64 bx = __ballot(__popcll(x1) & 1), bz = __ballot(__popcll(z1) & 1);
+  const u64 lt = lanemask_lt();
+  const u32 px = cx ^ ((u32)__popcll(bx & lt) & 1u), pz = cz ^ ((u32)__popcll(bz & lt) & 1u);
+  const u64 ex = (prefix_xor_incl(x1) << 1) ^ (px ? ~0ULL : 0ULL);
+  const u64 ez = (prefix_xor_incl(z1) << 1) ^ (pz ? ~0ULL : 0ULL);
+  const u64 p_x = x1 & ~z1, p_y = x1 & z1, p_z = ~x1 & z1;
+  const u64 plus = (p_x & ex & ez) | (p_y & ~ex & ez) | (p_z & ex & ~ez);
+  const u64 minus = (p_x & ~ex & ez) | (p_y & ex & ~ez) | (p_z & ex & ez);
+  acc += __popcll(plus) - __popcll(minus);
+  cx ^= (u32)__popcll(bx) & 1u;
+  cz ^= (u32)__popcll(bz) & 1u;
+}
+
 // k_post. Random case (p >= 0), by global thread index t:
 //   * t < L (plain) or t < K (sampler): for a masked row word, add the chunk
 //     counters mod 4; the exponent 2 r_h + 2 r_p + sum g must be even and
@@ -296,9 +349,10 @@ __device__ __forceinline__ u64 prefix_xor_incl(u64 v) {
 // the mask). The product of S_i over A in ascending i is +-Z_q. Per column j
 // the running product before row i has x/z bits equal to the exclusive prefix
 // XOR over A of column j's stabilizer bits, so the phase exponent adds
-// g(P_ij, prefix) for each i in A. Block b takes columns [b*cpw, (b+1)*cpw);
-// a column is walked in rounds of 2*blockDim words with a wave ballot scan, a
-// cross-wave LDS scan and the carry of earlier rounds. The column's total XOR
+// g(P_ij, prefix) for each i in A. Block b takes columns [b*cpw, (b+1)*cpw),
+// its waves one column at a time each; a wave walks only the words of A that
+// k_pivot listed (alist/amask), 64 per wave-wide step (det_word), so a column
+// costs the bytes of A's words, not of all K. The column's total XOR
 // must be 0 for x and [j == q] for z. Blocks add their sums to det_acc; the
 // last block to finish (atomic ticket, no waiting) forms the outcome: parity of
 // S_i's signs over A xor bit 1 of the sum (which must be even). The sampler's
@@ -308,9 +362,10 @@ template <bool SYM>
 __global__ __launch_bounds__(256) void k_post(u64 *__restrict__ X, u64 *__restrict__ Z, u64 *__restrict__ R,
                                               const u64 *__restrict__ mask, const u64 *__restrict__ pivx,
                                               const u64 *__restrict__ pivz, const u64 *__restrict__ cnt0,
-                                              const u64 *__restrict__ cnt1, MeasState *__restrict__ st,
-                                              MeasStats *__restrict__ stats, const Cursor *__restrict__ cur, u32 Ls,
-                                              u32 L, u32 K, u32 n, u32 cpc, u32 cpw, SymCtx sym) {
+                                              const u64 *__restrict__ cnt1, const u32 *__restrict__ alist,
+                                              MeasState *__restrict__ st, MeasStats *__restrict__ stats,
+                                              const Cursor *__restrict__ cur, u32 Ls, u32 L, u32 K, u32 n, u32 cpc,
+                                              u32 cpw, SymCtx sym) {
   const int32_t p = st->p;
   if (p == P_NONE) return;  // the slot measures nothing alone
   const u32 q = st->q, li = st->i;  // the qubit and its list position
@@ -390,56 +445,64 @@ __global__ __launch_bounds__(256) void k_post(u64 *__restrict__ X, u64 *__restri
   }
 
   // ---- deterministic case
-  __shared__ u32 s_px[4], s_pz[4], s_last;
+  __shared__ u32 s_px[4], s_last;
   __shared__ int s_acc[4];
+  const u32 aw = st->awords;
+  const u64 *amask = pivx;  // the compacted rows of A (k_pivot; pivx is free here)
   int acc = 0;
   u32 bad = 0;
   const u32 j0 = blockIdx.x * cpw, j1 = min(j0 + cpw, n);
-  for (u32 j = j0; j < j1; ++j) {
-    const u64 *xc = X + (size_t)j * Ls + K;
-    const u64 *zc = Z + (size_t)j * Ls + K;
-    u32 carry_x = 0, carry_z = 0;
-    for (u32 base = 0; base < K; base += blockDim.x * 2) {
-      const u32 w0 = base + tid * 2;
-      u64 sx[2], sz[2];
-      u32 tpx = 0, tpz = 0;
+  if (aw <= 64u) {
+    // A within one round: the list is loop-invariant, and DET_CB columns'
+    // loads are issued before any of their scans
+    const bool on = lane < aw;
+    const u32 w = on ? alist[lane] : 0u;
+    const u64 a = on ? amask[lane] : 0ULL;
+    for (u32 j = j0 + wave; j < j1; j += DET_CB * nwaves) {
+      u64 sx[DET_CB], sz[DET_CB];
 #pragma unroll
-      for (int k = 0; k < 2; ++k) {
-        const u32 w = w0 + k;
-        const u64 a = (w < K) ? mask[w] : 0ULL;
-        sx[k] = a ? (xc[w] & a) : 0ULL;
-        sz[k] = a ? (zc[w] & a) : 0ULL;
-        tpx ^= (u32)__popcll(sx[k]) & 1u;
-        tpz ^= (u32)__popcll(sz[k]) & 1u;
+      for (u32 k = 0; k < DET_CB; ++k) {
+        const u32 jj = j + k * nwaves;
+        const bool ok = on && jj < j1;
+        sx[k] = ok ? (X[(size_t)jj * Ls + K + w] & a) : 0ULL;
+        sz[k] = ok ? (Z[(size_t)jj * Ls + K + w] & a) : 0ULL;
       }
-      const u64 bx = __ballot(tpx), bz = __ballot(tpz);
-      if (lane == 0) {
-        s_px[wave] = (u32)__popcll(bx) & 1u;
-        s_pz[wave] = (u32)__popcll(bz) & 1u;
-      }
-      __syncthreads();
-      u32 cx = carry_x ^ ((u32)__popcll(bx & lanemask_lt()) & 1u);
-      u32 cz = carry_z ^ ((u32)__popcll(bz & lanemask_lt()) & 1u);
-      for (u32 v = 0; v < nwaves; ++v) {
-        if (v < wave) { cx ^= s_px[v]; cz ^= s_pz[v]; }
-        carry_x ^= s_px[v];
-        carry_z ^= s_pz[v];
-      }
-      __syncthreads();
 #pragma unroll
-      for (int k = 0; k < 2; ++k) {
-        const u64 ex = (prefix_xor_incl(sx[k]) << 1) ^ (cx ? ~0ULL : 0ULL);
-        const u64 ez = (prefix_xor_incl(sz[k]) << 1) ^ (cz ? ~0ULL : 0ULL);
-        const u64 x1 = sx[k], z1 = sz[k];
-        const u64 p_x = x1 & ~z1, p_y = x1 & z1, p_z = ~x1 & z1;
-        const u64 plus = (p_x & ex & ez) | (p_y & ~ex & ez) | (p_z & ex & ~ez);
-        const u64 minus = (p_x & ~ex & ez) | (p_y & ex & ~ez) | (p_z & ex & ez);
-        acc += __popcll(plus) - __popcll(minus);
-        cx ^= (u32)__popcll(sx[k]) & 1u;
-        cz ^= (u32)__popcll(sz[k]) & 1u;
+      for (u32 k = 0; k < DET_CB; ++k) {
+        const u32 jj = j + k * nwaves;
+        if (jj < j1) {  // uniform over the wave
+          u32 cx = 0, cz = 0;
+          det_word(sx[k], sz[k], cx, cz, acc);
+          if (cx != 0u || cz != (u32)(jj == q)) bad = 1;
+        }
       }
     }
-    if (carry_x != 0u || carry_z != (u32)(j == q)) bad = 1;
+  } else {
+    // rounds of DET_U list entries per lane (entry base + k*64 + lane), the
+    // loads of a round issued before its scans
+    for (u32 j = j0 + wave; j < j1; j += nwaves) {
+      const u64 *xc = X + (size_t)j * Ls + K;
+      const u64 *zc = Z + (size_t)j * Ls + K;
+      u32 cx = 0, cz = 0;
+      for (u32 base = 0; base < aw; base += 64u * DET_U) {
+        u64 sx[DET_U], sz[DET_U];
+#pragma unroll
+        for (u32 k = 0; k < DET_U; ++k) {
+          const u32 e = base + k * 64u + lane;
+          sx[k] = 0;
+          sz[k] = 0;
+          if (e < aw) {
+            const u32 w = alist[e];
+            const u64 a = amask[e];
+            sx[k] = xc[w] & a;
+            sz[k] = zc[w] & a;
+          }
+        }
+#pragma unroll
+        for (u32 k = 0; k < DET_U; ++k) det_word(sx[k], sz[k], cx, cz, acc);
+      }
+      if (cx != 0u || cz != (u32)(j == q)) bad = 1;
+    }
   }
   if (SYM) {
     // Coin coefficients of the outcome's affine form: bit v of F_i is the
@@ -459,8 +522,9 @@ __global__ __launch_bounds__(256) void k_post(u64 *__restrict__ X, u64 *__restri
       u32 par[PER];
 #pragma unroll
       for (u32 k = 0; k < PER; ++k) par[k] = 0;
-      for (u32 w = lane; w < K; w += 64u) {
-        const u64 m = mask[w];
+      for (u32 e = lane; e < aw; e += 64u) {
+        const u32 w = alist[e];
+        const u64 m = amask[e];
         u64 c[PER];
 #pragma unroll
         for (u32 k = 0; k < PER; ++k) c[k] = (v0 + k < li) ? sym.sg[(size_t)(v0 + k) * sym.Ks + w] : 0ULL;
@@ -492,7 +556,7 @@ __global__ __launch_bounds__(256) void k_post(u64 *__restrict__ X, u64 *__restri
   // last block: sign parity over A, then the outcome (or the constant of its affine form)
   u32 par = 0;
   const u64 *sgn = SYM ? (sym.sg + (size_t)sym.count * sym.Ks) : (R + K);
-  for (u32 w = tid; w < K; w += blockDim.x) par ^= (u32)__popcll(sgn[w] & mask[w]) & 1u;
+  for (u32 e = tid; e < aw; e += blockDim.x) par ^= (u32)__popcll(sgn[alist[e]] & amask[e]) & 1u;
   const u64 b = __ballot(par);
   if (lane == 0) s_px[wave] = (u32)__popcll(b) & 1u;
   __syncthreads();
@@ -538,8 +602,9 @@ hipError_t launch_cursor_init(Cursor *c, u32 end, u32 kb, u64 seed, u64 shot, u6
   return hipGetLastError();
 }
 
-hipError_t launch_pivot(const TabDev &t, Cursor *cur, MeasState *st, u64 *mask, hipStream_t s) {
-  hipLaunchKernelGGL(k_pivot, dim3(1), dim3(1024), 0, s, t.X, t.Ls, t.K, t.L, cur, st, mask);
+hipError_t launch_pivot(const TabDev &t, Cursor *cur, MeasState *st, u64 *mask, u32 *alist, u64 *amask,
+                        hipStream_t s) {
+  hipLaunchKernelGGL(k_pivot, dim3(1), dim3(1024), 0, s, t.X, t.Ls, t.K, t.L, cur, st, mask, alist, amask);
   return hipGetLastError();
 }
 
@@ -582,19 +647,19 @@ hipError_t launch_rowsum(const TabDev &t, const u64 *mask, const u32 *cols, cons
 }
 
 hipError_t launch_post(const TabDev &t, const Cursor *cur, const u64 *mask, const u64 *pivx, const u64 *pivz,
-                       const u64 *cnt0, const u64 *cnt1, MeasState *st, MeasStats *stats, u32 cpc, u32 cpw,
-                       const SymCtx *sym, hipStream_t s) {
+                       const u64 *cnt0, const u64 *cnt1, const u32 *alist, MeasState *st, MeasStats *stats, u32 cpc,
+                       u32 cpw, const SymCtx *sym, hipStream_t s) {
   // roles: a wave per sign word (4 per block), a thread per column, a block per
   // deterministic column range (and per affine-form word on the sampling path,
   // up to the last list position)
   u32 blocks = std::max(std::max(cdiv(t.L, 4), cdiv(t.n, 256)), cdiv(t.n, cpw));
   if (sym) blocks = std::max(blocks, cdiv(sym->count + 1, 64));
   if (sym)
-    hipLaunchKernelGGL(k_post<true>, dim3(blocks), dim3(256), 0, s, t.X, t.Z, t.R, mask, pivx, pivz, cnt0, cnt1, st,
-                       stats, cur, t.Ls, t.L, t.K, t.n, cpc, cpw, *sym);
+    hipLaunchKernelGGL(k_post<true>, dim3(blocks), dim3(256), 0, s, t.X, t.Z, t.R, mask, pivx, pivz, cnt0, cnt1,
+                       alist, st, stats, cur, t.Ls, t.L, t.K, t.n, cpc, cpw, *sym);
   else
-    hipLaunchKernelGGL(k_post<false>, dim3(blocks), dim3(256), 0, s, t.X, t.Z, t.R, mask, pivx, pivz, cnt0, cnt1, st,
-                       stats, cur, t.Ls, t.L, t.K, t.n, cpc, cpw, SymCtx{});
+    hipLaunchKernelGGL(k_post<false>, dim3(blocks), dim3(256), 0, s, t.X, t.Z, t.R, mask, pivx, pivz, cnt0, cnt1,
+                       alist, st, stats, cur, t.Ls, t.L, t.K, t.n, cpc, cpw, SymCtx{});
   return hipGetLastError();
 }
 

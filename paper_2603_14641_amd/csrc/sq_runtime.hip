@@ -245,7 +245,7 @@ u32 rowsum_cpc(const sq_tableau *T) {
 
 u32 det_cpw(const sq_tableau *T) {
   if (T->tun.det_cols) return T->tun.det_cols;
-  return std::max<u32>(1, cdiv(T->d.n, 2048));
+  return std::max<u32>(4, cdiv(T->d.n, 2048));  // 2048 workgroups of 4 waves at most
 }
 
 hipEvent_t take_event(sq_tableau *T) {
@@ -520,7 +520,8 @@ sq_status queue_slot(sq_tableau *T, const SweepCtx &c, u32 kb) {
   if (kb <= 1) {
     const u32 cpc = rowsum_cpc(T);
     const u32 max_chunks = cdiv(T->d.n, cpc);
-    SQ_TRY(timed(T, SQ_K_PIVOT, [&] { return launch_pivot(c.tab, T->cur, T->st, T->mask, T->stream); }));
+    SQ_TRY(timed(T, SQ_K_PIVOT,
+                 [&] { return launch_pivot(c.tab, T->cur, T->st, T->mask, T->cols, T->pivx, T->stream); }));
     SQ_TRY(timed(T, SQ_K_GATHER, [&] {
       return launch_gather(c.tab, T->st, T->pivx, T->pivz, T->cols, c.sym, T->stream);
     }));
@@ -529,8 +530,8 @@ sq_status queue_slot(sq_tableau *T, const SweepCtx &c, u32 kb) {
                            cpc, max_chunks, c.sym, T->stream);
     }));
     SQ_TRY(timed(T, SQ_K_POST, [&] {
-      return launch_post(c.tab, T->cur, T->mask, T->pivx, T->pivz, T->cnt0, T->cnt1, T->st, T->stats, cpc, det_cpw(T),
-                         c.sym, T->stream);
+      return launch_post(c.tab, T->cur, T->mask, T->pivx, T->pivz, T->cnt0, T->cnt1, T->cols, T->st, T->stats, cpc,
+                         det_cpw(T), c.sym, T->stream);
     }));
     return SQ_OK;
   }
@@ -546,10 +547,11 @@ sq_status queue_slot(sq_tableau *T, const SweepCtx &c, u32 kb) {
   // the deterministic measurement that ended the block: its product only
   // (pivot search, mask snapshot, then the ordered product in k_post)
   const u32 cpc = rowsum_cpc(T);
-  SQ_TRY(timed(T, SQ_K_PIVOT, [&] { return launch_pivot(c.tab, T->cur, T->st, T->mask, T->stream); }));
+  SQ_TRY(timed(T, SQ_K_PIVOT,
+               [&] { return launch_pivot(c.tab, T->cur, T->st, T->mask, T->cols, T->pivx, T->stream); }));
   SQ_TRY(timed(T, SQ_K_POST, [&] {
-    return launch_post(c.tab, T->cur, T->mask, T->pivx, T->pivz, T->cnt0, T->cnt1, T->st, T->stats, cpc, det_cpw(T),
-                       c.sym, T->stream);
+    return launch_post(c.tab, T->cur, T->mask, T->pivx, T->pivz, T->cnt0, T->cnt1, T->cols, T->st, T->stats, cpc,
+                       det_cpw(T), c.sym, T->stream);
   }));
   return SQ_OK;
 }

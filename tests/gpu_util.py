@@ -76,3 +76,17 @@ def gpu_run_calls(t, ops, seed, shot=0, meas_base=0):
     if not bits:
         return np.zeros(0, np.uint8), np.zeros(0, np.uint8)
     return np.concatenate(bits), np.concatenate(rnd)
+
+
+def otableau_state(ot):
+    """The operator-tableau oracle's arrays in the library's export order:
+    rows i < n the destabilizer half (XD, ZD), rows n + i the stabilizer half
+    (XS, ZS); sign byte i < n the image of X_i, n + i the image of Z_i."""
+    xs, xd, zs, zd, ss, sd = ot.arrays()
+    n = ot.n
+
+    def signs(vec):
+        return np.unpackbits(np.ascontiguousarray(vec, dtype="<u8").view(np.uint8), bitorder="little")[:n]
+
+    return (np.concatenate([xd, xs]), np.concatenate([zd, zs]),
+            np.concatenate([signs(sd), signs(ss)]).astype(np.uint8))

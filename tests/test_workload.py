@@ -53,3 +53,25 @@ def test_served_mix_ranges():
     assert all(10 <= r.depth <= 500 for r in reqs)
     assert all(1 <= r.shots <= 4096 for r in reqs)
     assert all(b.arrival_s > a.arrival_s for a, b in zip(reqs, reqs[1:]))
+
+
+def test_basis_circuit_planted_bits_match_the_oracle():
+    """The planted bit string of basis_circuit is what the CHP oracle measures:
+    every qubit deterministic, outcome b_q (and the generator's pairs are
+    disjoint within a layer, so layers can be fused)."""
+    from oracle import oracle as orc
+    from workload import basis_circuit
+    n, layers = 257, 40
+    ops, bits = basis_circuit(n, layers, seed=11)
+    assert set(np.unique(ops["type"])) <= {orc.CX, orc.CZ, orc.SWAP, orc.S, orc.SDG, orc.X, orc.Y, orc.Z}
+    assert 0 < bits.sum() < n
+    arr = np.stack([ops["type"], ops["q0"], ops["q1"]], 1).astype(np.uint32)
+    meas = np.stack([np.full(n, orc.MEASURE), np.arange(n), np.zeros(n)], 1).astype(np.uint32)
+    t = orc.Tableau(n)
+    out, rnd, _ = t.run(np.concatenate([arr, meas]), seed=1)
+    assert not rnd.any()
+    assert np.array_equal(out, bits)
+    # dense products: after 40 layers the destabilizers' X parts are about
+    # half full (|A| near n/2 for every qubit)
+    x, _, _ = t.rows_array()
+    assert np.mean([bin(int(w)).count("1") for w in x[:n].reshape(-1)]) > 16
