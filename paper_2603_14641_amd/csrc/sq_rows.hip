@@ -117,9 +117,15 @@ __global__ __launch_bounds__(1024) void k_transpose(u64 *__restrict__ X, u64 *__
   const u32 bj = bi + (t - row0(bi));
   u64 *M = (blockIdx.y >> 1) ? Z : X;
   const u32 off = (blockIdx.y & 1u) ? K : 0u;
+  // The stabilizer half starts at word K: its tile grid is shifted back by
+  // K mod 16 tiles in both directions (a transpose keeps a symmetric grid),
+  // so that every 16-word slot segment it moves starts on a 128-byte line.
+  // Tiles before the first (negative indices, which wrap around in u32)
+  // fail the range checks of the staging loops.
+  const u32 sh = (blockIdx.y & 1u) ? (K & 15u) : 0u;
   const bool diag = bi == bj;
-  const u32 slotA = 64u * TB * bi, wordA = TB * bj;  // side A: its slots hold words wordA ..
-  const u32 slotB = 64u * TB * bj, wordB = TB * bi;  // the mirror side
+  const u32 slotA = 64u * (TB * bi - sh), wordA = TB * bj - sh;  // side A: its slots hold words wordA ..
+  const u32 slotB = 64u * (TB * bj - sh), wordB = TB * bi - sh;  // the mirror side
   u64 A[TB], B[TB];
   side_in(M, buf, Ls, K, off, slotA, wordA, A);
   if (!diag) side_in(M, buf, Ls, K, off, slotB, wordB, B);
@@ -415,7 +421,7 @@ __global__ __launch_bounds__(1024) void k_row_finish(u64 *__restrict__ X, u64 *_
 
 // Launchers.
 hipError_t launch_transpose(const TabDev &t, hipStream_t s) {
-  const u32 nb = cdiv(t.K, TB);
+  const u32 nb = cdiv(t.K + (t.K & 15u), TB);  // blocks per side, room for the shifted grid
   hipLaunchKernelGGL(k_transpose, dim3(nb * (nb + 1) / 2, 4), dim3(1024), 0, s, t.X, t.Z, t.Ls, t.K, nb);
   return hipGetLastError();
 }
