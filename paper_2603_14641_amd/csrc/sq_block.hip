@@ -341,6 +341,10 @@ __device__ __forceinline__ void blk_masks(const u64 *__restrict__ X, u64 *__rest
     if (s < k) bm[(size_t)s * Ls + w] = b[s] & ~special;
 }
 
+// Distinct row words holding pivots whose loads a thread issues together
+// (k_blk_special, k_blk_sv_prep).
+constexpr u32 SPEC_B = 8;
+
 // -------------------------------------------------------------- pivot rows and their algebra
 // Grid cdiv(n, ROWS_T): thread per column j, wave per 64-column word cw.
 // (1) The original pivot rows' bits at the wave's columns: one read of x and
@@ -783,7 +787,9 @@ __global__ __launch_bounds__(BLK_SIGN_T) void k_blk_signs(u64 *__restrict__ R, c
 
 // Thread per column: the column's bits of the special rows, one
 // read-modify-write per distinct row word holding pivots: D_{p_s} = P_s times
-// its later hits, S_{p_s} = Z_{q_s}.
+// its later hits, S_{p_s} = Z_{q_s}. The words are distinct, so a thread
+// loads SPEC_B of them (x and z, both halves) before changing any: a memory
+// round trip per SPEC_B words instead of one per word.
 __global__ void k_blk_special(u64 *__restrict__ X, u64 *__restrict__ Z, const u32 *__restrict__ patx,
                               const u32 *__restrict__ patz, const BlkState *__restrict__ bs, u32 Ls, u32 K, u32 n) {
   __shared__ u32 spv[KB], sdh[KB], sqb[KB];  // per pivot: row, D-row factors, measured qubit
@@ -802,22 +808,38 @@ __global__ void k_blk_special(u64 *__restrict__ X, u64 *__restrict__ Z, const u3
   u64 *x = X + (size_t)j * Ls;
   u64 *z = Z + (size_t)j * Ls;
   const u32 nw = bs->nwords;
-  for (u32 i = 0; i < nw; ++i) {
-    const u32 wd = bs->word[i], mem = bs->wmem[i];
-    u64 mask = 0, xd = 0, zd = 0, zs = 0;
-    for (u32 m = mem; m; m &= m - 1) {
-      const u32 s = (u32)__builtin_ctz(m);
-      const u64 bit = 1ULL << (spv[s] & 63u);
-      const u32 dh = sdh[s];
-      mask |= bit;
-      if (__popc(px & dh) & 1) xd |= bit;
-      if (__popc(pz & dh) & 1) zd |= bit;
-      if (j == sqb[s]) zs |= bit;
+  for (u32 i0 = 0; i0 < nw; i0 += SPEC_B) {
+    u64 dx[SPEC_B], dz[SPEC_B], sx[SPEC_B], sz[SPEC_B];
+#pragma unroll
+    for (u32 u = 0; u < SPEC_B; ++u) {
+      if (i0 + u < nw) {  // uniform
+        const u32 wd = bs->word[i0 + u];
+        dx[u] = x[wd];
+        dz[u] = z[wd];
+        sx[u] = x[K + wd];
+        sz[u] = z[K + wd];
+      }
     }
-    x[wd] = (x[wd] & ~mask) | xd;
-    z[wd] = (z[wd] & ~mask) | zd;
-    x[K + wd] &= ~mask;
-    z[K + wd] = (z[K + wd] & ~mask) | zs;
+#pragma unroll
+    for (u32 u = 0; u < SPEC_B; ++u) {
+      if (i0 + u < nw) {
+        const u32 wd = bs->word[i0 + u], mem = bs->wmem[i0 + u];
+        u64 mask = 0, xd = 0, zd = 0, zs = 0;
+        for (u32 m = mem; m; m &= m - 1) {
+          const u32 s = (u32)__builtin_ctz(m);
+          const u64 bit = 1ULL << (spv[s] & 63u);
+          const u32 dh = sdh[s];
+          mask |= bit;
+          if (__popc(px & dh) & 1) xd |= bit;
+          if (__popc(pz & dh) & 1) zd |= bit;
+          if (j == sqb[s]) zs |= bit;
+        }
+        x[wd] = (dx[u] & ~mask) | xd;
+        z[wd] = (dz[u] & ~mask) | zd;
+        x[K + wd] = sx[u] & ~mask;
+        z[K + wd] = (sz[u] & ~mask) | zs;
+      }
+    }
   }
 }
 
@@ -841,11 +863,17 @@ __global__ void k_blk_sv_prep(const u64 *__restrict__ sg, u32 Ks, u32 count, con
   const u32 v = t < m0 ? t : count;
   const u32 nw = bs->nwords;
   u32 s0 = 0;  // coefficients of the original pivot rows
-  for (u32 i = 0; i < nw; ++i) {
-    const u64 wv = sg[(size_t)v * Ks + bs->word[i]];
-    for (u32 m = bs->wmem[i]; m; m &= m - 1) {
-      const u32 s = (u32)__builtin_ctz(m);
-      if ((wv >> (bs->p[s] & 63u)) & 1ULL) s0 |= 1u << s;
+  for (u32 i0 = 0; i0 < nw; i0 += SPEC_B) {
+    u64 wv[SPEC_B];
+#pragma unroll
+    for (u32 u = 0; u < SPEC_B; ++u) wv[u] = i0 + u < nw ? sg[(size_t)v * Ks + bs->word[i0 + u]] : 0ULL;
+#pragma unroll
+    for (u32 u = 0; u < SPEC_B; ++u) {
+      if (i0 + u >= nw) break;
+      for (u32 m = bs->wmem[i0 + u]; m; m &= m - 1) {
+        const u32 s = (u32)__builtin_ctz(m);
+        if ((wv[u] >> (bs->p[s] & 63u)) & 1ULL) s0 |= 1u << s;
+      }
     }
   }
   u32 lin = 0;
@@ -856,8 +884,10 @@ __global__ void k_blk_sv_prep(const u64 *__restrict__ sg, u32 Ks, u32 count, con
 // Grid (stabilizer-word tiles, workgroups over column chunks of SV_CHUNK):
 // thread per stabilizer word; workgroup y takes the chunks y, y + gridDim.y,
 // ... of the columns t in [0, m0 + k]: t < m0 coin columns, m0 <= t < m0 + k
-// this block's coins, t = m0 + k the constant.
-constexpr u32 SV_CHUNK = 16, SV_GROUP = 16, SV_MAX_Y = 64;
+// this block's coins, t = m0 + k the constant. Up to SV_MAX_Y workgroups
+// along y, so that late in a sweep (thousands of coin columns) a workgroup
+// walks a few chunks, not dozens, one memory round trip each.
+constexpr u32 SV_CHUNK = 16, SV_GROUP = 16, SV_MAX_Y = 512;
 
 __global__ __launch_bounds__(64) void k_blk_sv_update(u64 *__restrict__ sg, u32 Ks, u32 count,
                                                        const BlkState *__restrict__ bs, const u64 *__restrict__ bm,

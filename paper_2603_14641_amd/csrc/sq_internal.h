@@ -95,7 +95,7 @@ struct MeasState {
   u32 awords;     // nonzero destabilizer-half words of column q (deterministic case)
   u32 nx, nz;     // pivot-row columns with x_pj = 1, with z_pj = 1
   u32 nsv;        // sampling: coin columns in which S_p has a 1 (compacted list length)
-  u32 det_done;   // deterministic case: blocks of k_post that have added their phase sums
+  u32 det_done;   // deterministic case: k_post's blocks done (bits 0..23) and their phase sum mod 256 (bits 24..31)
   u32 inj;        // CX-injection collapse: bit 0 inverse-phase rotation (else H), bit 1 X injection
   u32 pc;         // row layout: pivot candidate (grid-wide minimum; 0xFFFFFFFF none)
   u32 naff;       // row layout: rows multiplied by the pivot in this measurement

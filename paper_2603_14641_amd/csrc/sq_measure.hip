@@ -353,8 +353,8 @@ __device__ __forceinline__ void det_word(u64 x1, u64 z1, u32 &cx, u32 &cz, int &
 // its waves one column at a time each; a wave walks only the words of A that
 // k_pivot listed (alist/amask), 64 per wave-wide step (det_word), so a column
 // costs the bytes of A's words, not of all K. The column's total XOR
-// must be 0 for x and [j == q] for z. Blocks add their sums to det_acc; the
-// last block to finish (atomic ticket, no waiting) forms the outcome: parity of
+// must be 0 for x and [j == q] for z. Blocks add their sums into the ticket
+// word det_done; the last block to finish (no waiting) forms the outcome: parity of
 // S_i's signs over A xor bit 1 of the sum (which must be even). The sampler's
 // blocks also compute the coin coefficients of the outcome's affine form
 // (parity of sign column v over A, v < i), and the last block its constant.
@@ -445,7 +445,7 @@ __global__ __launch_bounds__(256) void k_post(u64 *__restrict__ X, u64 *__restri
   }
 
   // ---- deterministic case
-  __shared__ u32 s_px[4], s_last;
+  __shared__ u32 s_px[4], s_last, s_e;
   __shared__ int s_acc[4];
   const u32 aw = st->awords;
   const u64 *amask = pivx;  // the compacted rows of A (k_pivot; pivx is free here)
@@ -545,14 +545,16 @@ __global__ __launch_bounds__(256) void k_post(u64 *__restrict__ X, u64 *__restri
   if (tid == 0) {
     int tot = 0;
     for (u32 v = 0; v < nwaves; ++v) tot += s_acc[v];
-    atomicAdd(&st->det_acc, (u32)tot);
     if (bad) atomicOr(&st->flags, 2u);
-    __threadfence();
-    s_last = (atomicAdd(&st->det_done, 1u) == gridDim.x - 1) ? 1u : 0u;
+    // One atomic carries both the ticket (bits 0..23: blocks done) and the
+    // phase sum (bits 24..31, mod 256: only its value mod 4 is used), so the
+    // last block has the whole sum without a device-scope fence per block.
+    const u32 old = atomicAdd(&st->det_done, 1u + ((u32)tot << 24));
+    s_last = ((old & 0xFFFFFFu) == gridDim.x - 1) ? 1u : 0u;
+    s_e = ((old >> 24) + (u32)tot) & 3u;
   }
   __syncthreads();
   if (!s_last) return;
-  __threadfence();
   // last block: sign parity over A, then the outcome (or the constant of its affine form)
   u32 par = 0;
   const u64 *sgn = SYM ? (sym.sg + (size_t)sym.count * sym.Ks) : (R + K);
@@ -563,7 +565,7 @@ __global__ __launch_bounds__(256) void k_post(u64 *__restrict__ X, u64 *__restri
   if (tid == 0) {
     u32 tot = 0;
     for (u32 v = 0; v < nwaves; ++v) tot ^= s_px[v];
-    const u32 e = atomicAdd(&st->det_acc, 0u) & 3u;
+    const u32 e = s_e;
     if (e & 1u) atomicOr(&st->flags, 1u);
     const uint8_t outcome = (uint8_t)(tot ^ (e >> 1));
     if (SYM) {
