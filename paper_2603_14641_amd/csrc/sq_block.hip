@@ -105,7 +105,6 @@ __device__ void pivots_finish(u32 lane, u32 k, u32 want, u32 i0, const u32 *sq, 
     bs->i0 = i0;
     bs->nwords = (u32)__popcll(fb);
     bs->ncols = 0;
-    bs->done = 0;
     cur->i = i0 + k;
     cur->single = k < want ? 1u : 0u;
   }
@@ -356,19 +355,17 @@ constexpr u32 SPEC_B = 8;
 // for pivot a: bits b of z_{P_a} . x_{P_b} (Qz) and of z_{P_a} . x_{S0_b}
 // (R0), |x & z| of the final D_{p_a} (P_a times its later hits) and of the
 // original row S0_{p_a}, the counts mod 4; the block combines its waves'
-// shares in LDS and writes one. The last block to finish sums the blocks'
-// shares and forms lam(P_s) and the final signs of the D_{p_s}.
+// shares in LDS and writes one; blk_algebra then sums the blocks' shares
+// and forms lam(P_s) and the final signs of the D_{p_s}.
 constexpr u32 ROWS_T = 256;
 constexpr u32 ROWS_W = ROWS_T / 64;  // waves per block
 
 __device__ __forceinline__ void blk_rows(const u64 *__restrict__ X, const u64 *__restrict__ Z,
                                          const u64 *__restrict__ R, u32 Ls, u32 K, u32 n, BlkState *__restrict__ bs,
                                          u32 *__restrict__ patx, u32 *__restrict__ patz, u32 *__restrict__ wpart,
-                                         u32 *__restrict__ clist, MeasState *__restrict__ st, u32 bid,
-                                         u32 nblocks) {
+                                         u32 *__restrict__ clist, u32 bid) {
   __shared__ u64 s0x[ROWS_W][KB], s0z[ROWS_W][KB], sx[ROWS_W][KB], sz[ROWS_W][KB];
-  __shared__ u32 red[4][ROWS_T / KB][KB];  // per-wave shares, then per-group sums
-  __shared__ u32 s_last;
+  __shared__ u32 red[4][ROWS_T / KB][KB];  // per-wave shares
   const u32 k = bs->k;
   if (k == 0) return;  // the same for every workgroup
   const u32 tid = threadIdx.x, lane = tid & 63u, wv = tid >> 6;
@@ -483,12 +480,19 @@ __device__ __forceinline__ void blk_rows(const u64 *__restrict__ X, const u64 *_
     wp[2 * KB + tid] = d;
     wp[3 * KB + tid] = p0;
   }
-  __threadfence();
-  __syncthreads();
-  if (tid == 0) s_last = (atomicAdd(&bs->done, 1u) == nblocks - 1) ? 1u : 0u;
-  __syncthreads();
-  if (!s_last) return;
-  __threadfence();
+}
+
+// The pivot algebra of a block, once its row workgroups have written their
+// shares (one workgroup of ROWS_T threads in a later launch, the last one of
+// k_blk_reduce's grid): sums over the shares, lam(P_s) and the final signs
+// of the D_{p_s}. The kernel boundary orders the shares' writes before these
+// reads, so the row workgroups need no fence.
+__device__ __forceinline__ void blk_algebra(const u32 *__restrict__ wpart, BlkState *__restrict__ bs,
+                                            MeasState *__restrict__ st, u32 nblocks) {
+  __shared__ u32 red[4][ROWS_T / KB][KB];
+  const u32 k = bs->k;
+  if (k == 0) return;
+  const u32 tid = threadIdx.x, lane = tid & 63u, wv = tid >> 6;
   // sums over the blocks' shares: thread t takes pivot t mod KB and the
   // blocks g, g + G, ... with g = t / KB, G = ROWS_T / KB groups
   {
@@ -566,13 +570,12 @@ __global__ __launch_bounds__(ROWS_T) void k_blk_masks_rows(const u64 *__restrict
                                                            const u64 *__restrict__ R, u64 *__restrict__ bm,
                                                            BlkState *__restrict__ bs,
                                                            u32 *__restrict__ patx, u32 *__restrict__ patz,
-                                                           u32 *__restrict__ wpart, u32 *__restrict__ clist,
-                                                           MeasState *__restrict__ st, u32 Ls, u32 L, u32 K, u32 n,
-                                                           u32 mblocks) {
+                                                           u32 *__restrict__ wpart, u32 *__restrict__ clist, u32 Ls,
+                                                           u32 L, u32 K, u32 n, u32 mblocks) {
   if (blockIdx.x < mblocks)
     blk_masks(X, bm, bs, Ls, L, K, blockIdx.x);
   else
-    blk_rows(X, Z, R, Ls, K, n, bs, patx, patz, wpart, clist, st, blockIdx.x - mblocks, gridDim.x - mblocks);
+    blk_rows(X, Z, R, Ls, K, n, bs, patx, patz, wpart, clist, blockIdx.x - mblocks);
 }
 
 constexpr u32 BLK_PASS_T = 512;
@@ -670,20 +673,31 @@ __global__ __launch_bounds__(BLK_PASS_T) void k_blk_pass(u64 *__restrict__ X, u6
 // -------------------------------------------------------------- chunk reduction
 // A wave per (row word, field): lanes take every 64th chunk, then a butterfly
 // combines them. Field 0 adds the 2-bit counters (mod 4), field 1 XORs the
-// parity words. The result goes to chunk 0's slots.
-__global__ void k_blk_reduce(u64 *__restrict__ part, const u64 *__restrict__ bm, const BlkState *__restrict__ bs,
-                             u32 Ls, u32 L, u32 nchunks) {
+// parity words. The result goes to chunk 0's slots. The grid has one column
+// of workgroups more (of ROWS_T threads): its first does the block's pivot
+// algebra (blk_algebra), the second nothing.
+__global__ __launch_bounds__(ROWS_T) void k_blk_reduce(u64 *__restrict__ part, const u64 *__restrict__ bm,
+                                                       const u32 *__restrict__ wpart, BlkState *__restrict__ bs,
+                                                       MeasState *__restrict__ st, u32 Ls, u32 L, u32 nchunks,
+                                                       u32 rblocks) {
+  if (blockIdx.x == gridDim.x - 1) {  // uniform over the workgroup
+    if (blockIdx.y == 0) blk_algebra(wpart, bs, st, rblocks);
+    return;
+  }
   const u32 k = bs->k;
   const u32 lane = threadIdx.x & 63u;
   const u32 w = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
   const u32 f = blockIdx.y;
   if (w >= L) return;  // uniform over the wave
   u64 any = 0;
-  for (u32 s = 0; s < k; ++s) any |= bm[(size_t)s * Ls + w];
+#pragma unroll
+  for (u32 s = 0; s < KB; ++s)  // loads in flight together (rows past k: not used)
+    any |= s < k ? bm[(size_t)s * Ls + w] : 0ULL;
   if (any == 0) return;  // k_blk_pass wrote nothing for this row word
   const size_t stride = (size_t)BLK_PART * Ls;
   if (f == 0) {
     u64 d0 = 0, d1 = 0;
+#pragma unroll 4
     for (u32 c = lane; c < nchunks; c += 64u) {
       const u64 a0 = part[c * stride + w], a1 = part[c * stride + Ls + w];
       const u64 carry = d0 & a0;
@@ -703,6 +717,7 @@ __global__ void k_blk_reduce(u64 *__restrict__ part, const u64 *__restrict__ bm,
   } else {
     const size_t o = 2 * (size_t)Ls + w;
     u64 y = 0;
+#pragma unroll 4
     for (u32 c = lane; c < nchunks; c += 64u) y ^= part[c * stride + o];
     for (int off = 32; off > 0; off >>= 1) y ^= shfl_xor_u64(y, off);
     if (lane == 0) part[o] = y;
@@ -960,10 +975,10 @@ hipError_t launch_blk_pivots(const TabDev &t, Cursor *cur, const BlkBuffers &b, 
 }
 
 // Stage 1: hit masks, pivot rows and their algebra.
-hipError_t launch_blk_prep(const TabDev &t, const BlkBuffers &b, MeasState *st, hipStream_t s) {
+hipError_t launch_blk_prep(const TabDev &t, const BlkBuffers &b, hipStream_t s) {
   const u32 mblocks = cdiv(t.L, ROWS_T), rblocks = cdiv(t.n, ROWS_T);
   hipLaunchKernelGGL(k_blk_masks_rows, dim3(mblocks + rblocks), dim3(ROWS_T), 0, s, t.X, t.Z, t.R, b.bm, b.bs,
-                     b.patx, b.patz, b.wpart, b.clist, st, t.Ls, t.L, t.K, t.n, mblocks);
+                     b.patx, b.patz, b.wpart, b.clist, t.Ls, t.L, t.K, t.n, mblocks);
   return hipGetLastError();
 }
 
@@ -979,7 +994,9 @@ hipError_t launch_blk_pass(const TabDev &t, const BlkBuffers &b, u32 cpc, hipStr
 hipError_t launch_blk_final(const TabDev &t, const BlkBuffers &b, MeasState *st, MeasStats *stats, u32 cpc,
                             hipStream_t s) {
   const u32 nchunks = cdiv(t.n, cpc);
-  hipLaunchKernelGGL(k_blk_reduce, dim3(cdiv(t.L, 4), 2), dim3(256), 0, s, b.part, b.bm, b.bs, t.Ls, t.L, nchunks);
+  // k_blk_reduce: a wave per (row word, field), then one workgroup for the pivot algebra
+  hipLaunchKernelGGL(k_blk_reduce, dim3(cdiv(t.L, ROWS_T / 64) + 1, 2), dim3(ROWS_T), 0, s, b.part, b.bm, b.wpart,
+                     b.bs, st, t.Ls, t.L, nchunks, cdiv(t.n, ROWS_T));
   hipLaunchKernelGGL(k_blk_signs, dim3(cdiv(t.L, BLK_SIGN_T)), dim3(BLK_SIGN_T), 0, s, t.R, b.bm, b.part, b.bs, st,
                      stats, t.Ls, t.L, t.K);
   hipLaunchKernelGGL(k_blk_special, dim3(cdiv(t.n, 256)), dim3(256), 0, s, t.X, t.Z, b.patx, b.patz, b.bs, t.Ls, t.K,

@@ -145,7 +145,6 @@ struct BlkState {
   u32 lam[KB];    // lam(P_s) = 2 r + |x & z| (mod 4)
   u32 dsign[KB];  // final sign of D_{p_s}
   u32 ncols;      // columns where some pivot is not the identity
-  u32 done;       // blocks of k_blk_pivalg finished (last-block ticket)
   u32 nwords;     // distinct row words (within a half) holding the pivots
   u32 word[KB];   // those words
   u32 wmem[KB];   // bit s: pivot s lies in word[i]
@@ -230,7 +229,7 @@ hipError_t launch_batch(const BatchItem *items, u32 nitems, u32 *next, u32 block
 // with that many waves
 constexpr u32 PIVOT_AUTO = 255;
 hipError_t launch_blk_pivots(const TabDev &t, Cursor *cur, const BlkBuffers &b, u32 waves, hipStream_t s);
-hipError_t launch_blk_prep(const TabDev &t, const BlkBuffers &b, MeasState *st, hipStream_t s);
+hipError_t launch_blk_prep(const TabDev &t, const BlkBuffers &b, hipStream_t s);
 hipError_t launch_blk_pass(const TabDev &t, const BlkBuffers &b, u32 cpc, hipStream_t s);
 hipError_t launch_blk_final(const TabDev &t, const BlkBuffers &b, MeasState *st, MeasStats *stats, u32 cpc,
                             hipStream_t s);
