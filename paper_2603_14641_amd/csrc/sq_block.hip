@@ -113,7 +113,8 @@ __device__ void pivots_finish(u32 lane, u32 k, u32 want, u32 i0, const u32 *sq, 
 
 __global__ __launch_bounds__(64 * PW_WAVES) void k_blk_pivots(const u64 *__restrict__ X, u64 *__restrict__ bm,
                                                                u32 Ls, u32 K, Cursor *__restrict__ cur,
-                                                               BlkState *__restrict__ bs) {
+                                                               BlkState *__restrict__ bs, u64 *__restrict__ zw,
+                                                               u32 nzw) {
   __shared__ u32 s_wmin[2];  // double-buffered: step s uses s_wmin[s & 1]
   // per-step state in LDS (indexed by step, which is not a compile-time
   // constant); done[] is per wave and written by its lane 0
@@ -130,6 +131,7 @@ __global__ __launch_bounds__(64 * PW_WAVES) void k_blk_pivots(const u64 *__restr
   if (tid < KB) { piv[tid] = 0; mrow[tid] = 0; mcol[tid] = 0; hits[tid] = 0; }
   if (tid < 2) s_wmin[tid] = 0xFFFFFFFFu;
   if (lane < KB) done[lane] = 0;
+  for (u32 i = tid; i < nzw; i += blockDim.x) zw[i] = 0;  // words the slot's later kernels need zeroed
   u32 i0, want;
   block_take(cur, sq, s_hdr, i0, want);
   auto word_of = [&](u32 j) { return (j * nwv + wave) * 64u + lane; };  // local tile j
@@ -229,7 +231,8 @@ constexpr u32 PR_WAVES = 8;
 
 __global__ __launch_bounds__(64 * PR_WAVES) void k_blk_pivots_reg(const u64 *__restrict__ X, u32 Ls, u32 K,
                                                                   Cursor *__restrict__ cur,
-                                                                  BlkState *__restrict__ bs) {
+                                                                  BlkState *__restrict__ bs, u64 *__restrict__ zw,
+                                                                  u32 nzw) {
   __shared__ u32 s_wmin[2];  // double-buffered: step s uses s_wmin[s & 1]
   __shared__ u32 piv[KB], mrow[KB], mcol[KB], hits[KB], sq[KB], s_hdr[2];
   const u32 tid = threadIdx.x, lane = tid & 63u, wave = tid >> 6;
@@ -237,6 +240,7 @@ __global__ __launch_bounds__(64 * PR_WAVES) void k_blk_pivots_reg(const u64 *__r
   const bool in = w < K;
   if (tid < KB) { piv[tid] = 0; mrow[tid] = 0; mcol[tid] = 0; hits[tid] = 0; }
   if (tid < 2) s_wmin[tid] = 0xFFFFFFFFu;
+  for (u32 i = tid; i < nzw; i += blockDim.x) zw[i] = 0;  // words the slot's later kernels need zeroed
   u32 i0, want;
   block_take(cur, sq, s_hdr, i0, want);
   u64 sn[KB], rv[KB];
@@ -341,7 +345,7 @@ __device__ __forceinline__ void blk_masks(const u64 *__restrict__ X, u64 *__rest
 }
 
 // Distinct row words holding pivots whose loads a thread issues together
-// (k_blk_special, k_blk_sv_prep).
+// (blk_special, k_blk_sv_prep).
 constexpr u32 SPEC_B = 8;
 
 // -------------------------------------------------------------- pivot rows and their algebra
@@ -725,18 +729,17 @@ __global__ __launch_bounds__(ROWS_T) void k_blk_reduce(u64 *__restrict__ part, c
 }
 
 // -------------------------------------------------------------- final
-// Thread per row word (blocks of BLK_SIGN_T): new signs of the hit rows from
+// Thread per row word (blocks of BLK_FIN_T): new signs of the hit rows from
 // the lam algebra, then the special rows' signs (dsign, the coins). The hit
 // masks stay in registers (the pivot conditions are uniform). The block's
 // byte count (x and z of every supported column, read and written, for each
 // row word holding a hit row) is added here too.
-constexpr u32 BLK_SIGN_T = 128;
+constexpr u32 BLK_FIN_T = 256;  // threads per workgroup of k_blk_signs_special
 
-__global__ __launch_bounds__(BLK_SIGN_T) void k_blk_signs(u64 *__restrict__ R, const u64 *__restrict__ bm,
-                                                           const u64 *__restrict__ part,
-                                                           const BlkState *__restrict__ bs,
-                                                           MeasState *__restrict__ st, MeasStats *__restrict__ stats,
-                                                           u32 Ls, u32 L, u32 K) {
+__device__ __forceinline__ void blk_signs(u64 *__restrict__ R, const u64 *__restrict__ bm,
+                                          const u64 *__restrict__ part, const BlkState *__restrict__ bs,
+                                          MeasState *__restrict__ st, MeasStats *__restrict__ stats, u32 Ls, u32 L,
+                                          u32 K, u32 bid) {
   __shared__ u32 spv[KB], sfl[KB];  // per pivot: row, D-row sign (bit 0) and coin (bit 1)
   const u32 k = bs->k;
   if (k == 0) return;  // the same for every workgroup
@@ -745,7 +748,7 @@ __global__ __launch_bounds__(BLK_SIGN_T) void k_blk_signs(u64 *__restrict__ R, c
     sfl[threadIdx.x] = (bs->dsign[threadIdx.x] ? 1u : 0u) | (bs->coin[threadIdx.x] ? 2u : 0u);
   }
   __syncthreads();
-  const u32 w = blockIdx.x * blockDim.x + threadIdx.x;
+  const u32 w = bid * blockDim.x + threadIdx.x;
   const bool in = w < L;
   u64 b[KB];
 #pragma unroll
@@ -805,8 +808,9 @@ __global__ __launch_bounds__(BLK_SIGN_T) void k_blk_signs(u64 *__restrict__ R, c
 // its later hits, S_{p_s} = Z_{q_s}. The words are distinct, so a thread
 // loads SPEC_B of them (x and z, both halves) before changing any: a memory
 // round trip per SPEC_B words instead of one per word.
-__global__ void k_blk_special(u64 *__restrict__ X, u64 *__restrict__ Z, const u32 *__restrict__ patx,
-                              const u32 *__restrict__ patz, const BlkState *__restrict__ bs, u32 Ls, u32 K, u32 n) {
+__device__ __forceinline__ void blk_special(u64 *__restrict__ X, u64 *__restrict__ Z, const u32 *__restrict__ patx,
+                                            const u32 *__restrict__ patz, const BlkState *__restrict__ bs, u32 Ls,
+                                            u32 K, u32 n, u32 bid) {
   __shared__ u32 spv[KB], sdh[KB], sqb[KB];  // per pivot: row, D-row factors, measured qubit
   const u32 k = bs->k;
   if (k == 0) return;  // the same for every workgroup
@@ -817,7 +821,7 @@ __global__ void k_blk_special(u64 *__restrict__ X, u64 *__restrict__ Z, const u3
     sqb[tid] = bs->q[tid];
   }
   __syncthreads();
-  const u32 j = blockIdx.x * blockDim.x + tid;
+  const u32 j = bid * blockDim.x + tid;
   if (j >= n) return;
   const u32 px = patx[j], pz = patz[j];
   u64 *x = X + (size_t)j * Ls;
@@ -858,11 +862,23 @@ __global__ void k_blk_special(u64 *__restrict__ X, u64 *__restrict__ Z, const u3
   }
 }
 
+// The sign update and the special rows in one launch (they do not depend on
+// each other): workgroups [0, sblocks) take row words, the others columns.
+__global__ __launch_bounds__(BLK_FIN_T) void k_blk_signs_special(
+    u64 *__restrict__ R, const u64 *__restrict__ bm, const u64 *__restrict__ part, const BlkState *__restrict__ bs,
+    MeasState *__restrict__ st, MeasStats *__restrict__ stats, u64 *__restrict__ X, u64 *__restrict__ Z,
+    const u32 *__restrict__ patx, const u32 *__restrict__ patz, u32 Ls, u32 L, u32 K, u32 n, u32 sblocks) {
+  if (blockIdx.x < sblocks)
+    blk_signs(R, bm, part, bs, st, stats, Ls, L, K, blockIdx.x);
+  else
+    blk_special(X, Z, patx, patz, bs, Ls, K, n, blockIdx.x - sblocks);
+}
+
 // -------------------------------------------------------------- symbolic signs (sampling sweep)
 // With stabilizer signs kept as affine forms in the coins (sign column v =
 // coefficient of coin v, column `count` = the constant), a block acts on the
 // forms linearly. With every original sign set to 0 the block's algebra gives
-// a constant c(h) per hit row (k_blk_signs writes it when run on a zeroed sign
+// a constant c(h) per hit row (blk_signs writes it when run on a zeroed sign
 // word array); the sign-dependent part is
 //   r'(h) = r(h) ^ XOR_s b_s(h) Lin(P_s),  Lin(P_s) = r(S0_{p_s}) ^ XOR_{s' hits s} Lin(P_{s'}),
 // and S_{p_s} becomes Z_{q_s} with its own coin (column m0 + s) as sign.
@@ -964,13 +980,15 @@ __global__ __launch_bounds__(64) void k_blk_sv_update(u64 *__restrict__ sg, u32 
 // Stage 0: the sequential pivot step on the cursor's next measurements (it
 // writes BlkState::k, which every later kernel of the block reads, and
 // advances the cursor).
-hipError_t launch_blk_pivots(const TabDev &t, Cursor *cur, const BlkBuffers &b, u32 waves, hipStream_t s) {
+hipError_t launch_blk_pivots(const TabDev &t, Cursor *cur, const BlkBuffers &b, u32 waves, u64 *zero_words,
+                             u32 nzero, hipStream_t s) {
   const u32 tiles = std::max<u32>(1, cdiv(t.K, 64));
   if (waves == PIVOT_AUTO && tiles <= PR_WAVES)
-    hipLaunchKernelGGL(k_blk_pivots_reg, dim3(1), dim3(64 * tiles), 0, s, t.X, t.Ls, t.K, cur, b.bs);
+    hipLaunchKernelGGL(k_blk_pivots_reg, dim3(1), dim3(64 * tiles), 0, s, t.X, t.Ls, t.K, cur, b.bs, zero_words,
+                       nzero);
   else
     hipLaunchKernelGGL(k_blk_pivots, dim3(1), dim3(64 * std::min<u32>({PW_WAVES, tiles, waves})), 0, s, t.X,
-                       b.bm, t.Ls, t.K, cur, b.bs);
+                       b.bm, t.Ls, t.K, cur, b.bs, zero_words, nzero);
   return hipGetLastError();
 }
 
@@ -997,10 +1015,9 @@ hipError_t launch_blk_final(const TabDev &t, const BlkBuffers &b, MeasState *st,
   // k_blk_reduce: a wave per (row word, field), then one workgroup for the pivot algebra
   hipLaunchKernelGGL(k_blk_reduce, dim3(cdiv(t.L, ROWS_T / 64) + 1, 2), dim3(ROWS_T), 0, s, b.part, b.bm, b.wpart,
                      b.bs, st, t.Ls, t.L, nchunks, cdiv(t.n, ROWS_T));
-  hipLaunchKernelGGL(k_blk_signs, dim3(cdiv(t.L, BLK_SIGN_T)), dim3(BLK_SIGN_T), 0, s, t.R, b.bm, b.part, b.bs, st,
-                     stats, t.Ls, t.L, t.K);
-  hipLaunchKernelGGL(k_blk_special, dim3(cdiv(t.n, 256)), dim3(256), 0, s, t.X, t.Z, b.patx, b.patz, b.bs, t.Ls, t.K,
-                     t.n);
+  const u32 sblocks = cdiv(t.L, BLK_FIN_T);
+  hipLaunchKernelGGL(k_blk_signs_special, dim3(sblocks + cdiv(t.n, BLK_FIN_T)), dim3(BLK_FIN_T), 0, s, t.R, b.bm,
+                     b.part, b.bs, st, stats, t.X, t.Z, b.patx, b.patz, t.Ls, t.L, t.K, t.n, sblocks);
   return hipGetLastError();
 }
 

@@ -228,7 +228,10 @@ hipError_t launch_batch(const BatchItem *items, u32 nitems, u32 *next, u32 block
 // waves: PIVOT_AUTO (the C-ABI's SQ_PIVOT_AUTO), or 1..16 for the tiled search
 // with that many waves
 constexpr u32 PIVOT_AUTO = 255;
-hipError_t launch_blk_pivots(const TabDev &t, Cursor *cur, const BlkBuffers &b, u32 waves, hipStream_t s);
+// zero_words[0 .. nzero) are cleared by the pivot kernel (the sampler's
+// zeroed sign words for the slot's later kernels); nullptr, 0 for none.
+hipError_t launch_blk_pivots(const TabDev &t, Cursor *cur, const BlkBuffers &b, u32 waves, u64 *zero_words,
+                             u32 nzero, hipStream_t s);
 hipError_t launch_blk_prep(const TabDev &t, const BlkBuffers &b, hipStream_t s);
 hipError_t launch_blk_pass(const TabDev &t, const BlkBuffers &b, u32 cpc, hipStream_t s);
 hipError_t launch_blk_final(const TabDev &t, const BlkBuffers &b, MeasState *st, MeasStats *stats, u32 cpc,

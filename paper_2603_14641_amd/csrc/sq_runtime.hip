@@ -535,8 +535,9 @@ sq_status queue_slot(sq_tableau *T, const SweepCtx &c, u32 kb) {
     }));
     return SQ_OK;
   }
-  if (c.cvec) HIP_TRY(launch_fill_zero(c.cvec, T->d.Ls, T->stream));
-  SQ_TRY(timed(T, SQ_K_BPIVOT, [&] { return launch_blk_pivots(c.tabb, T->cur, T->blk, T->tun.pivot_waves, T->stream); }));
+  SQ_TRY(timed(T, SQ_K_BPIVOT, [&] {
+    return launch_blk_pivots(c.tabb, T->cur, T->blk, T->tun.pivot_waves, c.cvec, c.cvec ? T->d.Ls : 0u, T->stream);
+  }));
   SQ_TRY(timed(T, SQ_K_BPREP, [&] { return launch_blk_prep(c.tabb, T->blk, T->stream); }));
   SQ_TRY(timed(T, SQ_K_BPASS, [&] { return launch_blk_pass(c.tabb, T->blk, T->blk_cpc, T->stream); }));
   SQ_TRY(timed(T, SQ_K_BFINAL, [&] {
