@@ -345,7 +345,7 @@ __device__ __forceinline__ void blk_masks(const u64 *__restrict__ X, u64 *__rest
 }
 
 // Distinct row words holding pivots whose loads a thread issues together
-// (blk_special, k_blk_sv_prep).
+// (blk_special, blk_sv_prep).
 constexpr u32 SPEC_B = 8;
 
 // -------------------------------------------------------------- pivot rows and their algebra
@@ -862,17 +862,6 @@ __device__ __forceinline__ void blk_special(u64 *__restrict__ X, u64 *__restrict
   }
 }
 
-// The sign update and the special rows in one launch (they do not depend on
-// each other): workgroups [0, sblocks) take row words, the others columns.
-__global__ __launch_bounds__(BLK_FIN_T) void k_blk_signs_special(
-    u64 *__restrict__ R, const u64 *__restrict__ bm, const u64 *__restrict__ part, const BlkState *__restrict__ bs,
-    MeasState *__restrict__ st, MeasStats *__restrict__ stats, u64 *__restrict__ X, u64 *__restrict__ Z,
-    const u32 *__restrict__ patx, const u32 *__restrict__ patz, u32 Ls, u32 L, u32 K, u32 n, u32 sblocks) {
-  if (blockIdx.x < sblocks)
-    blk_signs(R, bm, part, bs, st, stats, Ls, L, K, blockIdx.x);
-  else
-    blk_special(X, Z, patx, patz, bs, Ls, K, n, blockIdx.x - sblocks);
-}
 
 // -------------------------------------------------------------- symbolic signs (sampling sweep)
 // With stabilizer signs kept as affine forms in the coins (sign column v =
@@ -886,10 +875,10 @@ __global__ __launch_bounds__(BLK_FIN_T) void k_blk_signs_special(
 // Thread t <= m0 (m0 = the block's list position): sign column v = t
 // (t < m0) or the constant (t = m0); bit s of svt[t] = coefficient of column
 // v in Lin(P_s).
-__global__ void k_blk_sv_prep(const u64 *__restrict__ sg, u32 Ks, u32 count, const BlkState *__restrict__ bs,
-                              u32 *__restrict__ svt) {
+__device__ __forceinline__ void blk_sv_prep(const u64 *__restrict__ sg, u32 Ks, u32 count,
+                                            const BlkState *__restrict__ bs, u32 *__restrict__ svt, u32 bid) {
   const u32 k = bs->k, m0 = bs->i0;
-  const u32 t = blockIdx.x * blockDim.x + threadIdx.x;
+  const u32 t = bid * blockDim.x + threadIdx.x;
   if (k == 0 || t > m0) return;
   const u32 v = t < m0 ? t : count;
   const u32 nw = bs->nwords;
@@ -910,6 +899,23 @@ __global__ void k_blk_sv_prep(const u64 *__restrict__ sg, u32 Ks, u32 count, con
   u32 lin = 0;
   for (u32 s = 0; s < k; ++s) lin |= ((((s0 >> s) & 1u) ^ ((u32)__popc(lin & bs->hitS[s]) & 1u)) << s);
   svt[t] = lin;
+}
+
+// The sign update, the special rows and (sampling) the coefficients of the
+// pivots' sign forms in one launch (none depends on another): workgroups
+// [0, sblocks) take row words, [sblocks, sblocks + cblocks) columns, the
+// rest the sign-form columns (sg != nullptr only on the sampling path).
+__global__ __launch_bounds__(BLK_FIN_T) void k_blk_signs_special(
+    u64 *__restrict__ R, const u64 *__restrict__ bm, const u64 *__restrict__ part, const BlkState *__restrict__ bs,
+    MeasState *__restrict__ st, MeasStats *__restrict__ stats, u64 *__restrict__ X, u64 *__restrict__ Z,
+    const u32 *__restrict__ patx, const u32 *__restrict__ patz, const u64 *__restrict__ sg, u32 Ks, u32 count,
+    u32 *__restrict__ svt, u32 Ls, u32 L, u32 K, u32 n, u32 sblocks, u32 cblocks) {
+  if (blockIdx.x < sblocks)
+    blk_signs(R, bm, part, bs, st, stats, Ls, L, K, blockIdx.x);
+  else if (blockIdx.x < sblocks + cblocks)
+    blk_special(X, Z, patx, patz, bs, Ls, K, n, blockIdx.x - sblocks);
+  else
+    blk_sv_prep(sg, Ks, count, bs, svt, blockIdx.x - sblocks - cblocks);
 }
 
 // Grid (stabilizer-word tiles, workgroups over column chunks of SV_CHUNK):
@@ -1008,26 +1014,29 @@ hipError_t launch_blk_pass(const TabDev &t, const BlkBuffers &b, u32 cpc, hipStr
   return hipGetLastError();
 }
 
-// Stage 3: chunk reduction, signs and the special rows.
+// Stage 3: chunk reduction with the pivot algebra, then signs, the special
+// rows and (sampling: sg != nullptr) the pivots' sign-form coefficients svt.
 hipError_t launch_blk_final(const TabDev &t, const BlkBuffers &b, MeasState *st, MeasStats *stats, u32 cpc,
-                            hipStream_t s) {
+                            const u64 *sg, u32 Ks, u32 count, u32 *svt, hipStream_t s) {
   const u32 nchunks = cdiv(t.n, cpc);
   // k_blk_reduce: a wave per (row word, field), then one workgroup for the pivot algebra
   hipLaunchKernelGGL(k_blk_reduce, dim3(cdiv(t.L, ROWS_T / 64) + 1, 2), dim3(ROWS_T), 0, s, b.part, b.bm, b.wpart,
                      b.bs, st, t.Ls, t.L, nchunks, cdiv(t.n, ROWS_T));
-  const u32 sblocks = cdiv(t.L, BLK_FIN_T);
-  hipLaunchKernelGGL(k_blk_signs_special, dim3(sblocks + cdiv(t.n, BLK_FIN_T)), dim3(BLK_FIN_T), 0, s, t.R, b.bm,
-                     b.part, b.bs, st, stats, t.X, t.Z, b.patx, b.patz, t.Ls, t.L, t.K, t.n, sblocks);
+  const u32 sblocks = cdiv(t.L, BLK_FIN_T), cblocks = cdiv(t.n, BLK_FIN_T);
+  const u32 vblocks = sg ? cdiv(count + 1, BLK_FIN_T) : 0u;  // sign-form columns 0 .. count
+  hipLaunchKernelGGL(k_blk_signs_special, dim3(sblocks + cblocks + vblocks), dim3(BLK_FIN_T), 0, s, t.R, b.bm,
+                     b.part, b.bs, st, stats, t.X, t.Z, b.patx, b.patz, sg, Ks, count, svt, t.Ls, t.L, t.K, t.n,
+                     sblocks, cblocks);
   return hipGetLastError();
 }
 
-// Symbolic signs after a block whose pass and special rows are done; cvec
-// holds the constants c(h) (the block ran with it as its zeroed sign array).
+// Symbolic signs after a block whose pass, special rows and svt are done;
+// cvec holds the constants c(h) (the block ran with it as its zeroed sign
+// array).
 // The block's list position is read on the device, so the grid covers every
 // position up to `count`.
-hipError_t launch_blk_sv(u64 *sg, u32 Ks, u32 count, const BlkBuffers &b, u32 *svt, const u64 *cvec, u32 Ls, u32 K,
-                         hipStream_t s) {
-  hipLaunchKernelGGL(k_blk_sv_prep, dim3(cdiv(count + 1, 256)), dim3(256), 0, s, sg, Ks, count, b.bs, svt);
+hipError_t launch_blk_sv(u64 *sg, u32 Ks, u32 count, const BlkBuffers &b, const u32 *svt, const u64 *cvec, u32 Ls,
+                         u32 K, hipStream_t s) {
   const u32 ychunks = std::min<u32>(SV_MAX_Y, cdiv(count + 1, SV_CHUNK));
   hipLaunchKernelGGL(k_blk_sv_update, dim3(cdiv(K, 64), ychunks), dim3(64), 0, s, sg, Ks, count, b.bs, b.bm, svt,
                      cvec, Ls, K);

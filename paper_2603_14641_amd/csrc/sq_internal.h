@@ -235,9 +235,9 @@ hipError_t launch_blk_pivots(const TabDev &t, Cursor *cur, const BlkBuffers &b, 
 hipError_t launch_blk_prep(const TabDev &t, const BlkBuffers &b, hipStream_t s);
 hipError_t launch_blk_pass(const TabDev &t, const BlkBuffers &b, u32 cpc, hipStream_t s);
 hipError_t launch_blk_final(const TabDev &t, const BlkBuffers &b, MeasState *st, MeasStats *stats, u32 cpc,
-                            hipStream_t s);
-hipError_t launch_blk_sv(u64 *sg, u32 Ks, u32 count, const BlkBuffers &b, u32 *svt, const u64 *cvec, u32 Ls, u32 K,
-                         hipStream_t s);
+                            const u64 *sg, u32 Ks, u32 count, u32 *svt, hipStream_t s);
+hipError_t launch_blk_sv(u64 *sg, u32 Ks, u32 count, const BlkBuffers &b, const u32 *svt, const u64 *cvec, u32 Ls,
+                         u32 K, hipStream_t s);
 hipError_t launch_frame_init(u64 *Fx, u64 *Fz, u32 n, u32 Lf, u32 Ls, u64 seed, hipStream_t s);
 hipError_t launch_frame_measure(const u64 *Fx, u64 *Fz, const u32 *qubits, u32 count, u64 m0, const uint8_t *ref,
                                 u64 *rec, u32 n, u32 Lf, u32 Ls, u64 seed, hipStream_t s);

@@ -541,7 +541,8 @@ sq_status queue_slot(sq_tableau *T, const SweepCtx &c, u32 kb) {
   SQ_TRY(timed(T, SQ_K_BPREP, [&] { return launch_blk_prep(c.tabb, T->blk, T->stream); }));
   SQ_TRY(timed(T, SQ_K_BPASS, [&] { return launch_blk_pass(c.tabb, T->blk, T->blk_cpc, T->stream); }));
   SQ_TRY(timed(T, SQ_K_BFINAL, [&] {
-    return launch_blk_final(c.tabb, T->blk, T->st, c.bstats, T->blk_cpc, T->stream);
+    return launch_blk_final(c.tabb, T->blk, T->st, c.bstats, T->blk_cpc, c.sym ? c.sym->sg : nullptr,
+                            c.sym ? c.sym->Ks : 0u, c.sym ? c.sym->count : 0u, c.svt, T->stream);
   }));
   if (c.sym) HIP_TRY(launch_blk_sv(c.sym->sg, c.sym->Ks, c.sym->count, T->blk, c.svt, c.cvec, T->d.Ls, T->d.K,
                                    T->stream));
