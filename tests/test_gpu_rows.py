@@ -64,7 +64,8 @@ def _slots(buf, info, which):
     return words.view(64 * K, Ls).cpu().numpy().view(np.uint64)
 
 
-@pytest.mark.parametrize("n", [1, 63, 64, 65, 200, 1100, 4100])
+# K = ceil(n / 64) covers the stabilizer half's grid shifts K mod 16 = 0, 1, 2, 4, 15
+@pytest.mark.parametrize("n", [1, 63, 64, 65, 200, 960, 1024, 1100, 2047, 4100])
 def test_transposed_block_is_row_major(n):
     from paper_2603_14641_amd import LAYOUT_COLUMNS, LAYOUT_ROWS
     rng = np.random.default_rng(n)
