@@ -313,6 +313,12 @@ __device__ __forceinline__ u64 prefix_xor_incl(u64 v) {
   return v;
 }
 
+// The deterministic product's column walk (k_post): list entries per lane
+// per round when A's words take more than one wave-wide step, and columns
+// whose loads are issued together when they fit in one.
+constexpr u32 DET_U = 4;
+constexpr u32 DET_CB = 4;
+
 // One word of a deterministic product in a column: x1/z1 are the column's
 // stabilizer bits at 64 rows of A (zero outside A), one word per lane in
 // ascending row order across the wave; cx/cz the XOR of the column's bits over
@@ -320,9 +326,6 @@ __device__ __forceinline__ u64 prefix_xor_incl(u64 v) {
 // row i has x/z equal to that carry plus the exclusive prefix XOR inside the
 // word group, and S_i's phase contribution against it is +1, -1 or 0 (the
 // g function of the rowsum). Call with the whole wave.
-constexpr u32 DET_U = 4;   // list entries per lane per round (A beyond one round)
-constexpr u32 DET_CB = 4;  // columns per batch of loads (A within one round)
-
 __device__ __forceinline__ void det_word(u64 x1, u64 z1, u32 &cx, u32 &cz, int &acc) {
   const u64 bx = __ballot(__popcll(x1) & 1), bz = __ballot(__popcll(z1) & 1);
   const u64 lt = lanemask_lt();
@@ -354,9 +357,9 @@ __device__ __forceinline__ void det_word(u64 x1, u64 z1, u32 &cx, u32 &cz, int &
 // k_pivot listed (alist/amask), 64 per wave-wide step (det_word), so a column
 // costs the bytes of A's words, not of all K. The column's total XOR
 // must be 0 for x and [j == q] for z. Blocks add their sums into the ticket
-// word det_done; the last block to finish (no waiting) forms the outcome: parity of
-// S_i's signs over A xor bit 1 of the sum (which must be even). The sampler's
-// blocks also compute the coin coefficients of the outcome's affine form
+// word det_done; the last block to finish (no waiting) forms the outcome:
+// parity of S_i's signs over A xor bit 1 of the sum (which must be even). The
+// sampler's blocks also compute the coin coefficients of the outcome's affine form
 // (parity of sign column v over A, v < i), and the last block its constant.
 template <bool SYM>
 __global__ __launch_bounds__(256) void k_post(u64 *__restrict__ X, u64 *__restrict__ Z, u64 *__restrict__ R,
