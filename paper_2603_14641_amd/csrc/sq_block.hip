@@ -111,10 +111,36 @@ __device__ void pivots_finish(u32 lane, u32 k, u32 want, u32 i0, const u32 *sq, 
 }
 
 
+// Before the tiled search: where each measured column's stabilizer half
+// starts to be nonzero. Grid (cdiv(K, 256), KB): workgroup (g, s) writes the
+// first stabilizer word in [256 g, 256 g + 256) where column q_s of X is
+// nonzero (0xFFFFFFFF for none) to fz[s * G + g], for the s < want of the
+// block the cursor offers. Step s of the search then starts at
+//   lb_s = min over s' <= s of (column q_s' first nonzero word):
+// below lb_s the column and every earlier step's row (a sum of hit rows of
+// the earlier columns) are zero, so those tiles need no visit.
+__global__ __launch_bounds__(256) void k_blk_firstnz(const u64 *__restrict__ X, u32 Ls, u32 K,
+                                                     const Cursor *__restrict__ cur, u32 *__restrict__ fz, u32 G) {
+  __shared__ u32 s_min;
+  const u32 s = blockIdx.y, g = blockIdx.x, tid = threadIdx.x;
+  const u32 i = cur->i, end = cur->end;
+  const u32 want = i < end ? min(cur->kb, end - i) : 0u;
+  if (s >= want) return;  // uniform over the workgroup
+  const u32 q = cur->qubits[i + s];
+  if (tid == 0) s_min = 0xFFFFFFFFu;
+  __syncthreads();
+  const u32 w = g * 256u + tid;
+  const bool nz = w < K && X[(size_t)q * Ls + K + w] != 0ULL;
+  const u64 b = __ballot(nz);
+  if (b && (tid & 63u) == 0) atomicMin(&s_min, g * 256u + (tid & ~63u) + (u32)__builtin_ctzll(b));
+  __syncthreads();
+  if (tid == 0) fz[s * G + g] = s_min;
+}
+
 __global__ __launch_bounds__(64 * PW_WAVES) void k_blk_pivots(const u64 *__restrict__ X, u64 *__restrict__ bm,
                                                                u32 Ls, u32 K, Cursor *__restrict__ cur,
                                                                BlkState *__restrict__ bs, u64 *__restrict__ zw,
-                                                               u32 nzw) {
+                                                               u32 nzw, const u32 *__restrict__ fz, u32 G) {
   __shared__ u32 s_wmin[2];  // double-buffered: step s uses s_wmin[s & 1]
   // per-step state in LDS (indexed by step, which is not a compile-time
   // constant); done[] is per wave and written by its lane 0
@@ -125,21 +151,44 @@ __global__ __launch_bounds__(64 * PW_WAVES) void k_blk_pivots(const u64 *__restr
   __shared__ u32 sdone[PW_WAVES][KB];  // tiles of each wave computed per step
   __shared__ u32 sq[KB];               // measured qubits (step s reads column q_s of X)
   __shared__ u32 s_hdr[2];
+  __shared__ u32 slb[KB];              // lb_s: below this word step s (and its row) is zero
   const u32 tid = threadIdx.x, lane = tid & 63u, wave = tid >> 6, nwv = blockDim.x >> 6;
   const u32 ntiles = (K + 63u) / 64u;
   u32 *done = sdone[wave];
   if (tid < KB) { piv[tid] = 0; mrow[tid] = 0; mcol[tid] = 0; hits[tid] = 0; }
   if (tid < 2) s_wmin[tid] = 0xFFFFFFFFu;
-  if (lane < KB) done[lane] = 0;
   for (u32 i = tid; i < nzw; i += blockDim.x) zw[i] = 0;  // words the slot's later kernels need zeroed
   u32 i0, want;
   block_take(cur, sq, s_hdr, i0, want);
+  // each column's first nonzero stabilizer word: 32 threads per step, a
+  // minimum over the chunks, then the prefix minimum over the steps
+  for (u32 s = tid >> 5; s < KB; s += blockDim.x >> 5) {
+    u32 m = 0xFFFFFFFFu;
+    if (s < want)
+      for (u32 g = tid & 31u; g < G; g += 32u) m = min(m, fz[s * G + g]);
+#pragma unroll
+    for (int off = 16; off > 0; off >>= 1) m = min(m, (u32)__shfl_xor((int)m, off));
+    if ((tid & 31u) == 0) slb[s] = m;
+  }
+  __syncthreads();
+  if (tid == 0)
+    for (u32 s = 1; s < want; ++s) slb[s] = min(slb[s], slb[s - 1]);
+  __syncthreads();
+  // this wave's first tile at or past word lb (local tile j is tile j nwv + wave)
+  auto first_tile = [&](u32 lb) -> u32 {
+    const u32 t = lb >> 6;
+    return t <= wave ? 0u : (t - wave + nwv - 1u) / nwv;
+  };
+  if (lane < KB) done[lane] = lane < want ? first_tile(slb[lane]) : 0u;  // tiles below are known zero
   auto word_of = [&](u32 j) { return (j * nwv + wave) * 64u + lane; };  // local tile j
   auto tile_word = [&](u32 s, u32 w) -> u64 {
+    // earlier rows whose bound lies past this tile were not written in this
+    // block (they are zero there); w >> 6 is the same over the wave
+    const u32 below = (u32)__ballot(lane < KB && (slb[lane & (KB - 1u)] >> 6) > (w >> 6));
     if (w >= K) return 0ULL;
     const u64 *col = bm + K + w;
     u64 v = X[(size_t)sq[s] * Ls + K + w];
-    const u32 sel = mcol[s] & ((1u << s) - 1u);
+    const u32 sel = mcol[s] & ((1u << s) - 1u) & ~below;
     // every row is loaded (rows the step does not use are masked), so the
     // loads are independent and in flight together
 #pragma unroll
@@ -158,7 +207,7 @@ __global__ __launch_bounds__(64 * PW_WAVES) void k_blk_pivots(const u64 *__restr
   u32 k = want;
   for (u32 s = 0; s < want; ++s) {
     u64 vlast = 0;  // this lane's word of step s in the last tile the wave computed
-    for (u32 j = 0; j < myt; ++j) {
+    for (u32 j = first_tile(slb[s]); j < myt; ++j) {
       // earlier steps first (their pivots are known, so their own bits are
       // cleared too); done[] never increases with the step, so done[s - 1]
       // tells whether any earlier step lacks tile j
@@ -200,7 +249,7 @@ __global__ __launch_bounds__(64 * PW_WAVES) void k_blk_pivots(const u64 *__restr
       const u64 bit = 1ULL << pb;
       // rows of earlier steps at word wmin (written before the barrier) and
       // every measured column of X there
-      const u64 hv = lane < s ? bm[(size_t)lane * Ls + K + wmin] : 0ULL;
+      const u64 hv = (lane < s && (wmin >> 6) >= (slb[lane & (KB - 1u)] >> 6)) ? bm[(size_t)lane * Ls + K + wmin] : 0ULL;
       const u64 sv = lane < want ? X[(size_t)sq[lane] * Ls + K + wmin] : 0ULL;
       const u32 hit = (u32)__ballot((hv & bit) != 0);  // earlier pivots that hit S_p
       // x bit of P_s at the later measured column q_lane: X's bit at p plus
@@ -992,9 +1041,12 @@ hipError_t launch_blk_pivots(const TabDev &t, Cursor *cur, const BlkBuffers &b, 
   if (waves == PIVOT_AUTO && tiles <= PR_WAVES)
     hipLaunchKernelGGL(k_blk_pivots_reg, dim3(1), dim3(64 * tiles), 0, s, t.X, t.Ls, t.K, cur, b.bs, zero_words,
                        nzero);
-  else
+  else {
+    const u32 G = cdiv(t.K, 256);  // chunks of the first-nonzero search (fz in wpart: KB * G <= 4 KB K words)
+    hipLaunchKernelGGL(k_blk_firstnz, dim3(G, KB), dim3(256), 0, s, t.X, t.Ls, t.K, cur, b.wpart, G);
     hipLaunchKernelGGL(k_blk_pivots, dim3(1), dim3(64 * std::min<u32>({PW_WAVES, tiles, waves})), 0, s, t.X,
-                       b.bm, t.Ls, t.K, cur, b.bs, zero_words, nzero);
+                       b.bm, t.Ls, t.K, cur, b.bs, zero_words, nzero, b.wpart, G);
+  }
   return hipGetLastError();
 }
 
