@@ -127,17 +127,20 @@ def test_blocked_measurements(n, mb):
         assert st.blocks > 0
 
 
-def _deep_pivot_program(rng, n, lo, hi0, count):
+def _deep_pivot_program(rng, n, lo, hi0, count, qs=None):
     """Superpositions on qubits [0, lo) and [hi0, n) only: measuring a high
     qubit finds its pivot among stabilizer rows >= hi0 (later 64-word tiles),
     a low one in the first word, an untouched one nothing (deterministic,
-    which ends a block). The measured qubits mix all three."""
+    which ends a block). The measured qubits mix all three (or are qs)."""
     hi = np.arange(hi0, n)
     ops = [[orc.H, int(q), 0] for q in hi] + [[orc.H, q, 0] for q in range(lo)]
     perm = rng.permutation(hi)
     ops += [[orc.CX, int(a), int(b)] for a, b in zip(perm[::2], perm[1::2])]
     ops += [[orc.S, int(q), 0] for q in rng.choice(hi, hi.size // 4, replace=False)]
     ops += [[orc.CX, a, a + 1] for a in range(0, lo - 1, 2)]
+    if qs is not None:
+        ops += [[orc.MEASURE, int(q), 0] for q in qs]
+        return np.array(ops, dtype=np.uint32)
     qs = []
     for _ in range(count):
         u = rng.random()
@@ -168,6 +171,38 @@ def test_blocked_deep_pivots(n, hi0, pw):
     if pw != "auto":
         tun["pivot_waves"] = pw
     t = _tab(n, tun)
+    bits, rnd = gpu_run_calls(t, ops, seed, shot=1)
+    _assert_same(bits, rb, "outcomes")
+    _assert_same(rnd, rr, "random flags")
+    _compare_full(t, (x, z, r))
+    assert t.measure_stats().blocks > 0
+
+
+@pytest.mark.parametrize("n,hi0", [(5000, 4100), (20000, 16500)])
+@pytest.mark.parametrize("pw", [1, 2, 16])
+def test_tiled_search_starts_at_first_nonzero_bound(n, hi0, pw):
+    """The tiled search starts step s at the smallest first-nonzero
+    stabilizer word of the block's columns so far. Blocks here open with
+    high qubits (columns zero below word hi0 / 64) and then drop to low ones,
+    so later steps start below where earlier rows were written (those rows
+    are stale there and must read as zero). Other blocks are all high, or
+    hold an untouched qubit (a column with no nonzero word) first or in the
+    middle. Outcomes, flags and the whole tableau bit-exact with CHP."""
+    rng = np.random.default_rng(77 * n + pw)
+    lo = 40
+    hi = np.arange(hi0, n)
+    mid = np.arange(lo, hi0)
+    pick = lambda a, m: [int(x) for x in rng.choice(a, m, replace=False)]
+    qs = (pick(hi, 1) + pick(range(lo), 31)          # bound drops after step 0
+          + pick(hi, 32)                              # bound stays high
+          + pick(mid, 1) + pick(hi, 4)                # deterministic first
+          + pick(hi, 3) + pick(range(lo), 4) + pick(mid, 1) + pick(hi, 8)
+          + pick(hi, 2) + pick(range(lo), 30))
+    ops = _deep_pivot_program(rng, n, lo, hi0, 0, qs=qs)
+    seed = int(rng.integers(1 << 40))
+    rb, rr, x, z, r, _ = oracle_run(n, ops, seed, shot=1)
+    assert rr.sum() >= 40 and (rr == 0).sum() >= 2
+    t = _tab(n, dict(meas_block=32, pivot_waves=pw))
     bits, rnd = gpu_run_calls(t, ops, seed, shot=1)
     _assert_same(bits, rb, "outcomes")
     _assert_same(rnd, rr, "random flags")
