@@ -504,8 +504,8 @@ typedef struct {
   uint32_t det_cols;           /* columns per workgroup of the deterministic-product phase */
   uint32_t meas_block;         /* sq_measure: random measurements per blocked pass (1 = one at a time, <= 32) */
   uint32_t pivot_waves;        /* blocked pivot search: SQ_PIVOT_AUTO (default: registers when the stabilizer
-                                  half has at most 512 words, else tiles over up to 16 waves), or 1..16 =
-                                  tiles, computed lazily, over that many waves */
+                                  half has at most 512 words, else tiles over up to 8 waves), or 1..16 =
+                                  tiles over that many waves (at most 8) */
 } sq_tuning;
 #define SQ_PIVOT_AUTO 255u
 /* (Launch control of this library; no passage of the paper. Shapes never

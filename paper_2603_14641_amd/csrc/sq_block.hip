@@ -31,15 +31,20 @@ namespace sq {
 // stabilizer half of column q_s as it stands before measurement s is
 //   X_{q_s} ^ XOR_{s' < s, M[s'][s] = 1} (hit mask of s'),
 // with X as it stands before the block (nothing writes X until the pass) and
-// the rows S_{p_s'} (now Z_{q_s'}, no x) cleared. Words come in tiles of
-// 64; wave v owns the tiles t = v mod (waves) and lane l word 64t + l, so a
-// lane only ever reads words it wrote itself. Each wave computes its tiles
-// lazily, in order (for every earlier step first), and stops at its first
-// nonzero tile; the smallest such word over the waves holds the pivot. A
-// block ends before its first deterministic measurement (no nonzero word).
+// the rows S_{p_s'} (now Z_{q_s'}, no x) cleared. Unrolled, that sum is a
+// fixed GF(2) combination of the block's columns: with C = (I + M)^-1 (upper
+// triangular, column s = e_s plus the columns s' < s with M[s'][s] = 1),
+// step s's word is XOR_{t: C[t][s] = 1} X_{q_t}, earlier pivot rows cleared
+// (a cleared bit stays cleared through every later sum). The tiled search
+// computes any word of any step straight from the columns; the register
+// search keeps the rows themselves. Words come in tiles of 64; wave v owns
+// the tiles t = v mod (waves) and lane l word 64t + l; each wave walks its
+// tiles in order and stops at its first nonzero tile; the smallest such
+// word over the waves holds the pivot. A block ends before its first
+// deterministic measurement (no nonzero word).
 // The lane that owns the pivot word does the step's bookkeeping, so a step
 // costs two barriers; the per-pivot outputs are written once at the end.
-constexpr u32 PW_WAVES = 16;
+constexpr u32 PW_WAVES = 8;
 
 // The block's measurements: list[i0 .. i0 + want) from the cursor, want =
 // min(kb, end - i0), 0 once the list is done. Thread 0 reads the cursor and
@@ -137,25 +142,24 @@ __global__ __launch_bounds__(256) void k_blk_firstnz(const u64 *__restrict__ X, 
   if (tid == 0) fz[s * G + g] = s_min;
 }
 
-__global__ __launch_bounds__(64 * PW_WAVES) void k_blk_pivots(const u64 *__restrict__ X, u64 *__restrict__ bm,
-                                                               u32 Ls, u32 K, Cursor *__restrict__ cur,
-                                                               BlkState *__restrict__ bs, u64 *__restrict__ zw,
-                                                               u32 nzw, const u32 *__restrict__ fz, u32 G) {
+__global__ __launch_bounds__(64 * PW_WAVES) void k_blk_pivots(const u64 *__restrict__ X, u32 Ls, u32 K,
+                                                               Cursor *__restrict__ cur, BlkState *__restrict__ bs,
+                                                               u64 *__restrict__ zw, u32 nzw,
+                                                               const u32 *__restrict__ fz, u32 G) {
   __shared__ u32 s_wmin[2];  // double-buffered: step s uses s_wmin[s & 1]
   // per-step state in LDS (indexed by step, which is not a compile-time
-  // constant); done[] is per wave and written by its lane 0
-  __shared__ u32 piv[KB];              // pivot of each decided step
-  __shared__ u32 mrow[KB];             // M[s]: bit s2 = x of P_s at q_{s2}
-  __shared__ u32 mcol[KB];             // bit s' of mcol[s] = M[s'][s]
-  __shared__ u32 hits[KB];             // earlier pivots that hit S_{p_s}
-  __shared__ u32 sdone[PW_WAVES][KB];  // tiles of each wave computed per step
-  __shared__ u32 sq[KB];               // measured qubits (step s reads column q_s of X)
+  // constant)
+  __shared__ u32 piv[KB];   // pivot of each decided step
+  __shared__ u32 mrow[KB];  // M[s]: bit s2 = x of P_s at q_{s2}
+  __shared__ u32 mcol[KB];  // bit s' of mcol[s] = M[s'][s]
+  __shared__ u32 hits[KB];  // earlier pivots that hit S_{p_s}
+  __shared__ u32 ccol[KB];  // bit t of ccol[s] = C[t][s]: row s is the sum of the columns q_t in it
+  __shared__ u32 sq[KB];    // measured qubits (step s reads column q_s of X)
   __shared__ u32 s_hdr[2];
-  __shared__ u32 slb[KB];              // lb_s: below this word step s (and its row) is zero
+  __shared__ u32 slb[KB];   // lb_s: below this word step s's row is zero
   const u32 tid = threadIdx.x, lane = tid & 63u, wave = tid >> 6, nwv = blockDim.x >> 6;
   const u32 ntiles = (K + 63u) / 64u;
-  u32 *done = sdone[wave];
-  if (tid < KB) { piv[tid] = 0; mrow[tid] = 0; mcol[tid] = 0; hits[tid] = 0; }
+  if (tid < KB) { piv[tid] = 0; mrow[tid] = 0; mcol[tid] = 0; hits[tid] = 0; ccol[tid] = 0; }
   if (tid < 2) s_wmin[tid] = 0xFFFFFFFFu;
   for (u32 i = tid; i < nzw; i += blockDim.x) zw[i] = 0;  // words the slot's later kernels need zeroed
   u32 i0, want;
@@ -179,23 +183,18 @@ __global__ __launch_bounds__(64 * PW_WAVES) void k_blk_pivots(const u64 *__restr
     const u32 t = lb >> 6;
     return t <= wave ? 0u : (t - wave + nwv - 1u) / nwv;
   };
-  if (lane < KB) done[lane] = lane < want ? first_tile(slb[lane]) : 0u;  // tiles below are known zero
   auto word_of = [&](u32 j) { return (j * nwv + wave) * 64u + lane; };  // local tile j
-  auto tile_word = [&](u32 s, u32 w) -> u64 {
-    // earlier rows whose bound lies past this tile were not written in this
-    // block (they are zero there); w >> 6 is the same over the wave
-    const u32 below = (u32)__ballot(lane < KB && (slb[lane & (KB - 1u)] >> 6) > (w >> 6));
+  // Row s at word w: the columns q_t with bit t of c (C[t][s]) summed, the
+  // earlier pivot rows cleared. Every column is loaded (the ones not in c
+  // are masked), so the loads are independent and in flight together.
+  auto tile_word = [&](u32 s, u32 c, u32 w) -> u64 {
     if (w >= K) return 0ULL;
-    const u64 *col = bm + K + w;
-    u64 v = X[(size_t)sq[s] * Ls + K + w];
-    const u32 sel = mcol[s] & ((1u << s) - 1u) & ~below;
-    // every row is loaded (rows the step does not use are masked), so the
-    // loads are independent and in flight together
+    u64 b[KB];
 #pragma unroll
-    for (u32 sp = 0; sp < KB; ++sp) {
-      const u64 b = col[(size_t)sp * Ls];
-      v ^= ((sel >> sp) & 1u) ? b : 0ULL;
-    }
+    for (u32 t = 0; t < KB; ++t) b[t] = X[(size_t)sq[t] * Ls + K + w];  // past want: column q_0's word
+    u64 v = 0;
+#pragma unroll
+    for (u32 t = 0; t < KB; ++t) v ^= ((c >> t) & 1u) ? b[t] : 0ULL;
 #pragma unroll
     for (u32 sp = 0; sp < KB; ++sp) {
       const u32 pv = piv[sp];
@@ -206,26 +205,15 @@ __global__ __launch_bounds__(64 * PW_WAVES) void k_blk_pivots(const u64 *__restr
   const u32 myt = ntiles > wave ? (ntiles - wave + nwv - 1) / nwv : 0;  // tiles of this wave
   u32 k = want;
   for (u32 s = 0; s < want; ++s) {
+    // C's column s: step s's own column plus the columns of the earlier rows
+    // that hit it (M[s'][s] of every s' < s is known)
+    u32 c = 1u << s;
+    for (u32 m = mcol[s]; m != 0u; m &= m - 1u) c ^= ccol[__builtin_ctz(m)];
+    if (tid == 0) ccol[s] = c;  // read by later steps, after this step's barriers
     u64 vlast = 0;  // this lane's word of step s in the last tile the wave computed
     for (u32 j = first_tile(slb[s]); j < myt; ++j) {
-      // earlier steps first (their pivots are known, so their own bits are
-      // cleared too); done[] never increases with the step, so done[s - 1]
-      // tells whether any earlier step lacks tile j
-      if (s > 0 && done[s - 1] <= j) {
-        for (u32 sp = 0; sp < s; ++sp) {
-          for (u32 d = done[sp]; d <= j; ++d) {
-            const u32 w = word_of(d);
-            u64 v = tile_word(sp, w);
-            if ((piv[sp] >> 6) == w) v &= ~(1ULL << (piv[sp] & 63u));
-            if (w < K) bm[(size_t)sp * Ls + K + w] = v;
-          }
-          if (lane == 0 && done[sp] <= j) done[sp] = j + 1;
-        }
-      }
       const u32 w = word_of(j);
-      const u64 v = tile_word(s, w);
-      if (w < K) bm[(size_t)s * Ls + K + w] = v;
-      if (lane == 0) done[s] = j + 1;
+      const u64 v = tile_word(s, c, w);
       vlast = v;
       const u64 nz = __ballot(v != 0);
       if (nz) {  // uniform over the wave
@@ -244,20 +232,20 @@ __global__ __launch_bounds__(64 * PW_WAVES) void k_blk_pivots(const u64 *__restr
     // step's bookkeeping, one lane per step
     if (wave == (wmin >> 6) % nwv) {
       const u32 pl = wmin & 63u;
-      const u64 vmin = shfl_u64(vlast, (int)pl);
-      const u32 pb = (u32)__builtin_ctzll(vmin);
-      const u64 bit = 1ULL << pb;
-      // rows of earlier steps at word wmin (written before the barrier) and
-      // every measured column of X there
-      const u64 hv = (lane < s && (wmin >> 6) >= (slb[lane & (KB - 1u)] >> 6)) ? bm[(size_t)lane * Ls + K + wmin] : 0ULL;
+      const u32 pb = (u32)__builtin_ctzll(shfl_u64(vlast, (int)pl));
+      // every measured column of X at word wmin; bit t of xb: column q_t has
+      // x at row p
       const u64 sv = lane < want ? X[(size_t)sq[lane] * Ls + K + wmin] : 0ULL;
-      const u32 hit = (u32)__ballot((hv & bit) != 0);  // earlier pivots that hit S_p
+      const u32 xb = (u32)__ballot(((sv >> pb) & 1ULL) != 0);
+      // earlier pivots that hit S_p: row s' has x at p (p is none of the
+      // earlier pivots, so the cleared bits do not matter there)
+      const bool h = lane < s && (__popc(ccol[lane & (KB - 1u)] & xb) & 1);
+      const u32 hit = (u32)__ballot(h);
       // x bit of P_s at the later measured column q_lane: X's bit at p plus
       // the earlier pivots that hit S_p (M is known for those)
       const bool later = lane > s && lane < want;
       const bool mine = later && ((((u32)(sv >> pb)) ^ (u32)__popc(hit & mcol[lane & (KB - 1u)])) & 1u);
       const u32 mb = (u32)__ballot(mine);
-      if (lane == pl) bm[(size_t)s * Ls + K + wmin] = vmin & ~bit;  // S_p is not multiplied by P_s
       if (mine) mcol[lane] |= 1u << s;
       if (lane == 0) {
         piv[s] = wmin * 64u + pb;
@@ -1045,7 +1033,7 @@ hipError_t launch_blk_pivots(const TabDev &t, Cursor *cur, const BlkBuffers &b, 
     const u32 G = cdiv(t.K, 256);  // chunks of the first-nonzero search (fz in wpart: KB * G <= 4 KB K words)
     hipLaunchKernelGGL(k_blk_firstnz, dim3(G, KB), dim3(256), 0, s, t.X, t.Ls, t.K, cur, b.wpart, G);
     hipLaunchKernelGGL(k_blk_pivots, dim3(1), dim3(64 * std::min<u32>({PW_WAVES, tiles, waves})), 0, s, t.X,
-                       b.bm, t.Ls, t.K, cur, b.bs, zero_words, nzero, b.wpart, G);
+                       t.Ls, t.K, cur, b.bs, zero_words, nzero, b.wpart, G);
   }
   return hipGetLastError();
 }

@@ -158,10 +158,11 @@ def _deep_pivot_program(rng, n, lo, hi0, count, qs=None):
 @pytest.mark.parametrize("pw", ["auto", 1, 2, 16])
 def test_blocked_deep_pivots(n, hi0, pw):
     """Pivots spread over several 64-word tiles of the stabilizer half, for
-    both pivot searches: registers (automatic at these sizes) and the lazy
-    tiled one with 1, 2 or 16 waves (a wave owning several tiles computes
-    later tiles of earlier steps on demand). Outcomes, flags and the whole
-    tableau bit-exact with one-at-a-time CHP."""
+    both pivot searches: registers (automatic at these sizes) and the tiled
+    one with 1, 2 or 16 waves (16 runs as 8, its maximum; a wave owning
+    several tiles walks them in order, each word formed from the block's
+    columns). Outcomes, flags and the whole tableau bit-exact with
+    one-at-a-time CHP."""
     rng = np.random.default_rng(n + (0 if pw == "auto" else pw))
     ops = _deep_pivot_program(rng, n, 40, hi0, 96)
     seed = int(rng.integers(1 << 40))
